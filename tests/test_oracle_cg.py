@@ -1,0 +1,116 @@
+"""Pins for the oracle's PCG (Alg. 1) and FP32-in-FP64 refinement.
+
+Checked against: a dense textbook solve (numpy.linalg.solve) on tiny grids;
+the one-step convergence of CG on an eigenvector right-hand side; exact
+homogeneity A(2 mu) = 2 A(mu) (power-of-two scaling commutes with rounding,
+so the residual history is bitwise identical and x is exactly halved);
+mirror symmetry; the zero-iteration exit of an exact start (the L = 0 rows of
+the paper's Table 1); the L_max exit; and breakdown on an indefinite system.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_13862_amd import workloads as W
+
+
+@pytest.mark.parametrize("prec", [oracle.PREC_NONE, oracle.PREC_JACOBI])
+@pytest.mark.parametrize("spec", [W.Problem(4, W.KIND_BLOCKS, W.BLOCKS3),
+                                  W.Problem(6, W.KIND_BLOCKS, W.BLOCKS4),
+                                  W.Problem(5, W.KIND_OCTANTS),
+                                  W.Problem(5, W.KIND_OCTANTS_ANISO, (), W.F_GAUSS)])
+def test_cg_matches_dense_solve(spec, prec):
+    P = oracle.Problem(spec)
+    for m in W.sample_mu(spec, 0.01, 100.0, 3, 4):
+        A = P.dense(m)
+        f = P.rhs(m)
+        ref = np.linalg.solve(A, f)
+        x, st = P.cg(m, prec=prec, tol=1e-13)
+        assert st["status"] == oracle.CONVERGED
+        assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+        # the reported final residual is the true one, f - A x
+        r = f - P.apply(m, x)
+        assert oracle.exact_dot(r, r) == st["final_rr"]
+        assert st["final_rr"] <= (1e-13 * 1e-13) * oracle.exact_dot(f, f)
+
+
+def test_eigenvector_one_iteration():
+    n = 9
+    h = 1.0 / (n + 1)
+    g = np.sin(np.pi * h * np.arange(1, n + 1))
+    w = np.einsum("k,j,i->kji", g, g, g).reshape(-1)
+    P = oracle.Problem(W.Problem(n, W.KIND_OCTANTS))
+    for prec in (oracle.PREC_NONE, oracle.PREC_JACOBI):
+        x, st = P.cg(np.full(8, 2.5), f=w, prec=prec, tol=1e-12, maxit=10)
+        assert st["iters"] == 1 and st["status"] == oracle.CONVERGED
+
+
+def test_homogeneity_bitwise():
+    spec = W.Problem(8, W.KIND_OCTANTS)
+    P = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 2, 1)
+    for prec in (oracle.PREC_NONE, oracle.PREC_JACOBI):
+        for m in mu:
+            x1, s1, h1 = P.cg(m, prec=prec, tol=1e-10, hist=True)
+            x2, s2, h2 = P.cg(2.0 * m, prec=prec, tol=1e-10, hist=True)
+            assert s1["iters"] == s2["iters"]
+            assert np.array_equal(h1, h2)
+            assert np.array_equal(x2 * 2.0, x1)
+
+
+def test_mirror_symmetry():
+    # x -> 1 - x maps octant bit 0 to its complement; the solution mirrors.
+    n = 7
+    spec = W.Problem(n, W.KIND_OCTANTS)
+    P = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.1, 10.0, 1, 8)[0]
+    mu_m = mu[[o ^ 1 for o in range(8)]]
+    x, _ = P.cg(mu, prec=oracle.PREC_JACOBI, tol=1e-13)
+    y, _ = P.cg(mu_m, prec=oracle.PREC_JACOBI, tol=1e-13)
+    y = y.reshape(n, n, n)[:, :, ::-1].reshape(-1)
+    assert np.abs(x - y).max() <= 1e-11 * np.abs(x).max()
+
+
+def test_exact_start_zero_iterations_and_limits():
+    spec = W.Problem(6, W.KIND_BLOCKS, W.BLOCKS3)
+    P = oracle.Problem(spec)
+    m = np.array([0.3, 4.0, 2.0])
+    x, st = P.cg(m, prec=oracle.PREC_JACOBI, tol=1e-13)
+    x2, st2 = P.cg(m, u0=x, prec=oracle.PREC_JACOBI, tol=1e-12)
+    assert st2["iters"] == 0 and st2["status"] == oracle.CONVERGED and np.array_equal(x2, x)
+    _, st3 = P.cg(m, prec=oracle.PREC_JACOBI, tol=1e-12, maxit=3)
+    assert st3["iters"] == 3 and st3["status"] == oracle.MAXITER
+    _, st4 = P.cg(m, prec=oracle.PREC_NONE, tol=1e-12, maxit=0)
+    assert st4["iters"] == 0 and st4["status"] == oracle.MAXITER
+    _, st5 = P.cg(m, f=np.zeros(P.ndof), tol=1e-12)
+    assert st5["iters"] == 0 and st5["status"] == oracle.CONVERGED
+
+
+def test_breakdown_on_indefinite():
+    P = oracle.Problem(W.Problem(4, W.KIND_OCTANTS))
+    _, st = P.cg(-np.ones(8), prec=oracle.PREC_NONE, tol=1e-12)
+    assert st["status"] == oracle.BREAKDOWN and st["iters"] == 0
+
+
+def test_cg_batch_equals_single():
+    spec = W.Problem(6, W.KIND_BLOCKS, W.BLOCKS4)
+    P = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.1, 10.0, 5, 2)
+    xb, sb = P.cg_batch(mu, prec=oracle.PREC_JACOBI, tol=1e-10, nthreads=3)
+    for i, m in enumerate(mu):
+        x, s = P.cg(m, prec=oracle.PREC_JACOBI, tol=1e-10)
+        assert np.array_equal(x, xb[i]) and s == sb[i]
+
+
+@pytest.mark.parametrize("prec", [oracle.PREC_NONE, oracle.PREC_JACOBI])
+def test_ir_reaches_fp64_accuracy(prec):
+    spec = W.Problem(10, W.KIND_OCTANTS)
+    P = oracle.Problem(spec)
+    for m in W.sample_mu(spec, 0.01, 100.0, 2, 6):
+        ref = np.linalg.solve(P.dense(m), P.rhs(m))
+        u, st = P.ir(m, prec=prec, tol=1e-10, eta=1e-4)
+        assert st["status"] == oracle.CONVERGED and st["outer"] >= 2
+        assert st["final_rr"] <= 1e-20 * st["ff"]
+        assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
