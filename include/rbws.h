@@ -1,0 +1,179 @@
+/*
+ * rbws.h -- C ABI of the MI355X reduced-basis warm-start solver (librbws.so).
+ *
+ * The library solves many instances of the parametrized linear system
+ *     A_h(mu) u_h(mu) = f_h(mu)                     (paper, Eq. 1)
+ * for the 3D diffusion problem -div(kappa(mu) grad u) = f on (0,1)^3 with
+ * zero Dirichlet data (the paper's model PDE, Sec. 4), discretised by
+ * 7-point finite differences on an n^3 grid of interior points.  The operator
+ * is affine in the parameters, A_h(mu) = sum_q theta_q(mu) A_q.
+ *
+ * Calls follow the paper's statement of the method:
+ *   - operator setup                       (Eq. 1; model PDE of Sec. 4)
+ *   - offline greedy reduced-basis build   (Alg. 4: snapshots by Alg. 1,
+ *     Gram-Schmidt, reduced matrices A_q^N = V^T A_q V)
+ *   - batched solve from a zero, RB or learned initial value (Alg. 5 with
+ *     the PCG of Alg. 1; RB value from the Galerkin system, Eq. "RB system").
+ *
+ * Conventions (all entry points):
+ *   - Every call returns rbws_status; RBWS_OK is 0.  On failure
+ *     rbws_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).  No exception crosses the ABI.
+ *   - Handles are opaque and owned by the library until their *_destroy.
+ *   - "host" pointers are ordinary CPU memory, read or written during the call.
+ *     "device" pointers are GPU memory on the handle's device (e.g. the
+ *     data_ptr() of a torch tensor); device work is ordered on `stream`
+ *     (a hipStream_t, NULL = the default stream).
+ *   - Vectors of one solve are n^3 contiguous values, x fastest:
+ *     index (k-1) n^2 + (j-1) n + (i-1) for the interior point (i,j,k),
+ *     1 <= i,j,k <= n, at coordinates (i,j,k)/(n+1).  A batch of B solves is
+ *     B such vectors back to back.
+ *   - Parameters mu are row-major (count, p) float64 host arrays.
+ *   - Not reaching the tolerance within the iteration limit is not an error:
+ *     it is reported per solve in rbws_solve_stat.status.
+ *   - A handle may be used by one host thread at a time.
+ */
+#ifndef RBWS_H
+#define RBWS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBWS_OK = 0,
+  RBWS_EINVAL = -1,   /* invalid argument (null pointer, size, range, p mismatch) */
+  RBWS_ENOMEM = -2,   /* device or host allocation failed */
+  RBWS_EDEVICE = -3,  /* a HIP call failed */
+  RBWS_ESTATE = -4,   /* the call needs state it was not given (e.g. RB start without a basis) */
+  RBWS_ENUMERIC = -5  /* reduced matrix not positive definite, Gram-Schmidt breakdown */
+} rbws_status;
+
+/* problem kinds: how kappa(mu) depends on the parameters */
+enum {
+  RBWS_KIND_BLOCKS = 0,        /* kappa = 1, or mu_b inside axis-aligned block b (last listed
+                                  block wins where blocks overlap); p = nblocks, Q = nblocks+1,
+                                  theta = (1, mu_1, ..., mu_p) */
+  RBWS_KIND_OCTANTS = 1,       /* kappa = mu_q on octant q = bx + 2 by + 4 bz of the 2x2x2
+                                  split at 1/2; p = Q = 8, theta = mu */
+  RBWS_KIND_OCTANTS_ANISO = 2  /* kappa = diag(mu[3q], mu[3q+1], mu[3q+2]) on octant q;
+                                  Q = 24, p = 24 (+3 with the Gaussian source) */
+};
+/* right-hand sides: f_h = h^2 f(x_P), h = 1/(n+1) */
+enum {
+  RBWS_F_ONE = 0,   /* f = 1 */
+  RBWS_F_GAUSS = 1  /* f = exp(-|x - x0|^2 / gauss_width), x0 = mu[24..26] (ANISO only) */
+};
+enum { RBWS_INIT_ZERO = 0, RBWS_INIT_RB = 1, RBWS_INIT_LEARNED = 2 };
+enum { RBWS_FP64 = 0, RBWS_FP32_IR = 1 };
+enum { RBWS_PREC_NONE = 0, RBWS_PREC_JACOBI = 1 };
+enum {
+  RBWS_SOLVE_CONVERGED = 0,
+  RBWS_SOLVE_MAXITER = 1,   /* the iteration limit (L_max of Alg. 1) was reached */
+  RBWS_SOLVE_BREAKDOWN = 2, /* p^T A p <= 0 */
+  RBWS_SOLVE_NAN = 3        /* a non-finite value appeared */
+};
+enum { RBWS_LIFT_EXACT = 0, RBWS_LIFT_MFMA = 1 };
+/* rbws_solve_opts.flags */
+enum {
+  RBWS_FLAG_FORCE_EXACT_DOTS = 1 /* take the exact integer path for every inner product
+                                    (results are identical; for testing the fallback) */
+};
+
+typedef struct rbws_problem rbws_problem;
+typedef struct rbws_basis rbws_basis;
+typedef struct rbws_mlp rbws_mlp;
+
+/* Problem description.  Coordinates of block bounds are in tenths of the unit
+ * cube: blocks[6*b .. 6*b+5] = xlo, xhi, ylo, yhi, zlo, zhi (integers 0..10).
+ * A face coefficient is kappa at the face midpoint; where the midpoint lies on
+ * a sub-domain boundary along t axes it is the mean of the 2^t one-sided
+ * values.  Copied during rbws_problem_create. */
+typedef struct {
+  int n;              /* interior points per axis, 2 <= n <= 1024 */
+  int kind;           /* RBWS_KIND_* */
+  int nblocks;        /* RBWS_KIND_BLOCKS: number of blocks, 1..31 */
+  const int* blocks;  /* host, [nblocks][6], RBWS_KIND_BLOCKS only */
+  int f_kind;         /* RBWS_F_* */
+  double gauss_width; /* RBWS_F_GAUSS: the width w */
+} rbws_problem_desc;
+
+/* Per-solve statistics (host output of rbws_solve). */
+typedef struct {
+  int iters;         /* CG iterations: SpMVs inside the loop of Alg. 1 (FP32_IR: inner, summed) */
+  int outer_iters;   /* FP32_IR refinement steps (0 for FP64) */
+  int extra_spmv;    /* true-residual evaluations beyond the initial one */
+  int status;        /* RBWS_SOLVE_* */
+  int init_used;     /* RBWS_INIT_* actually used (learned start may fall back to RB) */
+  int pad;
+  double init_rr;    /* ||f - A u0||^2 */
+  double final_rr;   /* ||f - A u||^2 at exit (the true residual when converged) */
+  double ff;         /* ||f||^2 */
+  double t_done_ms;  /* completion time after the start of the solve phase (device clock) */
+} rbws_solve_stat;
+
+typedef struct {
+  double tol;        /* stop when ||f - A u|| <= tol ||f|| (tested on squares) */
+  int max_iter;      /* L_max (FP64); FP32_IR: cap on inner iterations per refinement step */
+  int precond;       /* RBWS_PREC_* (the P of Alg. 1) */
+  int precision;     /* RBWS_FP64 or RBWS_FP32_IR */
+  int init;          /* RBWS_INIT_* */
+  int lift;          /* RBWS_LIFT_EXACT (correctly rounded u0 = V c) or RBWS_LIFT_MFMA */
+  double eta_inner;  /* FP32_IR: inner relative tolerance */
+  int max_outer;     /* FP32_IR: refinement steps */
+  int fallback;      /* learned start: 0 = start from whichever of u_MLP, u_RB has the smaller
+                        true residual; 1 = use u_MLP unless its relative residual exceeds the
+                        basis's final greedy indicator */
+  int flags;         /* RBWS_FLAG_* */
+  int check_every;   /* rounds between host checks for completion (0 = library default) */
+} rbws_solve_opts;
+
+/* ---- errors and defaults ------------------------------------------------ */
+const char* rbws_last_error(void);
+const char* rbws_version(void);
+/* Fill *o with defaults: tol 1e-10, max_iter 50000, Jacobi, FP64, zero start,
+ * exact lift, eta_inner 1e-4, max_outer 40, fallback 0, flags 0. */
+void rbws_solve_opts_default(rbws_solve_opts* o);
+
+/* ---- operator setup (Eq. 1; Sec. 4 model PDE) ----------------------------
+ * Creates the face-class tables of the grid on `device`.  Errors: EINVAL for
+ * an invalid description, EDEVICE/ENOMEM for HIP failures. */
+rbws_status rbws_problem_create(const rbws_problem_desc* desc, int device, rbws_problem** out);
+void rbws_problem_destroy(rbws_problem* p);
+/* Sizes: any output pointer may be NULL. */
+rbws_status rbws_problem_info(const rbws_problem* p, int* n, int* np, int* nq, long long* ndof);
+/* theta(mu) of the affine form: host mu (nmu x p) -> host theta (nmu x Q). */
+rbws_status rbws_theta(const rbws_problem* p, const double* mu, int nmu, double* theta);
+
+/* y = A_h(mu_b) x_b for b < nmu.  x, y: device, nmu*ndof values of type
+ * double (precision RBWS_FP64) or float (RBWS_FP32_IR: coefficients rounded
+ * to float, float arithmetic).  The FP64 result is evaluated in a fixed order
+ * (d_P x_P, then fma with the interior neighbours x-, x+, y-, y+, z-, z+) and
+ * is bitwise reproducible. */
+rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x, void* y,
+                      int precision, void* stream);
+
+/* Correctly rounded dot products out[b] = sum_i x[b*len+i] y[b*len+i]
+ * (exact sum of exact products rounded once to nearest-even), b < count.
+ * x, y device (double); out host.  Used by every FP64 inner product. */
+rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int count,
+                            double* out, int flags, void* stream);
+
+/* ---- batched solve (Alg. 5 driving Alg. 1) --------------------------------
+ * Solves nmu systems in one batch.  problems[0..nprob) may have different
+ * grid sizes (the uneven batch); problem_of[b] (NULL = all 0) picks the
+ * problem of solve b; all problems must share p.  bases/mlps are indexed like
+ * problems and may be NULL when init does not need them (ESTATE otherwise).
+ * u_out: NULL, or nmu device pointers (double, ndof of that solve's problem)
+ * that receive the solutions; stats: host, nmu entries (NULL allowed).
+ * Returns after the stats are on the host; solutions are written on
+ * `stream`.  */
+rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* bases,
+                       const rbws_mlp* const* mlps, int nprob, const int* problem_of,
+                       const double* mu, int nmu, const rbws_solve_opts* opts, void* stream,
+                       void* const* u_out, rbws_solve_stat* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBWS_H */

@@ -1,0 +1,215 @@
+// capi.hip -- extern "C" entry points of librbws.so (declared in include/rbws.h).
+// Argument checking, error translation and orchestration of the batched solve.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "solver.hpp"
+
+namespace rbws {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+Problem* problem_create(const rbws_problem_desc* d, int device);
+void problem_destroy(Problem* P);
+
+__global__ void k_fill64(double* x, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void k_stamp(unsigned long long* t) { *t = wall_clock64(); }
+
+void fill64(double* x, long long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  long long blocks = std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill64, dim3((unsigned)blocks), dim3(256), 0, s, x, n, v);
+  RBWS_HIP(hipGetLastError());
+}
+
+// stats of all solves of a batch after a run
+void collect_stats(Batch& B, unsigned long long t0, int init_used, int outer_field_from_extra,
+                   rbws_solve_stat* out, hipStream_t s) {
+  std::vector<CgState> st;
+  states_to_host(B, st, s);
+  const double khz = wall_clock_khz(B.device);
+  for (int b = 0; b < B.nsolve; b++) {
+    rbws_solve_stat& o = out[b];
+    std::memset(&o, 0, sizeof o);
+    o.iters = st[b].k;
+    o.extra_spmv = st[b].extra;
+    o.outer_iters = outer_field_from_extra ? st[b].pad0 : 0;
+    o.status = st[b].status < 0 ? RBWS_SOLVE_MAXITER : st[b].status;
+    o.init_used = init_used;
+    o.init_rr = st[b].init_rr;
+    o.final_rr = st[b].rr;
+    o.ff = st[b].ff;
+    o.t_done_ms = st[b].t_done > t0 ? (double)(st[b].t_done - t0) / khz : 0.0;
+  }
+}
+
+}  // namespace rbws
+
+using namespace rbws;
+
+#define API_BEGIN try {
+#define API_END                                              \
+  }                                                          \
+  catch (const Error& e) {                                   \
+    set_error(e.msg);                                        \
+    return e.code;                                           \
+  }                                                          \
+  catch (const std::bad_alloc&) {                            \
+    set_error("host allocation failed");                     \
+    return RBWS_ENOMEM;                                      \
+  }                                                          \
+  catch (const std::exception& e) {                          \
+    set_error(e.what());                                     \
+    return RBWS_EDEVICE;                                     \
+  }                                                          \
+  return RBWS_OK;
+
+static inline Problem* PP(rbws_problem* p) { return reinterpret_cast<Problem*>(p); }
+static inline const Problem* PP(const rbws_problem* p) { return reinterpret_cast<const Problem*>(p); }
+
+extern "C" {
+
+const char* rbws_last_error(void) { return g_err.c_str(); }
+const char* rbws_version(void) { return "rbws 0.1 (gfx950)"; }
+
+void rbws_solve_opts_default(rbws_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->tol = 1e-10;
+  o->max_iter = 50000;
+  o->precond = RBWS_PREC_JACOBI;
+  o->precision = RBWS_FP64;
+  o->init = RBWS_INIT_ZERO;
+  o->lift = RBWS_LIFT_EXACT;
+  o->eta_inner = 1e-4;
+  o->max_outer = 40;
+  o->fallback = 0;
+  o->flags = 0;
+  o->check_every = 0;
+}
+
+rbws_status rbws_problem_create(const rbws_problem_desc* desc, int device, rbws_problem** out) {
+  API_BEGIN
+  RBWS_REQUIRE(out != nullptr, RBWS_EINVAL, "out is NULL");
+  *out = nullptr;
+  Problem* P = problem_create(desc, device);
+  *out = reinterpret_cast<rbws_problem*>(P);
+  API_END
+}
+
+void rbws_problem_destroy(rbws_problem* p) { problem_destroy(PP(p)); }
+
+rbws_status rbws_problem_info(const rbws_problem* p, int* n, int* np, int* nq, long long* ndof) {
+  API_BEGIN
+  RBWS_REQUIRE(p != nullptr, RBWS_EINVAL, "problem is NULL");
+  const Problem* P = PP(p);
+  if (n) *n = P->n;
+  if (np) *np = P->p;
+  if (nq) *nq = P->Q;
+  if (ndof) *ndof = P->ndof;
+  API_END
+}
+
+rbws_status rbws_theta(const rbws_problem* p, const double* mu, int nmu, double* theta) {
+  API_BEGIN
+  RBWS_REQUIRE(p != nullptr, RBWS_EINVAL, "problem is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  RBWS_REQUIRE(nmu == 0 || (mu && theta), RBWS_EINVAL, "mu/theta is NULL");
+  const Problem* P = PP(p);
+  for (int b = 0; b < nmu; b++) theta_host(*P, mu + (long long)b * P->p, theta + (long long)b * P->Q);
+  API_END
+}
+
+rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x, void* y,
+                      int precision, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(p != nullptr, RBWS_EINVAL, "problem is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  RBWS_REQUIRE(precision == RBWS_FP64 || precision == RBWS_FP32_IR, RBWS_EINVAL, "bad precision");
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(mu && x && y, RBWS_EINVAL, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local Batch B;
+  std::vector<const Problem*> probs{PP(p)};
+  batch_setup(B, probs, nullptr, nmu, mu, PP(p)->p, s);
+  spmv_batch(B, x, y, precision == RBWS_FP32_IR, s);
+  RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int count, double* out,
+                            int flags, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(len >= 0 && count >= 0, RBWS_EINVAL, "negative size");
+  if (count == 0) return RBWS_OK;
+  RBWS_REQUIRE(out != nullptr, RBWS_EINVAL, "out is NULL");
+  if (len == 0) {
+    for (int i = 0; i < count; i++) out[i] = 0.0;
+    return RBWS_OK;
+  }
+  RBWS_REQUIRE(x && y, RBWS_EINVAL, "NULL pointer");
+  exact_dots(x, y, len, count, out, flags, (hipStream_t)stream);
+  API_END
+}
+
+rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* bases,
+                       const rbws_mlp* const* mlps, int nprob, const int* problem_of,
+                       const double* mu, int nmu, const rbws_solve_opts* opts, void* stream,
+                       void* const* u_out, rbws_solve_stat* stats) {
+  API_BEGIN
+  RBWS_REQUIRE(problems != nullptr && nprob >= 1, RBWS_EINVAL, "no problems");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  RBWS_REQUIRE(opts != nullptr, RBWS_EINVAL, "opts is NULL");
+  RBWS_REQUIRE(opts->tol >= 0.0 && std::isfinite(opts->tol), RBWS_EINVAL, "tol must be finite, >= 0");
+  RBWS_REQUIRE(opts->max_iter >= 0, RBWS_EINVAL, "max_iter < 0");
+  RBWS_REQUIRE(opts->precond == RBWS_PREC_NONE || opts->precond == RBWS_PREC_JACOBI, RBWS_EINVAL,
+               "bad precond");
+  RBWS_REQUIRE(opts->precision == RBWS_FP64 || opts->precision == RBWS_FP32_IR, RBWS_EINVAL,
+               "bad precision");
+  RBWS_REQUIRE(opts->init >= RBWS_INIT_ZERO && opts->init <= RBWS_INIT_LEARNED, RBWS_EINVAL, "bad init");
+  (void)bases;
+  (void)mlps;
+  std::vector<const Problem*> probs(nprob);
+  for (int q = 0; q < nprob; q++) {
+    RBWS_REQUIRE(problems[q] != nullptr, RBWS_EINVAL, "problem is NULL");
+    probs[q] = PP(problems[q]);
+  }
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(mu != nullptr, RBWS_EINVAL, "mu is NULL");
+  RBWS_REQUIRE(opts->init == RBWS_INIT_ZERO, RBWS_ESTATE, "this init needs a basis");
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local Batch B;
+  batch_setup(B, probs, problem_of, nmu, mu, probs[0]->p, s);
+  double* x = (double*)B.x.get(sizeof(double) * B.total, B.device);
+  fill64(x, B.total, 0.0, s);
+  static thread_local DevBuf tbuf;
+  unsigned long long* tdev = (unsigned long long*)tbuf.get(sizeof(unsigned long long), B.device);
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, tdev);
+  CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every};
+  cg_fp64_run(B, co, s);
+  unsigned long long t0 = 0;
+  RBWS_HIP(hipMemcpyAsync(&t0, tdev, sizeof t0, hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  if (u_out) {
+    for (int b = 0; b < nmu; b++)
+      if (u_out[b])
+        RBWS_HIP(hipMemcpyAsync(u_out[b], x + B.sd_h[b].off,
+                                sizeof(double) * B.probs[B.sd_h[b].prob]->ndof,
+                                hipMemcpyDeviceToDevice, s));
+  }
+  if (stats) collect_stats(B, t0, opts->init, 0, stats, s);
+  RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,702 @@
+// solver.hip -- batched FP64 PCG on gfx950 (the paper's Alg. 1, P in {I, Jacobi}).
+//
+// One "round" advances every unfinished solve of the batch by one CG
+// iteration, in five launches over all (solve, tile) work items:
+//   pup  : p = s + beta p          (s = P(r); p = s after a (re)start)
+//   ap   : gamma = p^T A p         (ITER solves)      | r = f - A x, ||r||^2,
+//                                                      | r^T s, ||f||^2 (RESID solves)
+//   fin1 : per solve: alpha = rho / gamma, or the convergence decision of a
+//          residual evaluation (initial residual or true-residual confirmation)
+//   up2  : x += alpha p, r -= alpha A p (A p recomputed), ||r||^2, r^T s
+//   fin2 : per solve: convergence test on the recursive residual, beta
+// The matrix is never stored: face coefficients come from a per-solve class
+// table in LDS (see problem.cpp), so a stencil application reads one vector.
+// Every inner product is correctly rounded (crdot.hpp); together with the
+// fixed evaluation order of the stencil and of every vector update this makes
+// each solve's trajectory independent of tiling and batch composition.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "solver.hpp"
+
+namespace rbws {
+
+enum { OP_PUP = 0, OP_AP = 1, OP_UP2 = 2 };
+enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3 };
+constexpr int kSlots = 3;  // partial accumulators per work item
+
+void* DevBuf::get(size_t need, int dev) {
+  if (need == 0) need = 1;
+  if (ptr && bytes >= need && device == dev) return ptr;
+  release();
+  RBWS_HIP(hipSetDevice(dev));
+  hipError_t e = hipMalloc(&ptr, need);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    throw Error{RBWS_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed"};
+  }
+  bytes = need;
+  device = dev;
+  return ptr;
+}
+
+void DevBuf::release() {
+  if (ptr) {
+    (void)hipSetDevice(device);
+    (void)hipFree(ptr);
+  }
+  ptr = nullptr;
+  bytes = 0;
+}
+
+Batch::~Batch() {
+  if (active_host) (void)hipHostFree(active_host);
+}
+
+void choose_tile(int n, int* TX, int* TY, int* TZ) {
+  int tx;
+  if (n % 64 == 0) tx = 64;
+  else if (n % 32 == 0) tx = 32;
+  else if (n >= 64) tx = 64;
+  else if (n >= 32) tx = 32;
+  else tx = 16;
+  *TX = tx;
+  *TY = 256 / tx;
+  *TZ = std::min(n, 16);
+}
+
+double wall_clock_khz(int device) {
+  int khz = 0;
+  RBWS_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+  return (double)khz;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long vidx(int n, int i, int j, int k) {
+  return ((long long)(k - 1) * n + (j - 1)) * n + (i - 1);
+}
+
+__device__ __forceinline__ double fval(const ProbDev& P, const SolveDev& S, int i, int j, int k) {
+  if (P.f_kind == RBWS_F_ONE) return P.h2;
+  double dx = i * P.h - S.x0[0], dy = j * P.h - S.x0[1], dz = k * P.h - S.x0[2];
+  return P.h2 * exp(-(dx * dx + dy * dy + dz * dz) / P.gw);
+}
+
+// the six face coefficients of point (i,j,k) from a class table in any memory
+__device__ __forceinline__ void point_kappa(const GridDev& g, const double* kap, int i, int j, int k,
+                                            double kk[6]) {
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  const double* kX = kap;
+  const double* kY = kap + (g.ndir == 3 ? g.nclass : 0);
+  const double* kZ = kap + (g.ndir == 3 ? 2 * g.nclass : 0);
+  int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+  int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+  int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+  kk[0] = kX[(cxm * N1 + cyn) * N2 + czn];
+  kk[1] = kX[(cxp * N1 + cyn) * N2 + czn];
+  kk[2] = kY[(cxn * N1 + cym) * N2 + czn];
+  kk[3] = kY[(cxn * N1 + cyp) * N2 + czn];
+  kk[4] = kZ[(cxn * N1 + cyn) * N2 + czm];
+  kk[5] = kZ[(cxn * N1 + cyn) * N2 + czp];
+}
+
+__device__ __forceinline__ double diag6(const double kk[6]) {
+  return ((((kk[0] + kk[1]) + kk[2]) + kk[3]) + kk[4]) + kk[5];
+}
+
+// (A v)_c in the fixed order: d v_c, then fma with interior neighbours x-,x+,y-,y+,z-,z+
+__device__ __forceinline__ double stencil(const double kk[6], double dg, const double* v, long long c,
+                                          int n, int i, int j, int k) {
+  const long long n2 = (long long)n * n;
+  double acc = dg * v[c];
+  if (i > 1) acc = __fma_rn(-kk[0], v[c - 1], acc);
+  if (i < n) acc = __fma_rn(-kk[1], v[c + 1], acc);
+  if (j > 1) acc = __fma_rn(-kk[2], v[c - n], acc);
+  if (j < n) acc = __fma_rn(-kk[3], v[c + n], acc);
+  if (k > 1) acc = __fma_rn(-kk[4], v[c - n2], acc);
+  if (k < n) acc = __fma_rn(-kk[5], v[c + n2], acc);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// face-class coefficient tables per solve: kappa = pairwise corner sum * 2^-t
+// ---------------------------------------------------------------------------
+__global__ void k_kappa(const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                        const double* __restrict__ theta, const uint8_t* const* ncorner,
+                        const uint8_t* const* thidx, double* __restrict__ kap64,
+                        float* __restrict__ kap32) {
+  const int b = blockIdx.x;
+  const SolveDev S = sd[b];
+  const GridDev& g = pd[S.prob].g;
+  const uint8_t* nc = ncorner[S.prob];
+  const uint8_t* ti = thidx[S.prob];
+  const double* th = theta + (long long)b * kMaxQ;
+  const int tot = g.ndir * g.nclass;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int cls = e % g.nclass;
+    const uint8_t* id = ti + (long long)e * 8;
+    double v;
+    switch (nc[cls]) {
+      case 1: v = th[id[0]]; break;
+      case 2: v = (th[id[0]] + th[id[1]]) * 0.5; break;
+      case 4: v = ((th[id[0]] + th[id[1]]) + (th[id[2]] + th[id[3]])) * 0.25; break;
+      default:
+        v = (((th[id[0]] + th[id[1]]) + (th[id[2]] + th[id[3]])) +
+             ((th[id[4]] + th[id[5]]) + (th[id[6]] + th[id[7]]))) * 0.125;
+    }
+    kap64[S.kap_off + e] = v;
+    kap32[S.kap_off + e] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sweeps over (solve, tile) work items
+// ---------------------------------------------------------------------------
+template <int OP>
+__global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
+                                                 const SolveDev* __restrict__ sd,
+                                                 const ProbDev* __restrict__ pd,
+                                                 const CgState* __restrict__ st,
+                                                 const double* __restrict__ kap,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ p, CrAcc* __restrict__ part) {
+  extern __shared__ double kl[];
+  __shared__ CrAcc red[4];
+  const int2 it = items[blockIdx.x];
+  const int b = it.x, tile = it.y;
+  const int mode = st[b].mode;
+  bool run;
+  if (OP == OP_PUP) run = mode == MODE_ITER;
+  else if (OP == OP_AP) run = mode == MODE_ITER || mode == MODE_RESID;
+  else run = mode == MODE_ITER && st[b].skip2 == 0;
+  if (!run) return;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const GridDev& g = P.g;
+  const int ntab = g.ndir * g.nclass;
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
+  __syncthreads();
+
+  const int n = g.n;
+  const long long n2 = (long long)n * n;
+  const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
+  const int lx = threadIdx.x % P.TX, ly = threadIdx.x / P.TX;
+  const int i = tx * P.TX + lx + 1, j = ty * P.TY + ly + 1;
+  const bool act = i <= n && j <= n;
+  const int kb = tz * P.TZ + 1, ke = min(n, (tz + 1) * P.TZ);
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  const double* kX = kl;
+  const double* kY = kl + (g.ndir == 3 ? g.nclass : 0);
+  const double* kZ = kl + (g.ndir == 3 ? 2 * g.nclass : 0);
+  const double alpha = st[b].alpha, beta = st[b].beta;
+  const int prec = st[b].prec, restart = st[b].restart, first = st[b].first;
+
+  CrAcc a0 = cr_zero(), a1 = cr_zero(), a2 = cr_zero();
+  if (act) {
+    const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+    const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+    const int bXm = (cxm * N1 + cyn) * N2, bXp = (cxp * N1 + cyn) * N2;
+    const int bYm = (cxn * N1 + cym) * N2, bYp = (cxn * N1 + cyp) * N2;
+    const int bZ = (cxn * N1 + cyn) * N2;
+    double* X = x + S.off;
+    double* R = r + S.off;
+    double* Pv = p + S.off;
+    const double* V = (OP == OP_AP && mode == MODE_RESID) ? X : Pv;
+    for (int k = kb; k <= ke; k++) {
+      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      double kk[6];
+      kk[0] = kX[bXm + czn];
+      kk[1] = kX[bXp + czn];
+      kk[2] = kY[bYm + czn];
+      kk[3] = kY[bYp + czn];
+      kk[4] = kZ[bZ + czm];
+      kk[5] = kZ[bZ + czp];
+      const double dg = diag6(kk);
+      const long long c = vidx(n, i, j, k);
+      if (OP == OP_PUP) {
+        const double rv = R[c];
+        const double s = prec ? rv / dg : rv;
+        Pv[c] = restart ? s : __fma_rn(beta, Pv[c], s);
+      } else {
+        const double q = stencil(kk, dg, V, c, n, i, j, k);
+        if (OP == OP_AP) {
+          if (mode == MODE_ITER) {
+            cr_add_prod(a0, V[c], q);
+          } else {
+            const double f = fval(P, S, i, j, k);
+            const double rv = f - q;
+            R[c] = rv;
+            cr_add_prod(a0, rv, rv);
+            if (prec) cr_add_prod(a1, rv, rv / dg);
+            if (first) cr_add_prod(a2, f, f);
+          }
+        } else {
+          X[c] = __fma_rn(alpha, V[c], X[c]);
+          const double rv = __fma_rn(-alpha, q, R[c]);
+          R[c] = rv;
+          cr_add_prod(a0, rv, rv);
+          if (prec) cr_add_prod(a1, rv, rv / dg);
+        }
+      }
+    }
+    (void)n2;
+  }
+  if (OP != OP_PUP) {
+    CrAcc* out = part + (long long)blockIdx.x * kSlots;
+    a0 = cr_block_reduce(a0, red);
+    if (threadIdx.x == 0) out[0] = a0;
+    if (prec || (OP == OP_AP && mode == MODE_RESID)) {
+      a1 = cr_block_reduce(a1, red);
+      if (threadIdx.x == 0) out[1] = a1;
+    }
+    if (OP == OP_AP && mode == MODE_RESID && first) {
+      a2 = cr_block_reduce(a2, red);
+      if (threadIdx.x == 0) out[2] = a2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-solve finalisation (one workgroup per solve)
+// ---------------------------------------------------------------------------
+struct FinShared {
+  CrAcc red[4];
+  XAcc xa;
+  uint32_t dig[XA_WORDS];
+  double val;
+  int ok;
+};
+
+// exact recomputation of one inner product of solve b (workgroup-cooperative)
+__device__ double exact_solve_dot(FinShared& sh, int which, const ProbDev& P, const SolveDev& S,
+                                  const double* kap, const double* x, const double* r,
+                                  const double* p) {
+  const GridDev& g = P.g;
+  const int n = g.n;
+  __syncthreads();
+  xa_clear(&sh.xa);
+  __syncthreads();
+  const double* X = x + S.off;
+  const double* R = r + S.off;
+  const double* Pv = p + S.off;
+  const double* kt = kap + S.kap_off;
+  for (long long c = threadIdx.x; c < g.ndof; c += blockDim.x) {
+    const int i = (int)(c % n) + 1, j = (int)((c / n) % n) + 1, k = (int)(c / ((long long)n * n)) + 1;
+    if (which == DOT_PAP) {
+      double kk[6];
+      point_kappa(g, kt, i, j, k, kk);
+      xa_add_prod(&sh.xa, Pv[c], stencil(kk, diag6(kk), Pv, c, n, i, j, k));
+    } else if (which == DOT_RR) {
+      xa_add_prod(&sh.xa, R[c], R[c]);
+    } else if (which == DOT_RS) {
+      double kk[6];
+      point_kappa(g, kt, i, j, k, kk);
+      xa_add_prod(&sh.xa, R[c], R[c] / diag6(kk));
+    } else {
+      const double f = fval(P, S, i, j, k);
+      xa_add_prod(&sh.xa, f, f);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh.val = xa_round(&sh.xa, sh.dig);
+  __syncthreads();
+  return sh.val;
+}
+
+// reduce slot `slot` of the solve's partials; fall back to the exact path
+__device__ double solve_dot(FinShared& sh, int slot, int which, const ProbDev& P, const SolveDev& S,
+                            const double* kap, const double* x, const double* r, const double* p,
+                            const CrAcc* part, int force_exact) {
+  CrAcc a = cr_zero();
+  for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x)
+    a = cr_combine(a, part[(long long)(S.item0 + t) * kSlots + slot]);
+  a = cr_block_reduce(a, sh.red);
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    sh.ok = (!force_exact && cr_finalize(a, &v)) ? 1 : 0;
+    sh.val = v;
+  }
+  __syncthreads();
+  const int ok = sh.ok;
+  const double v = sh.val;
+  __syncthreads();
+  if (ok) return v;
+  return exact_solve_dot(sh, which, P, S, kap, x, r, p);
+}
+
+__device__ __forceinline__ void mark_done(CgState& s, int status, int* active) {
+  s.status = status;
+  s.mode = MODE_DONE;
+  s.t_done = wall_clock64();
+  atomicSub(active, 1);
+}
+
+__global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
+                                              const ProbDev* __restrict__ pd, CgState* st,
+                                              const double* __restrict__ kap, const double* x,
+                                              const double* r, const double* p,
+                                              const CrAcc* __restrict__ part, int* active,
+                                              int force_exact) {
+  __shared__ FinShared sh;
+  const int b = blockIdx.x;
+  const int mode = st[b].mode;
+  if (mode == MODE_DONE) return;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  CgState s = st[b];
+  if (mode == MODE_ITER) {
+    const double g = solve_dot(sh, 0, DOT_PAP, P, S, kap, x, r, p, part, force_exact);
+    if (threadIdx.x == 0) {
+      if (!__builtin_isfinite(g)) mark_done(s, RBWS_SOLVE_NAN, active);
+      else if (!(g > 0.0)) mark_done(s, RBWS_SOLVE_BREAKDOWN, active);
+      else s.alpha = s.rho / g;
+      st[b] = s;
+    }
+    return;
+  }
+  // residual evaluation: the initial residual or a true-residual confirmation
+  const double rr = solve_dot(sh, 0, DOT_RR, P, S, kap, x, r, p, part, force_exact);
+  const double rs = s.prec ? solve_dot(sh, 1, DOT_RS, P, S, kap, x, r, p, part, force_exact) : rr;
+  double ff = s.ff;
+  if (s.first) ff = solve_dot(sh, 2, DOT_FF, P, S, kap, x, r, p, part, force_exact);
+  if (threadIdx.x == 0) {
+    if (s.first) {
+      s.ff = ff;
+      s.thr = s.tol2 * ff;
+      s.init_rr = rr;
+      s.first = 0;
+    }
+    s.rr = rr;
+    if (!__builtin_isfinite(rr)) mark_done(s, RBWS_SOLVE_NAN, active);
+    else if (rr <= s.thr) mark_done(s, RBWS_SOLVE_CONVERGED, active);
+    else if (s.k >= s.maxit) mark_done(s, RBWS_SOLVE_MAXITER, active);
+    else {
+      s.rho = rs;
+      s.restart = 1;
+      s.mode = MODE_ITER;
+      s.skip2 = 1;  // no update this round: the next round starts with p = s
+    }
+    st[b] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
+                                              const ProbDev* __restrict__ pd, CgState* st,
+                                              const double* __restrict__ kap, const double* x,
+                                              const double* r, const double* p,
+                                              const CrAcc* __restrict__ part, int* active,
+                                              int force_exact) {
+  __shared__ FinShared sh;
+  const int b = blockIdx.x;
+  const int mode = st[b].mode;
+  if (mode != MODE_ITER) return;
+  CgState s = st[b];
+  if (s.skip2) {
+    if (threadIdx.x == 0) st[b].skip2 = 0;
+    return;
+  }
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const double rr = solve_dot(sh, 0, DOT_RR, P, S, kap, x, r, p, part, force_exact);
+  const double rs = s.prec ? solve_dot(sh, 1, DOT_RS, P, S, kap, x, r, p, part, force_exact) : rr;
+  if (threadIdx.x == 0) {
+    s.k += 1;
+    s.rr = rr;
+    if (!__builtin_isfinite(rr)) mark_done(s, RBWS_SOLVE_NAN, active);
+    else if (rr <= s.thr) {  // confirm with the true residual next round
+      s.mode = MODE_RESID;
+      s.extra += 1;
+    } else if (s.k >= s.maxit) mark_done(s, RBWS_SOLVE_MAXITER, active);
+    else {
+      s.beta = rs / s.rho;
+      s.rho = rs;
+      s.restart = 0;
+    }
+    st[b] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y = A x (FP64 or FP32) for every solve of the batch
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items,
+                                              const SolveDev* __restrict__ sd,
+                                              const ProbDev* __restrict__ pd,
+                                              const T* __restrict__ kap, const T* __restrict__ x,
+                                              T* __restrict__ y) {
+  extern __shared__ double kl_raw[];
+  T* kl = reinterpret_cast<T*>(kl_raw);
+  const int2 it = items[blockIdx.x];
+  const SolveDev S = sd[it.x];
+  const ProbDev& P = pd[S.prob];
+  const GridDev& g = P.g;
+  const int ntab = g.ndir * g.nclass;
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
+  __syncthreads();
+  const int n = g.n, tile = it.y;
+  const long long n2 = (long long)n * n;
+  const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
+  const int i = tx * P.TX + (int)threadIdx.x % P.TX + 1, j = ty * P.TY + (int)threadIdx.x / P.TX + 1;
+  if (i > n || j > n) return;
+  const int kb = tz * P.TZ + 1, ke = min(n, (tz + 1) * P.TZ);
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  const T* kX = kl;
+  const T* kY = kl + (g.ndir == 3 ? g.nclass : 0);
+  const T* kZ = kl + (g.ndir == 3 ? 2 * g.nclass : 0);
+  const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+  const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+  const T* X = x + S.off;
+  T* Y = y + S.off;
+  for (int k = kb; k <= ke; k++) {
+    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+    const T k0 = kX[(cxm * N1 + cyn) * N2 + czn], k1 = kX[(cxp * N1 + cyn) * N2 + czn];
+    const T k2 = kY[(cxn * N1 + cym) * N2 + czn], k3 = kY[(cxn * N1 + cyp) * N2 + czn];
+    const T k4 = kZ[(cxn * N1 + cyn) * N2 + czm], k5 = kZ[(cxn * N1 + cyn) * N2 + czp];
+    const T dg = ((((k0 + k1) + k2) + k3) + k4) + k5;
+    const long long c = vidx(n, i, j, k);
+    T acc = dg * X[c];
+    if (i > 1) acc = fma(-k0, X[c - 1], acc);
+    if (i < n) acc = fma(-k1, X[c + 1], acc);
+    if (j > 1) acc = fma(-k2, X[c - n], acc);
+    if (j < n) acc = fma(-k3, X[c + n], acc);
+    if (k > 1) acc = fma(-k4, X[c - n2], acc);
+    if (k < n) acc = fma(-k5, X[c + n2], acc);
+    Y[c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// generic correctly rounded dots (for the ABI and the reduced-basis code)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ x,
+                                                  const double* __restrict__ y, long long len,
+                                                  int per_block, CrAcc* __restrict__ part) {
+  __shared__ CrAcc red[4];
+  const int v = blockIdx.y;
+  const long long beg = (long long)blockIdx.x * per_block;
+  const long long end = min(len, beg + per_block);
+  const double* X = x + (long long)v * len;
+  const double* Y = y + (long long)v * len;
+  CrAcc a = cr_zero();
+  for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) cr_add_prod(a, X[c], Y[c]);
+  a = cr_block_reduce(a, red);
+  if (threadIdx.x == 0) part[(long long)v * gridDim.x + blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void k_dot_fin(const double* __restrict__ x,
+                                                 const double* __restrict__ y, long long len,
+                                                 int nparts, const CrAcc* __restrict__ part,
+                                                 double* __restrict__ out, int force_exact) {
+  __shared__ FinShared sh;
+  const int v = blockIdx.x;
+  CrAcc a = cr_zero();
+  for (int t = threadIdx.x; t < nparts; t += blockDim.x) a = cr_combine(a, part[(long long)v * nparts + t]);
+  a = cr_block_reduce(a, sh.red);
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    sh.ok = (!force_exact && cr_finalize(a, &r)) ? 1 : 0;
+    sh.val = r;
+  }
+  __syncthreads();
+  if (sh.ok) {
+    if (threadIdx.x == 0) out[v] = sh.val;
+    return;
+  }
+  __syncthreads();
+  xa_clear(&sh.xa);
+  __syncthreads();
+  const double* X = x + (long long)v * len;
+  const double* Y = y + (long long)v * len;
+  for (long long c = threadIdx.x; c < len; c += blockDim.x) xa_add_prod(&sh.xa, X[c], Y[c]);
+  __syncthreads();
+  if (threadIdx.x == 0) out[v] = xa_round(&sh.xa, sh.dig);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
+                 const double* mu, int p, hipStream_t s) {
+  RBWS_REQUIRE(!probs.empty(), RBWS_EINVAL, "no problem");
+  B.device = probs[0]->device;
+  RBWS_HIP(hipSetDevice(B.device));
+  B.probs = probs;
+  B.nprob = (int)probs.size();
+  B.nsolve = nsolve;
+  B.pd_h.assign(B.nprob, ProbDev{});
+  std::vector<const uint8_t*> ncp(B.nprob), thp(B.nprob);
+  for (int q = 0; q < B.nprob; q++) {
+    const Problem* P = probs[q];
+    RBWS_REQUIRE(P->device == B.device, RBWS_EINVAL, "problems of one batch must share a device");
+    RBWS_REQUIRE(P->p == p, RBWS_EINVAL, "problems of one batch must share p");
+    ProbDev& d = B.pd_h[q];
+    d.g = P->grid;
+    choose_tile(P->n, &d.TX, &d.TY, &d.TZ);
+    d.ntx = (P->n + d.TX - 1) / d.TX;
+    d.nty = (P->n + d.TY - 1) / d.TY;
+    d.ntz = (P->n + d.TZ - 1) / d.TZ;
+    d.ntiles = d.ntx * d.nty * d.ntz;
+    d.f_kind = P->desc.f_kind;
+    d.h = 1.0 / (P->n + 1);
+    d.h2 = d.h * d.h;
+    d.gw = P->desc.gauss_width;
+    ncp[q] = P->ct_ncorner_dev;
+    thp[q] = P->ct_theta_dev;
+  }
+  B.sd_h.assign(nsolve, SolveDev{});
+  B.items_h.clear();
+  std::vector<double> theta((size_t)std::max(nsolve, 1) * kMaxQ, 0.0);
+  long long off = 0, koff = 0;
+  B.kap_max = 0;
+  for (int b = 0; b < nsolve; b++) {
+    int q = prob_of ? prob_of[b] : 0;
+    RBWS_REQUIRE(q >= 0 && q < B.nprob, RBWS_EINVAL, "problem_of entry out of range");
+    const Problem* P = probs[q];
+    const ProbDev& d = B.pd_h[q];
+    SolveDev& S = B.sd_h[b];
+    S.prob = q;
+    S.ntiles = d.ntiles;
+    S.item0 = (int)B.items_h.size();
+    S.off = off;
+    S.kap_off = koff;
+    const double* m = mu + (long long)b * p;
+    for (int t = 0; t < p; t++)
+      RBWS_REQUIRE(std::isfinite(m[t]), RBWS_EINVAL, "mu must be finite");
+    if (P->desc.f_kind == RBWS_F_GAUSS) {
+      S.x0[0] = m[24];
+      S.x0[1] = m[25];
+      S.x0[2] = m[26];
+    }
+    theta_host(*P, m, &theta[(size_t)b * kMaxQ]);
+    off += P->ndof;
+    int tab = P->grid.ndir * P->grid.nclass;
+    koff += tab;
+    B.kap_max = std::max(B.kap_max, tab);
+    for (int t = 0; t < d.ntiles; t++) B.items_h.push_back(make_int2(b, t));
+  }
+  B.total = off;
+  B.kap_total = koff;
+  B.nitems = (int)B.items_h.size();
+  RBWS_HIP(hipMemcpyAsync(B.pd.get(sizeof(ProbDev) * B.nprob, B.device), B.pd_h.data(),
+                          sizeof(ProbDev) * B.nprob, hipMemcpyHostToDevice, s));
+  if (nsolve > 0) {
+    RBWS_HIP(hipMemcpyAsync(B.sd.get(sizeof(SolveDev) * nsolve, B.device), B.sd_h.data(),
+                            sizeof(SolveDev) * nsolve, hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipMemcpyAsync(B.items.get(sizeof(int2) * B.nitems, B.device), B.items_h.data(),
+                            sizeof(int2) * B.nitems, hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipMemcpyAsync(B.theta.get(sizeof(double) * theta.size(), B.device), theta.data(),
+                            sizeof(double) * theta.size(), hipMemcpyHostToDevice, s));
+  }
+  RBWS_HIP(hipMemcpyAsync(B.ncorner.get(sizeof(void*) * B.nprob, B.device), ncp.data(),
+                          sizeof(void*) * B.nprob, hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipMemcpyAsync(B.thidx.get(sizeof(void*) * B.nprob, B.device), thp.data(),
+                          sizeof(void*) * B.nprob, hipMemcpyHostToDevice, s));
+  B.kap64.get(sizeof(double) * std::max<long long>(B.kap_total, 1), B.device);
+  B.kap32.get(sizeof(float) * std::max<long long>(B.kap_total, 1), B.device);
+  if (nsolve > 0) {
+    hipLaunchKernelGGL(k_kappa, dim3(nsolve), dim3(256), 0, s, (const SolveDev*)B.sd.ptr,
+                       (const ProbDev*)B.pd.ptr, (const double*)B.theta.ptr,
+                       (const uint8_t* const*)B.ncorner.ptr, (const uint8_t* const*)B.thidx.ptr,
+                       (double*)B.kap64.ptr, (float*)B.kap32.ptr);
+    RBWS_HIP(hipGetLastError());
+  }
+  if (!B.active_host) RBWS_HIP(hipHostMalloc((void**)&B.active_host, 64, hipHostMallocDefault));
+}
+
+void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
+  RBWS_HIP(hipSetDevice(B.device));
+  const int ns = B.nsolve;
+  if (ns == 0) return;
+  std::vector<CgState> init(ns);
+  for (int b = 0; b < ns; b++) {
+    CgState& c = init[b];
+    std::memset(&c, 0, sizeof c);
+    c.tol2 = o.tol * o.tol;
+    c.status = -1;
+    c.mode = MODE_RESID;
+    c.restart = 1;
+    c.maxit = o.maxit;
+    c.prec = o.prec;
+    c.first = 1;
+  }
+  CgState* st = (CgState*)B.state.get(sizeof(CgState) * ns, B.device);
+  RBWS_HIP(hipMemcpyAsync(st, init.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, s));
+  int* active = (int*)B.active.get(sizeof(int), B.device);
+  RBWS_HIP(hipMemcpyAsync(active, &ns, sizeof(int), hipMemcpyHostToDevice, s));
+  CrAcc* part = (CrAcc*)B.part.get(sizeof(CrAcc) * kSlots * B.nitems, B.device);
+  double* x = (double*)B.x.ptr;
+  double* r = (double*)B.r.get(sizeof(double) * B.total, B.device);
+  double* p = (double*)B.p.get(sizeof(double) * B.total, B.device);
+  RBWS_REQUIRE(x != nullptr && B.x.bytes >= sizeof(double) * B.total, RBWS_ESTATE, "initial guess missing");
+  const int2* items = (const int2*)B.items.ptr;
+  const SolveDev* sd = (const SolveDev*)B.sd.ptr;
+  const ProbDev* pd = (const ProbDev*)B.pd.ptr;
+  const double* kap = (const double*)B.kap64.ptr;
+  const size_t lds = sizeof(double) * B.kap_max;
+  const int fe = (o.flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
+  const int check = o.check_every > 0 ? o.check_every : 4;
+  const long long max_rounds = 2LL * o.maxit + 16;
+  for (long long round = 0; round < max_rounds; round++) {
+    hipLaunchKernelGGL(k_sweep64<OP_PUP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
+    hipLaunchKernelGGL(k_sweep64<OP_AP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
+    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe);
+    hipLaunchKernelGGL(k_sweep64<OP_UP2>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
+    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe);
+    RBWS_HIP(hipGetLastError());
+    if ((round + 1) % check == 0) {
+      RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+      if (*B.active_host == 0) break;
+    }
+  }
+}
+
+void states_to_host(Batch& B, std::vector<CgState>& out, hipStream_t s) {
+  out.resize(B.nsolve);
+  if (B.nsolve == 0) return;
+  RBWS_HIP(hipMemcpyAsync(out.data(), B.state.ptr, sizeof(CgState) * B.nsolve, hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+}
+
+void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s) {
+  RBWS_HIP(hipSetDevice(B.device));
+  if (B.nsolve == 0) return;
+  if (fp32) {
+    hipLaunchKernelGGL(k_spmv<float>, dim3(B.nitems), dim3(256), sizeof(float) * B.kap_max, s,
+                       (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
+                       (const float*)B.kap32.ptr, (const float*)x, (float*)y);
+  } else {
+    hipLaunchKernelGGL(k_spmv<double>, dim3(B.nitems), dim3(256), sizeof(double) * B.kap_max, s,
+                       (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
+                       (const double*)B.kap64.ptr, (const double*)x, (double*)y);
+  }
+  RBWS_HIP(hipGetLastError());
+}
+
+void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
+                int flags, hipStream_t s) {
+  if (count <= 0) return;
+  int dev = 0;
+  RBWS_HIP(hipGetDevice(&dev));
+  static thread_local DevBuf part, out;
+  const int per_block = 4096;
+  long long nb = std::max<long long>(1, (len + per_block - 1) / per_block);
+  RBWS_REQUIRE(nb < (1LL << 31), RBWS_EINVAL, "vector too long");
+  CrAcc* pp = (CrAcc*)part.get(sizeof(CrAcc) * nb * count, dev);
+  double* o = (double*)out.get(sizeof(double) * count, dev);
+  hipLaunchKernelGGL(k_dot_part, dim3((unsigned)nb, count), dim3(256), 0, s, x, y, len, per_block, pp);
+  hipLaunchKernelGGL(k_dot_fin, dim3(count), dim3(256), 0, s, x, y, len, (int)nb, pp, o,
+                     (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0);
+  RBWS_HIP(hipGetLastError());
+  RBWS_HIP(hipMemcpyAsync(out_host, o, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace rbws

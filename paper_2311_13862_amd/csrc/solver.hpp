@@ -1,0 +1,88 @@
+// solver.hpp -- batched solver internals shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "crdot.hpp"
+#include "rbws_internal.hpp"
+
+namespace rbws {
+
+// one problem (grid) of a batch, as the kernels see it
+struct ProbDev {
+  GridDev g;
+  int TX, TY, TZ, ntx, nty, ntz, ntiles, f_kind;
+  double h, h2, gw;
+};
+
+// one solve of a batch
+struct SolveDev {
+  int prob, ntiles, item0, pad;
+  long long off;      // offset of the solve's vectors, in elements
+  long long kap_off;  // offset of its face-class coefficient table, in elements
+  double x0[3];       // centre of the Gaussian source
+};
+
+// device arrays of a batch (grow-only allocations, reused across calls)
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  void* get(size_t need, int dev);
+  void release();
+  ~DevBuf() { release(); }
+};
+
+struct Batch {
+  int device = 0;
+  int nsolve = 0, nprob = 0, nitems = 0;
+  long long total = 0;      // sum of ndof over solves
+  long long kap_total = 0;  // sum of table sizes
+  int kap_max = 0;          // largest table (elements), for LDS sizing
+  std::vector<const Problem*> probs;
+  std::vector<ProbDev> pd_h;
+  std::vector<SolveDev> sd_h;
+  std::vector<int2> items_h;
+  DevBuf pd, sd, items, kap64, kap32, theta, ncorner, thidx, state, part, active;
+  // FP64 CG vectors
+  DevBuf x, r, p;
+  // FP32 inner vectors (refinement)
+  DevBuf d32, r32, p32;
+  int* active_host = nullptr;  // pinned
+  ~Batch();
+};
+
+// tile choice for one grid size (kernels assume TX*TY == 256)
+void choose_tile(int n, int* TX, int* TY, int* TZ);
+
+// build the batch description: problems[prob_of[b]] for solve b; mu (nsolve x p) on host
+void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
+                 const double* mu, int p, hipStream_t s);
+
+// FP64 PCG (Alg. 1) over all solves of the batch from the x already in B.x.
+// Results: B.x (solutions), states in B.state.
+struct CgOpts {
+  double tol;
+  int maxit, prec, flags, check_every;
+};
+void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s);
+void states_to_host(Batch& B, std::vector<CgState>& out, hipStream_t s);
+
+// y = A x for every solve (FP64 or FP32), x/y laid out like the batch
+void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s);
+
+// FP32-inner / FP64-outer refinement from the x already in B.x
+struct IrOpts {
+  double tol, eta;
+  int prec, inner_max, max_outer, flags, check_every;
+};
+void ir_run(Batch& B, const IrOpts& o, hipStream_t s);
+
+// correctly rounded dots of `count` pairs of length len (device vectors)
+void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
+                int flags, hipStream_t s);
+
+double wall_clock_khz(int device);
+
+}  // namespace rbws

@@ -1,0 +1,208 @@
+"""ctypes binding of librbws.so (C ABI in include/rbws.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device buffers are torch tensors on a ROCm device (``tensor.data_ptr()``);
+streams are torch streams.  Importing this module loads the library and
+raises if it has not been built (``python -m paper_2311_13862_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbws.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+KIND_BLOCKS, KIND_OCTANTS, KIND_OCTANTS_ANISO = 0, 1, 2
+F_ONE, F_GAUSS = 0, 1
+INIT_ZERO, INIT_RB, INIT_LEARNED = 0, 1, 2
+FP64, FP32_IR = 0, 1
+PREC_NONE, PREC_JACOBI = 0, 1
+SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
+LIFT_EXACT, LIFT_MFMA = 0, 1
+FLAG_FORCE_EXACT_DOTS = 1
+
+
+class RbwsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rbws error {code}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n", C.c_int), ("kind", C.c_int), ("nblocks", C.c_int),
+                ("blocks", C.POINTER(C.c_int)), ("f_kind", C.c_int), ("gauss_width", C.c_double)]
+
+
+class SolveStat(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer_iters", C.c_int), ("extra_spmv", C.c_int),
+                ("status", C.c_int), ("init_used", C.c_int), ("pad", C.c_int),
+                ("init_rr", C.c_double), ("final_rr", C.c_double), ("ff", C.c_double),
+                ("t_done_ms", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precond", C.c_int),
+                ("precision", C.c_int), ("init", C.c_int), ("lift", C.c_int),
+                ("eta_inner", C.c_double), ("max_outer", C.c_int), ("fallback", C.c_int),
+                ("flags", C.c_int), ("check_every", C.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_13862_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+    dp = C.POINTER(C.c_double)
+    sigs = {
+        "rbws_last_error": (C.c_char_p, []),
+        "rbws_version": (C.c_char_p, []),
+        "rbws_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
+        "rbws_problem_create": (i, [C.POINTER(ProblemDesc), i, C.POINTER(vp)]),
+        "rbws_problem_destroy": (None, [vp]),
+        "rbws_problem_info": (i, [vp, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(ll)]),
+        "rbws_theta": (i, [vp, dp, i, dp]),
+        "rbws_spmv": (i, [vp, dp, i, vp, vp, i, vp]),
+        "rbws_exact_dots": (i, [vp, vp, ll, i, dp, i, vp]),
+        "rbws_solve": (i, [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i, C.POINTER(i), dp, i,
+                           C.POINTER(SolveOpts), vp, C.POINTER(vp), C.POINTER(SolveStat)]),
+    }
+    optional = {
+        "rbws_rb_build": (i, [vp, dp, i, i, d, i, i, vp, C.POINTER(vp), C.POINTER(i), dp,
+                              C.POINTER(i)]),
+        "rbws_basis_destroy": (None, [vp]),
+        "rbws_basis_info": (i, [vp, C.POINTER(i), C.POINTER(i), C.POINTER(ll), dp]),
+        "rbws_basis_get": (i, [vp, dp, dp, dp]),
+        "rbws_basis_device_v": (i, [vp, C.POINTER(vp)]),
+        "rbws_rb_coeffs": (i, [vp, dp, i, dp, vp]),
+        "rbws_rb_lift": (i, [vp, vp, i, vp, i, vp]),
+        "rbws_basis_save": (i, [vp, C.c_char_p]),
+        "rbws_basis_load": (i, [vp, C.c_char_p, C.POINTER(vp)]),
+    }
+    for name, (res, args) in list(sigs.items()) + list(optional.items()):
+        fn = getattr(L, name, None)
+        if fn is None:
+            if name in sigs:
+                raise ImportError(f"{LIB_PATH} does not export {name}")
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+_L = _load()
+
+
+def lib():
+    return _L
+
+
+def _check(code: int):
+    if code != OK:
+        raise RbwsError(code, _L.rbws_last_error().decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def version() -> str:
+    return _L.rbws_version().decode()
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _L.rbws_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Operator setup (rbws_problem_create) for one grid and parameter family."""
+
+    def __init__(self, spec, device: int = 0):
+        self.spec = spec
+        blocks = np.ascontiguousarray(np.asarray(spec.blocks, dtype=np.int32).reshape(-1))
+        self._blocks = blocks
+        bp = blocks.ctypes.data_as(C.POINTER(C.c_int)) if blocks.size else None
+        desc = ProblemDesc(spec.n, spec.kind, len(spec.blocks), bp, spec.f_kind, spec.gauss_width)
+        h = C.c_void_p()
+        _check(_L.rbws_problem_create(C.byref(desc), device, C.byref(h)))
+        self.handle = h
+        n, p, q, nd = C.c_int(), C.c_int(), C.c_int(), C.c_longlong()
+        _check(_L.rbws_problem_info(h, C.byref(n), C.byref(p), C.byref(q), C.byref(nd)))
+        self.n, self.p, self.Q, self.ndof = n.value, p.value, q.value, nd.value
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _L is not None:
+            _L.rbws_problem_destroy(h)
+            self.handle = None
+
+    def theta(self, mu) -> np.ndarray:
+        mu = _f64(mu).reshape(-1, self.p)
+        out = np.empty((mu.shape[0], self.Q))
+        _check(_L.rbws_theta(self.handle, _dp(mu), mu.shape[0], _dp(out)))
+        return out
+
+    def spmv(self, mu, x, y, precision=FP64, stream=None):
+        """y[b] = A(mu[b]) x[b]; x, y torch device tensors (nmu, ndof)."""
+        mu = _f64(mu).reshape(-1, self.p)
+        _check(_L.rbws_spmv(self.handle, _dp(mu), mu.shape[0], C.c_void_p(x.data_ptr()),
+                            C.c_void_p(y.data_ptr()), precision, _stream(stream)))
+
+
+def exact_dots(x, y, flags: int = 0, stream=None) -> np.ndarray:
+    """Correctly rounded row-wise dots of two (count, len) float64 device tensors."""
+    count, length = x.shape
+    out = np.empty(count)
+    _check(_L.rbws_exact_dots(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), length, count,
+                              _dp(out), flags, _stream(stream)))
+    return out
+
+
+def stats_to_dicts(st, n: int) -> List[dict]:
+    return [{k: getattr(st[i], k) for k, _ in SolveStat._fields_ if k != "pad"} for i in range(n)]
+
+
+def solve(problems: Sequence[Problem], mu, opts: SolveOpts, problem_of=None, bases=None,
+          mlps=None, u_out=None, stream=None):
+    """Batched solve (rbws_solve).  u_out: None or a list of device tensors
+    (one per solve).  Returns a list of per-solve stat dicts."""
+    problems = list(problems)
+    nprob = len(problems)
+    p = problems[0].p
+    mu = _f64(mu).reshape(-1, p)
+    nmu = mu.shape[0]
+    ph = (C.c_void_p * nprob)(*[pr.handle for pr in problems])
+    bh = (C.c_void_p * nprob)(*[(b.handle if b is not None else None) for b in (bases or [None] * nprob)])
+    mh = (C.c_void_p * nprob)(*[(m.handle if m is not None else None) for m in (mlps or [None] * nprob)])
+    po = None
+    if problem_of is not None:
+        po_arr = np.ascontiguousarray(problem_of, dtype=np.int32)
+        po = po_arr.ctypes.data_as(C.POINTER(C.c_int))
+    uo = None
+    if u_out is not None:
+        uo = (C.c_void_p * nmu)(*[t.data_ptr() if t is not None else None for t in u_out])
+    st = (SolveStat * max(nmu, 1))()
+    _check(_L.rbws_solve(ph, bh, mh, nprob, po, _dp(mu), nmu, C.byref(opts), _stream(stream), uo, st))
+    return stats_to_dicts(st, nmu)

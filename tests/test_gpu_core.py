@@ -1,0 +1,175 @@
+"""GPU parity of the FP64 core against the CPU oracle, through the C ABI.
+
+- rbws_spmv (FP64) is bitwise equal to the oracle's stencil (fixed evaluation
+  order, fma, 0 bytes of stored coefficients) on grids that exercise ragged
+  tiles, face ties on sub-domain boundaries and every problem kind.
+- rbws_exact_dots is bitwise equal to the oracle's correctly rounded dot on
+  random and adversarial data, also when the exact fallback is forced.
+- the batched PCG (Alg. 1, P = I or Jacobi) reproduces the oracle's iteration
+  counts exactly and its solutions bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_13862_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rb():
+    from paper_2311_13862_amd import rbws
+    assert torch.cuda.is_available()
+    return rbws
+
+
+def dev_tensor(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+SPMV_CASES = [
+    W.Problem(3, W.KIND_BLOCKS, W.BLOCKS3),
+    W.Problem(16, W.KIND_BLOCKS, W.BLOCKS3),
+    W.Problem(17, W.KIND_BLOCKS, W.BLOCKS4),
+    W.Problem(39, W.KIND_BLOCKS, W.BLOCKS4),     # face ties at 0.1/0.3/0.7/0.9, node ties at 0.4/0.6? (n+1=40)
+    W.Problem(16, W.KIND_OCTANTS),              # x-faces on the 1/2 plane
+    W.Problem(17, W.KIND_OCTANTS),              # nodes on the 1/2 plane
+    W.Problem(12, W.KIND_OCTANTS_ANISO, (), W.F_GAUSS, 0.02),
+    W.Problem(70, W.KIND_OCTANTS),              # ragged x tiles
+]
+
+
+@pytest.mark.parametrize("spec", SPMV_CASES, ids=lambda s: f"k{s.kind}n{s.n}")
+def test_spmv_fp64_bitwise(rb, spec):
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    rng = np.random.default_rng(spec.n)
+    mu = W.sample_mu(spec, 0.01, 100.0, 3, 7)
+    x = rng.standard_normal((3, P.ndof))
+    y = torch.empty((3, P.ndof), dtype=torch.float64, device="cuda")
+    P.spmv(mu, dev_tensor(x), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    for b in range(3):
+        want = O.apply(mu[b], x[b])
+        assert np.array_equal(got[b], want), f"solve {b}: max diff {np.abs(got[b]-want).max()}"
+
+
+@pytest.mark.parametrize("spec", SPMV_CASES[:3] + SPMV_CASES[6:7], ids=lambda s: f"k{s.kind}n{s.n}")
+def test_spmv_fp32(rb, spec):
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    rng = np.random.default_rng(1)
+    mu = W.sample_mu(spec, 0.1, 10.0, 2, 3)
+    x = rng.standard_normal((2, P.ndof)).astype(np.float32)
+    y = torch.empty((2, P.ndof), dtype=torch.float32, device="cuda")
+    P.spmv(mu, dev_tensor(x), y, precision=rb.FP32_IR)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        want = O.apply(mu[b], x[b].astype(np.float64))
+        scale = O.apply(mu[b], np.abs(x[b]).astype(np.float64) * 0 + 1.0).max() * np.abs(x[b]).max()
+        assert np.abs(got[b] - want).max() <= 2e-6 * max(scale, np.abs(want).max())
+
+
+def adversarial_vectors():
+    rng = np.random.default_rng(5)
+    out = []
+    n = 100_000
+    out.append((rng.standard_normal(n), rng.standard_normal(n)))
+    s = 10.0 ** rng.uniform(-150, 150, n)
+    out.append((rng.standard_normal(n) * s, rng.standard_normal(n) / s))
+    x = rng.standard_normal(n)
+    y = x.copy()
+    y[1::2] *= -1.0
+    out.append((x, y))                                      # massive cancellation
+    a = np.full(n, 1.0)
+    b = np.full(n, 2.0 ** -53)
+    b[0] = 1.0
+    out.append((a, b))                                      # ties
+    out.append((np.full(n, 1e-170), np.full(n, 1e-160)))    # underflowing products
+    z = np.zeros(n)
+    out.append((z, rng.standard_normal(n)))                 # exact zero
+    return out
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_exact_dots_bitwise(rb, flags):
+    for x, y in adversarial_vectors():
+        want = oracle.exact_dot(x, y)
+        got = rb.exact_dots(dev_tensor(x[None]), dev_tensor(y[None]), flags=flags)[0]
+        assert got == want or (np.isnan(got) and np.isnan(want)), (got, want)
+    # several rows at once, ragged length
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((5, 12345))
+    Y = rng.standard_normal((5, 12345)) * 1e3
+    got = rb.exact_dots(dev_tensor(X), dev_tensor(Y), flags=flags)
+    assert [oracle.exact_dot(X[i], Y[i]) for i in range(5)] == list(got)
+
+
+def run_gpu_cg(rb, spec, mu, prec, tol, maxit=50000, flags=0):
+    P = rb.Problem(spec)
+    u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mu))]
+    opts = rb.default_opts(tol=tol, max_iter=maxit, precond=prec, flags=flags)
+    st = rb.solve([P], mu, opts, u_out=u)
+    torch.cuda.synchronize()
+    return np.stack([t.cpu().numpy() for t in u]), st
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cg_parity_blocks3_16(rb, prec):
+    wl = W.blocks3_16()
+    mu = W.sample_mu(wl.problem, wl.mu_lo, wl.mu_hi, wl.n_test, W.SEED_TEST)
+    O = oracle.Problem(wl.problem)
+    xo, so = O.cg_batch(mu, prec=prec, tol=wl.tol)
+    xg, sg = run_gpu_cg(rb, wl.problem, mu, prec, wl.tol)
+    for b in range(len(mu)):
+        assert sg[b]["status"] == so[b]["status"] == 0
+        assert sg[b]["iters"] == so[b]["iters"], b
+        assert sg[b]["extra_spmv"] == so[b]["extra_spmv"]
+        assert sg[b]["final_rr"] == so[b]["final_rr"]
+        assert sg[b]["init_rr"] == so[b]["init_rr"] and sg[b]["ff"] == so[b]["ff"]
+        assert np.array_equal(xg[b], xo[b])
+
+
+def test_cg_forced_exact_dots_identical(rb):
+    spec = W.Problem(9, W.KIND_BLOCKS, W.BLOCKS4)
+    mu = W.sample_mu(spec, 0.1, 10.0, 3, 4)
+    x0, s0 = run_gpu_cg(rb, spec, mu, 1, 1e-11)
+    x1, s1 = run_gpu_cg(rb, spec, mu, 1, 1e-11, flags=rb.FLAG_FORCE_EXACT_DOTS)
+    strip = lambda ss: [{k: v for k, v in d.items() if k != "t_done_ms"} for d in ss]
+    assert strip(s0) == strip(s1) and np.array_equal(x0, x1)
+
+
+def test_cg_limits_and_edge_cases(rb):
+    spec = W.Problem(10, W.KIND_OCTANTS)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 2, 2)
+    xg, sg = run_gpu_cg(rb, spec, mu, 1, 1e-12, maxit=3)
+    for b in range(2):
+        xo, so = O.cg(mu[b], prec=1, tol=1e-12, maxit=3)
+        assert sg[b]["status"] == rb.SOLVE_MAXITER and sg[b]["iters"] == 3 == so["iters"]
+        assert np.array_equal(xg[b], xo)
+    _, s0 = run_gpu_cg(rb, spec, mu, 0, 1e-12, maxit=0)
+    assert all(s["iters"] == 0 and s["status"] == rb.SOLVE_MAXITER for s in s0)
+    # indefinite operator: breakdown at the first step
+    _, sb = run_gpu_cg(rb, spec, -np.ones((1, 8)), 0, 1e-12)
+    assert sb[0]["status"] == rb.SOLVE_BREAKDOWN and sb[0]["iters"] == 0
+    # an empty batch is a no-op
+    assert rb.solve([rb.Problem(spec)], np.zeros((0, 8)), rb.default_opts()) == []
+
+
+def test_cg_parity_blocks4_64_sample(rb):
+    # full 64^3 grid; the oracle solves a seeded sample of the batch
+    wl = W.blocks4_64()
+    mu = W.sample_mu(wl.problem, wl.mu_lo, wl.mu_hi, 16, W.SEED_TEST)
+    xg, sg = run_gpu_cg(rb, wl.problem, mu, 1, wl.tol)
+    O = oracle.Problem(wl.problem)
+    pick = [0, 11]
+    xo, so = O.cg_batch(mu[pick], prec=1, tol=wl.tol)
+    for t, b in enumerate(pick):
+        assert sg[b]["iters"] == so[t]["iters"] and sg[b]["final_rr"] == so[t]["final_rr"]
+        assert np.array_equal(xg[b], xo[t])
+    assert all(s["status"] == 0 for s in sg)
