@@ -159,6 +159,45 @@ rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x,
 rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int count,
                             double* out, int flags, void* stream);
 
+/* ---- offline: greedy reduced basis (Alg. 4 skeleton) ---------------------
+ * Builds V (N orthonormal vectors), A_q^N = V^T A_q V and f^N = V^T f from the
+ * training set mu_train (host, ntrain x p).  Step n: snapshot u(mu_l) by PCG
+ * (Alg. 1) from zero to snap_tol with preconditioner `precond` and at most
+ * snap_maxit iterations; two classical Gram-Schmidt passes against V; append
+ * v / ||v||; then the indicator Delta(mu) = ||f - A(mu) V c(mu)|| / ||f|| on
+ * the whole training set; the next parameter is the first maximiser.  The
+ * first parameter is mu_train[0].  Stops early (n_reached < N) when the
+ * maximiser is already selected or a snapshot adds nothing new (remainder
+ * below 1e-10 of its norm).  All inner products are correctly rounded, so the
+ * basis is reproducible.  Requires f = 1 (RBWS_F_ONE).
+ * Outputs (host, nullable): selected[N] (training indices), indicator_hist
+ * [N x ntrain] (row k: indicator with k+1 vectors), n_reached.
+ * Errors: EINVAL (N outside [1, min(64, ntrain)], snap_tol <= 0),
+ * ENUMERIC (reduced matrix not positive definite), EDEVICE, ENOMEM. */
+rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
+                          int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
+                          double* indicator_hist, int* n_reached);
+void rbws_basis_destroy(rbws_basis* b);
+/* N (reached), Q, ndof and the largest final indicator over the training set. */
+rbws_status rbws_basis_info(const rbws_basis* b, int* N, int* nq, long long* ndof, double* final_max);
+/* Host copies: V [N x ndof], AqN [Q x N x N], fN [N]; each may be NULL. */
+rbws_status rbws_basis_get(const rbws_basis* b, double* V, double* AqN, double* fN);
+/* Device pointer to V (N x ndof, row-major); valid until rbws_basis_destroy. */
+rbws_status rbws_basis_device_v(const rbws_basis* b, const double** V);
+/* Online RB solve (Eq. "RB system"): c(mu) from A_N(mu) = sum_q theta_q A_q^N
+ * (accumulated with fma in q order), Cholesky and two triangular solves, every
+ * inner sum correctly rounded.  mu host (nmu x p), c host (nmu x N).
+ * ENUMERIC when a reduced matrix is not positive definite. */
+rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, double* c, void* stream);
+/* Lift u_b = V c_b for b < nmu: c device (nmu x N), u device (nmu x ndof).
+ * mode RBWS_LIFT_EXACT: every entry a correctly rounded N-term dot;
+ * RBWS_LIFT_MFMA: FP64 matrix cores (rounding depends on the blocking). */
+rbws_status rbws_rb_lift(const rbws_basis* b, const double* c, int nmu, double* u, int mode, void* stream);
+/* Checkpoint: the basis, reduced matrices, selection and indicator history.
+ * Loading checks that the file belongs to problem p. */
+rbws_status rbws_basis_save(const rbws_basis* b, const char* path);
+rbws_status rbws_basis_load(rbws_problem* p, const char* path, rbws_basis** out);
+
 /* ---- batched solve (Alg. 5 driving Alg. 1) --------------------------------
  * Solves nmu systems in one batch.  problems[0..nprob) may have different
  * grid sizes (the uneven batch); problem_of[b] (NULL = all 0) picks the

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "solver.hpp"
+#include "rb.hpp"
 
 namespace rbws {
 
@@ -76,6 +76,8 @@ using namespace rbws;
 
 static inline Problem* PP(rbws_problem* p) { return reinterpret_cast<Problem*>(p); }
 static inline const Problem* PP(const rbws_problem* p) { return reinterpret_cast<const Problem*>(p); }
+static inline Basis* BB(rbws_basis* b) { return reinterpret_cast<Basis*>(b); }
+static inline const Basis* BB(const rbws_basis* b) { return reinterpret_cast<const Basis*>(b); }
 
 extern "C" {
 
@@ -139,7 +141,7 @@ rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x,
   if (nmu == 0) return RBWS_OK;
   RBWS_REQUIRE(mu && x && y, RBWS_EINVAL, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
-  static thread_local Batch B;
+  static thread_local Batch& B = *new Batch();
   std::vector<const Problem*> probs{PP(p)};
   batch_setup(B, probs, nullptr, nmu, mu, PP(p)->p, s);
   spmv_batch(B, x, y, precision == RBWS_FP32_IR, s);
@@ -162,6 +164,118 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
   API_END
 }
 
+rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
+                          int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
+                          double* indicator_hist, int* n_reached) {
+  API_BEGIN
+  RBWS_REQUIRE(p && mu_train && out, RBWS_EINVAL, "NULL argument");
+  RBWS_REQUIRE(precond == RBWS_PREC_NONE || precond == RBWS_PREC_JACOBI, RBWS_EINVAL, "bad precond");
+  RBWS_REQUIRE(snap_maxit >= 1, RBWS_EINVAL, "snap_maxit < 1");
+  *out = nullptr;
+  Basis* b = rb_build(PP(p), mu_train, ntrain, N, snap_tol, precond, snap_maxit, 0, (hipStream_t)stream);
+  if (selected)
+    for (int i = 0; i < N; i++) selected[i] = i < b->N ? b->selected[i] : -1;
+  if (indicator_hist)
+    for (size_t i = 0; i < (size_t)N * ntrain; i++)
+      indicator_hist[i] = i < b->hist.size() ? b->hist[i] : std::nan("");
+  if (n_reached) *n_reached = b->N;
+  *out = reinterpret_cast<rbws_basis*>(b);
+  API_END
+}
+
+void rbws_basis_destroy(rbws_basis* b) { delete BB(b); }
+
+rbws_status rbws_basis_info(const rbws_basis* b, int* N, int* nq, long long* ndof, double* final_max) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  const Basis* B = BB(b);
+  if (N) *N = B->N;
+  if (nq) *nq = B->Q;
+  if (ndof) *ndof = B->ndof;
+  if (final_max) *final_max = B->final_max;
+  API_END
+}
+
+rbws_status rbws_basis_get(const rbws_basis* b, double* V, double* AqN, double* fN) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  const Basis* B = BB(b);
+  if (V) {
+    RBWS_HIP(hipSetDevice(B->prob->device));
+    RBWS_HIP(hipMemcpy(V, B->V.ptr, sizeof(double) * B->N * B->ndof, hipMemcpyDeviceToHost));
+  }
+  if (AqN)
+    for (int q = 0; q < B->Q; q++)
+      for (int i = 0; i < B->N; i++)
+        for (int j = 0; j < B->N; j++)
+          AqN[((size_t)q * B->N + i) * B->N + j] = B->AqN[((size_t)q * B->Nmax + i) * B->Nmax + j];
+  if (fN)
+    for (int i = 0; i < B->N; i++) fN[i] = B->fN[i];
+  API_END
+}
+
+rbws_status rbws_basis_device_v(const rbws_basis* b, const double** V) {
+  API_BEGIN
+  RBWS_REQUIRE(b && V, RBWS_EINVAL, "NULL argument");
+  *V = (const double*)BB(b)->V.ptr;
+  API_END
+}
+
+rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, double* c, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(mu && c, RBWS_EINVAL, "NULL argument");
+  const Basis* B = BB(b);
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local Batch& bt = *new Batch();
+  RBWS_SCRATCH(cb);
+  std::vector<const Problem*> probs{B->prob};
+  batch_setup(bt, probs, nullptr, nmu, mu, B->prob->p, s);
+  double* cd = (double*)cb.get(sizeof(double) * nmu * B->N, bt.device);
+  std::vector<const Basis*> bl{B};
+  const int bad = rb_coeffs(bt, bl, cd, B->N, 0, s);
+  RBWS_REQUIRE(bad == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
+  RBWS_HIP(hipMemcpyAsync(c, cd, sizeof(double) * nmu * B->N, hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+rbws_status rbws_rb_lift(const rbws_basis* b, const double* c, int nmu, double* u, int mode, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  RBWS_REQUIRE(mode == RBWS_LIFT_EXACT || mode == RBWS_LIFT_MFMA, RBWS_EINVAL, "bad lift mode");
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(c && u, RBWS_EINVAL, "NULL argument");
+  const Basis* B = BB(b);
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local Batch& bt = *new Batch();
+  std::vector<const Problem*> probs{B->prob};
+  std::vector<double> th((size_t)nmu * B->Q, 1.0);
+  batch_setup(bt, probs, nullptr, nmu, nullptr, B->prob->p, s, th.data());
+  std::vector<const Basis*> bl{B};
+  if (mode == RBWS_LIFT_EXACT) rb_lift_exact(bt, bl, c, B->N, u, 0, s);
+  else rb_lift_mfma(bt, B, c, B->N, u, s);
+  RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+rbws_status rbws_basis_save(const rbws_basis* b, const char* path) {
+  API_BEGIN
+  basis_save(BB(b), path);
+  API_END
+}
+
+rbws_status rbws_basis_load(rbws_problem* p, const char* path, rbws_basis** out) {
+  API_BEGIN
+  RBWS_REQUIRE(p && path && out, RBWS_EINVAL, "NULL argument");
+  *out = nullptr;
+  *out = reinterpret_cast<rbws_basis*>(basis_load(PP(p), path, nullptr));
+  API_END
+}
+
 rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* bases,
                        const rbws_mlp* const* mlps, int nprob, const int* problem_of,
                        const double* mu, int nmu, const rbws_solve_opts* opts, void* stream,
@@ -177,7 +291,6 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   RBWS_REQUIRE(opts->precision == RBWS_FP64 || opts->precision == RBWS_FP32_IR, RBWS_EINVAL,
                "bad precision");
   RBWS_REQUIRE(opts->init >= RBWS_INIT_ZERO && opts->init <= RBWS_INIT_LEARNED, RBWS_EINVAL, "bad init");
-  (void)bases;
   (void)mlps;
   std::vector<const Problem*> probs(nprob);
   for (int q = 0; q < nprob; q++) {
@@ -186,13 +299,32 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   }
   if (nmu == 0) return RBWS_OK;
   RBWS_REQUIRE(mu != nullptr, RBWS_EINVAL, "mu is NULL");
-  RBWS_REQUIRE(opts->init == RBWS_INIT_ZERO, RBWS_ESTATE, "this init needs a basis");
+  RBWS_REQUIRE(opts->init != RBWS_INIT_LEARNED, RBWS_ESTATE, "no learned model given");
+  RBWS_REQUIRE(opts->lift == RBWS_LIFT_EXACT || opts->lift == RBWS_LIFT_MFMA, RBWS_EINVAL, "bad lift");
+  std::vector<const Basis*> bl(nprob, nullptr);
+  if (opts->init == RBWS_INIT_RB) {
+    RBWS_REQUIRE(bases != nullptr, RBWS_ESTATE, "RB start needs a basis per problem");
+    for (int q = 0; q < nprob; q++) {
+      RBWS_REQUIRE(bases[q] != nullptr, RBWS_ESTATE, "RB start needs a basis per problem");
+      bl[q] = BB(bases[q]);
+      RBWS_REQUIRE(bl[q]->prob == probs[q], RBWS_EINVAL, "basis belongs to another problem");
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
-  static thread_local Batch B;
+  static thread_local Batch& B = *new Batch();
+  RBWS_SCRATCH(cbuf);
   batch_setup(B, probs, problem_of, nmu, mu, probs[0]->p, s);
   double* x = (double*)B.x.get(sizeof(double) * B.total, B.device);
-  fill64(x, B.total, 0.0, s);
-  static thread_local DevBuf tbuf;
+  const int fe = (opts->flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
+  if (opts->init == RBWS_INIT_ZERO) {
+    fill64(x, B.total, 0.0, s);
+  } else {
+    double* cd = (double*)cbuf.get(sizeof(double) * 64 * nmu, B.device);
+    RBWS_REQUIRE(rb_coeffs(B, bl, cd, 64, fe, s) == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
+    if (opts->lift == RBWS_LIFT_MFMA && nprob == 1) rb_lift_mfma(B, bl[0], cd, 64, x, s);
+    else rb_lift_exact(B, bl, cd, 64, x, fe, s);
+  }
+  RBWS_SCRATCH(tbuf);
   unsigned long long* tdev = (unsigned long long*)tbuf.get(sizeof(unsigned long long), B.device);
   hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, tdev);
   CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every};

@@ -1,0 +1,736 @@
+// rb.hip -- reduced basis on gfx950.
+//
+// Offline (the paper's Alg. 4 skeleton with a residual-norm indicator):
+//   snapshot u(mu_l) by the batched PCG from zero; two classical Gram-Schmidt
+//   passes against V (each coefficient and each updated entry one correctly
+//   rounded dot); v_n = v / ||v||; W_q = A_q v_n for every affine term (the
+//   stencil with theta = e_q); A_q^N[i][n] = A_q^N[n][i] = v_i . W_q and
+//   f^N[n] = v_n . f; then the indicator ||f - A(mu) V c(mu)|| / ||f|| for the
+//   whole training set, evaluated directly (lift, stencil, norm); the next
+//   parameter is the first maximiser.
+// Online (Eq. "RB system"): A_N(mu) = sum_q theta_q A_q^N (fma in q order),
+//   Cholesky and two triangular solves in one wavefront per parameter, every
+//   inner sum a correctly rounded dot; then the lift u0 = V c.
+// Two lifts: exact (each entry a correctly rounded N-term dot; used where the
+// FP64 trajectory must be reproducible) and FP64 MFMA (v_mfma_f64_16x16x4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "rb.hpp"
+
+namespace rbws {
+
+constexpr int kMaxN = 64;
+constexpr int kRedoCap = 1 << 20;
+
+// ---------------------------------------------------------------------------
+// dots of pointer pairs: out[v] = xs[v] . ys[v], all of length len
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pdot_part(const double* const* xs, const double* const* ys,
+                                                   long long len, int per_block, CrAcc* part) {
+  __shared__ CrAcc red[4];
+  const int v = blockIdx.y;
+  const double* X = xs[v];
+  const double* Y = ys[v];
+  const long long beg = (long long)blockIdx.x * per_block, end = min(len, beg + per_block);
+  CrAcc a = cr_zero();
+  for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) cr_add_prod(a, X[c], Y[c]);
+  a = cr_block_reduce(a, red);
+  if (threadIdx.x == 0) part[(long long)v * gridDim.x + blockIdx.x] = a;
+}
+
+struct DotShared {
+  CrAcc red[4];
+  XAcc xa;
+  uint32_t dig[XA_WORDS];
+  double val;
+  int ok;
+};
+
+__global__ __launch_bounds__(256) void k_pdot_fin(const double* const* xs, const double* const* ys,
+                                                  long long len, int nparts, const CrAcc* part,
+                                                  double* out, int force_exact) {
+  __shared__ DotShared sh;
+  const int v = blockIdx.x;
+  CrAcc a = cr_zero();
+  for (int t = threadIdx.x; t < nparts; t += blockDim.x) a = cr_combine(a, part[(long long)v * nparts + t]);
+  a = cr_block_reduce(a, sh.red);
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    sh.ok = (!force_exact && cr_finalize(a, &r)) ? 1 : 0;
+    sh.val = r;
+  }
+  __syncthreads();
+  if (sh.ok) {
+    if (threadIdx.x == 0) out[v] = sh.val;
+    return;
+  }
+  __syncthreads();
+  xa_clear(&sh.xa);
+  __syncthreads();
+  const double* X = xs[v];
+  const double* Y = ys[v];
+  for (long long c = threadIdx.x; c < len; c += blockDim.x) xa_add_prod(&sh.xa, X[c], Y[c]);
+  __syncthreads();
+  if (threadIdx.x == 0) out[v] = xa_round(&sh.xa, sh.dig);
+}
+
+// out (device) = correctly rounded dots of the pairs (host pointer lists)
+static void pair_dots(const std::vector<const double*>& xs, const std::vector<const double*>& ys,
+                      long long len, double* out_dev, int force_exact, int dev, hipStream_t s) {
+  const int count = (int)xs.size();
+  if (count == 0) return;
+  RBWS_SCRATCH(ptrs);
+  RBWS_SCRATCH(part);
+  const int per_block = 8192;
+  const long long nb = std::max<long long>(1, (len + per_block - 1) / per_block);
+  const double** pp = (const double**)ptrs.get(sizeof(double*) * 2 * count, dev);
+  std::vector<const double*> h(xs);
+  h.insert(h.end(), ys.begin(), ys.end());
+  RBWS_HIP(hipMemcpyAsync(pp, h.data(), sizeof(double*) * 2 * count, hipMemcpyHostToDevice, s));
+  CrAcc* pa = (CrAcc*)part.get(sizeof(CrAcc) * nb * count, dev);
+  hipLaunchKernelGGL(k_pdot_part, dim3((unsigned)nb, count), dim3(256), 0, s, pp, pp + count, len, per_block, pa);
+  hipLaunchKernelGGL(k_pdot_fin, dim3(count), dim3(256), 0, s, pp, pp + count, len, (int)nb, pa, out_dev,
+                     force_exact);
+  RBWS_HIP(hipGetLastError());
+  // the host vector `h` must outlive the asynchronous copy
+  RBWS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Gram-Schmidt update v_c = v_c - sum_j coef_j V_j,c (one correctly rounded dot per entry)
+// ---------------------------------------------------------------------------
+struct Redo {
+  int count;
+  int overflow;
+  long long idx[1];  // kRedoCap entries follow
+};
+
+__device__ __forceinline__ void redo_push(Redo* r, long long e) {
+  int slot = atomicAdd(&r->count, 1);
+  if (slot < kRedoCap) r->idx[slot] = e;
+  else r->overflow = 1;
+}
+
+__global__ __launch_bounds__(256) void k_gs_update(double* v, const double* V, const double* coef, int nb,
+                                                   long long ndof, Redo* redo, int force_exact) {
+  __shared__ double cs[kMaxN];
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) cs[j] = -coef[j];
+  __syncthreads();
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ndof;
+       c += (long long)gridDim.x * blockDim.x) {
+    CrAcc a = cr_zero();
+    cr_add(a, v[c]);
+    for (int j = 0; j < nb; j++) cr_add_prod(a, cs[j], V[(long long)j * ndof + c]);
+    double r;
+    if (!force_exact && cr_finalize(a, &r)) v[c] = r;
+    else redo_push(redo, c);
+  }
+}
+
+// exact recomputation of the listed entries (one 64-thread block per entry)
+__global__ __launch_bounds__(64) void k_gs_redo(double* v, const double* V, const double* coef, int nb,
+                                                long long ndof, const Redo* redo) {
+  __shared__ XAcc xa;
+  __shared__ uint32_t dig[XA_WORDS];
+  const long long total = redo->overflow ? ndof : (long long)redo->count;
+  for (long long e = blockIdx.x; e < total; e += gridDim.x) {
+    const long long c = redo->overflow ? e : redo->idx[e];
+    __syncthreads();
+    xa_clear(&xa);
+    __syncthreads();
+    if (threadIdx.x == 0) xa_add(&xa, v[c]);
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) xa_add_prod(&xa, -coef[j], V[(long long)j * ndof + c]);
+    __syncthreads();
+    const double r = threadIdx.x == 0 ? xa_round(&xa, dig) : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) v[c] = r;
+  }
+}
+
+__global__ void k_div(double* out, const double* v, const double* nrm, long long ndof) {
+  const double d = *nrm;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ndof;
+       c += (long long)gridDim.x * blockDim.x)
+    out[c] = v[c] / d;
+}
+
+__global__ void k_copy_rep(double* dst, const double* src, long long ndof, int reps) {
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ndof * reps;
+       c += (long long)gridDim.x * blockDim.x)
+    dst[c] = src[c % ndof];
+}
+
+// ---------------------------------------------------------------------------
+// online solve: one wavefront per parameter
+// ---------------------------------------------------------------------------
+struct CholShared {
+  double A[kMaxN * kMaxN];  // assembled matrix; its lower triangle becomes L
+  double y[kMaxN];
+  double c[kMaxN];
+  XAcc xa;
+  uint32_t dig[XA_WORDS];
+  double val;
+  int ok;
+};
+
+// value of sum over lanes of the terms each lane added to `a` (all 64 lanes
+// call); exact fallback adds the same terms through `add_terms`
+template <typename F>
+__device__ __forceinline__ double wave_sum(CholShared& sh, CrAcc a, int force_exact, F add_terms) {
+  a = cr_wave_reduce(a);
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    sh.ok = (!force_exact && cr_finalize(a, &r)) ? 1 : 0;
+    sh.val = r;
+  }
+  __syncthreads();
+  if (!sh.ok) {
+    __syncthreads();
+    xa_clear(&sh.xa);
+    __syncthreads();
+    add_terms(&sh.xa);
+    __syncthreads();
+    if (threadIdx.x == 0) sh.val = xa_round(&sh.xa, sh.dig);
+  }
+  __syncthreads();
+  const double v = sh.val;
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_rb_coeffs(const RbDev* __restrict__ rbd, const int* __restrict__ solve_of,
+                                                  const double* __restrict__ theta, double* __restrict__ cout,
+                                                  int cstride, int* bad, int force_exact) {
+  __shared__ CholShared sh;
+  const int b = solve_of ? solve_of[blockIdx.x] : (int)blockIdx.x;
+  const RbDev R = rbd[b];
+  const int N = R.N, ld = R.ld, lane = threadIdx.x;
+  const double* th = theta + (long long)b * kMaxQ;
+  for (int e = lane; e < N * N; e += 64) {
+    const int i = e / N, j = e % N;
+    double a = 0.0;
+    for (int q = 0; q < R.Q; q++) a = __fma_rn(th[q], R.AqN[((long long)q * ld + i) * ld + j], a);
+    sh.A[i * kMaxN + j] = a;
+  }
+  __syncthreads();
+  double* A = sh.A;
+  int fail = 0;
+  for (int j = 0; j < N && !fail; j++) {
+    // pivot: A_jj - sum_{k<j} L_jk^2
+    CrAcc a = cr_zero();
+    if (lane < j) cr_add_prod(a, -A[j * kMaxN + lane], A[j * kMaxN + lane]);
+    if (lane == j) cr_add(a, A[j * kMaxN + j]);
+    const double piv = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane < j) xa_add_prod(x, -A[j * kMaxN + lane], A[j * kMaxN + lane]);
+      if (lane == j) xa_add(x, A[j * kMaxN + j]);
+    });
+    if (!(piv > 0.0) || !__builtin_isfinite(piv)) { fail = 1; break; }
+    const double ljj = sqrt(piv);
+    // column j below the diagonal: lane i computes its own entry
+    double lij = 0.0;
+    int amb = 0;
+    if (lane > j && lane < N) {
+      CrAcc t = cr_zero();
+      cr_add(t, A[lane * kMaxN + j]);
+      for (int k = 0; k < j; k++) cr_add_prod(t, -A[lane * kMaxN + k], A[j * kMaxN + k]);
+      double v;
+      if (!force_exact && cr_finalize(t, &v)) lij = v / ljj;
+      else amb = 1;
+    }
+    unsigned long long m = __ballot(amb);
+    while (m) {  // exact path for the rare ambiguous entries, one at a time
+      const int i = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      __syncthreads();
+      xa_clear(&sh.xa);
+      __syncthreads();
+      if (lane == 0) xa_add(&sh.xa, A[i * kMaxN + j]);
+      if (lane < j) xa_add_prod(&sh.xa, -A[i * kMaxN + lane], A[j * kMaxN + lane]);
+      __syncthreads();
+      if (lane == 0) sh.val = xa_round(&sh.xa, sh.dig);
+      __syncthreads();
+      if (lane == i) lij = sh.val / ljj;
+    }
+    __syncthreads();
+    if (lane > j && lane < N) A[lane * kMaxN + j] = lij;
+    if (lane == j) A[j * kMaxN + j] = ljj;
+    __syncthreads();
+  }
+  if (fail) {
+    if (lane == 0) atomicAdd(bad, 1);
+    for (int i = lane; i < N; i += 64) cout[(long long)b * cstride + i] = __builtin_nan("");
+    return;
+  }
+  // forward: L y = b_N
+  for (int i = 0; i < N; i++) {
+    CrAcc a = cr_zero();
+    if (lane < i) cr_add_prod(a, -A[i * kMaxN + lane], sh.y[lane]);
+    if (lane == i) cr_add(a, R.fN[i]);
+    const double v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane < i) xa_add_prod(x, -A[i * kMaxN + lane], sh.y[lane]);
+      if (lane == i) xa_add(x, R.fN[i]);
+    });
+    if (lane == 0) sh.y[i] = v / A[i * kMaxN + i];
+    __syncthreads();
+  }
+  // back: L^T c = y
+  for (int i = N - 1; i >= 0; i--) {
+    CrAcc a = cr_zero();
+    if (lane > i && lane < N) cr_add_prod(a, -A[lane * kMaxN + i], sh.c[lane]);
+    if (lane == i) cr_add(a, sh.y[i]);
+    const double v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane > i && lane < N) xa_add_prod(x, -A[lane * kMaxN + i], sh.c[lane]);
+      if (lane == i) xa_add(x, sh.y[i]);
+    });
+    if (lane == 0) sh.c[i] = v / A[i * kMaxN + i];
+    __syncthreads();
+  }
+  for (int i = lane; i < N; i += 64) cout[(long long)b * cstride + i] = sh.c[i];
+}
+
+// ---------------------------------------------------------------------------
+// exact lift: u[b][c] = sum_j V[j][c] C[b][j], each a correctly rounded dot.
+// A block owns 64 points; their V values stay in LDS while it walks solves.
+// ---------------------------------------------------------------------------
+constexpr int kLiftPts = 64;
+constexpr int kLiftGroup = 32;  // solves per block
+
+__global__ __launch_bounds__(256) void k_lift_exact(const double* __restrict__ V, int N, long long ndof,
+                                                    const int* __restrict__ solves, int nsol,
+                                                    const long long* __restrict__ off,
+                                                    const double* __restrict__ C, int cstride,
+                                                    double* __restrict__ u, Redo* redo, int force_exact) {
+  __shared__ double vt[kMaxN * kLiftPts];
+  const long long c0 = (long long)blockIdx.x * kLiftPts;
+  const int pl = threadIdx.x % kLiftPts, sl = threadIdx.x / kLiftPts;
+  for (int e = threadIdx.x; e < N * kLiftPts; e += blockDim.x) {
+    const int j = e / kLiftPts, q = e % kLiftPts;
+    vt[e] = (c0 + q < ndof) ? V[(long long)j * ndof + c0 + q] : 0.0;
+  }
+  __syncthreads();
+  const long long c = c0 + pl;
+  if (c >= ndof) return;
+  const int g0 = blockIdx.y * kLiftGroup;
+  for (int t = g0 + sl; t < min(nsol, g0 + kLiftGroup); t += blockDim.x / kLiftPts) {
+    const int b = solves ? solves[t] : t;
+    const double* cb = C + (long long)b * cstride;
+    CrAcc a = cr_zero();
+    for (int j = 0; j < N; j++) cr_add_prod(a, vt[j * kLiftPts + pl], cb[j]);
+    double r;
+    const long long e = off[b] + c;
+    if (!force_exact && cr_finalize(a, &r)) u[e] = r;
+    else redo_push(redo, ((long long)t << 32) | c);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_lift_redo(const double* V, int N, long long ndof, const int* solves,
+                                                  int nsol, const long long* off, const double* C,
+                                                  int cstride, double* u, const Redo* redo) {
+  __shared__ XAcc xa;
+  __shared__ uint32_t dig[XA_WORDS];
+  const long long total = redo->overflow ? ndof * nsol : (long long)redo->count;
+  for (long long e = blockIdx.x; e < total; e += gridDim.x) {
+    long long t, c;
+    if (redo->overflow) { t = e / ndof; c = e % ndof; }
+    else { t = redo->idx[e] >> 32; c = redo->idx[e] & 0xffffffffll; }
+    const int b = solves ? solves[t] : (int)t;
+    const double* cb = C + (long long)b * cstride;
+    __syncthreads();
+    xa_clear(&xa);
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += blockDim.x) xa_add_prod(&xa, V[(long long)j * ndof + c], cb[j]);
+    __syncthreads();
+    const double r = threadIdx.x == 0 ? xa_round(&xa, dig) : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) u[off[b] + c] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA lift: U (solves x points) = C (solves x N) * V (N x points), FP64
+// v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// D[i][j] in lane j + 16 (i % 4), register i / 4.
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_lift_mfma(const double* __restrict__ V, int N, long long ndof,
+                                                   const int* __restrict__ solves, int nsol,
+                                                   const long long* __restrict__ off,
+                                                   const double* __restrict__ C, int cstride,
+                                                   double* __restrict__ u) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long c0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  if (c0 >= ndof) return;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long cc = c0 + col;
+  const bool cin = cc < ndof;
+  // V fragment for this 16-point tile: K = N padded to a multiple of 4
+  double vb[kMaxN / 4];
+  const int ksteps = (N + 3) / 4;
+#pragma unroll
+  for (int s = 0; s < kMaxN / 4; s++) {
+    const int k = 4 * s + kq;
+    vb[s] = (s < ksteps && k < N && cin) ? V[(long long)k * ndof + cc] : 0.0;
+  }
+  for (int t0 = 0; t0 < nsol; t0 += 16) {
+    const int ta = t0 + col;  // the solve row this lane feeds into A
+    const int ba = ta < nsol ? (solves ? solves[ta] : ta) : -1;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kMaxN / 4; s++) {
+      if (s < ksteps) {
+        const int k = 4 * s + kq;
+        const double a = (ba >= 0 && k < N) ? C[(long long)ba * cstride + k] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[s], acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int t = t0 + 4 * r + kq;
+      if (t < nsol && cin) {
+        const int b = solves ? solves[t] : t;
+        u[off[b] + cc] = acc[r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void Basis::upload(hipStream_t s) {
+  const int dev = prob->device;
+  double* a = (double*)AqN_d.get(sizeof(double) * AqN.size(), dev);
+  RBWS_HIP(hipMemcpyAsync(a, AqN.data(), sizeof(double) * AqN.size(), hipMemcpyHostToDevice, s));
+  double* f = (double*)fN_d.get(sizeof(double) * fN.size(), dev);
+  RBWS_HIP(hipMemcpyAsync(f, fN.data(), sizeof(double) * fN.size(), hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+}
+
+static RbDev rbdev_of(const Basis* bs) {
+  RbDev r;
+  r.AqN = (const double*)bs->AqN_d.ptr;
+  r.fN = (const double*)bs->fN_d.ptr;
+  r.V = (const double*)bs->V.ptr;
+  r.N = bs->N;
+  r.ld = bs->Nmax;
+  r.Q = bs->Q;
+  r.pad = 0;
+  return r;
+}
+
+int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride, int force_exact,
+              hipStream_t s) {
+  const int ns = B.nsolve;
+  if (ns == 0) return 0;
+  std::vector<RbDev> h(ns);
+  for (int b = 0; b < ns; b++) {
+    const Basis* bs = bases[B.sd_h[b].prob];
+    RBWS_REQUIRE(bs != nullptr, RBWS_ESTATE, "a reduced basis is required for this start");
+    RBWS_REQUIRE(bs->prob == B.probs[B.sd_h[b].prob], RBWS_EINVAL, "basis belongs to another problem");
+    RBWS_REQUIRE(bs->prob->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL,
+                 "the online RB solve supports f = 1 (affine right-hand side)");
+    RBWS_REQUIRE(bs->N <= cstride, RBWS_EINVAL, "coefficient stride too small");
+    h[b] = rbdev_of(bs);
+  }
+  RBWS_SCRATCH(rbd);
+  RBWS_SCRATCH(badb);
+  RbDev* d = (RbDev*)rbd.get(sizeof(RbDev) * ns, B.device);
+  int* bad = (int*)badb.get(sizeof(int), B.device);
+  RBWS_HIP(hipMemcpyAsync(d, h.data(), sizeof(RbDev) * ns, hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_rb_coeffs, dim3(ns), dim3(64), 0, s, d, (const int*)nullptr,
+                     (const double*)B.theta.ptr, c, cstride, bad, force_exact);
+  RBWS_HIP(hipGetLastError());
+  int hb = 0;
+  RBWS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  return hb;
+}
+
+// solves of batch B that belong to problem q, and the vector offsets of all solves
+static void group_of(Batch& B, int q, std::vector<int>& sol) {
+  sol.clear();
+  for (int b = 0; b < B.nsolve; b++)
+    if (B.sd_h[b].prob == q) sol.push_back(b);
+}
+
+static long long* offsets_dev(Batch& B, hipStream_t s) {
+  RBWS_SCRATCH(offb);
+  std::vector<long long> o(std::max(B.nsolve, 1));
+  for (int b = 0; b < B.nsolve; b++) o[b] = B.sd_h[b].off;
+  long long* d = (long long*)offb.get(sizeof(long long) * o.size(), B.device);
+  RBWS_HIP(hipMemcpyAsync(d, o.data(), sizeof(long long) * o.size(), hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+void rb_lift_exact(Batch& B, const std::vector<const Basis*>& bases, const double* c, int cstride,
+                   double* u, int force_exact, hipStream_t s) {
+  if (B.nsolve == 0) return;
+  long long* off = offsets_dev(B, s);
+  RBWS_SCRATCH(solb);
+  RBWS_SCRATCH(redob);
+  Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, B.device);
+  std::vector<int> sol;
+  for (int q = 0; q < B.nprob; q++) {
+    group_of(B, q, sol);
+    if (sol.empty()) continue;
+    const Basis* bs = bases[q];
+    RBWS_REQUIRE(bs != nullptr && bs->N >= 1, RBWS_ESTATE, "a reduced basis is required for this start");
+    int* sd = (int*)solb.get(sizeof(int) * sol.size(), B.device);
+    RBWS_HIP(hipMemcpyAsync(sd, sol.data(), sizeof(int) * sol.size(), hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
+    const long long nd = bs->ndof;
+    dim3 grid((unsigned)((nd + kLiftPts - 1) / kLiftPts), (unsigned)((sol.size() + kLiftGroup - 1) / kLiftGroup));
+    hipLaunchKernelGGL(k_lift_exact, grid, dim3(256), 0, s, (const double*)bs->V.ptr, bs->N, nd, sd,
+                       (int)sol.size(), off, c, cstride, u, redo, force_exact);
+    hipLaunchKernelGGL(k_lift_redo, dim3(1024), dim3(64), 0, s, (const double*)bs->V.ptr, bs->N, nd, sd,
+                       (int)sol.size(), off, c, cstride, u, redo);
+    RBWS_HIP(hipGetLastError());
+    RBWS_HIP(hipStreamSynchronize(s));  // `sol` is reused by the next group
+  }
+}
+
+void rb_lift_mfma(Batch& B, const Basis* bs, const double* c, int cstride, double* u, hipStream_t s) {
+  if (B.nsolve == 0) return;
+  RBWS_REQUIRE(bs != nullptr && bs->N >= 1, RBWS_ESTATE, "a reduced basis is required for this start");
+  long long* off = offsets_dev(B, s);
+  const long long nd = bs->ndof;
+  const unsigned grid = (unsigned)((nd + 63) / 64);
+  hipLaunchKernelGGL(k_lift_mfma, dim3(grid), dim3(256), 0, s, (const double*)bs->V.ptr, bs->N, nd,
+                     (const int*)nullptr, B.nsolve, off, c, cstride, u);
+  RBWS_HIP(hipGetLastError());
+}
+
+Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol, int prec,
+                int snap_maxit, int flags, hipStream_t s) {
+  RBWS_REQUIRE(ntrain >= 1, RBWS_EINVAL, "empty training set");
+  RBWS_REQUIRE(N >= 1 && N <= kMaxN, RBWS_EINVAL, "N must be in [1, 64]");
+  RBWS_REQUIRE(N <= ntrain, RBWS_EINVAL, "N exceeds the training set");
+  RBWS_REQUIRE(snap_tol > 0.0 && std::isfinite(snap_tol), RBWS_EINVAL, "snap_tol must be positive");
+  RBWS_REQUIRE(P->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL, "the greedy build supports f = 1");
+  RBWS_HIP(hipSetDevice(P->device));
+  const int fe = (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
+  const long long nd = P->ndof;
+  const int Q = P->Q, dev = P->device;
+  Basis* bs = new Basis();
+  try {
+    bs->prob = P;
+    bs->Nmax = N;
+    bs->Q = Q;
+    bs->ndof = nd;
+    bs->ntrain = ntrain;
+    bs->AqN.assign((size_t)Q * N * N, 0.0);
+    bs->fN.assign(N, 0.0);
+    double* V = (double*)bs->V.get(sizeof(double) * N * nd, dev);
+    DevBuf vbuf, wbuf, fbuf, scal, cbuf, redob;
+    double* v = (double*)vbuf.get(sizeof(double) * nd, dev);
+    double* W = (double*)wbuf.get(sizeof(double) * Q * nd, dev);
+    double* f = (double*)fbuf.get(sizeof(double) * nd, dev);
+    double* sc = (double*)scal.get(sizeof(double) * (kMaxN * kMaxQ + 8), dev);
+    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, dev);
+    const double h = 1.0 / (P->n + 1);
+    fill64(f, nd, h * h, s);
+    std::vector<const Problem*> probs{P};
+    Batch snap, eq, tr;
+    // A_q = A(theta = e_q): a batch of Q "solves" with unit theta vectors
+    std::vector<double> eth((size_t)Q * Q, 0.0);
+    for (int q = 0; q < Q; q++) eth[(size_t)q * Q + q] = 1.0;
+    batch_setup(eq, probs, nullptr, Q, mu_train, P->p, s, eth.data());
+    // training batch in chunks of at most `chunk` parameters
+    const long long budget = 4LL << 30;  // bytes for the lifted training vectors
+    int chunk = (int)std::max<long long>(1, std::min<long long>(ntrain, budget / (8 * nd)));
+    const int stride = kMaxN;
+    std::vector<double> delta(ntrain), hrow;
+    int l = 0, nb = 0;
+    for (;;) {
+      // snapshot u(mu_l) by Alg. 1 from zero
+      batch_setup(snap, probs, nullptr, 1, mu_train + (long long)l * P->p, P->p, s);
+      double* x = (double*)snap.x.get(sizeof(double) * nd, dev);
+      fill64(x, nd, 0.0, s);
+      cg_fp64_run(snap, CgOpts{snap_tol, snap_maxit, prec, flags, 0}, s);
+      RBWS_HIP(hipMemcpyAsync(v, x, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+      // two classical Gram-Schmidt passes
+      for (int pass = 0; pass < 2 && nb > 0; pass++) {
+        std::vector<const double*> xs, ys;
+        for (int j = 0; j < nb; j++) {
+          xs.push_back(V + (long long)j * nd);
+          ys.push_back(v);
+        }
+        pair_dots(xs, ys, nd, sc, fe, dev, s);
+        RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
+        hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, v, (const double*)V, (const double*)sc, nb,
+                           nd, redo, fe);
+        hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, v, (const double*)V, (const double*)sc, nb,
+                           nd, (const Redo*)redo);
+        RBWS_HIP(hipGetLastError());
+      }
+      pair_dots({v, x}, {v, x}, nd, sc + kMaxN * kMaxQ, fe, dev, s);
+      double nn[2];
+      RBWS_HIP(hipMemcpyAsync(nn, sc + kMaxN * kMaxQ, sizeof nn, hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+      const double nrm = std::sqrt(nn[0]), unrm = std::sqrt(nn[1]);
+      if (!(nrm >= 1e-10 * unrm)) break;  // the snapshot adds nothing new
+      RBWS_HIP(hipMemcpyAsync(sc + kMaxN * kMaxQ + 2, &nrm, sizeof(double), hipMemcpyHostToDevice, s));
+      double* vn = V + (long long)nb * nd;
+      hipLaunchKernelGGL(k_div, dim3(2048), dim3(256), 0, s, vn, (const double*)v,
+                         (const double*)(sc + kMaxN * kMaxQ + 2), nd);
+      bs->selected.push_back(l);
+      // W_q = A_q v_n, then the new row/column of every A_q^N and f^N
+      hipLaunchKernelGGL(k_copy_rep, dim3(2048), dim3(256), 0, s, W, (const double*)vn, nd, Q);
+      {
+        double* Wx = (double*)eq.x.get(sizeof(double) * Q * nd, dev);
+        RBWS_HIP(hipMemcpyAsync(Wx, W, sizeof(double) * Q * nd, hipMemcpyDeviceToDevice, s));
+        spmv_batch(eq, Wx, W, false, s);
+      }
+      std::vector<const double*> xs, ys;
+      for (int q = 0; q < Q; q++)
+        for (int i = 0; i <= nb; i++) {
+          xs.push_back(V + (long long)i * nd);
+          ys.push_back(W + (long long)q * nd);
+        }
+      xs.push_back(vn);
+      ys.push_back(f);
+      pair_dots(xs, ys, nd, sc, fe, dev, s);
+      std::vector<double> hv(xs.size());
+      RBWS_HIP(hipMemcpyAsync(hv.data(), sc, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < Q; q++)
+        for (int i = 0; i <= nb; i++) {
+          const double a = hv[(size_t)q * (nb + 1) + i];
+          bs->AqN[((size_t)q * N + i) * N + nb] = a;
+          bs->AqN[((size_t)q * N + nb) * N + i] = a;
+        }
+      bs->fN[nb] = hv.back();
+      nb++;
+      bs->N = nb;
+      bs->upload(s);
+      // indicator over the training set with nb basis vectors
+      std::vector<const Basis*> bl{bs};
+      for (int t0 = 0; t0 < ntrain; t0 += chunk) {
+        const int cnt = std::min(chunk, ntrain - t0);
+        batch_setup(tr, probs, nullptr, cnt, mu_train + (long long)t0 * P->p, P->p, s);
+        double* cd = (double*)cbuf.get(sizeof(double) * stride * cnt, dev);
+        RBWS_REQUIRE(rb_coeffs(tr, bl, cd, stride, fe, s) == 0, RBWS_ENUMERIC,
+                     "reduced matrix not positive definite in the greedy");
+        double* ux = (double*)tr.x.get(sizeof(double) * cnt * nd, dev);
+        rb_lift_exact(tr, bl, cd, stride, ux, fe, s);
+        resid_norms(tr, ux, delta.data() + t0, nullptr, nullptr, fe, s);
+      }
+      bs->hist.insert(bs->hist.end(), delta.begin(), delta.end());
+      for (double dlt : delta) RBWS_REQUIRE(std::isfinite(dlt), RBWS_ENUMERIC, "non-finite indicator");
+      if (nb == N) break;
+      int best = 0;
+      for (int t = 1; t < ntrain; t++)
+        if (delta[t] > delta[best]) best = t;
+      if (std::find(bs->selected.begin(), bs->selected.end(), best) != bs->selected.end()) break;
+      l = best;
+    }
+    RBWS_REQUIRE(nb >= 1, RBWS_ENUMERIC, "the first snapshot is zero");
+    const double* last = bs->hist.data() + (size_t)(nb - 1) * ntrain;
+    bs->final_max = *std::max_element(last, last + ntrain);
+  } catch (...) {
+    delete bs;
+    throw;
+  }
+  return bs;
+}
+
+// ---------------------------------------------------------------------------
+// save / load: a small binary file (little-endian host layout)
+// ---------------------------------------------------------------------------
+struct BasisHeader {
+  char magic[8];
+  int n, kind, nblocks, f_kind;
+  int Nmax, N, Q, ntrain;
+  long long ndof;
+  double final_max;
+  int blocks[6 * 32];
+};
+
+void basis_save(const Basis* b, const char* path) {
+  RBWS_REQUIRE(b && path, RBWS_EINVAL, "NULL argument");
+  BasisHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, "RBWSBAS1", 8);
+  const Problem* P = b->prob;
+  h.n = P->n;
+  h.kind = P->desc.kind;
+  h.nblocks = P->desc.nblocks;
+  h.f_kind = P->desc.f_kind;
+  h.Nmax = b->Nmax;
+  h.N = b->N;
+  h.Q = b->Q;
+  h.ntrain = b->ntrain;
+  h.ndof = b->ndof;
+  h.final_max = b->final_max;
+  for (size_t i = 0; i < P->blocks.size() && i < 6 * 32; i++) h.blocks[i] = P->blocks[i];
+  std::vector<double> V((size_t)b->N * b->ndof);
+  RBWS_HIP(hipSetDevice(P->device));
+  RBWS_HIP(hipMemcpy(V.data(), b->V.ptr, sizeof(double) * V.size(), hipMemcpyDeviceToHost));
+  FILE* fp = std::fopen(path, "wb");
+  RBWS_REQUIRE(fp != nullptr, RBWS_EINVAL, std::string("cannot open ") + path);
+  bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
+  ok = ok && std::fwrite(b->AqN.data(), sizeof(double), b->AqN.size(), fp) == b->AqN.size();
+  ok = ok && std::fwrite(b->fN.data(), sizeof(double), b->fN.size(), fp) == b->fN.size();
+  ok = ok && std::fwrite(b->selected.data(), sizeof(int), b->selected.size(), fp) == b->selected.size();
+  ok = ok && std::fwrite(b->hist.data(), sizeof(double), b->hist.size(), fp) == b->hist.size();
+  ok = ok && std::fwrite(V.data(), sizeof(double), V.size(), fp) == V.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  RBWS_REQUIRE(ok, RBWS_EINVAL, std::string("write failed: ") + path);
+}
+
+Basis* basis_load(const Problem* P, const char* path, hipStream_t s) {
+  RBWS_REQUIRE(P && path, RBWS_EINVAL, "NULL argument");
+  FILE* fp = std::fopen(path, "rb");
+  RBWS_REQUIRE(fp != nullptr, RBWS_EINVAL, std::string("cannot open ") + path);
+  BasisHeader h;
+  Basis* b = nullptr;
+  try {
+    RBWS_REQUIRE(std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "RBWSBAS1", 8) == 0,
+                 RBWS_EINVAL, "not a basis file");
+    RBWS_REQUIRE(h.n == P->n && h.kind == P->desc.kind && h.nblocks == P->desc.nblocks &&
+                     h.f_kind == P->desc.f_kind && h.Q == P->Q && h.ndof == P->ndof,
+                 RBWS_EINVAL, "basis file belongs to another problem");
+    for (size_t i = 0; i < P->blocks.size(); i++)
+      RBWS_REQUIRE(h.blocks[i] == P->blocks[i], RBWS_EINVAL, "basis file belongs to another problem");
+    RBWS_REQUIRE(h.N >= 1 && h.N <= h.Nmax && h.Nmax <= kMaxN && h.ntrain >= 1, RBWS_EINVAL, "corrupt basis file");
+    b = new Basis();
+    b->prob = P;
+    b->Nmax = h.Nmax;
+    b->N = h.N;
+    b->Q = h.Q;
+    b->ndof = h.ndof;
+    b->ntrain = h.ntrain;
+    b->final_max = h.final_max;
+    b->AqN.resize((size_t)h.Q * h.Nmax * h.Nmax);
+    b->fN.resize(h.Nmax);
+    b->selected.resize(h.N);
+    b->hist.resize((size_t)h.N * h.ntrain);
+    std::vector<double> V((size_t)h.N * h.ndof);
+    bool ok = std::fread(b->AqN.data(), sizeof(double), b->AqN.size(), fp) == b->AqN.size();
+    ok = ok && std::fread(b->fN.data(), sizeof(double), b->fN.size(), fp) == b->fN.size();
+    ok = ok && std::fread(b->selected.data(), sizeof(int), b->selected.size(), fp) == b->selected.size();
+    ok = ok && std::fread(b->hist.data(), sizeof(double), b->hist.size(), fp) == b->hist.size();
+    ok = ok && std::fread(V.data(), sizeof(double), V.size(), fp) == V.size();
+    RBWS_REQUIRE(ok, RBWS_EINVAL, "truncated basis file");
+    RBWS_HIP(hipSetDevice(P->device));
+    double* d = (double*)b->V.get(sizeof(double) * h.Nmax * h.ndof, P->device);
+    RBWS_HIP(hipMemcpy(d, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice));
+    b->upload(s);
+  } catch (...) {
+    std::fclose(fp);
+    delete b;
+    throw;
+  }
+  std::fclose(fp);
+  return b;
+}
+
+}  // namespace rbws

@@ -1,0 +1,51 @@
+// rb.hpp -- reduced basis on the device: greedy build, online solve, lift.
+#pragma once
+#include <vector>
+
+#include "solver.hpp"
+
+namespace rbws {
+
+struct Basis {
+  const Problem* prob = nullptr;
+  int Nmax = 0, N = 0, Q = 0;
+  long long ndof = 0;
+  DevBuf V;                  // Nmax x ndof, row j = basis vector j (orthonormal)
+  std::vector<double> AqN;   // Q x Nmax x Nmax: A_q^N = V^T A_q V
+  std::vector<double> fN;    // Nmax: V^T f (f = 1 only)
+  DevBuf AqN_d, fN_d;        // device copies
+  std::vector<int> selected;
+  std::vector<double> hist;  // N x ntrain indicators (row k: k+1 basis vectors)
+  int ntrain = 0;
+  double final_max = 0.0;    // max over the training set of the final indicator
+  void upload(hipStream_t s);
+};
+
+// per-solve view of a basis for the online kernels
+struct RbDev {
+  const double* AqN;
+  const double* fN;
+  const double* V;
+  int N, ld, Q, pad;
+};
+
+Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol,
+                int prec, int snap_maxit, int flags, hipStream_t s);
+
+// c (device, nsolve x cstride) for every solve of batch B from the bases of its
+// problems (bases[prob]); theta comes from the batch.  Returns the number of
+// solves whose reduced matrix was not positive definite.
+int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride, int force_exact,
+              hipStream_t s);
+
+// u_b = V c_b (correctly rounded per entry) into the batch layout `u`
+void rb_lift_exact(Batch& B, const std::vector<const Basis*>& bases, const double* c, int cstride,
+                   double* u, int force_exact, hipStream_t s);
+
+// u_b = V c_b with FP64 MFMA (single problem, all solves use bases[0])
+void rb_lift_mfma(Batch& B, const Basis* basis, const double* c, int cstride, double* u, hipStream_t s);
+
+void basis_save(const Basis* b, const char* path);
+Basis* basis_load(const Problem* P, const char* path, hipStream_t s);
+
+}  // namespace rbws

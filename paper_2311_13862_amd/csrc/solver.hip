@@ -24,8 +24,8 @@
 
 namespace rbws {
 
-enum { OP_PUP = 0, OP_AP = 1, OP_UP2 = 2 };
-enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3 };
+enum { OP_PUP = 0, OP_AP = 1, OP_UP2 = 2, OP_RNORM = 3 };
+enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3, DOT_RESID = 4 };
 constexpr int kSlots = 3;  // partial accumulators per work item
 
 void* DevBuf::get(size_t need, int dev) {
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
   bool run;
   if (OP == OP_PUP) run = mode == MODE_ITER;
   else if (OP == OP_AP) run = mode == MODE_ITER || mode == MODE_RESID;
+  else if (OP == OP_RNORM) run = true;
   else run = mode == MODE_ITER && st[b].skip2 == 0;
   if (!run) return;
   const SolveDev S = sd[b];
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
     double* X = x + S.off;
     double* R = r + S.off;
     double* Pv = p + S.off;
-    const double* V = (OP == OP_AP && mode == MODE_RESID) ? X : Pv;
+    const double* V = ((OP == OP_AP && mode == MODE_RESID) || OP == OP_RNORM) ? X : Pv;
     for (int k = kb; k <= ke; k++) {
       const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
       double kk[6];
@@ -225,7 +226,12 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
         Pv[c] = restart ? s : __fma_rn(beta, Pv[c], s);
       } else {
         const double q = stencil(kk, dg, V, c, n, i, j, k);
-        if (OP == OP_AP) {
+        if (OP == OP_RNORM) {
+          const double f = fval(P, S, i, j, k);
+          const double rv = f - q;
+          cr_add_prod(a0, rv, rv);
+          cr_add_prod(a2, f, f);
+        } else if (OP == OP_AP) {
           if (mode == MODE_ITER) {
             cr_add_prod(a0, V[c], q);
           } else {
@@ -251,11 +257,11 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
     CrAcc* out = part + (long long)blockIdx.x * kSlots;
     a0 = cr_block_reduce(a0, red);
     if (threadIdx.x == 0) out[0] = a0;
-    if (prec || (OP == OP_AP && mode == MODE_RESID)) {
+    if (OP != OP_RNORM && (prec || (OP == OP_AP && mode == MODE_RESID))) {
       a1 = cr_block_reduce(a1, red);
       if (threadIdx.x == 0) out[1] = a1;
     }
-    if (OP == OP_AP && mode == MODE_RESID && first) {
+    if ((OP == OP_AP && mode == MODE_RESID && first) || OP == OP_RNORM) {
       a2 = cr_block_reduce(a2, red);
       if (threadIdx.x == 0) out[2] = a2;
     }
@@ -294,6 +300,11 @@ __device__ double exact_solve_dot(FinShared& sh, int which, const ProbDev& P, co
       xa_add_prod(&sh.xa, Pv[c], stencil(kk, diag6(kk), Pv, c, n, i, j, k));
     } else if (which == DOT_RR) {
       xa_add_prod(&sh.xa, R[c], R[c]);
+    } else if (which == DOT_RESID) {
+      double kk[6];
+      point_kappa(g, kt, i, j, k, kk);
+      const double rv = fval(P, S, i, j, k) - stencil(kk, diag6(kk), X, c, n, i, j, k);
+      xa_add_prod(&sh.xa, rv, rv);
     } else if (which == DOT_RS) {
       double kk[6];
       point_kappa(g, kt, i, j, k, kk);
@@ -422,6 +433,24 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
   }
 }
 
+__global__ __launch_bounds__(256) void k_fin_rnorm(const SolveDev* __restrict__ sd,
+                                                   const ProbDev* __restrict__ pd,
+                                                   const double* __restrict__ kap, const double* x,
+                                                   const CrAcc* __restrict__ part, double* out,
+                                                   int force_exact) {
+  __shared__ FinShared sh;
+  const int b = blockIdx.x;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const double rr = solve_dot(sh, 0, DOT_RESID, P, S, kap, x, nullptr, nullptr, part, force_exact);
+  const double ff = solve_dot(sh, 2, DOT_FF, P, S, kap, x, nullptr, nullptr, part, force_exact);
+  if (threadIdx.x == 0) {
+    out[3 * b + 0] = sqrt(rr / ff);
+    out[3 * b + 1] = rr;
+    out[3 * b + 2] = ff;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // y = A x (FP64 or FP32) for every solve of the batch
 // ---------------------------------------------------------------------------
@@ -523,7 +552,7 @@ __global__ __launch_bounds__(256) void k_dot_fin(const double* __restrict__ x,
 // host side
 // ---------------------------------------------------------------------------
 void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
-                 const double* mu, int p, hipStream_t s) {
+                 const double* mu, int p, hipStream_t s, const double* theta_override) {
   RBWS_REQUIRE(!probs.empty(), RBWS_EINVAL, "no problem");
   B.device = probs[0]->device;
   RBWS_HIP(hipSetDevice(B.device));
@@ -566,15 +595,19 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
     S.item0 = (int)B.items_h.size();
     S.off = off;
     S.kap_off = koff;
-    const double* m = mu + (long long)b * p;
-    for (int t = 0; t < p; t++)
-      RBWS_REQUIRE(std::isfinite(m[t]), RBWS_EINVAL, "mu must be finite");
-    if (P->desc.f_kind == RBWS_F_GAUSS) {
-      S.x0[0] = m[24];
-      S.x0[1] = m[25];
-      S.x0[2] = m[26];
+    if (theta_override) {
+      for (int t = 0; t < P->Q; t++) theta[(size_t)b * kMaxQ + t] = theta_override[(size_t)b * P->Q + t];
+    } else {
+      const double* m = mu + (long long)b * p;
+      for (int t = 0; t < p; t++)
+        RBWS_REQUIRE(std::isfinite(m[t]), RBWS_EINVAL, "mu must be finite");
+      if (P->desc.f_kind == RBWS_F_GAUSS) {
+        S.x0[0] = m[24];
+        S.x0[1] = m[25];
+        S.x0[2] = m[26];
+      }
+      theta_host(*P, m, &theta[(size_t)b * kMaxQ]);
     }
-    theta_host(*P, m, &theta[(size_t)b * kMaxQ]);
     off += P->ndof;
     int tab = P->grid.ndir * P->grid.nclass;
     koff += tab;
@@ -658,6 +691,32 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
   }
 }
 
+void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff, int force_exact,
+                 hipStream_t s) {
+  RBWS_HIP(hipSetDevice(B.device));
+  const int ns = B.nsolve;
+  if (ns == 0) return;
+  CrAcc* part = (CrAcc*)B.part.get(sizeof(CrAcc) * kSlots * B.nitems, B.device);
+  // the sweep reads the solve mode from a state array; any mode runs OP_RNORM
+  CgState* st = (CgState*)B.state.get(sizeof(CgState) * ns, B.device);
+  RBWS_SCRATCH(outb);
+  double* o = (double*)outb.get(sizeof(double) * 3 * ns, B.device);
+  hipLaunchKernelGGL(k_sweep64<OP_RNORM>, dim3(B.nitems), dim3(256), sizeof(double) * B.kap_max, s,
+                     (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
+                     st, (const double*)B.kap64.ptr, (double*)x, nullptr, nullptr, part);
+  hipLaunchKernelGGL(k_fin_rnorm, dim3(ns), dim3(256), 0, s, (const SolveDev*)B.sd.ptr,
+                     (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr, x, part, o, force_exact);
+  RBWS_HIP(hipGetLastError());
+  std::vector<double> h(3 * (size_t)ns);
+  RBWS_HIP(hipMemcpyAsync(h.data(), o, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < ns; b++) {
+    if (rel) rel[b] = h[3 * b];
+    if (rr) rr[b] = h[3 * b + 1];
+    if (ff) ff[b] = h[3 * b + 2];
+  }
+}
+
 void states_to_host(Batch& B, std::vector<CgState>& out, hipStream_t s) {
   out.resize(B.nsolve);
   if (B.nsolve == 0) return;
@@ -685,7 +744,8 @@ void exact_dots(const double* x, const double* y, long long len, int count, doub
   if (count <= 0) return;
   int dev = 0;
   RBWS_HIP(hipGetDevice(&dev));
-  static thread_local DevBuf part, out;
+  RBWS_SCRATCH(part);
+  RBWS_SCRATCH(out);
   const int per_block = 4096;
   long long nb = std::max<long long>(1, (len + per_block - 1) / per_block);
   RBWS_REQUIRE(nb < (1LL << 31), RBWS_EINVAL, "vector too long");

@@ -34,6 +34,12 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
+// function-local scratch that lives until the process ends (never freed, so no
+// HIP call runs during static destruction)
+#define RBWS_SCRATCH(name) static thread_local DevBuf& name = *new DevBuf()
+
+void fill64(double* x, long long n, double v, hipStream_t s);
+
 struct Batch {
   int device = 0;
   int nsolve = 0, nprob = 0, nitems = 0;
@@ -57,8 +63,14 @@ struct Batch {
 void choose_tile(int n, int* TX, int* TY, int* TZ);
 
 // build the batch description: problems[prob_of[b]] for solve b; mu (nsolve x p) on host
+// theta_override (nsolve x Q of problem 0, host) replaces theta(mu) when given
 void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
-                 const double* mu, int p, hipStream_t s);
+                 const double* mu, int p, hipStream_t s, const double* theta_override = nullptr);
+
+// ||f - A x_b|| / ||f|| per solve for the x in `x` (laid out like the batch);
+// rr and ff (correctly rounded) are returned too.  Host outputs.
+void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff, int force_exact,
+                 hipStream_t s);
 
 // FP64 PCG (Alg. 1) over all solves of the batch from the x already in B.x.
 // Results: B.x (solutions), states in B.state.

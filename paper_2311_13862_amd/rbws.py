@@ -206,3 +206,64 @@ def solve(problems: Sequence[Problem], mu, opts: SolveOpts, problem_of=None, bas
     st = (SolveStat * max(nmu, 1))()
     _check(_L.rbws_solve(ph, bh, mh, nprob, po, _dp(mu), nmu, C.byref(opts), _stream(stream), uo, st))
     return stats_to_dicts(st, nmu)
+
+
+class Basis:
+    """Reduced basis handle (rbws_rb_build / rbws_basis_load)."""
+
+    def __init__(self, problem: Problem, handle, selected=None, hist=None):
+        self.problem = problem
+        self.handle = handle
+        N, q, nd, fm = C.c_int(), C.c_int(), C.c_longlong(), C.c_double()
+        _check(_L.rbws_basis_info(handle, C.byref(N), C.byref(q), C.byref(nd), C.byref(fm)))
+        self.N, self.Q, self.ndof, self.final_max = N.value, q.value, nd.value, fm.value
+        self.selected = selected
+        self.hist = hist
+
+    @classmethod
+    def build(cls, problem: Problem, mu_train, N: int, snap_tol: float, precond=PREC_JACOBI,
+              snap_maxit: int = 50000, stream=None) -> "Basis":
+        mu = _f64(mu_train).reshape(-1, problem.p)
+        nt = mu.shape[0]
+        h = C.c_void_p()
+        sel = np.full(N, -1, dtype=np.int32)
+        hist = np.full((N, nt), np.nan)
+        nre = C.c_int()
+        _check(_L.rbws_rb_build(problem.handle, _dp(mu), nt, N, snap_tol, precond, snap_maxit,
+                                _stream(stream), C.byref(h), sel.ctypes.data_as(C.POINTER(C.c_int)),
+                                _dp(hist), C.byref(nre)))
+        k = nre.value
+        return cls(problem, h, sel[:k].copy(), hist[:k].copy())
+
+    @classmethod
+    def load(cls, problem: Problem, path: str) -> "Basis":
+        h = C.c_void_p()
+        _check(_L.rbws_basis_load(problem.handle, path.encode(), C.byref(h)))
+        return cls(problem, h)
+
+    def save(self, path: str):
+        _check(_L.rbws_basis_save(self.handle, path.encode()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _L is not None:
+            _L.rbws_basis_destroy(h)
+            self.handle = None
+
+    def get(self):
+        V = np.empty((self.N, self.ndof))
+        A = np.empty((self.Q, self.N, self.N))
+        f = np.empty(self.N)
+        _check(_L.rbws_basis_get(self.handle, _dp(V), _dp(A), _dp(f)))
+        return V, A, f
+
+    def coeffs(self, mu, stream=None) -> np.ndarray:
+        mu = _f64(mu).reshape(-1, self.problem.p)
+        c = np.empty((mu.shape[0], self.N))
+        _check(_L.rbws_rb_coeffs(self.handle, _dp(mu), mu.shape[0], _dp(c), _stream(stream)))
+        return c
+
+    def lift(self, c, u, mode=LIFT_EXACT, stream=None):
+        """u[b] = V c[b]; c (nmu, N) and u (nmu, ndof) float64 device tensors."""
+        _check(_L.rbws_rb_lift(self.handle, C.c_void_p(c.data_ptr()), c.shape[0],
+                               C.c_void_p(u.data_ptr()), mode, _stream(stream)))
