@@ -327,19 +327,50 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   RBWS_SCRATCH(tbuf);
   unsigned long long* tdev = (unsigned long long*)tbuf.get(sizeof(unsigned long long), B.device);
   hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, tdev);
-  CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every};
-  cg_fp64_run(B, co, s);
+  std::vector<const double*> sol(nmu);
+  std::vector<IrHost> ir;
+  if (opts->precision == RBWS_FP64) {
+    CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every};
+    cg_fp64_run(B, co, s);
+    for (int b = 0; b < nmu; b++) sol[b] = x + B.sd_h[b].off;
+  } else {
+    RBWS_REQUIRE(opts->eta_inner > 0.0 && opts->eta_inner < 1.0, RBWS_EINVAL, "eta_inner must be in (0,1)");
+    RBWS_REQUIRE(opts->max_outer >= 1, RBWS_EINVAL, "max_outer < 1");
+    RBWS_REQUIRE(opts->max_iter >= 1, RBWS_EINVAL, "max_iter < 1 for refinement");
+    IrOpts io{opts->tol, opts->eta_inner, opts->precond, opts->max_iter, opts->max_outer, opts->flags,
+              opts->check_every};
+    ir_run(B, io, s, ir);
+    for (int b = 0; b < nmu; b++) sol[b] = (ir[b].cur ? (const double*)B.r.ptr : x) + B.sd_h[b].off;
+  }
   unsigned long long t0 = 0;
   RBWS_HIP(hipMemcpyAsync(&t0, tdev, sizeof t0, hipMemcpyDeviceToHost, s));
   RBWS_HIP(hipStreamSynchronize(s));
   if (u_out) {
     for (int b = 0; b < nmu; b++)
       if (u_out[b])
-        RBWS_HIP(hipMemcpyAsync(u_out[b], x + B.sd_h[b].off,
-                                sizeof(double) * B.probs[B.sd_h[b].prob]->ndof,
+        RBWS_HIP(hipMemcpyAsync(u_out[b], sol[b], sizeof(double) * B.probs[B.sd_h[b].prob]->ndof,
                                 hipMemcpyDeviceToDevice, s));
   }
-  if (stats) collect_stats(B, t0, opts->init, 0, stats, s);
+  if (stats) {
+    if (opts->precision == RBWS_FP64) {
+      collect_stats(B, t0, opts->init, 0, stats, s);
+    } else {
+      const double khz = wall_clock_khz(B.device);
+      for (int b = 0; b < nmu; b++) {
+        rbws_solve_stat& o = stats[b];
+        std::memset(&o, 0, sizeof o);
+        o.iters = ir[b].iters;
+        o.outer_iters = ir[b].outer;
+        o.extra_spmv = ir[b].outer;
+        o.status = ir[b].status;
+        o.init_used = opts->init;
+        o.init_rr = ir[b].init_rr;
+        o.final_rr = ir[b].rr;
+        o.ff = ir[b].ff;
+        o.t_done_ms = ir[b].t_done > t0 ? (double)(ir[b].t_done - t0) / khz : 0.0;
+      }
+    }
+  }
   RBWS_HIP(hipStreamSynchronize(s));
   API_END
 }

@@ -89,7 +89,13 @@ struct IrOpts {
   double tol, eta;
   int prec, inner_max, max_outer, flags, check_every;
 };
-void ir_run(Batch& B, const IrOpts& o, hipStream_t s);
+struct IrHost {
+  int iters, outer, status, cur;
+  double init_rr, rr, ff;
+  unsigned long long t_done;
+};
+// On return the solution of solve b is in (cur ? B.r : B.x) at its offset.
+void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out);
 
 // correctly rounded dots of `count` pairs of length len (device vectors)
 void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
