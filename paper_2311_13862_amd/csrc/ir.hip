@@ -20,16 +20,9 @@
 #include <cmath>
 #include <cstring>
 
-#include "stencil.hpp"
+#include "fast.hpp"
 
 namespace rbws {
-
-struct IrState {
-  double thr, ff, tol2, rr, init_rr, scale, upd, eta2;
-  double rho, alpha, beta, thr_in, bb;
-  int outer, mode, first, status, cur, k_in, k_total, restart, skip2, inner_max, max_outer, prec;
-  unsigned long long t_done;
-};
 
 struct IrPart {
   CrAcc rr, ff;
@@ -37,151 +30,150 @@ struct IrPart {
   double pad;
 };
 
-enum { IOP_PUP = 0, IOP_AP = 1, IOP_UP2 = 2 };
-
-template <int OP>
-__global__ __launch_bounds__(256) void k_ir_sweep(const int2* __restrict__ items, const SolveDev* __restrict__ sd,
-                                                  const ProbDev* __restrict__ pd, const IrState* __restrict__ st,
-                                                  const double* __restrict__ kap64, const float* __restrict__ kap32,
-                                                  double* __restrict__ u0, double* __restrict__ u1,
-                                                  float* __restrict__ d, float* __restrict__ r,
-                                                  float* __restrict__ p, IrPart* __restrict__ part, int ntab_max) {
+// Outer pass (FP64) of every solve whose mode is RESID: u_new = u + upd d,
+// r = f - A64 u_new, b = fl32(r * scale) into r32, and the norms.
+__global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items, int per, int nitems,
+                                                  const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                  const IrState* __restrict__ st, const double* __restrict__ kap64,
+                                                  const float* __restrict__ kap32, double* __restrict__ u0,
+                                                  double* __restrict__ u1, const float* __restrict__ d,
+                                                  float* __restrict__ r, IrPart* __restrict__ part, int ktab) {
   extern __shared__ double lds[];
   __shared__ double redd[4][3];
   __shared__ CrAcc redc[4];
-  const int2 it = items[blockIdx.x];
-  const int b = it.x, tile = it.y;
-  const int mode = st[b].mode;
-  bool run;
-  if (OP == IOP_PUP) run = mode == MODE_ITER;
-  else if (OP == IOP_AP) run = mode == MODE_ITER || mode == MODE_RESID;
-  else run = mode == MODE_ITER && st[b].skip2 == 0;
-  if (!run) return;
-  const bool outer = (OP == IOP_AP && mode == MODE_RESID);
+  const int item = item_of(blockIdx.x, per);
+  if (item >= nitems) return;
+  const int2 it = items[item];
+  const int b = it.x;
+  if (st[b].mode != MODE_RESID) return;
   const SolveDev S = sd[b];
   const ProbDev& P = pd[S.prob];
   const GridDev& g = P.g;
   const int ntab = g.ndir * g.nclass;
   double* k64 = lds;
-  float* k32 = reinterpret_cast<float*>(lds + ntab_max);
+  float* k32 = reinterpret_cast<float*>(lds + ktab);
   for (int e = threadIdx.x; e < ntab; e += blockDim.x) {
     k32[e] = kap32[S.kap_off + e];
-    if (outer) k64[e] = kap64[S.kap_off + e];
+    k64[e] = kap64[S.kap_off + e];
   }
   __syncthreads();
+  QuadGeo G;
+  quad_geo(G, P, it.y);
   const int n = g.n;
   const long long n2 = (long long)n * n;
-  const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
-  const int i = tx * P.TX + (int)threadIdx.x % P.TX + 1, j = ty * P.TY + (int)threadIdx.x / P.TX + 1;
-  const bool act = i <= n && j <= n;
-  const int kb = tz * P.TZ + 1, ke = min(n, (tz + 1) * P.TZ);
-  const int N1 = g.ncode[1], N2 = g.ncode[2];
-  const int oY = g.ndir == 3 ? g.nclass : 0, oZ = g.ndir == 3 ? 2 * g.nclass : 0;
   const IrState& s = st[b];
-  const int prec = s.prec;
-  const float alpha = (float)s.alpha, beta = (float)s.beta;
-  const int restart = s.restart, first_inner = s.k_in == 0, first = s.first;
+  const int prec = s.prec, first = s.first;
   const double upd = s.upd, scale = s.scale;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  double g0 = 0.0, g1 = 0.0;
   CrAcc arr = cr_zero(), aff = cr_zero();
-  if (act) {
-    const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
-    const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
-    const int bXm = (cxm * N1 + cyn) * N2, bXp = (cxp * N1 + cyn) * N2;
-    const int bYm = oY + (cxn * N1 + cym) * N2, bYp = oY + (cxn * N1 + cyp) * N2;
-    const int bZ = oZ + (cxn * N1 + cyn) * N2;
-    float* D = d + S.off;
-    float* R = r + S.off;
-    float* Pv = p + S.off;
-    const double* Us = (s.cur ? u1 : u0) + S.off;
-    double* Ud = (s.cur ? u0 : u1) + S.off;
-    for (int k = kb; k <= ke; k++) {
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
-      const int ix[6] = {bXm + czn, bXp + czn, bYm + czn, bYp + czn, bZ + czm, bZ + czp};
+  const float* D = d + S.off;
+  float* R = r + S.off;
+  const double* Us = (s.cur ? u1 : u0) + S.off;
+  double* Ud = (s.cur ? u0 : u1) + S.off;
+  auto un = [&](long long e) { return upd != 0.0 ? __fma_rn(upd, (double)D[e], Us[e]) : Us[e]; };
+  for (int k = G.kb; k <= G.ke; k++) {
+    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (e >= G.nv) continue;
+      const int i = G.i + e, j = G.j;
       const long long c = vidx(n, i, j, k);
+      double kd[6];
       float kk[6];
-#pragma unroll
-      for (int t = 0; t < 6; t++) kk[t] = k32[ix[t]];
-      const float dg = ((((kk[0] + kk[1]) + kk[2]) + kk[3]) + kk[4]) + kk[5];
-      if (OP == IOP_PUP) {
-        const float rv = R[c];
-        const float sv = prec ? rv / dg : rv;
-        Pv[c] = restart ? sv : fmaf(beta, Pv[c], sv);
-      } else if (outer) {
-        // u_new = u + upd d at the point and its neighbours, then r = f - A64 u_new
-        double kd[6];
-#pragma unroll
-        for (int t = 0; t < 6; t++) kd[t] = k64[ix[t]];
-        const double dgd = diag6(kd);
-        auto un = [&](long long e) { return upd != 0.0 ? __fma_rn(upd, (double)D[e], Us[e]) : Us[e]; };
-        const double uc = un(c);
-        double acc = dgd * uc;
-        if (i > 1) acc = __fma_rn(-kd[0], un(c - 1), acc);
-        if (i < n) acc = __fma_rn(-kd[1], un(c + 1), acc);
-        if (j > 1) acc = __fma_rn(-kd[2], un(c - n), acc);
-        if (j < n) acc = __fma_rn(-kd[3], un(c + n), acc);
-        if (k > 1) acc = __fma_rn(-kd[4], un(c - n2), acc);
-        if (k < n) acc = __fma_rn(-kd[5], un(c + n2), acc);
-        if (upd != 0.0) Ud[c] = uc;
-        const double f = fval(P, S, i, j, k);
-        const double rv = f - acc;
-        const float r32 = (float)(rv * scale);
-        R[c] = r32;
-        cr_add_prod(arr, rv, rv);
-        if (first) cr_add_prod(aff, f, f);
-        g0 = __fma_rn((double)r32, (double)r32, g0);
-        if (prec) g1 = __fma_rn((double)r32, (double)(r32 / dg), g1);
-      } else {
-        float q = dg * Pv[c];
-        if (i > 1) q = fmaf(-kk[0], Pv[c - 1], q);
-        if (i < n) q = fmaf(-kk[1], Pv[c + 1], q);
-        if (j > 1) q = fmaf(-kk[2], Pv[c - n], q);
-        if (j < n) q = fmaf(-kk[3], Pv[c + n], q);
-        if (k > 1) q = fmaf(-kk[4], Pv[c - n2], q);
-        if (k < n) q = fmaf(-kk[5], Pv[c + n2], q);
-        if (OP == IOP_AP) {
-          g0 = __fma_rn((double)Pv[c], (double)q, g0);
-        } else {
-          const float pv = Pv[c];
-          D[c] = first_inner ? alpha * pv : fmaf(alpha, pv, D[c]);
-          const float rv = fmaf(-alpha, q, R[c]);
-          R[c] = rv;
-          g0 = __fma_rn((double)rv, (double)rv, g0);
-          if (prec) g1 = __fma_rn((double)rv, (double)(rv / dg), g1);
-        }
-      }
+      quad_kappa<double>(G, k64, e, czn, czm, czp, kd);
+      quad_kappa<float>(G, k32, e, czn, czm, czp, kk);
+      const float dg = diag6T<float>(kk);
+      const double uc = un(c);
+      double acc = diag6(kd) * uc;
+      if (i > 1) acc = __fma_rn(-kd[0], un(c - 1), acc);
+      if (i < n) acc = __fma_rn(-kd[1], un(c + 1), acc);
+      if (j > 1) acc = __fma_rn(-kd[2], un(c - n), acc);
+      if (j < n) acc = __fma_rn(-kd[3], un(c + n), acc);
+      if (k > 1) acc = __fma_rn(-kd[4], un(c - n2), acc);
+      if (k < n) acc = __fma_rn(-kd[5], un(c + n2), acc);
+      if (upd != 0.0) Ud[c] = uc;
+      const double f = fval(P, S, i, j, k);
+      const double rv = f - acc;
+      const float r32 = (float)(rv * scale);
+      R[c] = r32;
+      cr_add_prod(arr, rv, rv);
+      if (first) cr_add_prod(aff, f, f);
+      g0 = __fma_rn((double)r32, (double)r32, g0);
+      if (prec) g1 = __fma_rn((double)r32, (double)(r32 / dg), g1);
     }
   }
-  if (OP == IOP_PUP) return;
-  // block reduction of the plain FP64 sums (and the exact-path accumulators)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     g0 += __shfl_xor(g0, m, 64);
     g1 += __shfl_xor(g1, m, 64);
-    g2 += __shfl_xor(g2, m, 64);
   }
   if (lane == 0) {
     redd[w][0] = g0;
     redd[w][1] = g1;
-    redd[w][2] = g2;
   }
-  IrPart* out = part + blockIdx.x;
-  if (outer) {
-    CrAcc a = cr_block_reduce(arr, redc);
-    if (threadIdx.x == 0) out->rr = a;
-    if (first) {
-      a = cr_block_reduce(aff, redc);
-      if (threadIdx.x == 0) out->ff = a;
-    }
+  IrPart* out = part + item;
+  CrAcc a = cr_block_reduce(arr, redc);
+  if (threadIdx.x == 0) out->rr = a;
+  if (first) {
+    a = cr_block_reduce(aff, redc);
+    if (threadIdx.x == 0) out->ff = a;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int t = 0; t < 3; t++) {
-      double v = 0.0;
-      for (int q = 0; q < (int)(blockDim.x >> 6); q++) v += redd[q][t];
-      out->g[t] = v;
-    }
+    out->g[0] = redd[0][0] + redd[1][0] + redd[2][0] + redd[3][0];
+    out->g[1] = redd[0][1] + redd[1][1] + redd[2][1] + redd[3][1];
+  }
+}
+
+// inner FP32 iteration sweeps (fast.hpp); p alternates by the parity of k_total
+template <bool VEC, int OP>
+__global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, int per, int nitems,
+                                                const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                const IrState* __restrict__ st, const float* __restrict__ kap,
+                                                float* __restrict__ d, float* __restrict__ r, float* __restrict__ p0,
+                                                float* __restrict__ p1, IrPart* __restrict__ part, int ktab) {
+  extern __shared__ double smem_raw[];
+  float* smem = reinterpret_cast<float*>(smem_raw);
+  __shared__ double red[4][2];
+  const int item = item_of(blockIdx.x, per);
+  if (item >= nitems) return;
+  const int2 it = items[item];
+  const int b = it.x;
+  const IrState& s = st[b];
+  if (s.mode != MODE_ITER) return;
+  if (OP == FOP_UP2 && s.skip2) return;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const int ntab = P.g.ndir * P.g.nclass;
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
+  __syncthreads();
+  QuadGeo G;
+  quad_geo(G, P, it.y);
+  const int par = s.k_total & 1;
+  const float* Pold = (par ? p1 : p0) + S.off;
+  float* Pn = (par ? p0 : p1) + S.off;
+  DotAcc<float> a0, a1;
+  a0.zero();
+  a1.zero();
+  fast_body<float, VEC, OP>(G, P.g, smem, smem + ktab, r + S.off, r + S.off, Pold, Pn, d + S.off,
+                            (float)s.alpha, (float)s.beta, s.restart, s.prec, s.k_in == 0, a0, a1);
+  double g0 = a0.a, g1 = a1.a;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    g0 += __shfl_xor(g0, m, 64);
+    g1 += __shfl_xor(g1, m, 64);
+  }
+  if (lane == 0) {
+    red[w][0] = g0;
+    red[w][1] = g1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    IrPart* out = part + item;
+    out->g[0] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    out->g[1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
   }
 }
 
@@ -357,22 +349,27 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   float* d = (float*)B.d32.get(sizeof(float) * B.total, B.device);
   float* r = (float*)B.r32.get(sizeof(float) * B.total, B.device);
   float* p = (float*)B.p32.get(sizeof(float) * B.total, B.device);
+  float* p1 = (float*)B.p32b.get(sizeof(float) * B.total, B.device);
   const int2* items = (const int2*)B.items.ptr;
   const SolveDev* sd = (const SolveDev*)B.sd.ptr;
   const ProbDev* pd = (const ProbDev*)B.pd.ptr;
   const double* k64 = (const double*)B.kap64.ptr;
   const float* k32 = (const float*)B.kap32.ptr;
-  const size_t lds = (sizeof(double) + sizeof(float)) * B.kap_max;
+  const int ktab = (B.kap_max + 3) & ~3;
+  const size_t lds_outer = (sizeof(double) + sizeof(float)) * ktab;
+  const size_t lds_fast = sizeof(float) * (ktab + 2 * QPLANE);
+  const int per = B.per, ni = B.nitems;
+  const unsigned grid = grid_of(B);
+  auto ap = B.vec ? k_fast32<true, FOP_AP> : k_fast32<false, FOP_AP>;
+  auto up = B.vec ? k_fast32<true, FOP_UP2> : k_fast32<false, FOP_UP2>;
   const int check = o.check_every > 0 ? o.check_every : 8;
   const long long max_rounds = (long long)(o.inner_max + 2) * (o.max_outer + 1) + 16;
   for (long long round = 0; round < max_rounds; round++) {
-    hipLaunchKernelGGL(k_ir_sweep<IOP_PUP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, k64, k32,
-                       u0, u1, d, r, p, part, B.kap_max);
-    hipLaunchKernelGGL(k_ir_sweep<IOP_AP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, k64, k32,
-                       u0, u1, d, r, p, part, B.kap_max);
+    hipLaunchKernelGGL(ap, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, k32, d, r, p, p1, part, ktab);
+    hipLaunchKernelGGL(k_ir_outer, dim3(grid), dim3(256), lds_outer, s, items, per, ni, sd, pd, st, k64, k32, u0,
+                       u1, d, r, part, ktab);
     hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, active);
-    hipLaunchKernelGGL(k_ir_sweep<IOP_UP2>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, k64, k32,
-                       u0, u1, d, r, p, part, B.kap_max);
+    hipLaunchKernelGGL(up, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, k32, d, r, p, p1, part, ktab);
     hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part);
     RBWS_HIP(hipGetLastError());
     if ((round + 1) % check == 0) {

@@ -20,7 +20,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "stencil.hpp"
+#include "fast.hpp"
 
 namespace rbws {
 
@@ -57,16 +57,13 @@ Batch::~Batch() {
   if (active_host) (void)hipHostFree(active_host);
 }
 
-void choose_tile(int n, int* TX, int* TY, int* TZ) {
-  int tx;
-  if (n % 64 == 0) tx = 64;
-  else if (n % 32 == 0) tx = 32;
-  else if (n >= 64) tx = 64;
-  else if (n >= 32) tx = 32;
-  else tx = 16;
-  *TX = tx;
-  *TY = 256 / tx;
-  *TZ = std::min(n, 16);
+void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ) {
+  *TX = QX;
+  *TY = QY;
+  const long long cols = (long long)((n + QX - 1) / QX) * ((n + QY - 1) / QY) * std::max(1LL, nsolve_of_this_size);
+  int tz = 64;
+  while (tz > 4 && cols * ((n + tz - 1) / tz) < 4096) tz /= 2;
+  *TZ = std::min(tz, n);
 }
 
 double wall_clock_khz(int device) {
@@ -107,115 +104,115 @@ __global__ void k_kappa(const SolveDev* __restrict__ sd, const ProbDev* __restri
 }
 
 // ---------------------------------------------------------------------------
-// sweeps over (solve, tile) work items
+// residual evaluations over (solve, tile) work items: RESID r = f - A x (with
+// ||r||^2, r.P(r), ||f||^2 on the first pass), RNORM the same norms only.
+// These run a few times per solve; they read neighbours through the caches.
 // ---------------------------------------------------------------------------
 template <int OP>
-__global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
+__global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items, int per, int nitems,
                                                  const SolveDev* __restrict__ sd,
                                                  const ProbDev* __restrict__ pd,
                                                  const CgState* __restrict__ st,
                                                  const double* __restrict__ kap,
                                                  double* __restrict__ x, double* __restrict__ r,
-                                                 double* __restrict__ p, CrAcc* __restrict__ part) {
+                                                 CrAcc* __restrict__ part) {
   extern __shared__ double kl[];
   __shared__ CrAcc red[4];
-  const int2 it = items[blockIdx.x];
+  const int item = item_of(blockIdx.x, per);
+  if (item >= nitems) return;
+  const int2 it = items[item];
   const int b = it.x, tile = it.y;
-  const int mode = st[b].mode;
-  bool run;
-  if (OP == OP_PUP) run = mode == MODE_ITER;
-  else if (OP == OP_AP) run = mode == MODE_ITER || mode == MODE_RESID;
-  else if (OP == OP_RNORM) run = true;
-  else run = mode == MODE_ITER && st[b].skip2 == 0;
-  if (!run) return;
+  if (OP == OP_AP && st[b].mode != MODE_RESID) return;
   const SolveDev S = sd[b];
   const ProbDev& P = pd[S.prob];
   const GridDev& g = P.g;
   const int ntab = g.ndir * g.nclass;
   for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
   __syncthreads();
-
+  const int prec = OP == OP_AP ? st[b].prec : 0, first = OP == OP_AP ? st[b].first : 1;
+  QuadGeo G;
+  quad_geo(G, P, tile);
   const int n = g.n;
-  const long long n2 = (long long)n * n;
-  const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
-  const int lx = threadIdx.x % P.TX, ly = threadIdx.x / P.TX;
-  const int i = tx * P.TX + lx + 1, j = ty * P.TY + ly + 1;
-  const bool act = i <= n && j <= n;
-  const int kb = tz * P.TZ + 1, ke = min(n, (tz + 1) * P.TZ);
-  const int N1 = g.ncode[1], N2 = g.ncode[2];
-  const double* kX = kl;
-  const double* kY = kl + (g.ndir == 3 ? g.nclass : 0);
-  const double* kZ = kl + (g.ndir == 3 ? 2 * g.nclass : 0);
-  const double alpha = st[b].alpha, beta = st[b].beta;
-  const int prec = st[b].prec, restart = st[b].restart, first = st[b].first;
-
   CrAcc a0 = cr_zero(), a1 = cr_zero(), a2 = cr_zero();
-  if (act) {
-    const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
-    const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
-    const int bXm = (cxm * N1 + cyn) * N2, bXp = (cxp * N1 + cyn) * N2;
-    const int bYm = (cxn * N1 + cym) * N2, bYp = (cxn * N1 + cyp) * N2;
-    const int bZ = (cxn * N1 + cyn) * N2;
-    double* X = x + S.off;
-    double* R = r + S.off;
-    double* Pv = p + S.off;
-    const double* V = ((OP == OP_AP && mode == MODE_RESID) || OP == OP_RNORM) ? X : Pv;
-    for (int k = kb; k <= ke; k++) {
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+  double* X = x + S.off;
+  double* R = r + S.off;
+  for (int k = G.kb; k <= G.ke; k++) {
+    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (e >= G.nv) continue;
+      const int i = G.i + e, j = G.j;
       double kk[6];
-      kk[0] = kX[bXm + czn];
-      kk[1] = kX[bXp + czn];
-      kk[2] = kY[bYm + czn];
-      kk[3] = kY[bYp + czn];
-      kk[4] = kZ[bZ + czm];
-      kk[5] = kZ[bZ + czp];
+      quad_kappa<double>(G, kl, e, czn, czm, czp, kk);
       const double dg = diag6(kk);
       const long long c = vidx(n, i, j, k);
-      if (OP == OP_PUP) {
-        const double rv = R[c];
-        const double s = prec ? rv / dg : rv;
-        Pv[c] = restart ? s : __fma_rn(beta, Pv[c], s);
-      } else {
-        const double q = stencil(kk, dg, V, c, n, i, j, k);
-        if (OP == OP_RNORM) {
-          const double f = fval(P, S, i, j, k);
-          const double rv = f - q;
-          cr_add_prod(a0, rv, rv);
-          cr_add_prod(a2, f, f);
-        } else if (OP == OP_AP) {
-          if (mode == MODE_ITER) {
-            cr_add_prod(a0, V[c], q);
-          } else {
-            const double f = fval(P, S, i, j, k);
-            const double rv = f - q;
-            R[c] = rv;
-            cr_add_prod(a0, rv, rv);
-            if (prec) cr_add_prod(a1, rv, rv / dg);
-            if (first) cr_add_prod(a2, f, f);
-          }
-        } else {
-          X[c] = __fma_rn(alpha, V[c], X[c]);
-          const double rv = __fma_rn(-alpha, q, R[c]);
-          R[c] = rv;
-          cr_add_prod(a0, rv, rv);
-          if (prec) cr_add_prod(a1, rv, rv / dg);
-        }
+      const double q = stencil(kk, dg, X, c, n, i, j, k);
+      const double f = fval(P, S, i, j, k);
+      const double rv = f - q;
+      cr_add_prod(a0, rv, rv);
+      if (first) cr_add_prod(a2, f, f);
+      if (OP == OP_AP) {
+        R[c] = rv;
+        if (prec) cr_add_prod(a1, rv, rv / dg);
       }
     }
-    (void)n2;
   }
-  if (OP != OP_PUP) {
-    CrAcc* out = part + (long long)blockIdx.x * kSlots;
-    a0 = cr_block_reduce(a0, red);
-    if (threadIdx.x == 0) out[0] = a0;
-    if (OP != OP_RNORM && (prec || (OP == OP_AP && mode == MODE_RESID))) {
-      a1 = cr_block_reduce(a1, red);
-      if (threadIdx.x == 0) out[1] = a1;
-    }
-    if ((OP == OP_AP && mode == MODE_RESID && first) || OP == OP_RNORM) {
-      a2 = cr_block_reduce(a2, red);
-      if (threadIdx.x == 0) out[2] = a2;
-    }
+  CrAcc* out = part + (long long)item * kSlots;
+  a0 = cr_block_reduce(a0, red);
+  if (threadIdx.x == 0) out[0] = a0;
+  if (OP == OP_AP && prec) {
+    a1 = cr_block_reduce(a1, red);
+    if (threadIdx.x == 0) out[1] = a1;
+  }
+  if (first) {
+    a2 = cr_block_reduce(a2, red);
+    if (threadIdx.x == 0) out[2] = a2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the iteration sweeps of the FP64 path (fast.hpp)
+// ---------------------------------------------------------------------------
+template <bool VEC, int OP>
+__global__ __launch_bounds__(256) void k_fast64(const int2* __restrict__ items, int per, int nitems,
+                                                const SolveDev* __restrict__ sd,
+                                                const ProbDev* __restrict__ pd,
+                                                const CgState* __restrict__ st,
+                                                const double* __restrict__ kap, double* __restrict__ x,
+                                                double* __restrict__ r, double* __restrict__ p0,
+                                                double* __restrict__ p1, CrAcc* __restrict__ part,
+                                                int ktab) {
+  extern __shared__ double smem[];
+  __shared__ CrAcc red[4];
+  const int item = item_of(blockIdx.x, per);
+  if (item >= nitems) return;
+  const int2 it = items[item];
+  const int b = it.x;
+  const CgState& s = st[b];
+  if (s.mode != MODE_ITER) return;
+  if (OP == FOP_UP2 && s.skip2) return;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const int ntab = P.g.ndir * P.g.nclass;
+  double* kt = smem;
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+  __syncthreads();
+  QuadGeo G;
+  quad_geo(G, P, it.y);
+  const int par = s.k & 1;
+  const double* Pold = (par ? p1 : p0) + S.off;
+  double* Pn = (par ? p0 : p1) + S.off;
+  DotAcc<double> a0, a1;
+  a0.zero();
+  a1.zero();
+  fast_body<double, VEC, OP>(G, P.g, kt, smem + ktab, r + S.off, r + S.off, Pold, Pn, x + S.off, s.alpha,
+                             s.beta, s.restart, s.prec, 0, a0, a1);
+  CrAcc* out = part + (long long)item * kSlots;
+  CrAcc t = cr_block_reduce(a0.a, red);
+  if (threadIdx.x == 0) out[0] = t;
+  if (OP == FOP_UP2 && s.prec) {
+    t = cr_block_reduce(a1.a, red);
+    if (threadIdx.x == 0) out[1] = t;
   }
 }
 
@@ -302,7 +299,7 @@ __device__ __forceinline__ void mark_done(CgState& s, int status, int* active) {
 __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
                                               const ProbDev* __restrict__ pd, CgState* st,
                                               const double* __restrict__ kap, const double* x,
-                                              const double* r, const double* p,
+                                              const double* r, const double* p, const double* p1,
                                               const CrAcc* __restrict__ part, int* active,
                                               int force_exact) {
   __shared__ FinShared sh;
@@ -313,7 +310,8 @@ __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
   const ProbDev& P = pd[S.prob];
   CgState s = st[b];
   if (mode == MODE_ITER) {
-    const double g = solve_dot(sh, 0, DOT_PAP, P, S, kap, x, r, p, part, force_exact);
+    const double* pn = (s.k & 1) ? p : p1;  // the buffer this iteration's AP wrote
+    const double g = solve_dot(sh, 0, DOT_PAP, P, S, kap, x, r, pn, part, force_exact);
     if (threadIdx.x == 0) {
       if (!__builtin_isfinite(g)) mark_done(s, RBWS_SOLVE_NAN, active);
       else if (!(g > 0.0)) mark_done(s, RBWS_SOLVE_BREAKDOWN, active);
@@ -405,51 +403,27 @@ __global__ __launch_bounds__(256) void k_fin_rnorm(const SolveDev* __restrict__ 
 // ---------------------------------------------------------------------------
 // y = A x (FP64 or FP32) for every solve of the batch
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items,
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items, int per, int nitems,
                                               const SolveDev* __restrict__ sd,
                                               const ProbDev* __restrict__ pd,
                                               const T* __restrict__ kap, const T* __restrict__ x,
-                                              T* __restrict__ y) {
-  extern __shared__ double kl_raw[];
-  T* kl = reinterpret_cast<T*>(kl_raw);
-  const int2 it = items[blockIdx.x];
+                                              T* __restrict__ y, int ktab) {
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int item = item_of(blockIdx.x, per);
+  if (item >= nitems) return;
+  const int2 it = items[item];
   const SolveDev S = sd[it.x];
   const ProbDev& P = pd[S.prob];
-  const GridDev& g = P.g;
-  const int ntab = g.ndir * g.nclass;
-  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
+  const int ntab = P.g.ndir * P.g.nclass;
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
   __syncthreads();
-  const int n = g.n, tile = it.y;
-  const long long n2 = (long long)n * n;
-  const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
-  const int i = tx * P.TX + (int)threadIdx.x % P.TX + 1, j = ty * P.TY + (int)threadIdx.x / P.TX + 1;
-  if (i > n || j > n) return;
-  const int kb = tz * P.TZ + 1, ke = min(n, (tz + 1) * P.TZ);
-  const int N1 = g.ncode[1], N2 = g.ncode[2];
-  const T* kX = kl;
-  const T* kY = kl + (g.ndir == 3 ? g.nclass : 0);
-  const T* kZ = kl + (g.ndir == 3 ? 2 * g.nclass : 0);
-  const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
-  const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
-  const T* X = x + S.off;
-  T* Y = y + S.off;
-  for (int k = kb; k <= ke; k++) {
-    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
-    const T k0 = kX[(cxm * N1 + cyn) * N2 + czn], k1 = kX[(cxp * N1 + cyn) * N2 + czn];
-    const T k2 = kY[(cxn * N1 + cym) * N2 + czn], k3 = kY[(cxn * N1 + cyp) * N2 + czn];
-    const T k4 = kZ[(cxn * N1 + cyn) * N2 + czm], k5 = kZ[(cxn * N1 + cyn) * N2 + czp];
-    const T dg = ((((k0 + k1) + k2) + k3) + k4) + k5;
-    const long long c = vidx(n, i, j, k);
-    T acc = dg * X[c];
-    if (i > 1) acc = fma(-k0, X[c - 1], acc);
-    if (i < n) acc = fma(-k1, X[c + 1], acc);
-    if (j > 1) acc = fma(-k2, X[c - n], acc);
-    if (j < n) acc = fma(-k3, X[c + n], acc);
-    if (k > 1) acc = fma(-k4, X[c - n2], acc);
-    if (k < n) acc = fma(-k5, X[c + n2], acc);
-    Y[c] = acc;
-  }
+  QuadGeo G;
+  quad_geo(G, P, it.y);
+  DotAcc<T> a0, a1;
+  fast_body<T, VEC, FOP_SPMV>(G, P.g, smem, smem + ktab, nullptr, nullptr, nullptr,
+                              const_cast<T*>(x) + S.off, y + S.off, T(0), T(0), 0, 0, 0, a0, a1);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +492,9 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
     RBWS_REQUIRE(P->p == p, RBWS_EINVAL, "problems of one batch must share p");
     ProbDev& d = B.pd_h[q];
     d.g = P->grid;
-    choose_tile(P->n, &d.TX, &d.TY, &d.TZ);
+    long long cnt = 0;
+    for (int b = 0; b < nsolve; b++) cnt += (prob_of ? prob_of[b] : 0) == q;
+    choose_tile(P->n, cnt, &d.TX, &d.TY, &d.TZ);
     d.ntx = (P->n + d.TX - 1) / d.TX;
     d.nty = (P->n + d.TY - 1) / d.TY;
     d.ntz = (P->n + d.TZ - 1) / d.TZ;
@@ -568,6 +544,9 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
   B.total = off;
   B.kap_total = koff;
   B.nitems = (int)B.items_h.size();
+  B.per = (B.nitems + 7) / 8;
+  B.vec = true;
+  for (const Problem* P : probs) B.vec = B.vec && (P->n % 4 == 0);
   RBWS_HIP(hipMemcpyAsync(B.pd.get(sizeof(ProbDev) * B.nprob, B.device), B.pd_h.data(),
                           sizeof(ProbDev) * B.nprob, hipMemcpyHostToDevice, s));
   if (nsolve > 0) {
@@ -627,11 +606,18 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
   const int fe = (o.flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
   const int check = o.check_every > 0 ? o.check_every : 4;
   const long long max_rounds = 2LL * o.maxit + 16;
+  double* p1 = (double*)B.p2.get(sizeof(double) * B.total, B.device);
+  const int per = B.per, ni = B.nitems;
+  const unsigned grid = grid_of(B);
+  const int ktab = (B.kap_max + 3) & ~3;
+  const size_t lds_fast = sizeof(double) * (ktab + 2 * QPLANE);
+  auto ap = B.vec ? k_fast64<true, FOP_AP> : k_fast64<false, FOP_AP>;
+  auto up = B.vec ? k_fast64<true, FOP_UP2> : k_fast64<false, FOP_UP2>;
   for (long long round = 0; round < max_rounds; round++) {
-    hipLaunchKernelGGL(k_sweep64<OP_PUP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
-    hipLaunchKernelGGL(k_sweep64<OP_AP>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
-    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe);
-    hipLaunchKernelGGL(k_sweep64<OP_UP2>, dim3(B.nitems), dim3(256), lds, s, items, sd, pd, st, kap, x, r, p, part);
+    hipLaunchKernelGGL(ap, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, kap, x, r, p, p1, part, ktab);
+    hipLaunchKernelGGL(k_sweep64<OP_AP>, dim3(grid), dim3(256), lds, s, items, per, ni, sd, pd, st, kap, x, r, part);
+    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, p1, part, active, fe);
+    hipLaunchKernelGGL(up, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, kap, x, r, p, p1, part, ktab);
     hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe);
     RBWS_HIP(hipGetLastError());
     if ((round + 1) % check == 0) {
@@ -652,9 +638,9 @@ void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff,
   CgState* st = (CgState*)B.state.get(sizeof(CgState) * ns, B.device);
   RBWS_SCRATCH(outb);
   double* o = (double*)outb.get(sizeof(double) * 3 * ns, B.device);
-  hipLaunchKernelGGL(k_sweep64<OP_RNORM>, dim3(B.nitems), dim3(256), sizeof(double) * B.kap_max, s,
-                     (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
-                     st, (const double*)B.kap64.ptr, (double*)x, nullptr, nullptr, part);
+  hipLaunchKernelGGL(k_sweep64<OP_RNORM>, dim3(grid_of(B)), dim3(256), sizeof(double) * B.kap_max, s,
+                     (const int2*)B.items.ptr, B.per, B.nitems, (const SolveDev*)B.sd.ptr,
+                     (const ProbDev*)B.pd.ptr, st, (const double*)B.kap64.ptr, (double*)x, nullptr, part);
   hipLaunchKernelGGL(k_fin_rnorm, dim3(ns), dim3(256), 0, s, (const SolveDev*)B.sd.ptr,
                      (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr, x, part, o, force_exact);
   RBWS_HIP(hipGetLastError());
@@ -678,14 +664,18 @@ void states_to_host(Batch& B, std::vector<CgState>& out, hipStream_t s) {
 void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s) {
   RBWS_HIP(hipSetDevice(B.device));
   if (B.nsolve == 0) return;
+  const int ktab = (B.kap_max + 3) & ~3;
+  const int2* it = (const int2*)B.items.ptr;
+  const SolveDev* sd = (const SolveDev*)B.sd.ptr;
+  const ProbDev* pd = (const ProbDev*)B.pd.ptr;
   if (fp32) {
-    hipLaunchKernelGGL(k_spmv<float>, dim3(B.nitems), dim3(256), sizeof(float) * B.kap_max, s,
-                       (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
-                       (const float*)B.kap32.ptr, (const float*)x, (float*)y);
+    auto k = B.vec ? k_spmv<float, true> : k_spmv<float, false>;
+    hipLaunchKernelGGL(k, dim3(grid_of(B)), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), s, it, B.per,
+                       B.nitems, sd, pd, (const float*)B.kap32.ptr, (const float*)x, (float*)y, ktab);
   } else {
-    hipLaunchKernelGGL(k_spmv<double>, dim3(B.nitems), dim3(256), sizeof(double) * B.kap_max, s,
-                       (const int2*)B.items.ptr, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
-                       (const double*)B.kap64.ptr, (const double*)x, (double*)y);
+    auto k = B.vec ? k_spmv<double, true> : k_spmv<double, false>;
+    hipLaunchKernelGGL(k, dim3(grid_of(B)), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), s, it, B.per,
+                       B.nitems, sd, pd, (const double*)B.kap64.ptr, (const double*)x, (double*)y, ktab);
   }
   RBWS_HIP(hipGetLastError());
 }

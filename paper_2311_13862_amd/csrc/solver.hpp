@@ -24,6 +24,14 @@ struct SolveDev {
   double x0[3];       // centre of the Gaussian source
 };
 
+// per-solve state of the FP32-inner / FP64-outer refinement (device memory)
+struct IrState {
+  double thr, ff, tol2, rr, init_rr, scale, upd, eta2;
+  double rho, alpha, beta, thr_in, bb;
+  int outer, mode, first, status, cur, k_in, k_total, restart, skip2, inner_max, max_outer, prec;
+  unsigned long long t_done;
+};
+
 // device arrays of a batch (grow-only allocations, reused across calls)
 struct DevBuf {
   void* ptr = nullptr;
@@ -43,6 +51,8 @@ void fill64(double* x, long long n, double v, hipStream_t s);
 struct Batch {
   int device = 0;
   int nsolve = 0, nprob = 0, nitems = 0;
+  int per = 0;          // work items per XCD slot (grid = 8 * per)
+  bool vec = true;      // every grid size is a multiple of 4 (vector loads)
   long long total = 0;      // sum of ndof over solves
   long long kap_total = 0;  // sum of table sizes
   int kap_max = 0;          // largest table (elements), for LDS sizing
@@ -52,15 +62,17 @@ struct Batch {
   std::vector<int2> items_h;
   DevBuf pd, sd, items, kap64, kap32, theta, ncorner, thidx, state, part, active;
   // FP64 CG vectors
-  DevBuf x, r, p;
+  DevBuf x, r, p, p2;
   // FP32 inner vectors (refinement)
-  DevBuf d32, r32, p32;
+  DevBuf d32, r32, p32, p32b;
   int* active_host = nullptr;  // pinned
   ~Batch();
 };
 
-// tile choice for one grid size (kernels assume TX*TY == 256)
-void choose_tile(int n, int* TX, int* TY, int* TZ);
+// tiles: 32 x 32 grid columns (256 threads, 4 points each) by TZ planes; TZ
+// is the largest power of two in [4, 64] that still gives >= 4096 work items
+void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ);
+inline unsigned grid_of(const Batch& B) { return 8u * (unsigned)B.per; }
 
 // build the batch description: problems[prob_of[b]] for solve b; mu (nsolve x p) on host
 // theta_override (nsolve x Q of problem 0, host) replaces theta(mu) when given
