@@ -74,6 +74,11 @@ enum {
   RBWS_SOLVE_NAN = 3        /* a non-finite value appeared */
 };
 enum { RBWS_LIFT_EXACT = 0, RBWS_LIFT_MFMA = 1 };
+/* FP32_IR variants: RESTART = classic refinement (each outer step solves the
+ * correction equation from zero); RELIABLE = reliable updates (each outer
+ * step folds the correction into u, replaces the FP32 residual by the true
+ * FP64 one and continues CG with the current, rescaled search direction). */
+enum { RBWS_IR_RESTART = 0, RBWS_IR_RELIABLE = 1 };
 /* rbws_solve_opts.flags */
 enum {
   RBWS_FLAG_FORCE_EXACT_DOTS = 1 /* take the exact integer path for every inner product
@@ -126,13 +131,15 @@ typedef struct {
                         basis's final greedy indicator */
   int flags;         /* RBWS_FLAG_* */
   int check_every;   /* rounds between host checks for completion (0 = library default) */
+  int ir_mode;       /* RBWS_IR_RESTART or RBWS_IR_RELIABLE (FP32_IR only) */
 } rbws_solve_opts;
 
 /* ---- errors and defaults ------------------------------------------------ */
 const char* rbws_last_error(void);
 const char* rbws_version(void);
 /* Fill *o with defaults: tol 1e-10, max_iter 50000, Jacobi, FP64, zero start,
- * exact lift, eta_inner 1e-4, max_outer 40, fallback 0, flags 0. */
+ * exact lift, eta_inner 0.1, max_outer 40, fallback 0, flags 0, reliable updates
+ * (classic restarted refinement works best with eta_inner about 1e-4). */
 void rbws_solve_opts_default(rbws_solve_opts* o);
 
 /* ---- operator setup (Eq. 1; Sec. 4 model PDE) ----------------------------
@@ -211,6 +218,28 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
                        const rbws_mlp* const* mlps, int nprob, const int* problem_of,
                        const double* mu, int nmu, const rbws_solve_opts* opts, void* stream,
                        void* const* u_out, rbws_solve_stat* stats);
+
+/* ---- measurement ---------------------------------------------------------
+ * Opt-in HIP-event timing of the library's kernel launches on the calling
+ * thread, accumulated by kind: 0 A.p sweep (with the fused direction update),
+ * 1 residual pass (initial / confirmation / refinement outer pass), 2 and 4
+ * the per-solve scalar steps after each sweep, 3 update sweep (x, r and their
+ * inner products), 5 SpMV, 6 MFMA lift, 7 reduced solves.  The call first
+ * waits for recorded events and returns the totals so far (ms[8], launches[8],
+ * both nullable), then zeroes them if `reset`, then turns timing on or off. */
+rbws_status rbws_profile(int enable, double* ms, long long* launches, int reset);
+/* How often a correctly rounded inner product could not be certified from
+ * its double-double value and was recomputed exactly (current device):
+ * counts[4] = solver and norm dots, basis dots, per-entry sums (Gram-Schmidt,
+ * lift), reduced Cholesky/solves.  Diagnostics; results never depend on it. */
+rbws_status rbws_exact_fallbacks(long long* counts, int reset);
+/* Kernel-variant knobs (results are unaffected beyond FP32 rounding):
+ * RBWS_TUNE_SWEEP32, value bit 0 / bit 1: the FP32 A.p / update sweeps keep
+ * their face coefficients in registers (1) or look them up per plane (0).
+ * RBWS_TUNE_GRID: the sweeps launch one workgroup per work item (0, default)
+ * or a persistent grid of one full occupancy that loops over the items (1). */
+enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1 };
+rbws_status rbws_set_tuning(int key, int value);
 
 #ifdef __cplusplus
 }

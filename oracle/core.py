@@ -74,9 +74,9 @@ def lib():
             "orc_indicators": (None, [pp, i, i, d, d, d, d, i, d, i]),
             "orc_greedy": (i, [pp, d, i, i, C.c_double, i, i, d, d, d, C.POINTER(C.c_int), d,
                                C.POINTER(C.c_int), C.POINTER(Stats), i]),
-            "orc_ir_solve": (i, [pp, d, d, d, i, C.c_double, C.c_double, i, i, d,
-                                 C.POINTER(Stats)]),
-            "orc_ir_batch": (None, [pp, d, i, d, d, i, C.c_double, C.c_double, i, i, d,
+            "orc_ir_solve2": (i, [pp, d, d, d, i, C.c_double, C.c_double, i, i, i, d,
+                                  C.POINTER(Stats)]),
+            "orc_ir_batch": (None, [pp, d, i, d, d, i, C.c_double, C.c_double, i, i, i, d,
                                     C.POINTER(Stats), i]),
         }
         for name, (res, args) in sig.items():
@@ -200,24 +200,26 @@ class Problem:
 
     # -- FP32-in-FP64 refinement -------------------------------------------
     def ir(self, mu, u0=None, prec=PREC_JACOBI, tol=1e-10, eta=1e-4, kin_max=5000,
-           max_outer=40, f=None):
+           max_outer=40, f=None, reliable=False):
+        """FP32-inner / FP64-outer refinement: classic (restart) or reliable updates."""
         mu = _f64(mu)
         f = self.rhs(mu) if f is None else _f64(f)
         u = np.empty(self.ndof)
         st = Stats()
-        lib().orc_ir_solve(self.ref, _dp(mu), _dp(f), _dp(None if u0 is None else _f64(u0)),
-                           prec, tol, eta, kin_max, max_outer, _dp(u), C.byref(st))
+        lib().orc_ir_solve2(self.ref, _dp(mu), _dp(f), _dp(None if u0 is None else _f64(u0)),
+                            prec, tol, eta, kin_max, max_outer, 1 if reliable else 0, _dp(u),
+                            C.byref(st))
         return u, st.as_dict()
 
     def ir_batch(self, mu, u0=None, prec=PREC_JACOBI, tol=1e-10, eta=1e-4, kin_max=5000,
-                 max_outer=40, nthreads=None):
+                 max_outer=40, nthreads=None, reliable=False):
         mu = _f64(mu)
         B = mu.shape[0]
         f = _f64(np.stack([self.rhs(m) for m in mu]))
         u = np.empty((B, self.ndof))
         st = (Stats * max(B, 1))()
         lib().orc_ir_batch(self.ref, _dp(mu), B, _dp(f), _dp(None if u0 is None else _f64(u0)),
-                           prec, tol, eta, kin_max, max_outer, _dp(u), st,
+                           prec, tol, eta, kin_max, max_outer, 1 if reliable else 0, _dp(u), st,
                            nthreads or nthreads_default())
         return u, [st[i].as_dict() for i in range(B)]
 

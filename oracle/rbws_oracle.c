@@ -732,8 +732,22 @@ static void apply32(const float *kx, const float *ky, const float *kz, int n, co
             }
 }
 
+/* reliable = 1: reliable updates.  Each outer step folds the correction d
+ * into u, replaces the FP32 residual by the true one (rescaled) and continues
+ * CG with the current search direction p (rescaled by the same power of two)
+ * instead of restarting from zero; beta uses the new residual. */
+int orc_ir_solve2(const orc_problem *P, const double *mu, const double *f, const double *u0, int prec,
+                  double tol, double eta, int kin_max, int max_outer, int reliable, double *u,
+                  orc_stats *st);
+
 int orc_ir_solve(const orc_problem *P, const double *mu, const double *f, const double *u0, int prec,
                  double tol, double eta, int kin_max, int max_outer, double *u, orc_stats *st) {
+    return orc_ir_solve2(P, mu, f, u0, prec, tol, eta, kin_max, max_outer, 0, u, st);
+}
+
+int orc_ir_solve2(const orc_problem *P, const double *mu, const double *f, const double *u0, int prec,
+                  double tol, double eta, int kin_max, int max_outer, int reliable, double *u,
+                  orc_stats *st) {
     int n = P->n;
     long m = ndof_of(P), nf = nfaces_axis(n);
     faces F = faces_for_mu(P, mu);
@@ -759,7 +773,8 @@ int orc_ir_solve(const orc_problem *P, const double *mu, const double *f, const 
     st->ff = ff;
     if (u0) memcpy(u, u0, sizeof(double) * m); else memset(u, 0, sizeof(double) * m);
     int outer = 0, inner = 0, status = ORC_MAXITER;
-    double rr = 0;
+    double rr = 0, rho_prev = 0.0, sc_prev = 1.0;
+    int have_dir = 0;
     for (;;) {
         apply_faces(&F, n, u, q64);
         for (long i = 0; i < m; i++) r[i] = f[i] - q64[i];
@@ -775,14 +790,24 @@ int orc_ir_solve(const orc_problem *P, const double *mu, const double *f, const 
         for (long i = 0; i < m; i++) bb += (double)ri[i] * (double)ri[i];
         double thr_in = (eta * eta) * bb;
         for (long i = 0; i < m; i++) s[i] = (prec == ORC_PREC_JACOBI) ? ri[i] / dg[i] : ri[i];
-        double rho = 0.0;
-        for (long i = 0; i < m; i++) rho += (double)ri[i] * (double)s[i];
-        memcpy(p, s, sizeof(float) * m);
+        double rho_new = 0.0;
+        for (long i = 0; i < m; i++) rho_new += (double)ri[i] * (double)s[i];
+        if (reliable && have_dir) {
+            /* p (old units) times sc/sc_old is the direction in new units; with
+             * beta = rho_new / (rho_old (sc/sc_old)^2) the update is
+             * p = s + rho_new / (rho_old sc/sc_old) p_old */
+            float b = (float)(rho_new / (rho_prev * (sc / sc_prev)));
+            for (long i = 0; i < m; i++) p[i] = fmaf(b, p[i], s[i]);
+        } else {
+            memcpy(p, s, sizeof(float) * m);
+        }
+        double rho = rho_new;
+        have_dir = 0;
         for (int k = 0; k < kin_max; k++) {
             apply32(kx, ky, kz, n, p, q);
             double g = 0.0;
             for (long i = 0; i < m; i++) g += (double)p[i] * (double)q[i];
-            if (!(g > 0.0)) break;
+            if (!(g > 0.0)) { have_dir = 0; break; }
             float a = (float)(rho / g);
             for (long i = 0; i < m; i++) { d[i] = fmaf(a, p[i], d[i]); ri[i] = fmaf(-a, q[i], ri[i]); }
             inner++;
@@ -792,11 +817,14 @@ int orc_ir_solve(const orc_problem *P, const double *mu, const double *f, const 
                 rri += (double)ri[i] * (double)ri[i];
                 rs += (double)ri[i] * (double)s[i];
             }
+            have_dir = 1;
+            rho_prev = rho;
             if (rri <= thr_in) break;
             float b = (float)(rs / rho);
             for (long i = 0; i < m; i++) p[i] = fmaf(b, p[i], s[i]);
             rho = rs;
         }
+        sc_prev = sc;
         double inv = ldexp(1.0, e);
         for (long i = 0; i < m; i++) u[i] = fma(inv, (double)d[i], u[i]);
         outer++;
@@ -812,12 +840,12 @@ int orc_ir_solve(const orc_problem *P, const double *mu, const double *f, const 
 }
 
 void orc_ir_batch(const orc_problem *P, const double *mu, int nmu, const double *f, const double *u0,
-                  int prec, double tol, double eta, int kin_max, int max_outer, double *u,
+                  int prec, double tol, double eta, int kin_max, int max_outer, int reliable, double *u,
                   orc_stats *st, int nthreads) {
     long m = ndof_of(P);
     int p = P->kind == ORC_BLOCKS ? P->nblocks : (P->kind == ORC_OCTANTS ? 8 : 24 + (P->f_kind == ORC_F_GAUSS ? 3 : 0));
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
     for (int b = 0; b < nmu; b++)
-        orc_ir_solve(P, mu + (long)b * p, f + b * m, u0 ? u0 + b * m : NULL, prec, tol, eta, kin_max,
-                     max_outer, u + b * m, st + b);
+        orc_ir_solve2(P, mu + (long)b * p, f + b * m, u0 ? u0 + b * m : NULL, prec, tol, eta, kin_max,
+                      max_outer, reliable, u + b * m, st + b);
 }

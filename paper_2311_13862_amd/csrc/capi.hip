@@ -93,11 +93,12 @@ void rbws_solve_opts_default(rbws_solve_opts* o) {
   o->precision = RBWS_FP64;
   o->init = RBWS_INIT_ZERO;
   o->lift = RBWS_LIFT_EXACT;
-  o->eta_inner = 1e-4;
+  o->eta_inner = 0.1;
   o->max_outer = 40;
   o->fallback = 0;
   o->flags = 0;
   o->check_every = 0;
+  o->ir_mode = RBWS_IR_RELIABLE;
 }
 
 rbws_status rbws_problem_create(const rbws_problem_desc* desc, int device, rbws_problem** out) {
@@ -276,6 +277,47 @@ rbws_status rbws_basis_load(rbws_problem* p, const char* path, rbws_basis** out)
   API_END
 }
 
+rbws_status rbws_set_tuning(int key, int value) {
+  API_BEGIN
+  if (key == RBWS_TUNE_SWEEP32) {
+    RBWS_REQUIRE(value >= 0 && value <= 3, RBWS_EINVAL, "value out of range");
+    set_sweep32_variant(value);
+  } else if (key == RBWS_TUNE_GRID) {
+    RBWS_REQUIRE(value == 0 || value == 1, RBWS_EINVAL, "value out of range");
+    set_grid_mode(value);
+  } else {
+    throw Error{RBWS_EINVAL, "unknown tuning key"};
+  }
+  API_END
+}
+
+rbws_status rbws_exact_fallbacks(long long* counts, int reset) {
+  API_BEGIN
+  RBWS_REQUIRE(counts != nullptr, RBWS_EINVAL, "counts is NULL");
+  counts[0] = (long long)fallbacks_solver(reset != 0);
+  counts[1] = (long long)fallbacks_rb(0, false);
+  counts[2] = (long long)fallbacks_rb(1, false);
+  counts[3] = (long long)fallbacks_rb(2, reset != 0);
+  API_END
+}
+
+rbws_status rbws_profile(int enable, double* ms, long long* launches, int reset) {
+  API_BEGIN
+  KernelTimer& t = ktimer();
+  t.flush();
+  if (ms)
+    for (int k = 0; k < KK_COUNT; k++) ms[k] = t.ms[k];
+  if (launches)
+    for (int k = 0; k < KK_COUNT; k++) launches[k] = t.count[k];
+  if (reset)
+    for (int k = 0; k < KK_COUNT; k++) {
+      t.ms[k] = 0.0;
+      t.count[k] = 0;
+    }
+  t.on = enable != 0;
+  API_END
+}
+
 rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* bases,
                        const rbws_mlp* const* mlps, int nprob, const int* problem_of,
                        const double* mu, int nmu, const rbws_solve_opts* opts, void* stream,
@@ -337,8 +379,10 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
     RBWS_REQUIRE(opts->eta_inner > 0.0 && opts->eta_inner < 1.0, RBWS_EINVAL, "eta_inner must be in (0,1)");
     RBWS_REQUIRE(opts->max_outer >= 1, RBWS_EINVAL, "max_outer < 1");
     RBWS_REQUIRE(opts->max_iter >= 1, RBWS_EINVAL, "max_iter < 1 for refinement");
+    RBWS_REQUIRE(opts->ir_mode == RBWS_IR_RESTART || opts->ir_mode == RBWS_IR_RELIABLE, RBWS_EINVAL,
+                 "bad ir_mode");
     IrOpts io{opts->tol, opts->eta_inner, opts->precond, opts->max_iter, opts->max_outer, opts->flags,
-              opts->check_every};
+              opts->check_every, opts->ir_mode == RBWS_IR_RELIABLE ? 1 : 0};
     ir_run(B, io, s, ir);
     for (int b = 0; b < nmu; b++) sol[b] = (ir[b].cur ? (const double*)B.r.ptr : x) + B.sd_h[b].off;
   }

@@ -24,9 +24,30 @@ constexpr int QS = 36;                          // LDS row stride (elements)
 constexpr int QROWS = QY + 2;                   // rows with the two halo rows
 constexpr int QPLANE = QROWS * QS + 2 * QROWS;  // plane buffer: rows + left/right halo columns
 
-// Blocks are dealt round-robin to the 8 XCDs; give every XCD a contiguous run
-// of work items so that the tiles of one solve share one L2.
-__device__ __forceinline__ int item_of(int bid, int per) { return (bid & 7) * per + (bid >> 3); }
+// Persistent grid over a work list: blocks are dealt round-robin to the 8
+// XCDs, so every XCD takes a contiguous share of the list and the tiles of
+// one solve (contiguous in the list) share one L2.  gridDim.x is a multiple
+// of 8.  `list` == nullptr means all items 0..total-1.
+struct WorkRange {
+  int w, w1, step;
+};
+__device__ __forceinline__ WorkRange work_range(int total) {
+  const int x = blockIdx.x & 7, nx = gridDim.x >> 3;
+  const int chunk = (total + 7) >> 3;
+  const int w0 = x * chunk;
+  return WorkRange{w0 + (int)(blockIdx.x >> 3), min(total, w0 + chunk), nx};
+}
+
+// Append work items item0 .. item0+n-1 to a list (called by the whole
+// workgroup; `slot` is workgroup-shared scratch).  The order of solves in a
+// list depends on timing, but every item writes its own partial-result slot
+// and the per-solve reductions run in tile order, so results do not.
+__device__ __forceinline__ void list_push(int* list, int* cnt, int item0, int n, int* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(cnt, n);
+  __syncthreads();
+  const int base = *slot;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) list[base + t] = item0 + t;
+}
 
 template <typename T> struct V4T;
 template <> struct V4T<float> { typedef float4 t; };
@@ -34,9 +55,11 @@ template <> struct V4T<double> { typedef double4 t; };
 
 template <typename T, bool VEC>
 __device__ __forceinline__ void ld4(const T* __restrict__ a, long long c, int nv, T v[4]) {
-  if (VEC && nv == 4) {
-    const typename V4T<T>::t q = *reinterpret_cast<const typename V4T<T>::t*>(a + c);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  if (VEC) {  // nv is 0 or 4 when n % 4 == 0
+    if (nv == 4) {
+      const typename V4T<T>::t q = *reinterpret_cast<const typename V4T<T>::t*>(a + c);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++) v[e] = e < nv ? a[c + e] : T(0);
@@ -161,6 +184,8 @@ template <> struct DotAcc<float> {  // FP64 accumulation of exact float products
 enum { FOP_AP = 0, FOP_UP2 = 1, FOP_SPMV = 2 };  // SPMV: X = A Pn
 
 // Shared body.  X is x (FP64 CG) or d (FP32 refinement); first_x: X = alpha p.
+// The z-march is software-pipelined: loads for plane k+2 (own quad) and for
+// plane k+1 (halo point, x and r) are issued before plane k is consumed.
 template <typename T, bool VEC, int OP>
 __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, const T* kt, T* plane,
                                           const T* __restrict__ R0, T* __restrict__ R, const T* __restrict__ Pold,
@@ -169,85 +194,112 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
   const int n = G.n;
   const long long n2 = (long long)n * n;
   const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);  // + (k-1) n^2
+  const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
   const int nv = G.nv;
+  const bool hin = G.hi != 0;
 
-  // p_new of the own quad at plane k (AP) or p_new loaded (UP2)
-  auto quad_p = [&](int k, T out[4]) {
-    if (nv == 0) {
+  // raw loads of the own quad at plane k: r and p_old (AP) or p_new (UP2/SPMV)
+  auto quad_load = [&](int k, T ra[4], T rb[4]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int e = 0; e < 4; e++) out[e] = T(0);
-      return;
-    }
+    for (int e = 0; e < 4; e++) ra[e] = rb[e] = T(0);
+    if (nv == 0 || k < 1 || k > n) return;
     const long long c = (long long)(k - 1) * n2 + rowoff;
     if (OP != FOP_AP) {
-      ld4<T, VEC>(Pn, c, nv, out);
+      ld4<T, VEC>(Pn, c, nv, ra);
       return;
     }
-    T rv[4], po[4];
-    ld4<T, VEC>(R0, c, nv, rv);
-    if (!restart) ld4<T, VEC>(Pold, c, nv, po);
+    ld4<T, VEC>(R0, c, nv, ra);
+    if (!restart) ld4<T, VEC>(Pold, c, nv, rb);
+  };
+  // p_new of the own quad at plane k from its raw loads
+  auto quad_finish = [&](int k, const T ra[4], const T rb[4], T out[4]) __attribute__((always_inline)) {
+    if (OP != FOP_AP || nv == 0 || k < 1 || k > n) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = ra[e];
+      return;
+    }
     const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      T sv = rv[e];
+      T sv = ra[e];
       if (prec) {
         T kk[6];
         quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
-        sv = rv[e] / diag6T<T>(kk);
+        sv = ra[e] / diag6T<T>(kk);
       }
-      out[e] = (e < nv) ? (restart ? sv : fmaT(beta, po[e], sv)) : T(0);
+      out[e] = (e < nv) ? (restart ? sv : fmaT(beta, rb[e], sv)) : T(0);
     }
   };
-  // p_new at this thread's halo point of plane k
-  auto halo_p = [&](int k) -> T {
-    if (G.hi == 0) return T(0);
-    const long long c = (long long)(k - 1) * n2 + (long long)(G.hj - 1) * n + (G.hi - 1);
-    if (OP != FOP_AP) return Pn[c];
-    const T rv = R0[c];
-    T sv = rv;
+  auto halo_load = [&](int k, T& ha, T& hb) __attribute__((always_inline)) {
+    ha = hb = T(0);
+    if (!hin || k > n) return;
+    const long long c = (long long)(k - 1) * n2 + hoff;
+    if (OP != FOP_AP) {
+      ha = Pn[c];
+      return;
+    }
+    ha = R0[c];
+    if (!restart) hb = Pold[c];
+  };
+  auto halo_finish = [&](int k, T ha, T hb) __attribute__((always_inline)) -> T {
+    if (OP != FOP_AP || !hin) return ha;
+    T sv = ha;
     if (prec) {
       const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
       T kk[6] = {kt[G.hb[0] + czn], kt[G.hb[1] + czn], kt[G.hb[2] + czn],
                  kt[G.hb[3] + czn], kt[G.hb[4] + czm], kt[G.hb[4] + czp]};
-      sv = rv / diag6T<T>(kk);
+      sv = ha / diag6T<T>(kk);
     }
-    return restart ? sv : fmaT(beta, Pold[c], sv);
+    return restart ? sv : fmaT(beta, hb, sv);
+  };
+  auto xr_load = [&](int k, T xo[4], T ro[4]) __attribute__((always_inline)) {
+    if (OP != FOP_UP2 || nv == 0 || k > G.ke) return;
+    const long long c = (long long)(k - 1) * n2 + rowoff;
+    if (!first_x) ld4<T, VEC>(X, c, nv, xo);
+    ld4<T, VEC>(R, c, nv, ro);
   };
 
-  T pm[4], pc[4], pn[4];
-  if (G.kb > 1) quad_p(G.kb - 1, pm);
-  else {
-#pragma unroll
-    for (int e = 0; e < 4; e++) pm[e] = T(0);
+  T pm[4], pc[4], pn[4], ra[4], rb[4];
+  {
+    T qa[4], qb[4];
+    quad_load(G.kb - 1, qa, qb);
+    quad_finish(G.kb - 1, qa, qb, pm);
+    quad_load(G.kb, qa, qb);
+    quad_finish(G.kb, qa, qb, pc);
+    quad_load(G.kb + 1, qa, qb);
+    quad_finish(G.kb + 1, qa, qb, pn);
   }
-  quad_p(G.kb, pc);
-  if (OP == FOP_AP && nv > 0) st4<T, VEC>(Pn, (long long)(G.kb - 1) * n2 + rowoff, nv, pc);
+  if (OP == FOP_AP && nv > 0) {
+    st4<T, VEC>(Pn, (long long)(G.kb - 1) * n2 + rowoff, nv, pc);
+    if (G.kb + 1 <= G.ke) st4<T, VEC>(Pn, (long long)G.kb * n2 + rowoff, nv, pn);
+  }
+  T ha, hb, xo[4], ro[4];
+  halo_load(G.kb, ha, hb);
+#pragma unroll
+  for (int e = 0; e < 4; e++) xo[e] = ro[e] = T(0);
+  xr_load(G.kb, xo, ro);
   int buf = 0;
   const int mrow = (G.ly + 1) * QS + 4 * G.lx;
   const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
   for (int k = G.kb; k <= G.ke; k++) {
-    if (k < n) {
-      quad_p(k + 1, pn);
-      if (OP == FOP_AP && k + 1 <= G.ke && nv > 0) st4<T, VEC>(Pn, (long long)k * n2 + rowoff, nv, pn);
-    } else {
+    // issue the next loads
+    quad_load(k + 2, ra, rb);
+    T ha2, hb2, xo2[4], ro2[4];
+    halo_load(k + 1, ha2, hb2);
 #pragma unroll
-      for (int e = 0; e < 4; e++) pn[e] = T(0);
-    }
+    for (int e = 0; e < 4; e++) xo2[e] = ro2[e] = T(0);
+    xr_load(k + 1, xo2, ro2);
+    // consume plane k
     T* pl = plane + buf * QPLANE;
 #pragma unroll
     for (int e = 0; e < 4; e++) pl[mrow + e] = pc[e];
-    if (G.hslot >= 0) pl[G.hslot] = halo_p(k);
+    if (G.hslot >= 0) pl[G.hslot] = halo_finish(k, ha, hb);
     __syncthreads();
     if (nv > 0) {
       const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
       const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
       const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
-      const long long c = (long long)(k - 1) * n2 + rowoff;
-      T xo[4], ro[4];
-      if (OP == FOP_UP2) {
-        if (!first_x) ld4<T, VEC>(X, c, nv, xo);
-        ld4<T, VEC>(R, c, nv, ro);
-      }
+      T qo[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         T kk[6];
@@ -263,9 +315,8 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         q = fmaT(-kk[3], yp, q);
         q = fmaT(-kk[4], pm[e], q);
         q = fmaT(-kk[5], pn[e], q);
-        if (OP == FOP_SPMV) {
-          xo[e] = q;
-        } else if (e < nv) {
+        qo[e] = q;
+        if (OP != FOP_SPMV && e < nv) {
           if (OP == FOP_AP) {
             a0.add(pc[e], q);
           } else {
@@ -277,17 +328,329 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
           }
         }
       }
+      const long long c = (long long)(k - 1) * n2 + rowoff;
       if (OP == FOP_UP2) {
         st4<T, VEC>(X, c, nv, xo);
         st4<T, VEC>(R, c, nv, ro);
       }
-      if (OP == FOP_SPMV) st4<T, VEC>(X, c, nv, xo);
+      if (OP == FOP_SPMV) st4<T, VEC>(X, c, nv, qo);
+    }
+    // rotate; finish p_new of plane k+2 and store it when it is ours
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      pm[e] = pc[e];
+      pc[e] = pn[e];
+      xo[e] = xo2[e];
+      ro[e] = ro2[e];
+    }
+    quad_finish(k + 2, ra, rb, pn);
+    if (OP == FOP_AP && nv > 0 && k + 2 <= G.ke) st4<T, VEC>(Pn, (long long)(k + 1) * n2 + rowoff, nv, pn);
+    ha = ha2;
+    hb = hb2;
+    buf ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 variant of the sweeps.  The face coefficients of the own quad, its
+// diagonal and the diagonal's reciprocal are kept in registers and refreshed
+// only when the plane's z codes change (the codes are the same for the whole
+// block, so the test does not diverge); Jacobi is s = r * (1/d).
+// ---------------------------------------------------------------------------
+struct KCache32 {
+  int key;
+  float kx[5], kym[4], kyp[4], kzm[4], kzp[4], dg[4], inv[4];
+  float hinv;
+};
+
+__device__ __forceinline__ int zkey(const GridDev& g, int k) {
+  return g.code[2][0][k - 1] | (g.code[2][1][k - 1] << 8) | (g.code[2][1][k] << 16);
+}
+
+__device__ __forceinline__ void kc_fill(KCache32& C, const QuadGeo& G, const float* kt, int key) {
+  const int czn = key & 255, czm = (key >> 8) & 255, czp = key >> 16;
+#pragma unroll
+  for (int e = 0; e < 5; e++) C.kx[e] = kt[G.bxf[e] + czn];
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    C.kym[e] = kt[G.bym[e] + czn];
+    C.kyp[e] = kt[G.byp[e] + czn];
+    C.kzm[e] = kt[G.bz[e] + czm];
+    C.kzp[e] = kt[G.bz[e] + czp];
+    C.dg[e] = ((((C.kx[e] + C.kx[e + 1]) + C.kym[e]) + C.kyp[e]) + C.kzm[e]) + C.kzp[e];
+    C.inv[e] = 1.0f / C.dg[e];
+  }
+  C.hinv = 1.0f;
+  if (G.hi != 0) {
+    const float hd = ((((kt[G.hb[0] + czn] + kt[G.hb[1] + czn]) + kt[G.hb[2] + czn]) + kt[G.hb[3] + czn]) +
+                      kt[G.hb[4] + czm]) + kt[G.hb[4] + czp];
+    C.hinv = 1.0f / hd;
+  }
+  C.key = key;
+}
+
+template <bool VEC, int OP>
+__device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, const float* kt, float* plane,
+                                            const float* __restrict__ R0, float* __restrict__ R,
+                                            const float* __restrict__ Pold, float* __restrict__ Pn,
+                                            float* __restrict__ X, float alpha, float beta, int restart, int prec,
+                                            int first_x, double& a0, double& a1) {
+  const int n = G.n;
+  const long long n2 = (long long)n * n;
+  const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
+  const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
+  const int nv = G.nv;
+  const bool hin = G.hi != 0;
+  KCache32 C;
+  C.key = -1;
+
+  auto quad_load = [&](int k, float ra[4], float rb[4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) ra[e] = rb[e] = 0.0f;
+    if (nv == 0 || k < 1 || k > n) return;
+    const long long c = (long long)(k - 1) * n2 + rowoff;
+    if (OP != FOP_AP) {
+      ld4<float, VEC>(Pn, c, nv, ra);
+      return;
+    }
+    ld4<float, VEC>(R0, c, nv, ra);
+    if (!restart) ld4<float, VEC>(Pold, c, nv, rb);
+  };
+  // reciprocal diagonal of the own quad at plane k (from the cache when the codes match)
+  auto quad_inv = [&](int k, float inv[4]) __attribute__((always_inline)) {
+    const int key = zkey(g, k);
+    if (key == C.key) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) inv[e] = C.inv[e];
+      return;
+    }
+    KCache32 T2;
+    kc_fill(T2, G, kt, key);
+#pragma unroll
+    for (int e = 0; e < 4; e++) inv[e] = T2.inv[e];
+  };
+  auto quad_finish = [&](int k, const float ra[4], const float rb[4], float out[4]) __attribute__((always_inline)) {
+    if (OP != FOP_AP || nv == 0 || k < 1 || k > n) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = ra[e];
+      return;
+    }
+    float inv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if (prec) quad_inv(k, inv);
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const float sv = prec ? ra[e] * inv[e] : ra[e];
+      out[e] = (e < nv) ? (restart ? sv : fmaf(beta, rb[e], sv)) : 0.0f;
+    }
+  };
+  auto halo_load = [&](int k, float& ha, float& hb) __attribute__((always_inline)) {
+    ha = hb = 0.0f;
+    if (!hin || k > n) return;
+    const long long c = (long long)(k - 1) * n2 + hoff;
+    if (OP != FOP_AP) {
+      ha = Pn[c];
+      return;
+    }
+    ha = R0[c];
+    if (!restart) hb = Pold[c];
+  };
+  auto xr_load = [&](int k, float xo[4], float ro[4]) __attribute__((always_inline)) {
+    if (OP != FOP_UP2 || nv == 0 || k > G.ke) return;
+    const long long c = (long long)(k - 1) * n2 + rowoff;
+    if (!first_x) ld4<float, VEC>(X, c, nv, xo);
+    ld4<float, VEC>(R, c, nv, ro);
+  };
+
+  float pm[4], pc[4], pn[4], ra[4], rb[4];
+  {
+    float qa[4], qb[4];
+    quad_load(G.kb - 1, qa, qb);
+    quad_finish(G.kb - 1, qa, qb, pm);
+    quad_load(G.kb, qa, qb);
+    quad_finish(G.kb, qa, qb, pc);
+    quad_load(G.kb + 1, qa, qb);
+    quad_finish(G.kb + 1, qa, qb, pn);
+  }
+  if (OP == FOP_AP && nv > 0) {
+    st4<float, VEC>(Pn, (long long)(G.kb - 1) * n2 + rowoff, nv, pc);
+    if (G.kb + 1 <= G.ke) st4<float, VEC>(Pn, (long long)G.kb * n2 + rowoff, nv, pn);
+  }
+  float ha, hb, xo[4], ro[4];
+  halo_load(G.kb, ha, hb);
+#pragma unroll
+  for (int e = 0; e < 4; e++) xo[e] = ro[e] = 0.0f;
+  xr_load(G.kb, xo, ro);
+  int buf = 0;
+  const int mrow = (G.ly + 1) * QS + 4 * G.lx;
+  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+  for (int k = G.kb; k <= G.ke; k++) {
+    quad_load(k + 2, ra, rb);
+    float ha2, hb2, xo2[4], ro2[4];
+    halo_load(k + 1, ha2, hb2);
+#pragma unroll
+    for (int e = 0; e < 4; e++) xo2[e] = ro2[e] = 0.0f;
+    xr_load(k + 1, xo2, ro2);
+    const int key = zkey(g, k);
+    if (key != C.key) kc_fill(C, G, kt, key);
+    float* pl = plane + buf * QPLANE;
+#pragma unroll
+    for (int e = 0; e < 4; e++) pl[mrow + e] = pc[e];
+    if (G.hslot >= 0) {
+      float hv = ha;
+      if (OP == FOP_AP && hin) {
+        const float sv = prec ? ha * C.hinv : ha;
+        hv = restart ? sv : fmaf(beta, hb, sv);
+      }
+      pl[G.hslot] = hv;
+    }
+    __syncthreads();
+    if (nv > 0) {
+      const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
+      const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+      float qo[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const float xm = e > 0 ? pc[e - 1] : left;
+        const float xp = e < 3 ? pc[e + 1] : right;
+        const float ym = pl[mrow - QS + e], yp = pl[mrow + QS + e];
+        float q = C.dg[e] * pc[e];
+        q = fmaf(-C.kx[e], xm, q);
+        q = fmaf(-C.kx[e + 1], xp, q);
+        q = fmaf(-C.kym[e], ym, q);
+        q = fmaf(-C.kyp[e], yp, q);
+        q = fmaf(-C.kzm[e], pm[e], q);
+        q = fmaf(-C.kzp[e], pn[e], q);
+        qo[e] = q;
+        if (OP != FOP_SPMV && e < nv) {
+          if (OP == FOP_AP) {
+            a0 = __fma_rn((double)pc[e], (double)q, a0);
+          } else {
+            xo[e] = first_x ? alpha * pc[e] : fmaf(alpha, pc[e], xo[e]);
+            const float rv = fmaf(-alpha, q, ro[e]);
+            ro[e] = rv;
+            a0 = __fma_rn((double)rv, (double)rv, a0);
+            if (prec) a1 = __fma_rn((double)rv, (double)(rv * C.inv[e]), a1);
+          }
+        }
+      }
+      const long long c = (long long)(k - 1) * n2 + rowoff;
+      if (OP == FOP_UP2) {
+        st4<float, VEC>(X, c, nv, xo);
+        st4<float, VEC>(R, c, nv, ro);
+      }
+      if (OP == FOP_SPMV) st4<float, VEC>(X, c, nv, qo);
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       pm[e] = pc[e];
       pc[e] = pn[e];
+      xo[e] = xo2[e];
+      ro[e] = ro2[e];
     }
+    quad_finish(k + 2, ra, rb, pn);
+    if (OP == FOP_AP && nv > 0 && k + 2 <= G.ke) st4<float, VEC>(Pn, (long long)(k + 1) * n2 + rowoff, nv, pn);
+    ha = ha2;
+    hb = hb2;
+    buf ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer FP64 pass of the refinement on the same tiles: u_new = u + upd d
+// (own quad and halo, from u and the FP32 correction d), r = f - A64 u_new in
+// the fixed stencil order, b = fl32(r * scale); u_new goes to the other u
+// buffer.  Inner products: ||r||^2 (correctly rounded), ||b||^2 and b.P(b).
+// ---------------------------------------------------------------------------
+template <bool VEC, typename FV>
+__device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, const double* k64, const float* k32,
+                                           double* plane, const double* __restrict__ Us, double* __restrict__ Ud,
+                                           const float* __restrict__ D, float* __restrict__ R, double upd,
+                                           double scale, int prec, int first, FV fv, CrAcc& arr, CrAcc& aff,
+                                           double& bb, double& bs) {
+  const int n = G.n;
+  const long long n2 = (long long)n * n;
+  const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
+  const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
+  const int nv = G.nv;
+  const bool hin = G.hi != 0;
+  const bool up = upd != 0.0;
+  auto quad_u = [&](int k, double out[4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) out[e] = 0.0;
+    if (nv == 0 || k < 1 || k > n) return;
+    const long long c = (long long)(k - 1) * n2 + rowoff;
+    ld4<double, VEC>(Us, c, nv, out);
+    if (up) {
+      float dv[4] = {0.f, 0.f, 0.f, 0.f};
+      ld4<float, VEC>(D, c, nv, dv);
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = e < nv ? __fma_rn(upd, (double)dv[e], out[e]) : 0.0;
+    }
+  };
+  auto halo_u = [&](int k) __attribute__((always_inline)) -> double {
+    if (!hin || k > n) return 0.0;
+    const long long c = (long long)(k - 1) * n2 + hoff;
+    return up ? __fma_rn(upd, (double)D[c], Us[c]) : Us[c];
+  };
+  double um[4], uc[4], un[4];
+  quad_u(G.kb - 1, um);
+  quad_u(G.kb, uc);
+  double hv = halo_u(G.kb);
+  int buf = 0;
+  const int mrow = (G.ly + 1) * QS + 4 * G.lx;
+  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+  for (int k = G.kb; k <= G.ke; k++) {
+    quad_u(k + 1, un);
+    const double hv2 = halo_u(k + 1);
+    double* pl = plane + buf * QPLANE;
+#pragma unroll
+    for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+    if (G.hslot >= 0) pl[G.hslot] = hv;
+    __syncthreads();
+    if (nv > 0) {
+      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      const double left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
+      const double right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+      float ro[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        double kk[6];
+        quad_kappa<double>(G, k64, e, czn, czm, czp, kk);
+        const double xm = e > 0 ? uc[e - 1] : left;
+        const double xp = e < 3 ? uc[e + 1] : right;
+        double q = diag6T<double>(kk) * uc[e];
+        q = __fma_rn(-kk[0], xm, q);
+        q = __fma_rn(-kk[1], xp, q);
+        q = __fma_rn(-kk[2], pl[mrow - QS + e], q);
+        q = __fma_rn(-kk[3], pl[mrow + QS + e], q);
+        q = __fma_rn(-kk[4], um[e], q);
+        q = __fma_rn(-kk[5], un[e], q);
+        ro[e] = 0.0f;
+        if (e < nv) {
+          const double f = fv(G.i + e, G.j, k);
+          const double rv = f - q;
+          const float r32 = (float)(rv * scale);
+          ro[e] = r32;
+          cr_add_prod(arr, rv, rv);
+          if (first) cr_add_prod(aff, f, f);
+          bb = __fma_rn((double)r32, (double)r32, bb);
+          if (prec) {
+            float k3[6];
+            quad_kappa<float>(G, k32, e, czn, czm, czp, k3);
+            bs = __fma_rn((double)r32, (double)(r32 / diag6T<float>(k3)), bs);
+          }
+        }
+      }
+      const long long c = (long long)(k - 1) * n2 + rowoff;
+      st4<float, VEC>(R, c, nv, ro);
+      if (up) st4<double, VEC>(Ud, c, nv, uc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      um[e] = uc[e];
+      uc[e] = un[e];
+    }
+    hv = hv2;
     buf ^= 1;
   }
 }

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "fast.hpp"
@@ -30,19 +31,18 @@ struct IrPart {
   double pad;
 };
 
-// Outer pass (FP64) of every solve whose mode is RESID: u_new = u + upd d,
-// r = f - A64 u_new, b = fl32(r * scale) into r32, and the norms.
-__global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items, int per, int nitems,
+// Outer pass (FP64) of every solve whose mode is RESID (fast.hpp, outer_body)
+template <bool VEC>
+__device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict__ items,
                                                   const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,
                                                   const float* __restrict__ kap32, double* __restrict__ u0,
                                                   double* __restrict__ u1, const float* __restrict__ d,
                                                   float* __restrict__ r, IrPart* __restrict__ part, int ktab) {
   extern __shared__ double lds[];
-  __shared__ double redd[4][3];
+  __shared__ double redd[4][2];
   __shared__ CrAcc redc[4];
-  const int item = item_of(blockIdx.x, per);
-  if (item >= nitems) return;
+  __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
   if (st[b].mode != MODE_RESID) return;
@@ -52,6 +52,7 @@ __global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items
   const int ntab = g.ndir * g.nclass;
   double* k64 = lds;
   float* k32 = reinterpret_cast<float*>(lds + ktab);
+  double* plane = lds + ktab + (ktab + 1) / 2;
   for (int e = threadIdx.x; e < ntab; e += blockDim.x) {
     k32[e] = kap32[S.kap_off + e];
     k64[e] = kap64[S.kap_off + e];
@@ -59,49 +60,13 @@ __global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items
   __syncthreads();
   QuadGeo G;
   quad_geo(G, P, it.y);
-  const int n = g.n;
-  const long long n2 = (long long)n * n;
   const IrState& s = st[b];
-  const int prec = s.prec, first = s.first;
-  const double upd = s.upd, scale = s.scale;
+  const int first = s.first;
   double g0 = 0.0, g1 = 0.0;
   CrAcc arr = cr_zero(), aff = cr_zero();
-  const float* D = d + S.off;
-  float* R = r + S.off;
-  const double* Us = (s.cur ? u1 : u0) + S.off;
-  double* Ud = (s.cur ? u0 : u1) + S.off;
-  auto un = [&](long long e) { return upd != 0.0 ? __fma_rn(upd, (double)D[e], Us[e]) : Us[e]; };
-  for (int k = G.kb; k <= G.ke; k++) {
-    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      if (e >= G.nv) continue;
-      const int i = G.i + e, j = G.j;
-      const long long c = vidx(n, i, j, k);
-      double kd[6];
-      float kk[6];
-      quad_kappa<double>(G, k64, e, czn, czm, czp, kd);
-      quad_kappa<float>(G, k32, e, czn, czm, czp, kk);
-      const float dg = diag6T<float>(kk);
-      const double uc = un(c);
-      double acc = diag6(kd) * uc;
-      if (i > 1) acc = __fma_rn(-kd[0], un(c - 1), acc);
-      if (i < n) acc = __fma_rn(-kd[1], un(c + 1), acc);
-      if (j > 1) acc = __fma_rn(-kd[2], un(c - n), acc);
-      if (j < n) acc = __fma_rn(-kd[3], un(c + n), acc);
-      if (k > 1) acc = __fma_rn(-kd[4], un(c - n2), acc);
-      if (k < n) acc = __fma_rn(-kd[5], un(c + n2), acc);
-      if (upd != 0.0) Ud[c] = uc;
-      const double f = fval(P, S, i, j, k);
-      const double rv = f - acc;
-      const float r32 = (float)(rv * scale);
-      R[c] = r32;
-      cr_add_prod(arr, rv, rv);
-      if (first) cr_add_prod(aff, f, f);
-      g0 = __fma_rn((double)r32, (double)r32, g0);
-      if (prec) g1 = __fma_rn((double)r32, (double)(r32 / dg), g1);
-    }
-  }
+  auto fv = [&](int i, int j, int k) { return fval(P, S, i, j, k); };
+  outer_body<VEC>(G, g, k64, k32, plane, (s.cur ? u1 : u0) + S.off, (s.cur ? u0 : u1) + S.off, d + S.off,
+                  r + S.off, s.upd, s.scale, s.prec, first, fv, arr, aff, g0, g1);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
@@ -126,9 +91,22 @@ __global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items
   }
 }
 
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items, const int* __restrict__ list,
+                                                  const int* __restrict__ cnt, int nitems,
+                                                  const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                  const IrState* __restrict__ st, const double* __restrict__ kap64,
+                                                  const float* __restrict__ kap32, double* __restrict__ u0,
+                                                  double* __restrict__ u1, const float* __restrict__ d,
+                                                  float* __restrict__ r, IrPart* __restrict__ part, int ktab) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step)
+    k_ir_outer_item<VEC>(list ? list[w] : w, items, sd, pd, st, kap64, kap32, u0, u1, d, r, part, ktab);
+}
+
 // inner FP32 iteration sweeps (fast.hpp); p alternates by the parity of k_total
-template <bool VEC, int OP>
-__global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, int per, int nitems,
+template <bool VEC, int OP, bool CACHED>
+__device__ __forceinline__ void k_fast32_item(int item, const int2* __restrict__ items,
                                                 const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                 const IrState* __restrict__ st, const float* __restrict__ kap,
                                                 float* __restrict__ d, float* __restrict__ r, float* __restrict__ p0,
@@ -136,8 +114,7 @@ __global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, 
   extern __shared__ double smem_raw[];
   float* smem = reinterpret_cast<float*>(smem_raw);
   __shared__ double red[4][2];
-  const int item = item_of(blockIdx.x, per);
-  if (item >= nitems) return;
+  __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
   const IrState& s = st[b];
@@ -153,12 +130,19 @@ __global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, 
   const int par = s.k_total & 1;
   const float* Pold = (par ? p1 : p0) + S.off;
   float* Pn = (par ? p0 : p1) + S.off;
-  DotAcc<float> a0, a1;
-  a0.zero();
-  a1.zero();
-  fast_body<float, VEC, OP>(G, P.g, smem, smem + ktab, r + S.off, r + S.off, Pold, Pn, d + S.off,
-                            (float)s.alpha, (float)s.beta, s.restart, s.prec, s.k_in == 0, a0, a1);
-  double g0 = a0.a, g1 = a1.a;
+  double g0 = 0.0, g1 = 0.0;
+  if (CACHED) {
+    fast_body32<VEC, OP>(G, P.g, smem, smem + ktab, r + S.off, r + S.off, Pold, Pn, d + S.off,
+                         (float)s.alpha, (float)s.beta, s.restart, s.prec, s.k_in == 0, g0, g1);
+  } else {
+    DotAcc<float> a0, a1;
+    a0.zero();
+    a1.zero();
+    fast_body<float, VEC, OP>(G, P.g, smem, smem + ktab, r + S.off, r + S.off, Pold, Pn, d + S.off,
+                              (float)s.alpha, (float)s.beta, s.restart, s.prec, s.k_in == 0, a0, a1);
+    g0 = a0.a;
+    g1 = a1.a;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
@@ -177,6 +161,19 @@ __global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, 
   }
 }
 
+template <bool VEC, int OP, bool CACHED>
+__global__ __launch_bounds__(256) void k_fast32(const int2* __restrict__ items, const int* __restrict__ list,
+                                                const int* __restrict__ cnt, int nitems,
+                                                const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                const IrState* __restrict__ st, const float* __restrict__ kap,
+                                                float* __restrict__ d, float* __restrict__ r,
+                                                float* __restrict__ p0, float* __restrict__ p1,
+                                                IrPart* __restrict__ part, int ktab) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step)
+    k_fast32_item<VEC, OP, CACHED>(list ? list[w] : w, items, sd, pd, st, kap, d, r, p0, p1, part, ktab);
+}
+
 __device__ __forceinline__ void ir_done(IrState& s, int status, int* active) {
   s.status = status;
   s.mode = MODE_DONE;
@@ -185,20 +182,29 @@ __device__ __forceinline__ void ir_done(IrState& s, int status, int* active) {
 }
 
 // end of an inner solve: schedule the outer update with the correction found
-__device__ __forceinline__ void ir_end_inner(IrState& s, double rr_in) {
+// (with reliable updates the next outer step keeps the direction p, rescaled)
+__device__ __forceinline__ void ir_end_inner(IrState& s, double rr_in, int dir_ok) {
   s.upd = s.k_in > 0 ? 1.0 / s.scale : 0.0;
   double rho = (s.bb > 0.0 && rr_in >= 0.0) ? sqrt(rr_in / s.bb) : 1.0;
   if (!(rho <= 1.0)) rho = 1.0;
   if (rho < 0x1p-60) rho = 0x1p-60;
-  s.scale = ldexp(s.scale, -ilogb(rho));
+  const double ns = ldexp(s.scale, -ilogb(rho));
+  s.rescale = ns / s.scale;
+  s.scale = ns;
+  s.dir_ok = dir_ok && s.k_in > 0;
   s.mode = MODE_RESID;
 }
 
 __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd, IrState* st,
-                                                 const IrPart* __restrict__ part, int* active) {
+                                                 const IrPart* __restrict__ part, int* active, Lists L) {
   __shared__ double red[4][3];
   __shared__ CrAcc redc[4];
+  __shared__ int flag, slot;
   const int b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps of this round are done
+    L.cnt[WL_AP] = 0;
+    L.cnt[WL_RES] = 0;
+  }
   const int mode = st[b].mode;
   if (mode == MODE_DONE) return;
   const SolveDev S = sd[b];
@@ -231,59 +237,77 @@ __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  g0 = g1 = 0.0;
-  for (int q = 0; q < (int)(blockDim.x >> 6); q++) {
-    g0 += red[q][0];
-    g1 += red[q][1];
-  }
-  if (mode == MODE_ITER) {
-    const double gam = g0;
-    if (!(gam > 0.0) || !__builtin_isfinite(gam)) ir_end_inner(s, s.k_in > 0 ? s.rho : s.bb);
-    else s.alpha = (double)(float)(s.rho / gam);
+  if (threadIdx.x == 0) {
+    g0 = g1 = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) {
+      g0 += red[q][0];
+      g1 += red[q][1];
+    }
+    if (mode == MODE_ITER) {
+      const double gam = g0;
+      if (!(gam > 0.0) || !__builtin_isfinite(gam)) ir_end_inner(s, s.k_in > 0 ? s.rho : s.bb, 0);
+      else s.alpha = (double)(float)(s.rho / gam);
+    } else {
+      // outer pass finished
+      double rr, ff = s.ff;
+      if (!cr_finalize(arr, &rr)) rr = arr.s + arr.lo;
+      if (s.first) {
+        if (!cr_finalize(aff, &ff)) ff = aff.s + aff.lo;
+        s.ff = ff;
+        s.thr = s.tol2 * ff;
+        s.init_rr = rr;
+        s.first = 0;
+      }
+      if (s.upd != 0.0) s.cur = 1 - s.cur;
+      s.upd = 0.0;
+      s.rr = rr;
+      if (!__builtin_isfinite(rr)) ir_done(s, RBWS_SOLVE_NAN, active);
+      else if (rr <= s.thr) ir_done(s, RBWS_SOLVE_CONVERGED, active);
+      else if (s.outer >= s.max_outer) ir_done(s, RBWS_SOLVE_MAXITER, active);
+      else {
+        const double rho_new = s.prec ? g1 : g0;
+        s.outer += 1;
+        s.mode = MODE_ITER;
+        s.k_in = 0;
+        s.skip2 = 1;
+        s.bb = g0;
+        s.thr_in = s.eta2 * g0;
+        if (s.reliable && s.dir_ok && s.rho > 0.0) {
+          // continue CG with the true residual: p <- s + beta p, p rescaled by s.rescale
+          s.beta = (double)(float)(rho_new / (s.rescale * s.rho));
+          s.restart = 0;
+        } else {
+          s.restart = 1;
+        }
+        s.rho = rho_new;
+      }
+    }
     st[b] = s;
-    return;
+    flag = s.mode == MODE_ITER && !s.skip2;
   }
-  // outer pass finished
-  double rr, ff = s.ff;
-  if (!cr_finalize(arr, &rr)) rr = arr.s + arr.lo;
-  if (s.first) {
-    if (!cr_finalize(aff, &ff)) ff = aff.s + aff.lo;
-    s.ff = ff;
-    s.thr = s.tol2 * ff;
-    s.init_rr = rr;
-    s.first = 0;
-  }
-  if (s.upd != 0.0) s.cur = 1 - s.cur;
-  s.upd = 0.0;
-  s.rr = rr;
-  if (!__builtin_isfinite(rr)) ir_done(s, RBWS_SOLVE_NAN, active);
-  else if (rr <= s.thr) ir_done(s, RBWS_SOLVE_CONVERGED, active);
-  else if (s.outer >= s.max_outer) ir_done(s, RBWS_SOLVE_MAXITER, active);
-  else {
-    s.outer += 1;
-    s.mode = MODE_ITER;
-    s.k_in = 0;
-    s.restart = 1;
-    s.skip2 = 1;
-    s.bb = g0;
-    s.thr_in = s.eta2 * g0;
-    s.rho = s.prec ? g1 : g0;
-  }
-  st[b] = s;
+  __syncthreads();
+  if (flag) list_push(L.up, L.cnt + WL_UP, S.item0, S.ntiles, &slot);
 }
 
 __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd, IrState* st,
-                                                 const IrPart* __restrict__ part) {
+                                                 const IrPart* __restrict__ part, Lists L) {
   __shared__ double red[4][2];
+  __shared__ int flag, slot;
   const int b = blockIdx.x;
-  if (st[b].mode != MODE_ITER) return;
+  if (b == 0 && threadIdx.x == 0) L.cnt[WL_UP] = 0;  // the up sweep of this round is done
+  const int mode = st[b].mode;
+  if (mode == MODE_DONE) return;
+  const SolveDev S = sd[b];
+  if (mode == MODE_RESID) {
+    list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &slot);
+    return;
+  }
   IrState s = st[b];
   if (s.skip2) {
     if (threadIdx.x == 0) st[b].skip2 = 0;
+    list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &slot);
     return;
   }
-  const SolveDev S = sd[b];
   double g0 = 0.0, g1 = 0.0;
   for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) {
     g0 += part[S.item0 + t].g[0];
@@ -299,24 +323,41 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
     red[w][1] = g1;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  g0 = g1 = 0.0;
-  for (int q = 0; q < (int)(blockDim.x >> 6); q++) {
-    g0 += red[q][0];
-    g1 += red[q][1];
+  if (threadIdx.x == 0) {
+    g0 = g1 = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) {
+      g0 += red[q][0];
+      g1 += red[q][1];
+    }
+    const double rr = g0, rs = s.prec ? g1 : g0;
+    s.k_in += 1;
+    s.k_total += 1;
+    if (!__builtin_isfinite(rr) || rr <= s.thr_in || s.k_in >= s.inner_max) {
+      ir_end_inner(s, rr, __builtin_isfinite(rr) ? 1 : 0);
+    } else {
+      s.beta = (double)(float)(rs / s.rho);
+      s.rho = rs;
+      s.restart = 0;
+    }
+    st[b] = s;
+    flag = s.mode;
   }
-  const double rr = g0, rs = s.prec ? g1 : g0;
-  s.k_in += 1;
-  s.k_total += 1;
-  if (!__builtin_isfinite(rr) || rr <= s.thr_in || s.k_in >= s.inner_max) {
-    ir_end_inner(s, rr);
-  } else {
-    s.beta = (double)(float)(rs / s.rho);
-    s.rho = rs;
-    s.restart = 0;
-  }
-  st[b] = s;
+  __syncthreads();
+  if (flag == MODE_ITER) list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &slot);
+  else list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &slot);
 }
+
+// bit 0: A.p sweep with register-cached coefficients; bit 1: the same for the
+// update sweep.  RBWS_SWEEP32 overrides the default (for tuning runs).
+static int g_sweep32 = -1;
+int sweep32_variant() {
+  if (g_sweep32 < 0) {
+    const char* e = std::getenv("RBWS_SWEEP32");
+    g_sweep32 = e ? std::atoi(e) & 3 : 1;
+  }
+  return g_sweep32;
+}
+void set_sweep32_variant(int v) { g_sweep32 = v & 3; }
 
 void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) {
   RBWS_HIP(hipSetDevice(B.device));
@@ -337,6 +378,8 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     c.inner_max = o.inner_max;
     c.max_outer = o.max_outer;
     c.prec = o.prec;
+    c.reliable = o.reliable;
+    c.rescale = 1.0;
   }
   IrState* st = (IrState*)B.state.get(sizeof(IrState) * ns, B.device);
   RBWS_HIP(hipMemcpyAsync(st, init.data(), sizeof(IrState) * ns, hipMemcpyHostToDevice, s));
@@ -356,21 +399,42 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   const double* k64 = (const double*)B.kap64.ptr;
   const float* k32 = (const float*)B.kap32.ptr;
   const int ktab = (B.kap_max + 3) & ~3;
-  const size_t lds_outer = (sizeof(double) + sizeof(float)) * ktab;
+  const size_t lds_outer = sizeof(double) * (ktab + (ktab + 1) / 2 + 2 * QPLANE);
+  auto outer = B.vec ? k_ir_outer<true> : k_ir_outer<false>;
   const size_t lds_fast = sizeof(float) * (ktab + 2 * QPLANE);
-  const int per = B.per, ni = B.nitems;
-  const unsigned grid = grid_of(B);
-  auto ap = B.vec ? k_fast32<true, FOP_AP> : k_fast32<false, FOP_AP>;
-  auto up = B.vec ? k_fast32<true, FOP_UP2> : k_fast32<false, FOP_UP2>;
+  const int ni = B.nitems;
+  // sweep variants: coefficients cached in registers or looked up per plane
+  const int var = sweep32_variant();
+  auto ap = (var & 1) ? (B.vec ? k_fast32<true, FOP_AP, true> : k_fast32<false, FOP_AP, true>)
+                      : (B.vec ? k_fast32<true, FOP_AP, false> : k_fast32<false, FOP_AP, false>);
+  auto up = (var & 2) ? (B.vec ? k_fast32<true, FOP_UP2, true> : k_fast32<false, FOP_UP2, true>)
+                      : (B.vec ? k_fast32<true, FOP_UP2, false> : k_fast32<false, FOP_UP2, false>);
+  const unsigned g_ap = persistent_grid((const void*)ap, lds_fast, ni, B.device);
+  const unsigned g_up = persistent_grid((const void*)up, lds_fast, ni, B.device);
+  const unsigned g_res = persistent_grid((const void*)outer, lds_outer, ni, B.device);
+  const Lists L = lists_init(B, s);
   const int check = o.check_every > 0 ? o.check_every : 8;
   const long long max_rounds = (long long)(o.inner_max + 2) * (o.max_outer + 1) + 16;
+  KernelTimer& kt = ktimer();
   for (long long round = 0; round < max_rounds; round++) {
-    hipLaunchKernelGGL(ap, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, k32, d, r, p, p1, part, ktab);
-    hipLaunchKernelGGL(k_ir_outer, dim3(grid), dim3(256), lds_outer, s, items, per, ni, sd, pd, st, k64, k32, u0,
-                       u1, d, r, part, ktab);
-    hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, active);
-    hipLaunchKernelGGL(up, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, k32, d, r, p, p1, part, ktab);
-    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part);
+    kt.begin(s, KK_AP);
+    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, s, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, k32, d,
+                       r, p, p1, part, ktab);
+    kt.end(s);
+    kt.begin(s, KK_RESID);
+    hipLaunchKernelGGL(outer, dim3(g_res), dim3(256), lds_outer, s, items, L.res, L.cnt + WL_RES, ni, sd, pd, st,
+                       k64, k32, u0, u1, d, r, part, ktab);
+    kt.end(s);
+    kt.begin(s, KK_FIN1);
+    hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, active, L);
+    kt.end(s);
+    kt.begin(s, KK_UP2);
+    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, s, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, k32, d,
+                       r, p, p1, part, ktab);
+    kt.end(s);
+    kt.begin(s, KK_FIN2);
+    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, L);
+    kt.end(s);
     RBWS_HIP(hipGetLastError());
     if ((round + 1) % check == 0) {
       RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));

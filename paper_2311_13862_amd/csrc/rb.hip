@@ -27,6 +27,20 @@ namespace rbws {
 constexpr int kMaxN = 64;
 constexpr int kRedoCap = 1 << 20;
 
+// exact-path fallbacks of this translation unit: [0] pair dots, [1] per-entry
+// redo (Gram-Schmidt, lift), [2] reduced Cholesky and triangular solves
+__device__ unsigned long long g_fallback_rb[3];
+
+unsigned long long fallbacks_rb(int which, bool reset) {
+  unsigned long long v[3] = {0, 0, 0};
+  RBWS_HIP(hipMemcpyFromSymbol(v, HIP_SYMBOL(g_fallback_rb), sizeof v));
+  if (reset) {
+    const unsigned long long z[3] = {0, 0, 0};
+    RBWS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_fallback_rb), z, sizeof z));
+  }
+  return v[which];
+}
+
 // ---------------------------------------------------------------------------
 // dots of pointer pairs: out[v] = xs[v] . ys[v], all of length len
 // ---------------------------------------------------------------------------
@@ -69,6 +83,7 @@ __global__ __launch_bounds__(256) void k_pdot_fin(const double* const* xs, const
     if (threadIdx.x == 0) out[v] = sh.val;
     return;
   }
+  if (threadIdx.x == 0) atomicAdd(&g_fallback_rb[0], 1ull);
   __syncthreads();
   xa_clear(&sh.xa);
   __syncthreads();
@@ -111,6 +126,7 @@ struct Redo {
 };
 
 __device__ __forceinline__ void redo_push(Redo* r, long long e) {
+  atomicAdd(&g_fallback_rb[1], 1ull);
   int slot = atomicAdd(&r->count, 1);
   if (slot < kRedoCap) r->idx[slot] = e;
   else r->overflow = 1;
@@ -190,6 +206,7 @@ __device__ __forceinline__ double wave_sum(CholShared& sh, CrAcc a, int force_ex
   }
   __syncthreads();
   if (!sh.ok) {
+    if (threadIdx.x == 0) atomicAdd(&g_fallback_rb[2], 1ull);
     __syncthreads();
     xa_clear(&sh.xa);
     __syncthreads();
@@ -245,6 +262,7 @@ __global__ __launch_bounds__(64) void k_rb_coeffs(const RbDev* __restrict__ rbd,
     unsigned long long m = __ballot(amb);
     while (m) {  // exact path for the rare ambiguous entries, one at a time
       const int i = __ffsll((long long)m) - 1;
+      if (lane == 0) atomicAdd(&g_fallback_rb[2], 1ull);
       m &= m - 1;
       __syncthreads();
       xa_clear(&sh.xa);
@@ -444,8 +462,10 @@ int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int c
   int* bad = (int*)badb.get(sizeof(int), B.device);
   RBWS_HIP(hipMemcpyAsync(d, h.data(), sizeof(RbDev) * ns, hipMemcpyHostToDevice, s));
   RBWS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  ktimer().begin(s, KK_COEF);
   hipLaunchKernelGGL(k_rb_coeffs, dim3(ns), dim3(64), 0, s, d, (const int*)nullptr,
                      (const double*)B.theta.ptr, c, cstride, bad, force_exact);
+  ktimer().end(s);
   RBWS_HIP(hipGetLastError());
   int hb = 0;
   RBWS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -503,8 +523,10 @@ void rb_lift_mfma(Batch& B, const Basis* bs, const double* c, int cstride, doubl
   long long* off = offsets_dev(B, s);
   const long long nd = bs->ndof;
   const unsigned grid = (unsigned)((nd + 63) / 64);
+  ktimer().begin(s, KK_LIFT);
   hipLaunchKernelGGL(k_lift_mfma, dim3(grid), dim3(256), 0, s, (const double*)bs->V.ptr, bs->N, nd,
                      (const int*)nullptr, B.nsolve, off, c, cstride, u);
+  ktimer().end(s);
   RBWS_HIP(hipGetLastError());
 }
 

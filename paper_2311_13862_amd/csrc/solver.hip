@@ -1,32 +1,38 @@
 // solver.hip -- batched FP64 PCG on gfx950 (the paper's Alg. 1, P in {I, Jacobi}).
 //
 // One "round" advances every unfinished solve of the batch by one CG
-// iteration, in five launches over all (solve, tile) work items:
-//   pup  : p = s + beta p          (s = P(r); p = s after a (re)start)
-//   ap   : gamma = p^T A p         (ITER solves)      | r = f - A x, ||r||^2,
-//                                                      | r^T s, ||f||^2 (RESID solves)
+// iteration, in five launches:
+//   ap   : p = s + beta p (s = P(r); p = s after a (re)start) fused with
+//          gamma = p^T A p, over the tiles of ITER solves
+//   res  : r = f - A x, ||r||^2, r^T s, ||f||^2, over the tiles of RESID solves
 //   fin1 : per solve: alpha = rho / gamma, or the convergence decision of a
 //          residual evaluation (initial residual or true-residual confirmation)
 //   up2  : x += alpha p, r -= alpha A p (A p recomputed), ||r||^2, r^T s
 //   fin2 : per solve: convergence test on the recursive residual, beta
-// The matrix is never stored: face coefficients come from a per-solve class
-// table in LDS (see problem.cpp), so a stencil application reads one vector.
-// Every inner product is correctly rounded (crdot.hpp); together with the
-// fixed evaluation order of the stencil and of every vector update this makes
-// each solve's trajectory independent of tiling and batch composition.
+// The sweeps run a persistent grid over work lists that the finalisers fill
+// (solver.hpp, Lists).  The matrix is never stored: face coefficients come
+// from a per-solve class table in LDS (see problem.cpp), so a stencil
+// application reads one vector.  Every inner product is correctly rounded
+// (crdot.hpp); together with the fixed evaluation order of the stencil and of
+// every vector update this makes each solve's trajectory independent of
+// tiling, scheduling and batch composition.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "fast.hpp"
 
 namespace rbws {
 
-enum { OP_PUP = 0, OP_AP = 1, OP_UP2 = 2, OP_RNORM = 3 };
+enum { OP_AP = 1, OP_RNORM = 3 };
 enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3, DOT_RESID = 4 };
 constexpr int kSlots = 3;  // partial accumulators per work item
+
+// exact-path fallbacks taken by this translation unit's kernels (diagnostics)
+__device__ unsigned long long g_fallback_solver;
 
 void* DevBuf::get(size_t need, int dev) {
   if (need == 0) need = 1;
@@ -57,6 +63,54 @@ Batch::~Batch() {
   if (active_host) (void)hipHostFree(active_host);
 }
 
+Lists lists_init(Batch& B, hipStream_t s) {
+  const int ni = B.nitems;
+  const size_t head = 64;  // counters, padded
+  int* base = (int*)B.lists.get(sizeof(int) * (head + 3 * (size_t)ni), B.device);
+  B.lists_h.assign(head + ni, 0);
+  B.lists_h[WL_RES] = ni;
+  for (int t = 0; t < ni; t++) B.lists_h[head + t] = t;
+  RBWS_HIP(hipMemcpyAsync(base, B.lists_h.data(), sizeof(int) * B.lists_h.size(), hipMemcpyHostToDevice, s));
+  return Lists{base, base + head, base + head + ni, base + head + 2 * (size_t)ni};
+}
+
+static int g_grid_mode = -1;
+int grid_mode() {
+  if (g_grid_mode < 0) {
+    const char* e = std::getenv("RBWS_GRID");
+    g_grid_mode = e ? (std::atoi(e) & 1) : 0;
+  }
+  return g_grid_mode;
+}
+void set_grid_mode(int v) { g_grid_mode = v & 1; }
+
+unsigned persistent_grid(const void* fn, size_t lds, int nitems, int device) {
+  const unsigned need = 8u * (unsigned)((std::max(nitems, 1) + 7) / 8);
+  if (grid_mode() == 0) return need;
+  struct Key {
+    const void* fn;
+    size_t lds;
+    int dev;
+  };
+  struct Ent {
+    Key k;
+    unsigned blocks;
+  };
+  static thread_local std::vector<Ent> cache;
+  unsigned cap = 0;
+  for (const Ent& e : cache)
+    if (e.k.fn == fn && e.k.lds == lds && e.k.dev == device) cap = e.blocks;
+  if (cap == 0) {
+    int per_cu = 0, cus = 0;
+    RBWS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
+    RBWS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    cap = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
+    cap = std::max(8u, cap & ~7u);
+    cache.push_back(Ent{Key{fn, lds, device}, cap});
+  }
+  return std::min(cap, need);
+}
+
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ) {
   *TX = QX;
   *TY = QY;
@@ -64,6 +118,51 @@ void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ
   int tz = 64;
   while (tz > 4 && cols * ((n + tz - 1) / tz) < 4096) tz /= 2;
   *TZ = std::min(tz, n);
+}
+
+unsigned long long fallbacks_solver(bool reset) {
+  unsigned long long v = 0;
+  RBWS_HIP(hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_fallback_solver), sizeof v));
+  if (reset) {
+    const unsigned long long z = 0;
+    RBWS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_fallback_solver), &z, sizeof z));
+  }
+  return v;
+}
+
+KernelTimer& ktimer() {
+  static thread_local KernelTimer& t = *new KernelTimer();
+  return t;
+}
+
+void KernelTimer::begin(hipStream_t s, int k) {
+  if (!on) return;
+  while (pool.size() < used + 2) {
+    hipEvent_t e;
+    RBWS_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  kind.push_back(k);
+  RBWS_HIP(hipEventRecord(pool[used++], s));
+}
+
+void KernelTimer::end(hipStream_t s) {
+  if (!on) return;
+  RBWS_HIP(hipEventRecord(pool[used++], s));
+  if (used >= 4096) flush();
+}
+
+void KernelTimer::flush() {
+  if (used == 0) return;
+  RBWS_HIP(hipEventSynchronize(pool[used - 1]));
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float t = 0.f;
+    RBWS_HIP(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
+    ms[kind[i / 2]] += t;
+    count[kind[i / 2]] += 1;
+  }
+  used = 0;
+  kind.clear();
 }
 
 double wall_clock_khz(int device) {
@@ -109,7 +208,7 @@ __global__ void k_kappa(const SolveDev* __restrict__ sd, const ProbDev* __restri
 // These run a few times per solve; they read neighbours through the caches.
 // ---------------------------------------------------------------------------
 template <int OP>
-__global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items, int per, int nitems,
+__device__ __forceinline__ void k_sweep64_item(int item, const int2* __restrict__ items,
                                                  const SolveDev* __restrict__ sd,
                                                  const ProbDev* __restrict__ pd,
                                                  const CgState* __restrict__ st,
@@ -118,8 +217,7 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
                                                  CrAcc* __restrict__ part) {
   extern __shared__ double kl[];
   __shared__ CrAcc red[4];
-  const int item = item_of(blockIdx.x, per);
-  if (item >= nitems) return;
+  __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x, tile = it.y;
   if (OP == OP_AP && st[b].mode != MODE_RESID) return;
@@ -170,11 +268,23 @@ __global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items,
   }
 }
 
+template <int OP>
+__global__ __launch_bounds__(256) void k_sweep64(const int2* __restrict__ items, const int* __restrict__ list,
+                                                 const int* __restrict__ cnt, int nitems,
+                                                 const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                 const CgState* __restrict__ st, const double* __restrict__ kap,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 CrAcc* __restrict__ part) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step)
+    k_sweep64_item<OP>(list ? list[w] : w, items, sd, pd, st, kap, x, r, part);
+}
+
 // ---------------------------------------------------------------------------
 // the iteration sweeps of the FP64 path (fast.hpp)
 // ---------------------------------------------------------------------------
 template <bool VEC, int OP>
-__global__ __launch_bounds__(256) void k_fast64(const int2* __restrict__ items, int per, int nitems,
+__device__ __forceinline__ void k_fast64_item(int item, const int2* __restrict__ items,
                                                 const SolveDev* __restrict__ sd,
                                                 const ProbDev* __restrict__ pd,
                                                 const CgState* __restrict__ st,
@@ -184,8 +294,7 @@ __global__ __launch_bounds__(256) void k_fast64(const int2* __restrict__ items, 
                                                 int ktab) {
   extern __shared__ double smem[];
   __shared__ CrAcc red[4];
-  const int item = item_of(blockIdx.x, per);
-  if (item >= nitems) return;
+  __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
   const CgState& s = st[b];
@@ -216,6 +325,19 @@ __global__ __launch_bounds__(256) void k_fast64(const int2* __restrict__ items, 
   }
 }
 
+template <bool VEC, int OP>
+__global__ __launch_bounds__(256) void k_fast64(const int2* __restrict__ items, const int* __restrict__ list,
+                                                const int* __restrict__ cnt, int nitems,
+                                                const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                const CgState* __restrict__ st, const double* __restrict__ kap,
+                                                double* __restrict__ x, double* __restrict__ r,
+                                                double* __restrict__ p0, double* __restrict__ p1,
+                                                CrAcc* __restrict__ part, int ktab) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step)
+    k_fast64_item<VEC, OP>(list ? list[w] : w, items, sd, pd, st, kap, x, r, p0, p1, part, ktab);
+}
+
 // ---------------------------------------------------------------------------
 // per-solve finalisation (one workgroup per solve)
 // ---------------------------------------------------------------------------
@@ -224,7 +346,7 @@ struct FinShared {
   XAcc xa;
   uint32_t dig[XA_WORDS];
   double val;
-  int ok;
+  int ok, flag, slot;
 };
 
 // exact recomputation of one inner product of solve b (workgroup-cooperative)
@@ -286,6 +408,7 @@ __device__ double solve_dot(FinShared& sh, int slot, int which, const ProbDev& P
   const double v = sh.val;
   __syncthreads();
   if (ok) return v;
+  if (threadIdx.x == 0) atomicAdd(&g_fallback_solver, 1ull);
   return exact_solve_dot(sh, which, P, S, kap, x, r, p);
 }
 
@@ -301,9 +424,13 @@ __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
                                               const double* __restrict__ kap, const double* x,
                                               const double* r, const double* p, const double* p1,
                                               const CrAcc* __restrict__ part, int* active,
-                                              int force_exact) {
+                                              int force_exact, Lists L) {
   __shared__ FinShared sh;
   const int b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps of this round are done
+    L.cnt[WL_AP] = 0;
+    L.cnt[WL_RES] = 0;
+  }
   const int mode = st[b].mode;
   if (mode == MODE_DONE) return;
   const SolveDev S = sd[b];
@@ -317,7 +444,10 @@ __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
       else if (!(g > 0.0)) mark_done(s, RBWS_SOLVE_BREAKDOWN, active);
       else s.alpha = s.rho / g;
       st[b] = s;
+      sh.flag = s.mode == MODE_ITER && !s.skip2;
     }
+    __syncthreads();
+    if (sh.flag) list_push(L.up, L.cnt + WL_UP, S.item0, S.ntiles, &sh.slot);
     return;
   }
   // residual evaluation: the initial residual or a true-residual confirmation
@@ -351,17 +481,23 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
                                               const double* __restrict__ kap, const double* x,
                                               const double* r, const double* p,
                                               const CrAcc* __restrict__ part, int* active,
-                                              int force_exact) {
+                                              int force_exact, Lists L) {
   __shared__ FinShared sh;
   const int b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) L.cnt[WL_UP] = 0;  // the up sweep of this round is done
   const int mode = st[b].mode;
-  if (mode != MODE_ITER) return;
+  if (mode == MODE_DONE) return;
+  const SolveDev S = sd[b];
+  if (mode == MODE_RESID) {
+    list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &sh.slot);
+    return;
+  }
   CgState s = st[b];
   if (s.skip2) {
     if (threadIdx.x == 0) st[b].skip2 = 0;
+    list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &sh.slot);
     return;
   }
-  const SolveDev S = sd[b];
   const ProbDev& P = pd[S.prob];
   const double rr = solve_dot(sh, 0, DOT_RR, P, S, kap, x, r, p, part, force_exact);
   const double rs = s.prec ? solve_dot(sh, 1, DOT_RS, P, S, kap, x, r, p, part, force_exact) : rr;
@@ -379,7 +515,12 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
       s.restart = 0;
     }
     st[b] = s;
+    sh.flag = s.mode;
   }
+  __syncthreads();
+  const int nm = sh.flag;
+  if (nm == MODE_ITER) list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &sh.slot);
+  else if (nm == MODE_RESID) list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &sh.slot);
 }
 
 __global__ __launch_bounds__(256) void k_fin_rnorm(const SolveDev* __restrict__ sd,
@@ -404,15 +545,14 @@ __global__ __launch_bounds__(256) void k_fin_rnorm(const SolveDev* __restrict__ 
 // y = A x (FP64 or FP32) for every solve of the batch
 // ---------------------------------------------------------------------------
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items, int per, int nitems,
+__device__ __forceinline__ void k_spmv_item(int item, const int2* __restrict__ items,
                                               const SolveDev* __restrict__ sd,
                                               const ProbDev* __restrict__ pd,
                                               const T* __restrict__ kap, const T* __restrict__ x,
                                               T* __restrict__ y, int ktab) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int item = item_of(blockIdx.x, per);
-  if (item >= nitems) return;
+  __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const SolveDev S = sd[it.x];
   const ProbDev& P = pd[S.prob];
@@ -424,6 +564,15 @@ __global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items, in
   DotAcc<T> a0, a1;
   fast_body<T, VEC, FOP_SPMV>(G, P.g, smem, smem + ktab, nullptr, nullptr, nullptr,
                               const_cast<T*>(x) + S.off, y + S.off, T(0), T(0), 0, 0, 0, a0, a1);
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_spmv(const int2* __restrict__ items, int nitems,
+                                              const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                              const T* __restrict__ kap, const T* __restrict__ x,
+                                              T* __restrict__ y, int ktab) {
+  const WorkRange R = work_range(nitems);
+  for (int w = R.w; w < R.w1; w += R.step) k_spmv_item<T, VEC>(w, items, sd, pd, kap, x, y, ktab);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,6 +612,7 @@ __global__ __launch_bounds__(256) void k_dot_fin(const double* __restrict__ x,
     if (threadIdx.x == 0) out[v] = sh.val;
     return;
   }
+  if (threadIdx.x == 0) atomicAdd(&g_fallback_solver, 1ull);
   __syncthreads();
   xa_clear(&sh.xa);
   __syncthreads();
@@ -544,7 +694,6 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
   B.total = off;
   B.kap_total = koff;
   B.nitems = (int)B.items_h.size();
-  B.per = (B.nitems + 7) / 8;
   B.vec = true;
   for (const Problem* P : probs) B.vec = B.vec && (P->n % 4 == 0);
   RBWS_HIP(hipMemcpyAsync(B.pd.get(sizeof(ProbDev) * B.nprob, B.device), B.pd_h.data(),
@@ -607,18 +756,36 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
   const int check = o.check_every > 0 ? o.check_every : 4;
   const long long max_rounds = 2LL * o.maxit + 16;
   double* p1 = (double*)B.p2.get(sizeof(double) * B.total, B.device);
-  const int per = B.per, ni = B.nitems;
-  const unsigned grid = grid_of(B);
+  const int ni = B.nitems;
   const int ktab = (B.kap_max + 3) & ~3;
   const size_t lds_fast = sizeof(double) * (ktab + 2 * QPLANE);
   auto ap = B.vec ? k_fast64<true, FOP_AP> : k_fast64<false, FOP_AP>;
   auto up = B.vec ? k_fast64<true, FOP_UP2> : k_fast64<false, FOP_UP2>;
+  auto res = k_sweep64<OP_AP>;
+  const unsigned g_ap = persistent_grid((const void*)ap, lds_fast, ni, B.device);
+  const unsigned g_up = persistent_grid((const void*)up, lds_fast, ni, B.device);
+  const unsigned g_res = persistent_grid((const void*)res, lds, ni, B.device);
+  const Lists L = lists_init(B, s);
+  KernelTimer& kt = ktimer();
   for (long long round = 0; round < max_rounds; round++) {
-    hipLaunchKernelGGL(ap, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, kap, x, r, p, p1, part, ktab);
-    hipLaunchKernelGGL(k_sweep64<OP_AP>, dim3(grid), dim3(256), lds, s, items, per, ni, sd, pd, st, kap, x, r, part);
-    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, p1, part, active, fe);
-    hipLaunchKernelGGL(up, dim3(grid), dim3(256), lds_fast, s, items, per, ni, sd, pd, st, kap, x, r, p, p1, part, ktab);
-    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe);
+    kt.begin(s, KK_AP);
+    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, s, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, kap,
+                       x, r, p, p1, part, ktab);
+    kt.end(s);
+    kt.begin(s, KK_RESID);
+    hipLaunchKernelGGL(res, dim3(g_res), dim3(256), lds, s, items, L.res, L.cnt + WL_RES, ni, sd, pd, st, kap, x,
+                       r, part);
+    kt.end(s);
+    kt.begin(s, KK_FIN1);
+    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, p1, part, active, fe, L);
+    kt.end(s);
+    kt.begin(s, KK_UP2);
+    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, s, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, kap,
+                       x, r, p, p1, part, ktab);
+    kt.end(s);
+    kt.begin(s, KK_FIN2);
+    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe, L);
+    kt.end(s);
     RBWS_HIP(hipGetLastError());
     if ((round + 1) % check == 0) {
       RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -638,8 +805,10 @@ void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff,
   CgState* st = (CgState*)B.state.get(sizeof(CgState) * ns, B.device);
   RBWS_SCRATCH(outb);
   double* o = (double*)outb.get(sizeof(double) * 3 * ns, B.device);
-  hipLaunchKernelGGL(k_sweep64<OP_RNORM>, dim3(grid_of(B)), dim3(256), sizeof(double) * B.kap_max, s,
-                     (const int2*)B.items.ptr, B.per, B.nitems, (const SolveDev*)B.sd.ptr,
+  const size_t lds = sizeof(double) * B.kap_max;
+  const unsigned grid = persistent_grid((const void*)k_sweep64<OP_RNORM>, lds, B.nitems, B.device);
+  hipLaunchKernelGGL(k_sweep64<OP_RNORM>, dim3(grid), dim3(256), lds, s, (const int2*)B.items.ptr,
+                     (const int*)nullptr, (const int*)nullptr, B.nitems, (const SolveDev*)B.sd.ptr,
                      (const ProbDev*)B.pd.ptr, st, (const double*)B.kap64.ptr, (double*)x, nullptr, part);
   hipLaunchKernelGGL(k_fin_rnorm, dim3(ns), dim3(256), 0, s, (const SolveDev*)B.sd.ptr,
                      (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr, x, part, o, force_exact);
@@ -668,15 +837,19 @@ void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s) {
   const int2* it = (const int2*)B.items.ptr;
   const SolveDev* sd = (const SolveDev*)B.sd.ptr;
   const ProbDev* pd = (const ProbDev*)B.pd.ptr;
+  ktimer().begin(s, KK_SPMV);
   if (fp32) {
     auto k = B.vec ? k_spmv<float, true> : k_spmv<float, false>;
-    hipLaunchKernelGGL(k, dim3(grid_of(B)), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), s, it, B.per,
+    const size_t lds = sizeof(float) * (ktab + 2 * QPLANE);
+    hipLaunchKernelGGL(k, dim3(persistent_grid((const void*)k, lds, B.nitems, B.device)), dim3(256), lds, s, it,
                        B.nitems, sd, pd, (const float*)B.kap32.ptr, (const float*)x, (float*)y, ktab);
   } else {
     auto k = B.vec ? k_spmv<double, true> : k_spmv<double, false>;
-    hipLaunchKernelGGL(k, dim3(grid_of(B)), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), s, it, B.per,
+    const size_t lds = sizeof(double) * (ktab + 2 * QPLANE);
+    hipLaunchKernelGGL(k, dim3(persistent_grid((const void*)k, lds, B.nitems, B.device)), dim3(256), lds, s, it,
                        B.nitems, sd, pd, (const double*)B.kap64.ptr, (const double*)x, (double*)y, ktab);
   }
+  ktimer().end(s);
   RBWS_HIP(hipGetLastError());
 }
 

@@ -30,6 +30,9 @@ struct IrState {
   double rho, alpha, beta, thr_in, bb;
   int outer, mode, first, status, cur, k_in, k_total, restart, skip2, inner_max, max_outer, prec;
   unsigned long long t_done;
+  double rescale;  // scale after / scale before the last outer correction (a power of two)
+  int reliable;    // keep the search direction across outer corrections
+  int dir_ok;      // the last inner solve ended with a usable direction
 };
 
 // device arrays of a batch (grow-only allocations, reused across calls)
@@ -48,10 +51,23 @@ struct DevBuf {
 
 void fill64(double* x, long long n, double v, hipStream_t s);
 
+// Work lists of the iteration rounds.  Each round runs three sweeps: the A p
+// sweep over the tiles of solves in CG iterations (ap), the residual sweep of
+// solves whose residual is (re)evaluated (res), and the update sweep (up).  The
+// per-solve finalisers append each unfinished solve's tiles to the list of the
+// sweep it needs next, so a sweep touches active tiles only and the work of a
+// shrinking batch stays spread over all XCDs.  cnt[WL_*] holds the lengths.
+enum { WL_AP = 0, WL_RES = 1, WL_UP = 2 };
+struct Lists {
+  int* cnt;
+  int* res;
+  int* ap;
+  int* up;
+};
+
 struct Batch {
   int device = 0;
   int nsolve = 0, nprob = 0, nitems = 0;
-  int per = 0;          // work items per XCD slot (grid = 8 * per)
   bool vec = true;      // every grid size is a multiple of 4 (vector loads)
   long long total = 0;      // sum of ndof over solves
   long long kap_total = 0;  // sum of table sizes
@@ -60,7 +76,8 @@ struct Batch {
   std::vector<ProbDev> pd_h;
   std::vector<SolveDev> sd_h;
   std::vector<int2> items_h;
-  DevBuf pd, sd, items, kap64, kap32, theta, ncorner, thidx, state, part, active;
+  DevBuf pd, sd, items, kap64, kap32, theta, ncorner, thidx, state, part, active, lists;
+  std::vector<int> lists_h;  // initial list image: counts, then res = all items
   // FP64 CG vectors
   DevBuf x, r, p, p2;
   // FP32 inner vectors (refinement)
@@ -72,7 +89,19 @@ struct Batch {
 // tiles: 32 x 32 grid columns (256 threads, 4 points each) by TZ planes; TZ
 // is the largest power of two in [4, 64] that still gives >= 4096 work items
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ);
-inline unsigned grid_of(const Batch& B) { return 8u * (unsigned)B.per; }
+
+// Lists with every item on the residual list and the others empty (stream-ordered)
+Lists lists_init(Batch& B, hipStream_t s);
+
+// Grid for a sweep kernel over up to `nitems` work items, a multiple of 8: one
+// workgroup per item, or (grid_mode 1) as many 256-thread workgroups as fit on
+// the device at once (occupancy with `lds` bytes of dynamic LDS), each looping
+// over several items.
+unsigned persistent_grid(const void* fn, size_t lds, int nitems, int device);
+// 0: sweep grids have one workgroup per work item (the hardware dispatcher
+// balances the load); 1: persistent grids.  RBWS_GRID overrides the default.
+int grid_mode();
+void set_grid_mode(int v);
 
 // build the batch description: problems[prob_of[b]] for solve b; mu (nsolve x p) on host
 // theta_override (nsolve x Q of problem 0, host) replaces theta(mu) when given
@@ -99,7 +128,7 @@ void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s);
 // FP32-inner / FP64-outer refinement from the x already in B.x
 struct IrOpts {
   double tol, eta;
-  int prec, inner_max, max_outer, flags, check_every;
+  int prec, inner_max, max_outer, flags, check_every, reliable;
 };
 struct IrHost {
   int iters, outer, status, cur;
@@ -108,11 +137,33 @@ struct IrHost {
 };
 // On return the solution of solve b is in (cur ? B.r : B.x) at its offset.
 void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out);
+int sweep32_variant();
+void set_sweep32_variant(int v);
 
 // correctly rounded dots of `count` pairs of length len (device vectors)
 void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
                 int flags, hipStream_t s);
 
 double wall_clock_khz(int device);
+
+// Opt-in HIP-event timing of every launch of the solver's kernels, by kind.
+enum KernelKind { KK_AP = 0, KK_RESID = 1, KK_FIN1 = 2, KK_UP2 = 3, KK_FIN2 = 4, KK_SPMV = 5, KK_LIFT = 6,
+                  KK_COEF = 7, KK_COUNT = 8 };
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> kind;  // per pair of events
+  size_t used = 0;        // events in use
+  double ms[KK_COUNT] = {};
+  long long count[KK_COUNT] = {};
+  void begin(hipStream_t s, int k);
+  void end(hipStream_t s);
+  void flush();           // wait for the recorded events and accumulate
+};
+KernelTimer& ktimer();
+
+// exact-path fallback counters (diagnostics), per translation unit
+unsigned long long fallbacks_solver(bool reset);
+unsigned long long fallbacks_rb(int which, bool reset);
 
 }  // namespace rbws

@@ -24,6 +24,7 @@ FP64, FP32_IR = 0, 1
 PREC_NONE, PREC_JACOBI = 0, 1
 SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 LIFT_EXACT, LIFT_MFMA = 0, 1
+IR_RESTART, IR_RELIABLE = 0, 1
 FLAG_FORCE_EXACT_DOTS = 1
 
 
@@ -49,7 +50,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("init", C.c_int), ("lift", C.c_int),
                 ("eta_inner", C.c_double), ("max_outer", C.c_int), ("fallback", C.c_int),
-                ("flags", C.c_int), ("check_every", C.c_int)]
+                ("flags", C.c_int), ("check_every", C.c_int), ("ir_mode", C.c_int)]
 
 
 def _load():
@@ -267,3 +268,38 @@ class Basis:
         """u[b] = V c[b]; c (nmu, N) and u (nmu, ndof) float64 device tensors."""
         _check(_L.rbws_rb_lift(self.handle, C.c_void_p(c.data_ptr()), c.shape[0],
                                C.c_void_p(u.data_ptr()), mode, _stream(stream)))
+
+
+KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs")
+
+
+def profile(enable: bool, reset: bool = True):
+    """Kernel times so far (ms, launches per kind), then reset / switch timing."""
+    fn = getattr(_L, "rbws_profile")
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
+    ms = (C.c_double * 8)()
+    n = (C.c_longlong * 8)()
+    _check(fn(1 if enable else 0, ms, n, 1 if reset else 0))
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def exact_fallbacks(reset: bool = True):
+    """Exact-path recomputations since the last reset (solver, basis dots, per-entry, Cholesky)."""
+    fn = getattr(_L, "rbws_exact_fallbacks")
+    fn.restype = C.c_int
+    fn.argtypes = [C.POINTER(C.c_longlong), C.c_int]
+    c = (C.c_longlong * 4)()
+    _check(fn(c, 1 if reset else 0))
+    return {"solver": c[0], "pair_dots": c[1], "entries": c[2], "cholesky": c[3]}
+
+
+TUNE_SWEEP32 = 0
+TUNE_GRID = 1
+
+
+def set_tuning(key: int, value: int):
+    fn = getattr(_L, "rbws_set_tuning")
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_int, C.c_int]
+    _check(fn(key, value))

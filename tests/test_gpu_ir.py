@@ -32,7 +32,7 @@ def test_ir_matches_fp64_reference(rb, spec, prec):
     mu = W.sample_mu(spec, 0.01, 100.0, 6, 3)
     u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mu))]
     opts = rb.default_opts(precision=rb.FP32_IR, precond=prec, tol=1e-10, eta_inner=1e-4,
-                           max_iter=20000)
+                           max_iter=20000, ir_mode=rb.IR_RESTART)
     st = rb.solve([P], mu, opts, u_out=u)
     ref, rst = O.cg_batch(mu, prec=1, tol=1e-12, maxit=20000)
     assert all(r["status"] == 0 for r in rst)
@@ -46,6 +46,28 @@ def test_ir_matches_fp64_reference(rb, spec, prec):
         # the oracle's own refinement converges in a comparable number of outer steps
         _, so = O.ir(mu[b], prec=prec, tol=1e-10, eta=1e-4)
         assert abs(so["outer"] - st[b]["outer_iters"]) <= 2
+
+
+@pytest.mark.parametrize("eta", [1e-2, 1e-1])
+def test_reliable_update_matches_oracle(rb, eta):
+    # the oracle's reliable-update refinement: the same number of outer steps
+    # (+-1) and inner counts within 10%; FP32 rounding differs (the GPU applies
+    # Jacobi as a multiply by the FP32 reciprocal, the oracle divides)
+    spec = W.Problem(32, W.KIND_OCTANTS)
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 4, 1)
+    u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mu))]
+    st = rb.solve([P], mu, rb.default_opts(precision=rb.FP32_IR, tol=1e-10, eta_inner=eta,
+                                          ir_mode=rb.IR_RELIABLE, max_iter=3000), u_out=u)
+    for b, m in enumerate(mu):
+        uo, so = O.ir(m, tol=1e-10, eta=eta, reliable=True)
+        assert st[b]["status"] == so["status"] == 0
+        assert abs(st[b]["outer_iters"] - so["outer"]) <= 1
+        assert abs(st[b]["iters"] - so["iters"]) <= 3 + 0.1 * so["iters"]
+        f = O.rhs(m)
+        r = f - O.apply(m, u[b].cpu().numpy())
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(f)
 
 
 def test_ir_rb_start(rb):
