@@ -15,8 +15,9 @@ build is timed separately (t_off).  All inputs are synthetic and seeded.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Prints one JSON line.  `--counters` runs a short solve for rocprofv3 counter
-collection and prints nothing else.
+Prints one JSON line.  `--counters` runs the offline build and one step, then
+a plain 1 GiB copy, for rocprofv3 counter collection, and prints the
+algorithmic bytes of that step instead.
 """
 from __future__ import annotations
 
@@ -77,18 +78,6 @@ def main():
     mu_train = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.ntrain, W.SEED_TRAIN)
     mu = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.batch, W.SEED_TEST)
 
-    if args.counters:
-        # rocprofv3 counter run: the iteration sweeps on the same batch, a few rounds only
-        opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
-                                 eta_inner=args.eta, init=rbws.INIT_ZERO, max_iter=24, max_outer=1)
-        rbws.solve([P], mu, opts)
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB reference copy
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("counters run done; reference copy of 1 GiB read + 1 GiB write")
-        return
-
     log(f"offline: greedy N={args.N} from {args.ntrain} training parameters at {spec.n}^3")
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -100,6 +89,22 @@ def main():
     opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
                              eta_inner=args.eta, init=rbws.INIT_RB, lift=rbws.LIFT_MFMA,
                              ir_mode=rbws.IR_RELIABLE)
+    if args.counters:
+        # rocprofv3 counter run: one step as timed below, then a plain copy of known size
+        st = solve_step(rbws, P, basis, mu, opts)
+        it = np.array([s["iters"] for s in st])
+        ou = np.array([s["outer_iters"] for s in st])
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "copy_bytes_read": a.numel() * 8,
+                          "copy_bytes_written": b.numel() * 8,
+                          "up2_algorithmic_bytes": float(np.sum(it * 20 - ou * 4)) * P.ndof,
+                          "ap_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
+                          "sources_sha256": kernel_sources_hash()}), flush=True)
+        return
+
     for w in range(args.warmup):
         solve_step(rbws, P, basis, mu, opts)
         log(f"warmup step {w + 1} done")
@@ -120,6 +125,19 @@ def main():
     outer = np.array([s["outer_iters"] for s in stats])
     lat = np.array([s["t_done_ms"] for s in stats])
     relres = np.array([np.sqrt(s["final_rr"] / s["ff"]) for s in stats])
+
+    # copy bandwidth of the device (a plain 1 GiB + 1 GiB copy), for context
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
 
     # roofline of the dominant kernel, from the events recorded over the timed steps
     nd = P.ndof
@@ -197,13 +215,43 @@ def main():
         "t_off_s": round(t_off, 2),
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
         "kernel_ms": {k: round(v, 2) for k, v in ms.items()},
+        "copy_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": per_launch_bytes,
-                     "ms_per_launch": per_launch_ms},
+                     "traffic": traffic_per_launch(dom), "bytes_per_launch": per_launch_bytes,
+                     "ms_per_launch": per_launch_ms, "frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+KERNEL_SOURCES = ("fast.hpp", "ir.hip", "solver.hpp", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_octants128_traffic.txt")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_13862_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or
+    None when there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith(("#", " ", "|")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != kernel_sources_hash():
+        return None
+    v = kv.get(f"{kernel}_traffic_bytes_per_launch")
+    return float(v) if v else None
 
 
 def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s):
