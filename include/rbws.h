@@ -205,6 +205,83 @@ rbws_status rbws_rb_lift(const rbws_basis* b, const double* c, int nmu, double* 
 rbws_status rbws_basis_save(const rbws_basis* b, const char* path);
 rbws_status rbws_basis_load(rbws_problem* p, const char* path, rbws_basis** out);
 
+/* ---- learned start (an addition to the method; Sec. 1 cites neural-network
+ * initial guesses as related work) --------------------------------------------
+ * A multilayer perceptron maps the parameters to the reduced coefficients:
+ *   x_i = (log10 mu_i - in_m) / in_s             for i < log_cols,
+ *   x_i = (mu_i - (lin_lo + lin_hi)/2) / ((lin_hi - lin_lo)/2)   otherwise;
+ *   h_1 = gelu(W_1 x + b_1), ..., h_D = gelu(W_D h_{D-1} + b_D)  (D = depth),
+ *   y = W_o h_D + b_o,  gelu(z) = z Phi(z) (the erf form);
+ *   c_j(mu) = (out_mean_j + out_std_j y_j) * 10^(-out_pow * l(mu)),
+ *   l(mu) = mean of log10 mu_i over i < log_cols.
+ * out_pow = 1 suits problems with A(t mu) = t A(mu) and f fixed (c(t mu) =
+ * c(mu) / t); out_mean/out_std (default 0/1) standardise the targets.
+ * Matrix products run on the BF16 matrix cores (weights and activations
+ * rounded to nearest-even bfloat16, FP32 accumulation); master weights, Adam
+ * moments and gradients are FP32.  Training minimises the mean over batch and
+ * outputs of (y - y_target)^2 with Adam (bias-corrected, beta 0.9/0.999,
+ * eps 1e-8) and a cosine step-size schedule.
+ * Parameter vectors (host, float) are packed layer by layer: W_l (out x in,
+ * row-major) then b_l, for l = 1..D, then W_o, b_o. */
+typedef struct {
+  int p;            /* inputs: the problem's parameter count */
+  int nout;         /* outputs: the basis dimension, 1..64 */
+  int hidden;       /* width of the hidden layers, a multiple of 32, <= 1024 */
+  int depth;        /* hidden layers, 1..8 */
+  int log_cols;     /* leading inputs that are log-scaled, 0..p */
+  double in_m, in_s;        /* log scaling (in_s != 0) */
+  double lin_lo, lin_hi;    /* linear scaling of the remaining inputs (lin_hi > lin_lo) */
+  double out_pow;           /* output scale exponent (see above) */
+} rbws_mlp_desc;
+typedef struct {
+  int epochs;       /* passes over the pairs */
+  int batch;        /* minibatch size (a partial last minibatch of an epoch is dropped) */
+  double lr;        /* initial step size; cosine decay to lr_min over all steps */
+  double lr_min;
+  unsigned long long seed;  /* minibatch order (a seeded shuffle per epoch) */
+  int use_graph;    /* 1: each epoch is one captured HIP graph, replayed; 0: launches */
+} rbws_mlp_train_cfg;
+/* Create a network on `device`.  params: host, rbws_mlp_param_count values,
+ * or NULL for a seeded initialisation (W uniform in +-1/sqrt(fan_in), b = 0).
+ * Errors: EINVAL for an invalid description. */
+rbws_status rbws_mlp_create(const rbws_mlp_desc* d, int device, const float* params,
+                            unsigned long long seed, rbws_mlp** out);
+void rbws_mlp_destroy(rbws_mlp* m);
+rbws_status rbws_mlp_param_count(const rbws_mlp* m, long long* count);
+/* The description the network was created with (host output). */
+rbws_status rbws_mlp_info(const rbws_mlp* m, rbws_mlp_desc* d);
+/* Host copies of the FP32 master parameters; set also resets Adam. */
+rbws_status rbws_mlp_get_params(const rbws_mlp* m, float* params);
+rbws_status rbws_mlp_set_params(rbws_mlp* m, const float* params);
+/* Output scaling: mean/std host arrays of nout values (NULL = 0 and 1). */
+rbws_status rbws_mlp_set_output_scaling(rbws_mlp* m, const double* mean, const double* stdev);
+rbws_status rbws_mlp_get_output_scaling(const rbws_mlp* m, double* mean, double* stdev);
+/* Set out_mean/out_std to the mean and standard deviation of the scaled
+ * targets c * 10^(out_pow l(mu)) of the given pairs (computed on the GPU). */
+rbws_status rbws_mlp_fit_output_scaling(rbws_mlp* m, const double* mu, const double* c, int npairs);
+/* c (host, nmu x nout, double) = the network's prediction for mu (host, nmu x p). */
+rbws_status rbws_mlp_predict(const rbws_mlp* m, const double* mu, int nmu, double* c);
+/* Raw outputs y (host, nmu x nout, float) before output scaling. */
+rbws_status rbws_mlp_forward(const rbws_mlp* m, const double* mu, int nmu, float* y);
+/* Loss and gradient of one minibatch (mu host nb x p, c host nb x nout):
+ * *loss = mean (y - y_target)^2 (accumulated in double); grads (host,
+ * nullable) packed like the parameters.  Does not change the parameters. */
+rbws_status rbws_mlp_grad(rbws_mlp* m, const double* mu, const double* c, int nb, double* loss,
+                          float* grads);
+/* One Adam step on one minibatch at step size lr (the gradient is the one
+ * rbws_mlp_grad returns).  *loss (nullable) is the minibatch loss before the step. */
+rbws_status rbws_mlp_adam_step(rbws_mlp* m, const double* mu, const double* c, int nb, double lr,
+                               double* loss);
+/* Train on npairs pairs (mu host npairs x p, c host npairs x nout, e.g. from
+ * rbws_rb_coeffs).  loss_hist: host, nullable, epochs * (npairs / batch)
+ * minibatch losses in step order.  Continues from the current parameters and
+ * Adam state.  Errors: EINVAL (batch < 1 or > npairs, epochs < 1). */
+rbws_status rbws_mlp_train(rbws_mlp* m, const double* mu, const double* c, int npairs,
+                           const rbws_mlp_train_cfg* cfg, double* loss_hist);
+/* Checkpoint: description, parameters, output scaling (not the Adam state). */
+rbws_status rbws_mlp_save(const rbws_mlp* m, const char* path);
+rbws_status rbws_mlp_load(const char* path, int device, rbws_mlp** out);
+
 /* ---- batched solve (Alg. 5 driving Alg. 1) --------------------------------
  * Solves nmu systems in one batch.  problems[0..nprob) may have different
  * grid sizes (the uneven batch); problem_of[b] (NULL = all 0) picks the

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "mlp.hpp"
 #include "rb.hpp"
 
 namespace rbws {
@@ -25,6 +26,16 @@ __global__ void k_fill64(double* x, long long n, double v) {
 
 __global__ void k_stamp(unsigned long long* t) { *t = wall_clock64(); }
 
+// x_b <- src_b for the solves with pick[b] != 0 (grid.y = solve)
+__global__ void k_pick(double* __restrict__ x, const double* __restrict__ src, const long long* __restrict__ off,
+                       const long long* __restrict__ len, const int* __restrict__ pick) {
+  const int b = blockIdx.y;
+  if (!pick[b]) return;
+  const long long o = off[b], n = len[b];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[o + i] = src[o + i];
+}
+
 void fill64(double* x, long long n, double v, hipStream_t s) {
   if (n <= 0) return;
   long long blocks = std::min<long long>((n + 255) / 256, 65536);
@@ -33,7 +44,7 @@ void fill64(double* x, long long n, double v, hipStream_t s) {
 }
 
 // stats of all solves of a batch after a run
-void collect_stats(Batch& B, unsigned long long t0, int init_used, int outer_field_from_extra,
+void collect_stats(Batch& B, unsigned long long t0, const std::vector<int>& init_used, int outer_field_from_extra,
                    rbws_solve_stat* out, hipStream_t s) {
   std::vector<CgState> st;
   states_to_host(B, st, s);
@@ -45,12 +56,84 @@ void collect_stats(Batch& B, unsigned long long t0, int init_used, int outer_fie
     o.extra_spmv = st[b].extra;
     o.outer_iters = outer_field_from_extra ? st[b].pad0 : 0;
     o.status = st[b].status < 0 ? RBWS_SOLVE_MAXITER : st[b].status;
-    o.init_used = init_used;
+    o.init_used = init_used[b];
     o.init_rr = st[b].init_rr;
     o.final_rr = st[b].rr;
     o.ff = st[b].ff;
     o.t_done_ms = st[b].t_done > t0 ? (double)(st[b].t_done - t0) / khz : 0.0;
   }
+}
+
+// The learned start: c from the networks, u = V c, and the fallback to the
+// reduced solve (0: per solve the start with the smaller true residual; 1: the
+// RB start where the network's relative residual exceeds the basis's final
+// greedy indicator).  `used` receives RBWS_INIT_LEARNED or RBWS_INIT_RB.
+template <class Lift>
+void learned_start(Batch& B, const std::vector<const Basis*>& bl, const std::vector<Mlp*>& ml,
+                   const int* problem_of, const double* mu, int fallback, int fe, hipStream_t s, Lift lift,
+                   std::vector<int>& used) {
+  const int ns = B.nsolve, nprob = B.nprob, p = B.probs[0]->p;
+  RBWS_SCRATCH(cm_b);
+  RBWS_SCRATCH(cr_b);
+  RBWS_SCRATCH(rows_b);
+  RBWS_SCRATCH(meta_b);
+  double* cm = (double*)cm_b.get(sizeof(double) * 64 * ns, B.device);
+  double* x = (double*)B.x.ptr;
+  for (int q = 0; q < nprob; q++) {
+    if (nprob == 1) {
+      mlp_predict_dev(ml[0], mu, ns, nullptr, cm, 64, s);
+      break;
+    }
+    std::vector<int> rows;
+    std::vector<double> mq;
+    for (int b = 0; b < ns; b++)
+      if ((problem_of ? problem_of[b] : 0) == q) {
+        rows.push_back(b);
+        mq.insert(mq.end(), mu + (long long)b * p, mu + (long long)(b + 1) * p);
+      }
+    if (rows.empty()) continue;
+    int* rd = (int*)rows_b.get(sizeof(int) * rows.size(), B.device);
+    RBWS_HIP(hipMemcpyAsync(rd, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
+    mlp_predict_dev(ml[q], mq.data(), (int)rows.size(), rd, cm, 64, s);
+    RBWS_HIP(hipStreamSynchronize(s));  // rows_b is reused by the next problem
+  }
+  lift(cm, x);
+  std::vector<double> rel_m(ns), rel_r(ns);
+  resid_norms(B, x, rel_m.data(), nullptr, nullptr, fe, s);
+  std::vector<int> pick(ns, 0);
+  bool any = false;
+  for (int b = 0; b < ns; b++) {
+    const double thr = bl[B.sd_h[b].prob]->final_max;
+    const bool need = fallback == 0 || !(rel_m[b] <= thr);
+    pick[b] = need ? 1 : 0;
+    any = any || need;
+  }
+  if (any) {
+    double* cr = (double*)cr_b.get(sizeof(double) * 64 * ns, B.device);
+    RBWS_REQUIRE(rb_coeffs(B, bl, cr, 64, fe, s) == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
+    double* tmp = (double*)B.r.get(sizeof(double) * B.total, B.device);
+    lift(cr, tmp);
+    if (fallback == 0) {
+      resid_norms(B, tmp, rel_r.data(), nullptr, nullptr, fe, s);
+      for (int b = 0; b < ns; b++) pick[b] = (rel_r[b] < rel_m[b] || !(rel_m[b] == rel_m[b])) ? 1 : 0;
+    }
+    std::vector<long long> meta(3 * (size_t)ns);
+    for (int b = 0; b < ns; b++) {
+      meta[b] = B.sd_h[b].off;
+      meta[ns + b] = B.probs[B.sd_h[b].prob]->ndof;
+      meta[2 * ns + b] = pick[b];
+    }
+    long long* md = (long long*)meta_b.get(sizeof(long long) * meta.size(), B.device);
+    RBWS_HIP(hipMemcpyAsync(md, meta.data(), sizeof(long long) * meta.size(), hipMemcpyHostToDevice, s));
+    std::vector<int> pk(pick);
+    int* pd = (int*)rows_b.get(sizeof(int) * ns, B.device);
+    RBWS_HIP(hipMemcpyAsync(pd, pk.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_pick, dim3(256, ns), dim3(256), 0, s, x, (const double*)tmp, (const long long*)md,
+                       (const long long*)(md + ns), (const int*)pd);
+    RBWS_HIP(hipGetLastError());
+    RBWS_HIP(hipStreamSynchronize(s));
+  }
+  for (int b = 0; b < ns; b++) used[b] = pick[b] ? RBWS_INIT_RB : RBWS_INIT_LEARNED;
 }
 
 }  // namespace rbws
@@ -78,6 +161,8 @@ static inline Problem* PP(rbws_problem* p) { return reinterpret_cast<Problem*>(p
 static inline const Problem* PP(const rbws_problem* p) { return reinterpret_cast<const Problem*>(p); }
 static inline Basis* BB(rbws_basis* b) { return reinterpret_cast<Basis*>(b); }
 static inline const Basis* BB(const rbws_basis* b) { return reinterpret_cast<const Basis*>(b); }
+static inline Mlp* MM(rbws_mlp* m) { return reinterpret_cast<Mlp*>(m); }
+static inline const Mlp* MM(const rbws_mlp* m) { return reinterpret_cast<const Mlp*>(m); }
 
 extern "C" {
 
@@ -341,15 +426,26 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   }
   if (nmu == 0) return RBWS_OK;
   RBWS_REQUIRE(mu != nullptr, RBWS_EINVAL, "mu is NULL");
-  RBWS_REQUIRE(opts->init != RBWS_INIT_LEARNED, RBWS_ESTATE, "no learned model given");
   RBWS_REQUIRE(opts->lift == RBWS_LIFT_EXACT || opts->lift == RBWS_LIFT_MFMA, RBWS_EINVAL, "bad lift");
+  RBWS_REQUIRE(opts->fallback == 0 || opts->fallback == 1, RBWS_EINVAL, "bad fallback");
   std::vector<const Basis*> bl(nprob, nullptr);
-  if (opts->init == RBWS_INIT_RB) {
-    RBWS_REQUIRE(bases != nullptr, RBWS_ESTATE, "RB start needs a basis per problem");
+  std::vector<Mlp*> ml(nprob, nullptr);
+  if (opts->init != RBWS_INIT_ZERO) {
+    RBWS_REQUIRE(bases != nullptr, RBWS_ESTATE, "RB and learned starts need a basis per problem");
     for (int q = 0; q < nprob; q++) {
-      RBWS_REQUIRE(bases[q] != nullptr, RBWS_ESTATE, "RB start needs a basis per problem");
+      RBWS_REQUIRE(bases[q] != nullptr, RBWS_ESTATE, "RB and learned starts need a basis per problem");
       bl[q] = BB(bases[q]);
       RBWS_REQUIRE(bl[q]->prob == probs[q], RBWS_EINVAL, "basis belongs to another problem");
+    }
+  }
+  if (opts->init == RBWS_INIT_LEARNED) {
+    RBWS_REQUIRE(mlps != nullptr, RBWS_ESTATE, "learned start needs a network per problem");
+    for (int q = 0; q < nprob; q++) {
+      RBWS_REQUIRE(mlps[q] != nullptr, RBWS_ESTATE, "learned start needs a network per problem");
+      ml[q] = const_cast<Mlp*>(MM(mlps[q]));
+      RBWS_REQUIRE(ml[q]->d.p == probs[q]->p && ml[q]->d.nout == bl[q]->N, RBWS_EINVAL,
+                   "network inputs/outputs do not match the problem and basis");
+      RBWS_REQUIRE(ml[q]->device == probs[q]->device, RBWS_EINVAL, "network on another device");
     }
   }
   hipStream_t s = (hipStream_t)stream;
@@ -358,13 +454,19 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   batch_setup(B, probs, problem_of, nmu, mu, probs[0]->p, s);
   double* x = (double*)B.x.get(sizeof(double) * B.total, B.device);
   const int fe = (opts->flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
+  std::vector<int> used(nmu, opts->init);
+  auto lift = [&](const double* c, double* out) {
+    if (opts->lift == RBWS_LIFT_MFMA && nprob == 1) rb_lift_mfma(B, bl[0], c, 64, out, s);
+    else rb_lift_exact(B, bl, c, 64, out, fe, s);
+  };
   if (opts->init == RBWS_INIT_ZERO) {
     fill64(x, B.total, 0.0, s);
-  } else {
+  } else if (opts->init == RBWS_INIT_RB) {
     double* cd = (double*)cbuf.get(sizeof(double) * 64 * nmu, B.device);
     RBWS_REQUIRE(rb_coeffs(B, bl, cd, 64, fe, s) == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
-    if (opts->lift == RBWS_LIFT_MFMA && nprob == 1) rb_lift_mfma(B, bl[0], cd, 64, x, s);
-    else rb_lift_exact(B, bl, cd, 64, x, fe, s);
+    lift(cd, x);
+  } else {
+    learned_start(B, bl, ml, problem_of, mu, opts->fallback, fe, s, lift, used);
   }
   RBWS_SCRATCH(tbuf);
   unsigned long long* tdev = (unsigned long long*)tbuf.get(sizeof(unsigned long long), B.device);
@@ -397,7 +499,7 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   }
   if (stats) {
     if (opts->precision == RBWS_FP64) {
-      collect_stats(B, t0, opts->init, 0, stats, s);
+      collect_stats(B, t0, used, 0, stats, s);
     } else {
       const double khz = wall_clock_khz(B.device);
       for (int b = 0; b < nmu; b++) {
@@ -407,7 +509,7 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
         o.outer_iters = ir[b].outer;
         o.extra_spmv = ir[b].outer;
         o.status = ir[b].status;
-        o.init_used = opts->init;
+        o.init_used = used[b];
         o.init_rr = ir[b].init_rr;
         o.final_rr = ir[b].rr;
         o.ff = ir[b].ff;
@@ -416,6 +518,151 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
     }
   }
   RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned start
+// ---------------------------------------------------------------------------
+extern "C" {
+
+rbws_status rbws_mlp_create(const rbws_mlp_desc* d, int device, const float* params, unsigned long long seed,
+                            rbws_mlp** out) {
+  API_BEGIN
+  RBWS_REQUIRE(out != nullptr, RBWS_EINVAL, "out is NULL");
+  *out = nullptr;
+  *out = reinterpret_cast<rbws_mlp*>(mlp_create(d, device, params, seed));
+  API_END
+}
+
+void rbws_mlp_destroy(rbws_mlp* m) { mlp_destroy(MM(m)); }
+
+rbws_status rbws_mlp_param_count(const rbws_mlp* m, long long* count) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr && count != nullptr, RBWS_EINVAL, "NULL argument");
+  *count = MM(m)->np;
+  API_END
+}
+
+rbws_status rbws_mlp_info(const rbws_mlp* m, rbws_mlp_desc* d) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr && d != nullptr, RBWS_EINVAL, "NULL argument");
+  *d = MM(m)->d;
+  API_END
+}
+
+rbws_status rbws_mlp_get_params(const rbws_mlp* m, float* params) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  RBWS_HIP(hipSetDevice(MM(m)->device));
+  mlp_get_params(MM(m), params, nullptr);
+  API_END
+}
+
+rbws_status rbws_mlp_set_params(rbws_mlp* m, const float* params) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  RBWS_HIP(hipSetDevice(MM(m)->device));
+  mlp_set_params(MM(m), params, nullptr);
+  API_END
+}
+
+rbws_status rbws_mlp_set_output_scaling(rbws_mlp* m, const double* mean, const double* stdev) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  RBWS_HIP(hipSetDevice(MM(m)->device));
+  mlp_set_scaling(MM(m), mean, stdev, nullptr);
+  API_END
+}
+
+rbws_status rbws_mlp_get_output_scaling(const rbws_mlp* m, double* mean, double* stdev) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  for (int j = 0; j < MM(m)->d.nout; j++) {
+    if (mean) mean[j] = MM(m)->out_mean[j];
+    if (stdev) stdev[j] = MM(m)->out_std[j];
+  }
+  API_END
+}
+
+rbws_status rbws_mlp_fit_output_scaling(rbws_mlp* m, const double* mu, const double* c, int npairs) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  mlp_fit_scaling(MM(m), mu, c, npairs, nullptr);
+  API_END
+}
+
+rbws_status rbws_mlp_predict(const rbws_mlp* m, const double* mu, int nmu, double* c) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr && c != nullptr, RBWS_EINVAL, "NULL argument");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  if (nmu == 0) return RBWS_OK;
+  Mlp* mm = const_cast<Mlp*>(MM(m));
+  RBWS_HIP(hipSetDevice(mm->device));
+  RBWS_SCRATCH(cb);
+  const int no = mm->d.nout;
+  double* cd = (double*)cb.get(sizeof(double) * (size_t)nmu * no, mm->device);
+  mlp_predict_dev(mm, mu, nmu, nullptr, cd, no, nullptr);
+  RBWS_HIP(hipMemcpy(c, cd, sizeof(double) * (size_t)nmu * no, hipMemcpyDeviceToHost));
+  API_END
+}
+
+rbws_status rbws_mlp_forward(const rbws_mlp* m, const double* mu, int nmu, float* y) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr && y != nullptr, RBWS_EINVAL, "NULL argument");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  if (nmu == 0) return RBWS_OK;
+  Mlp* mm = const_cast<Mlp*>(MM(m));
+  RBWS_HIP(hipSetDevice(mm->device));
+  const float* o = mlp_forward_host(mm, mu, nmu, nullptr);
+  const int ld = mm->outp[mm->L - 1], no = mm->d.nout;
+  std::vector<float> h((size_t)nmu * ld);
+  RBWS_HIP(hipMemcpy(h.data(), o, sizeof(float) * h.size(), hipMemcpyDeviceToHost));
+  for (int r = 0; r < nmu; r++)
+    for (int j = 0; j < no; j++) y[(size_t)r * no + j] = h[(size_t)r * ld + j];
+  API_END
+}
+
+rbws_status rbws_mlp_grad(rbws_mlp* m, const double* mu, const double* c, int nb, double* loss, float* grads) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  const double l = mlp_grad(MM(m), mu, c, nb, grads, nullptr);
+  if (loss) *loss = l;
+  API_END
+}
+
+rbws_status rbws_mlp_adam_step(rbws_mlp* m, const double* mu, const double* c, int nb, double lr, double* loss) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  const double l = mlp_adam_step(MM(m), mu, c, nb, lr, nullptr);
+  if (loss) *loss = l;
+  API_END
+}
+
+rbws_status rbws_mlp_train(rbws_mlp* m, const double* mu, const double* c, int npairs,
+                           const rbws_mlp_train_cfg* cfg, double* loss_hist) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  RBWS_REQUIRE(npairs >= 1, RBWS_EINVAL, "npairs < 1");
+  mlp_train(MM(m), mu, c, npairs, cfg, loss_hist, nullptr);
+  API_END
+}
+
+rbws_status rbws_mlp_save(const rbws_mlp* m, const char* path) {
+  API_BEGIN
+  RBWS_REQUIRE(m != nullptr, RBWS_EINVAL, "network is NULL");
+  RBWS_HIP(hipSetDevice(MM(m)->device));
+  mlp_save(MM(m), path);
+  API_END
+}
+
+rbws_status rbws_mlp_load(const char* path, int device, rbws_mlp** out) {
+  API_BEGIN
+  RBWS_REQUIRE(out != nullptr, RBWS_EINVAL, "out is NULL");
+  *out = nullptr;
+  *out = reinterpret_cast<rbws_mlp*>(mlp_load(path, device));
   API_END
 }
 

@@ -53,6 +53,17 @@ class SolveOpts(C.Structure):
                 ("flags", C.c_int), ("check_every", C.c_int), ("ir_mode", C.c_int)]
 
 
+class MlpDesc(C.Structure):
+    _fields_ = [("p", C.c_int), ("nout", C.c_int), ("hidden", C.c_int), ("depth", C.c_int),
+                ("log_cols", C.c_int), ("in_m", C.c_double), ("in_s", C.c_double),
+                ("lin_lo", C.c_double), ("lin_hi", C.c_double), ("out_pow", C.c_double)]
+
+
+class MlpTrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("lr_min", C.c_double),
+                ("seed", C.c_ulonglong), ("use_graph", C.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_13862_amd.build`")
@@ -83,6 +94,22 @@ def _load():
         "rbws_rb_lift": (i, [vp, vp, i, vp, i, vp]),
         "rbws_basis_save": (i, [vp, C.c_char_p]),
         "rbws_basis_load": (i, [vp, C.c_char_p, C.POINTER(vp)]),
+        "rbws_mlp_create": (i, [C.POINTER(MlpDesc), i, C.POINTER(C.c_float), C.c_ulonglong, C.POINTER(vp)]),
+        "rbws_mlp_destroy": (None, [vp]),
+        "rbws_mlp_param_count": (i, [vp, C.POINTER(ll)]),
+        "rbws_mlp_info": (i, [vp, C.POINTER(MlpDesc)]),
+        "rbws_mlp_get_params": (i, [vp, C.POINTER(C.c_float)]),
+        "rbws_mlp_set_params": (i, [vp, C.POINTER(C.c_float)]),
+        "rbws_mlp_set_output_scaling": (i, [vp, dp, dp]),
+        "rbws_mlp_get_output_scaling": (i, [vp, dp, dp]),
+        "rbws_mlp_fit_output_scaling": (i, [vp, dp, dp, i]),
+        "rbws_mlp_predict": (i, [vp, dp, i, dp]),
+        "rbws_mlp_forward": (i, [vp, dp, i, C.POINTER(C.c_float)]),
+        "rbws_mlp_grad": (i, [vp, dp, dp, i, dp, C.POINTER(C.c_float)]),
+        "rbws_mlp_adam_step": (i, [vp, dp, dp, i, d, dp]),
+        "rbws_mlp_train": (i, [vp, dp, dp, i, C.POINTER(MlpTrainCfg), dp]),
+        "rbws_mlp_save": (i, [vp, C.c_char_p]),
+        "rbws_mlp_load": (i, [C.c_char_p, i, C.POINTER(vp)]),
     }
     for name, (res, args) in list(sigs.items()) + list(optional.items()):
         fn = getattr(L, name, None)
@@ -268,6 +295,138 @@ class Basis:
         """u[b] = V c[b]; c (nmu, N) and u (nmu, ndof) float64 device tensors."""
         _check(_L.rbws_rb_lift(self.handle, C.c_void_p(c.data_ptr()), c.shape[0],
                                C.c_void_p(u.data_ptr()), mode, _stream(stream)))
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """Learned start (rbws_mlp_*): a BF16-MFMA multilayer perceptron mu -> c(mu)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        desc = MlpDesc()
+        _check(_L.rbws_mlp_info(handle, C.byref(desc)))
+        self.desc = desc
+        n = C.c_longlong()
+        _check(_L.rbws_mlp_param_count(handle, C.byref(n)))
+        self.nparams = n.value
+        self.p, self.nout = desc.p, desc.nout
+
+    @classmethod
+    def create(cls, p: int, nout: int, hidden: int = 256, depth: int = 3, log_cols: Optional[int] = None,
+               in_m: float = 0.0, in_s: float = 1.0, lin_lo: float = 0.0, lin_hi: float = 1.0,
+               out_pow: float = 0.0, params=None, seed: int = 0, device: int = 0) -> "Mlp":
+        d = MlpDesc(p, nout, hidden, depth, p if log_cols is None else log_cols, in_m, in_s, lin_lo, lin_hi,
+                    out_pow)
+        h = C.c_void_p()
+        pp = None
+        if params is not None:
+            params = np.ascontiguousarray(params, dtype=np.float32)
+            pp = _fp(params)
+        _check(_L.rbws_mlp_create(C.byref(d), device, pp, seed, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "Mlp":
+        h = C.c_void_p()
+        _check(_L.rbws_mlp_load(path.encode(), device, C.byref(h)))
+        return cls(h)
+
+    def save(self, path: str):
+        _check(_L.rbws_mlp_save(self.handle, path.encode()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _L is not None:
+            _L.rbws_mlp_destroy(h)
+            self.handle = None
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(_L.rbws_mlp_get_params(self.handle, _fp(out)))
+        return out
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.size == self.nparams
+        _check(_L.rbws_mlp_set_params(self.handle, _fp(params)))
+
+    def set_output_scaling(self, mean=None, std=None):
+        m = None if mean is None else _f64(mean)
+        sd = None if std is None else _f64(std)
+        _check(_L.rbws_mlp_set_output_scaling(self.handle, None if m is None else _dp(m),
+                                              None if sd is None else _dp(sd)))
+
+    def output_scaling(self):
+        m = np.empty(self.nout)
+        sd = np.empty(self.nout)
+        _check(_L.rbws_mlp_get_output_scaling(self.handle, _dp(m), _dp(sd)))
+        return m, sd
+
+    def fit_output_scaling(self, mu, c):
+        mu = _f64(mu).reshape(-1, self.p)
+        c = _f64(c).reshape(-1, self.nout)
+        _check(_L.rbws_mlp_fit_output_scaling(self.handle, _dp(mu), _dp(c), mu.shape[0]))
+
+    def predict(self, mu) -> np.ndarray:
+        mu = _f64(mu).reshape(-1, self.p)
+        c = np.empty((mu.shape[0], self.nout))
+        _check(_L.rbws_mlp_predict(self.handle, _dp(mu), mu.shape[0], _dp(c)))
+        return c
+
+    def forward(self, mu) -> np.ndarray:
+        mu = _f64(mu).reshape(-1, self.p)
+        y = np.empty((mu.shape[0], self.nout), dtype=np.float32)
+        _check(_L.rbws_mlp_forward(self.handle, _dp(mu), mu.shape[0], _fp(y)))
+        return y
+
+    def grad(self, mu, c):
+        mu = _f64(mu).reshape(-1, self.p)
+        c = _f64(c).reshape(-1, self.nout)
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = C.c_double()
+        _check(_L.rbws_mlp_grad(self.handle, _dp(mu), _dp(c), mu.shape[0], C.byref(loss), _fp(g)))
+        return loss.value, g
+
+    def adam_step(self, mu, c, lr: float) -> float:
+        mu = _f64(mu).reshape(-1, self.p)
+        c = _f64(c).reshape(-1, self.nout)
+        loss = C.c_double()
+        _check(_L.rbws_mlp_adam_step(self.handle, _dp(mu), _dp(c), mu.shape[0], lr, C.byref(loss)))
+        return loss.value
+
+    def train(self, mu, c, epochs: int = 200, batch: int = 256, lr: float = 1e-3, lr_min: float = 0.0,
+              seed: int = 0, use_graph: bool = True) -> np.ndarray:
+        mu = _f64(mu).reshape(-1, self.p)
+        c = _f64(c).reshape(-1, self.nout)
+        cfg = MlpTrainCfg(epochs, batch, lr, lr_min, seed, 1 if use_graph else 0)
+        steps = epochs * (mu.shape[0] // batch)
+        hist = np.empty(max(steps, 1))
+        _check(_L.rbws_mlp_train(self.handle, _dp(mu), _dp(c), mu.shape[0], C.byref(cfg), _dp(hist)))
+        return hist[:steps]
+
+
+def unpack_params(params, p: int, nout: int, hidden: int, depth: int):
+    """Split a packed parameter vector into [(W, b), ...] (W of shape (out, in))."""
+    out = []
+    k = 0
+    params = np.asarray(params)
+    for layer in range(depth + 1):
+        i = p if layer == 0 else hidden
+        o = nout if layer == depth else hidden
+        W = params[k:k + o * i].reshape(o, i)
+        k += o * i
+        b = params[k:k + o]
+        k += o
+        out.append((W, b))
+    assert k == params.size
+    return out
+
+
+def pack_params(layers) -> np.ndarray:
+    return np.concatenate([np.concatenate([np.asarray(W).ravel(), np.asarray(b).ravel()]) for W, b in layers])
 
 
 KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs")

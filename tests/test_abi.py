@@ -1,0 +1,35 @@
+"""The C ABI: librbws.so loads on a machine without a GPU and exports every
+function that include/rbws.h declares (no compute calls are made here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbws.h")
+LIB = os.path.join(ROOT, "paper_2311_13862_amd", "librbws.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(rbws_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("rbws_problem_create", "rbws_rb_build", "rbws_rb_coeffs", "rbws_rb_lift", "rbws_solve",
+              "rbws_mlp_create", "rbws_mlp_train", "rbws_mlp_predict", "rbws_spmv", "rbws_exact_dots"):
+        assert n in names, n
+    assert len(names) >= 35, names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_2311_13862_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    lib.rbws_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.rbws_version()
