@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-zero", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--mlp-pairs", type=int, default=8192)
+    ap.add_argument("--mlp-epochs", type=int, default=200)
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc (a few refinement rounds)")
     return ap.parse_args()
@@ -165,6 +168,12 @@ def main():
         zero_iters = float(np.mean([s["iters"] for s in zst]))
         log(f"zero start: {zero_value:.2f} mu-solves/s, mean inner iterations {zero_iters:.1f}")
 
+    # learned start: a perceptron trained on the GPU on (mu, c(mu)) pairs of the reduced solve
+    learned = None
+    if not args.no_learned:
+        learned = learned_leg(rbws, W, wl, spec, P, basis, mu, args)
+        log(f"learned start: {learned}")
+
     # SpMV bandwidth (16 solves at 128^3, beyond the 256 MB infinity cache)
     spmv = {}
     nb = 16
@@ -210,6 +219,7 @@ def main():
         "zero_start_value": None if zero_value is None else round(zero_value, 3),
         "zero_start_inner_iters_mean": zero_iters,
         "rb_over_zero": None if zero_value is None else round(value / zero_value, 4),
+        "learned_start": learned,
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
         "t_off_s": round(t_off, 2),
@@ -223,6 +233,45 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
+    """Pairs from the reduced solve, GPU training, then the batch from the learned
+    start (strict fallback: per solve the smaller true residual of u_MLP, u_RB)."""
+    import torch
+    mup = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.mlp_pairs, W.SEED_MLP_PAIRS)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    c = basis.coeffs(mup)
+    t_pairs = time.perf_counter() - t
+    net = rbws.Mlp.create(spec.p, basis.N, hidden=256, depth=3, log_cols=spec.p, in_m=0.0, in_s=2.0,
+                          out_pow=1.0, seed=W.SEED_MLP_INIT)
+    net.fit_output_scaling(mup, c)
+    t = time.perf_counter()
+    hist = net.train(mup, c, epochs=args.mlp_epochs, batch=256, lr=1e-3, lr_min=1e-5, seed=W.SEED_MLP_PAIRS)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    c_rb = basis.coeffs(mu)
+    c_nn = net.predict(mu)
+    cerr = np.linalg.norm(c_nn - c_rb, axis=1) / np.linalg.norm(c_rb, axis=1)
+    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
+                             eta_inner=args.eta, init=rbws.INIT_LEARNED, lift=rbws.LIFT_MFMA,
+                             ir_mode=rbws.IR_RELIABLE, fallback=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = rbws.solve([P], mu, opts, bases=[basis], mlps=[net])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    used = [s["init_used"] for s in st]
+    return {"value": round(args.batch / el, 3), "unit": "mu-solves/s",
+            "all_converged": all(s["status"] == rbws.SOLVE_CONVERGED for s in st),
+            "inner_iters_mean": float(np.mean([s["iters"] for s in st])),
+            "init_relres_median": float(np.median([np.sqrt(s["init_rr"] / s["ff"]) for s in st])),
+            "started_from_mlp": int(sum(u == rbws.INIT_LEARNED for u in used)),
+            "coef_relerr_vs_rb_median": float(np.median(cerr)),
+            "train_pairs": args.mlp_pairs, "train_epochs": args.mlp_epochs, "t_pairs_s": round(t_pairs, 3),
+            "t_train_s": round(t_train, 3), "final_loss": float(np.mean(hist[-32:])),
+            "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
 
 
 KERNEL_SOURCES = ("fast.hpp", "ir.hip", "solver.hpp", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")

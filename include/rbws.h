@@ -176,7 +176,9 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
  * first parameter is mu_train[0].  Stops early (n_reached < N) when the
  * maximiser is already selected or a snapshot adds nothing new (remainder
  * below 1e-10 of its norm).  All inner products are correctly rounded, so the
- * basis is reproducible.  Requires f = 1 (RBWS_F_ONE).
+ * basis is reproducible.  With the Gaussian source (RBWS_F_GAUSS) the
+ * reduced right-hand side V^T f(mu) is projected per parameter (FP64 matrix
+ * cores, deterministic, not correctly rounded) and fN is unused.
  * Outputs (host, nullable): selected[N] (training indices), indicator_hist
  * [N x ntrain] (row k: indicator with k+1 vectors), n_reached.
  * Errors: EINVAL (N outside [1, min(64, ntrain)], snap_tol <= 0),
@@ -193,7 +195,8 @@ rbws_status rbws_basis_get(const rbws_basis* b, double* V, double* AqN, double* 
 rbws_status rbws_basis_device_v(const rbws_basis* b, const double** V);
 /* Online RB solve (Eq. "RB system"): c(mu) from A_N(mu) = sum_q theta_q A_q^N
  * (accumulated with fma in q order), Cholesky and two triangular solves, every
- * inner sum correctly rounded.  mu host (nmu x p), c host (nmu x N).
+ * inner sum correctly rounded; right-hand side f^N (f = 1) or V^T f(mu)
+ * (Gaussian source).  mu host (nmu x p), c host (nmu x N).
  * ENUMERIC when a reduced matrix is not positive definite. */
 rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, double* c, void* stream);
 /* Lift u_b = V c_b for b < nmu: c device (nmu x N), u device (nmu x ndof).

@@ -21,6 +21,7 @@
 #include <cstring>
 
 #include "rb.hpp"
+#include "stencil.hpp"
 
 namespace rbws {
 
@@ -442,6 +443,96 @@ static RbDev rbdev_of(const Basis* bs) {
   return r;
 }
 
+// ---------------------------------------------------------------------------
+// reduced right-hand side of a parameter-dependent source: b_N(mu) = V^T f(mu)
+// (the Gaussian source is not affine in mu, so it is projected per solve).
+// An FP64 matrix-core contraction over the points, with f generated in
+// registers: a workgroup takes a chunk of points and 16 solves, each wave 16
+// basis vectors; per step of 4 points, lane (i + 16 k) feeds V[j0 + i][c + k]
+// and f_{s0 + i}(c + k).  Chunks are summed in order by a second kernel, so
+// the result is deterministic (but not correctly rounded).
+// ---------------------------------------------------------------------------
+constexpr int kProjChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_project(const double* __restrict__ V, int N, long long ndof,
+                                                 const ProbDev* __restrict__ pd, const SolveDev* __restrict__ sd,
+                                                 const int* __restrict__ solves, int nsol,
+                                                 double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = wave * 16;
+  if (j0 >= N) return;
+  const int col = lane & 15, kq = lane >> 4;
+  const int s0 = blockIdx.y * 16;
+  const int sb = s0 + col < nsol ? solves[s0 + col] : -1;
+  const long long c0 = (long long)blockIdx.x * kProjChunk, c1 = min(ndof, c0 + kProjChunk);
+  const ProbDev& P = *pd;
+  const int n = P.g.n;
+  SolveDev S{};
+  if (sb >= 0) S = sd[sb];
+  const bool arow = j0 + col < N;
+  const double* vr = V + (long long)(arow ? j0 + col : 0) * ndof;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (long long c = c0; c < c1; c += 4) {
+    const long long cc = c + kq;
+    const bool in = cc < c1;
+    const double a = (arow && in) ? vr[cc] : 0.0;
+    double b = 0.0;
+    if (sb >= 0 && in) {
+      const int i = (int)(cc % n) + 1, j = (int)((cc / n) % n) + 1, k = (int)(cc / ((long long)n * n)) + 1;
+      b = fval(P, S, i, j, k);
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  // acc[r] = sum over the chunk of V[j0 + kq + 4 r][c] f_{s0 + col}(c)
+  if (s0 + col < nsol) {
+    double* out = part + ((long long)blockIdx.x * nsol + s0 + col) * kMaxN;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int j = j0 + kq + 4 * r;
+      if (j < N) out[j] = acc[r];
+    }
+  }
+}
+
+__global__ void k_project_fin(const double* __restrict__ part, int nchunk, int nsol, int N,
+                              const int* __restrict__ solves, double* __restrict__ bN) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nsol * N) return;
+  const int t = e / N, j = e % N;
+  double sum = 0.0;
+  for (int q = 0; q < nchunk; q++) sum += part[((long long)q * nsol + t) * kMaxN + j];
+  bN[(long long)solves[t] * kMaxN + j] = sum;
+}
+
+// b_N of every solve whose problem has a parameter-dependent source, into
+// bN (nsolve x kMaxN); returns false when no solve needs it
+static bool project_sources(Batch& B, const std::vector<const Basis*>& bases, double* bN, hipStream_t s) {
+  bool any = false;
+  RBWS_SCRATCH(partb);
+  RBWS_SCRATCH(solb);
+  for (int q = 0; q < B.nprob; q++) {
+    if (B.probs[q]->desc.f_kind == RBWS_F_ONE) continue;
+    std::vector<int> sol;
+    for (int b = 0; b < B.nsolve; b++)
+      if (B.sd_h[b].prob == q) sol.push_back(b);
+    if (sol.empty()) continue;
+    any = true;
+    const Basis* bs = bases[q];
+    const long long nd = bs->ndof;
+    const int nchunk = (int)((nd + kProjChunk - 1) / kProjChunk), ns = (int)sol.size();
+    double* part = (double*)partb.get(sizeof(double) * (size_t)nchunk * ns * kMaxN, B.device);
+    int* sd = (int*)solb.get(sizeof(int) * ns, B.device);
+    RBWS_HIP(hipMemcpyAsync(sd, sol.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_project, dim3(nchunk, (ns + 15) / 16), dim3(256), 0, s, (const double*)bs->V.ptr, bs->N,
+                       nd, (const ProbDev*)B.pd.ptr + q, (const SolveDev*)B.sd.ptr, (const int*)sd, ns, part);
+    hipLaunchKernelGGL(k_project_fin, dim3((ns * bs->N + 255) / 256), dim3(256), 0, s, (const double*)part, nchunk,
+                       ns, bs->N, (const int*)sd, bN);
+    RBWS_HIP(hipGetLastError());
+    RBWS_HIP(hipStreamSynchronize(s));  // partb / solb are reused by the next problem
+  }
+  return any;
+}
+
 int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride, int force_exact,
               hipStream_t s) {
   const int ns = B.nsolve;
@@ -451,11 +542,14 @@ int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int c
     const Basis* bs = bases[B.sd_h[b].prob];
     RBWS_REQUIRE(bs != nullptr, RBWS_ESTATE, "a reduced basis is required for this start");
     RBWS_REQUIRE(bs->prob == B.probs[B.sd_h[b].prob], RBWS_EINVAL, "basis belongs to another problem");
-    RBWS_REQUIRE(bs->prob->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL,
-                 "the online RB solve supports f = 1 (affine right-hand side)");
     RBWS_REQUIRE(bs->N <= cstride, RBWS_EINVAL, "coefficient stride too small");
     h[b] = rbdev_of(bs);
   }
+  RBWS_SCRATCH(bnb);
+  double* bN = (double*)bnb.get(sizeof(double) * (size_t)ns * kMaxN, B.device);
+  if (project_sources(B, bases, bN, s))
+    for (int b = 0; b < ns; b++)
+      if (B.probs[B.sd_h[b].prob]->desc.f_kind != RBWS_F_ONE) h[b].fN = bN + (size_t)b * kMaxN;
   RBWS_SCRATCH(rbd);
   RBWS_SCRATCH(badb);
   RbDev* d = (RbDev*)rbd.get(sizeof(RbDev) * ns, B.device);
@@ -536,7 +630,6 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
   RBWS_REQUIRE(N >= 1 && N <= kMaxN, RBWS_EINVAL, "N must be in [1, 64]");
   RBWS_REQUIRE(N <= ntrain, RBWS_EINVAL, "N exceeds the training set");
   RBWS_REQUIRE(snap_tol > 0.0 && std::isfinite(snap_tol), RBWS_EINVAL, "snap_tol must be positive");
-  RBWS_REQUIRE(P->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL, "the greedy build supports f = 1");
   RBWS_HIP(hipSetDevice(P->device));
   const int fe = (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
   const long long nd = P->ndof;
