@@ -81,8 +81,12 @@ enum { RBWS_LIFT_EXACT = 0, RBWS_LIFT_MFMA = 1 };
 enum { RBWS_IR_RESTART = 0, RBWS_IR_RELIABLE = 1 };
 /* rbws_solve_opts.flags */
 enum {
-  RBWS_FLAG_FORCE_EXACT_DOTS = 1 /* take the exact integer path for every inner product
-                                    (results are identical; for testing the fallback) */
+  RBWS_FLAG_FORCE_EXACT_DOTS = 1, /* take the exact integer path for every inner product
+                                     (results are identical; for testing the fallback) */
+  RBWS_FLAG_NO_GRAPH = 2          /* launch the iteration rounds one by one instead of
+                                     replaying a captured HIP graph of them (results are
+                                     identical; the graph is also skipped while kernel
+                                     timing is on) */
 };
 
 typedef struct rbws_problem rbws_problem;
@@ -320,6 +324,17 @@ rbws_status rbws_exact_fallbacks(long long* counts, int reset);
  * or a persistent grid of one full occupancy that loops over the items (1). */
 enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1 };
 rbws_status rbws_set_tuning(int key, int value);
+/* Tile autotuner.  Work items are 32 x 32 grid columns by TZ planes; a
+ * deeper tile re-reads fewer halo planes, a shallower one gives more items
+ * to spread over the 256 compute units.  Times y = A(mu) x for `nsolve` solves
+ * of problem p (precision RBWS_FP64 or RBWS_FP32_IR) at TZ = 4, 8, ..., 64 and
+ * keeps the fastest for later batches of this grid size whose solve count is
+ * in the same power-of-two range (per process).  tz: host, the choice; ms: host,
+ * nullable, 5 mean times in milliseconds (0 where not tried).  Results of the
+ * solver do not depend on the tiling.  Errors: EINVAL, ENOMEM, EDEVICE.
+ * rbws_autotune_clear drops every choice (back to the built-in rule). */
+rbws_status rbws_autotune(rbws_problem* p, int nsolve, int precision, void* stream, int* tz, double* ms);
+rbws_status rbws_autotune_clear(void);
 
 #ifdef __cplusplus
 }

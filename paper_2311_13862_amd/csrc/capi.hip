@@ -376,6 +376,20 @@ rbws_status rbws_set_tuning(int key, int value) {
   API_END
 }
 
+rbws_status rbws_autotune(rbws_problem* p, int nsolve, int precision, void* stream, int* tz, double* ms) {
+  API_BEGIN
+  RBWS_REQUIRE(p != nullptr && tz != nullptr, RBWS_EINVAL, "NULL argument");
+  RBWS_REQUIRE(precision == RBWS_FP64 || precision == RBWS_FP32_IR, RBWS_EINVAL, "bad precision");
+  *tz = autotune_tiles(PP(p), nsolve, precision == RBWS_FP32_IR, (hipStream_t)stream, ms);
+  API_END
+}
+
+rbws_status rbws_autotune_clear(void) {
+  API_BEGIN
+  clear_tile_table();
+  API_END
+}
+
 rbws_status rbws_exact_fallbacks(long long* counts, int reset) {
   API_BEGIN
   RBWS_REQUIRE(counts != nullptr, RBWS_EINVAL, "counts is NULL");

@@ -416,32 +416,27 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   const int check = o.check_every > 0 ? o.check_every : 8;
   const long long max_rounds = (long long)(o.inner_max + 2) * (o.max_outer + 1) + 16;
   KernelTimer& kt = ktimer();
-  for (long long round = 0; round < max_rounds; round++) {
-    kt.begin(s, KK_AP);
-    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, s, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, k32, d,
+  const bool graph = !(o.flags & RBWS_FLAG_NO_GRAPH) && !kt.on;
+  run_rounds(B, active, max_rounds, check, graph, s, [&](hipStream_t q) {
+    kt.begin(q, KK_AP);
+    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, q, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, k32, d,
                        r, p, p1, part, ktab);
-    kt.end(s);
-    kt.begin(s, KK_RESID);
-    hipLaunchKernelGGL(outer, dim3(g_res), dim3(256), lds_outer, s, items, L.res, L.cnt + WL_RES, ni, sd, pd, st,
+    kt.end(q);
+    kt.begin(q, KK_RESID);
+    hipLaunchKernelGGL(outer, dim3(g_res), dim3(256), lds_outer, q, items, L.res, L.cnt + WL_RES, ni, sd, pd, st,
                        k64, k32, u0, u1, d, r, part, ktab);
-    kt.end(s);
-    kt.begin(s, KK_FIN1);
-    hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, active, L);
-    kt.end(s);
-    kt.begin(s, KK_UP2);
-    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, s, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, k32, d,
+    kt.end(q);
+    kt.begin(q, KK_FIN1);
+    hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, active, L);
+    kt.end(q);
+    kt.begin(q, KK_UP2);
+    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, q, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, k32, d,
                        r, p, p1, part, ktab);
-    kt.end(s);
-    kt.begin(s, KK_FIN2);
-    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, s, sd, st, (const IrPart*)part, L);
-    kt.end(s);
-    RBWS_HIP(hipGetLastError());
-    if ((round + 1) % check == 0) {
-      RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));
-      RBWS_HIP(hipStreamSynchronize(s));
-      if (*B.active_host == 0) break;
-    }
-  }
+    kt.end(q);
+    kt.begin(q, KK_FIN2);
+    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, L);
+    kt.end(q);
+  });
   std::vector<IrState> h(ns);
   RBWS_HIP(hipMemcpyAsync(h.data(), st, sizeof(IrState) * ns, hipMemcpyDeviceToHost, s));
   RBWS_HIP(hipStreamSynchronize(s));

@@ -63,6 +63,19 @@ Batch::~Batch() {
   if (active_host) (void)hipHostFree(active_host);
 }
 
+RoundStreams& round_streams(int device) {
+  static thread_local std::vector<RoundStreams*> per;  // never destroyed (no HIP calls at exit)
+  if ((int)per.size() <= device) per.resize(device + 1, nullptr);
+  if (!per[device]) {
+    RoundStreams* r = new RoundStreams();
+    RBWS_HIP(hipStreamCreateWithFlags(&r->ws, hipStreamNonBlocking));
+    RBWS_HIP(hipEventCreateWithFlags(&r->in, hipEventDisableTiming));
+    RBWS_HIP(hipEventCreateWithFlags(&r->out, hipEventDisableTiming));
+    per[device] = r;
+  }
+  return *per[device];
+}
+
 Lists lists_init(Batch& B, hipStream_t s) {
   const int ni = B.nitems;
   const size_t head = 64;  // counters, padded
@@ -111,14 +124,105 @@ unsigned persistent_grid(const void* fn, size_t lds, int nitems, int device) {
   return std::min(cap, need);
 }
 
+// tile depths found by the autotuner, per (grid size, log2 of the number of solves of that size)
+struct TileEntry {
+  int n, bucket, tz;
+};
+static std::vector<TileEntry> g_tiles;
+static int g_force_tz = 0;
+static int count_bucket(long long c) {
+  int b = 0;
+  while ((2LL << b) <= std::max(1LL, c)) b++;
+  return b;
+}
+
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ) {
   *TX = QX;
   *TY = QY;
+  if (g_force_tz > 0) {
+    *TZ = std::min(g_force_tz, n);
+    return;
+  }
+  const int bk = count_bucket(nsolve_of_this_size);
+  for (const TileEntry& e : g_tiles)
+    if (e.n == n && e.bucket == bk) {
+      *TZ = std::min(e.tz, n);
+      return;
+    }
   const long long cols = (long long)((n + QX - 1) / QX) * ((n + QY - 1) / QY) * std::max(1LL, nsolve_of_this_size);
   int tz = 64;
   while (tz > 4 && cols * ((n + tz - 1) / tz) < 4096) tz /= 2;
   *TZ = std::min(tz, n);
 }
+
+// Times the stencil sweep (y = A x over `nsolve` solves of problem P, in FP32
+// or FP64) for every tile depth TZ in {4, 8, 16, 32, 64} (TZ <= n), keeps the
+// fastest for batches with this grid size and a solve count in the same
+// power-of-two range, and returns it.  ms[5] receives the mean times (0 for a
+// depth that was not tried).
+int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, double* ms) {
+  RBWS_REQUIRE(nsolve >= 1, RBWS_EINVAL, "nsolve < 1");
+  RBWS_HIP(hipSetDevice(P->device));
+  Batch B;
+  std::vector<double> mu((size_t)nsolve * P->p, 1.0);
+  if (P->desc.f_kind == RBWS_F_GAUSS)
+    for (int b = 0; b < nsolve; b++)
+      for (int t = P->p - 3; t < P->p; t++) mu[(size_t)b * P->p + t] = 0.5;
+  std::vector<const Problem*> probs{P};
+  const size_t el = fp32 ? sizeof(float) : sizeof(double);
+  const long long tot = (long long)nsolve * P->ndof;
+  DevBuf xb, yb;
+  void* x = xb.get(el * tot, P->device);
+  void* y = yb.get(el * tot, P->device);
+  RBWS_HIP(hipMemsetAsync(x, 0, el * tot, s));
+  hipEvent_t e0, e1;
+  RBWS_HIP(hipEventCreate(&e0));
+  RBWS_HIP(hipEventCreate(&e1));
+  const int cand[5] = {4, 8, 16, 32, 64};
+  int best = 0;
+  double best_ms = 0.0;
+  try {
+    for (int c = 0; c < 5; c++) {
+      if (ms) ms[c] = 0.0;
+      if (cand[c] > P->n && c > 0 && cand[c - 1] >= P->n) continue;
+      g_force_tz = cand[c];
+      batch_setup(B, probs, nullptr, nsolve, mu.data(), P->p, s);
+      g_force_tz = 0;
+      spmv_batch(B, x, y, fp32, s);
+      RBWS_HIP(hipEventRecord(e0, s));
+      const int reps = 3;
+      for (int r = 0; r < reps; r++) spmv_batch(B, x, y, fp32, s);
+      RBWS_HIP(hipEventRecord(e1, s));
+      RBWS_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      RBWS_HIP(hipEventElapsedTime(&t, e0, e1));
+      const double m = t / reps;
+      if (ms) ms[c] = m;
+      if (best == 0 || m < best_ms) {
+        best = cand[c];
+        best_ms = m;
+      }
+    }
+  } catch (...) {
+    g_force_tz = 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int bk = count_bucket(nsolve);
+  bool found = false;
+  for (TileEntry& e : g_tiles)
+    if (e.n == P->n && e.bucket == bk) {
+      e.tz = best;
+      found = true;
+    }
+  if (!found) g_tiles.push_back(TileEntry{P->n, bk, best});
+  return best;
+}
+
+void clear_tile_table() { g_tiles.clear(); }
 
 unsigned long long fallbacks_solver(bool reset) {
   unsigned long long v = 0;
@@ -767,32 +871,27 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
   const unsigned g_res = persistent_grid((const void*)res, lds, ni, B.device);
   const Lists L = lists_init(B, s);
   KernelTimer& kt = ktimer();
-  for (long long round = 0; round < max_rounds; round++) {
-    kt.begin(s, KK_AP);
-    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, s, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, kap,
+  const bool graph = !(o.flags & RBWS_FLAG_NO_GRAPH) && !kt.on;
+  run_rounds(B, active, max_rounds, check, graph, s, [&](hipStream_t q) {
+    kt.begin(q, KK_AP);
+    hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, q, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, kap,
                        x, r, p, p1, part, ktab);
-    kt.end(s);
-    kt.begin(s, KK_RESID);
-    hipLaunchKernelGGL(res, dim3(g_res), dim3(256), lds, s, items, L.res, L.cnt + WL_RES, ni, sd, pd, st, kap, x,
+    kt.end(q);
+    kt.begin(q, KK_RESID);
+    hipLaunchKernelGGL(res, dim3(g_res), dim3(256), lds, q, items, L.res, L.cnt + WL_RES, ni, sd, pd, st, kap, x,
                        r, part);
-    kt.end(s);
-    kt.begin(s, KK_FIN1);
-    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, p1, part, active, fe, L);
-    kt.end(s);
-    kt.begin(s, KK_UP2);
-    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, s, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, kap,
+    kt.end(q);
+    kt.begin(q, KK_FIN1);
+    hipLaunchKernelGGL(k_fin1, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, x, r, p, p1, part, active, fe, L);
+    kt.end(q);
+    kt.begin(q, KK_UP2);
+    hipLaunchKernelGGL(up, dim3(g_up), dim3(256), lds_fast, q, items, L.up, L.cnt + WL_UP, ni, sd, pd, st, kap,
                        x, r, p, p1, part, ktab);
-    kt.end(s);
-    kt.begin(s, KK_FIN2);
-    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, s, sd, pd, st, kap, x, r, p, part, active, fe, L);
-    kt.end(s);
-    RBWS_HIP(hipGetLastError());
-    if ((round + 1) % check == 0) {
-      RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));
-      RBWS_HIP(hipStreamSynchronize(s));
-      if (*B.active_host == 0) break;
-    }
-  }
+    kt.end(q);
+    kt.begin(q, KK_FIN2);
+    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, x, r, p, part, active, fe, L);
+    kt.end(q);
+  });
 }
 
 void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff, int force_exact,

@@ -89,6 +89,9 @@ struct Batch {
 // tiles: 32 x 32 grid columns (256 threads, 4 points each) by TZ planes; TZ
 // is the largest power of two in [4, 64] that still gives >= 4096 work items
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ);
+// autotuner of the tile depth (see solver.hip); its choices override the rule above
+int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, double* ms);
+void clear_tile_table();
 
 // Lists with every item on the residual list and the others empty (stream-ordered)
 Lists lists_init(Batch& B, hipStream_t s);
@@ -139,6 +142,62 @@ struct IrHost {
 void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out);
 int sweep32_variant();
 void set_sweep32_variant(int v);
+
+// The iteration rounds of a batched solve: `round(stream)` enqueues the launches
+// of one round.  Rounds run until the device counter `active` reads 0 (checked
+// every `check` rounds) or max_rounds.  With `graph`, `check` rounds are
+// captured once into a HIP graph on a library stream (ordered after and before
+// `s` by events) and the graph is replayed; otherwise the launches go to `s`.
+// The rounds contain kernel launches only (no memset or copy nodes).
+struct RoundStreams {
+  hipStream_t ws = nullptr;
+  hipEvent_t in = nullptr, out = nullptr;
+};
+RoundStreams& round_streams(int device);
+
+template <class F>
+void run_rounds(Batch& B, const int* active, long long max_rounds, int check, bool graph, hipStream_t s, F round) {
+  if (!graph) {
+    for (long long r = 0; r < max_rounds; r++) {
+      round(s);
+      RBWS_HIP(hipGetLastError());
+      if ((r + 1) % check == 0) {
+        RBWS_HIP(hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, s));
+        RBWS_HIP(hipStreamSynchronize(s));
+        if (*B.active_host == 0) break;
+      }
+    }
+    return;
+  }
+  RoundStreams& rs = round_streams(B.device);
+  RBWS_HIP(hipEventRecord(rs.in, s));
+  RBWS_HIP(hipStreamWaitEvent(rs.ws, rs.in, 0));
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  RBWS_HIP(hipStreamBeginCapture(rs.ws, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int r = 0; r < check; r++) round(rs.ws);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(rs.ws, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  RBWS_HIP(hipStreamEndCapture(rs.ws, &g));
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  const long long reps = (max_rounds + check - 1) / check;
+  for (long long k = 0; k < reps && e == hipSuccess; k++) {
+    e = hipGraphLaunch(ex, rs.ws);
+    if (e == hipSuccess) e = hipMemcpyAsync(B.active_host, active, sizeof(int), hipMemcpyDeviceToHost, rs.ws);
+    if (e == hipSuccess) e = hipStreamSynchronize(rs.ws);
+    if (e == hipSuccess && *B.active_host == 0) break;
+  }
+  if (ex) (void)hipGraphExecDestroy(ex);
+  (void)hipGraphDestroy(g);
+  RBWS_HIP(e);
+  RBWS_HIP(hipEventRecord(rs.out, rs.ws));
+  RBWS_HIP(hipStreamWaitEvent(s, rs.out, 0));
+}
 
 // correctly rounded dots of `count` pairs of length len (device vectors)
 void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,

@@ -26,6 +26,7 @@ SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 LIFT_EXACT, LIFT_MFMA = 0, 1
 IR_RESTART, IR_RELIABLE = 0, 1
 FLAG_FORCE_EXACT_DOTS = 1
+FLAG_NO_GRAPH = 2
 
 
 class RbwsError(RuntimeError):
@@ -462,3 +463,20 @@ def set_tuning(key: int, value: int):
     fn.restype = C.c_int
     fn.argtypes = [C.c_int, C.c_int]
     _check(fn(key, value))
+
+
+def autotune(problem: Problem, nsolve: int, precision=FP32_IR, stream=None):
+    """Tile-depth autotuner (rbws_autotune): returns (tz, {tz: ms})."""
+    fn = getattr(_L, "rbws_autotune")
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    tz = C.c_int()
+    ms = (C.c_double * 5)()
+    _check(fn(problem.handle, nsolve, precision, _stream(stream), C.byref(tz), ms))
+    return tz.value, {t: ms[i] for i, t in enumerate((4, 8, 16, 32, 64)) if ms[i] > 0}
+
+
+def autotune_clear():
+    fn = getattr(_L, "rbws_autotune_clear")
+    fn.restype = C.c_int
+    _check(fn())

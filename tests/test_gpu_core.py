@@ -173,3 +173,44 @@ def test_cg_parity_blocks4_64_sample(rb):
         assert sg[b]["iters"] == so[t]["iters"] and sg[b]["final_rr"] == so[t]["final_rr"]
         assert np.array_equal(xg[b], xo[t])
     assert all(s["status"] == 0 for s in sg)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32ir"])
+def test_graph_replay_matches_launches(rb, precision):
+    """The iteration rounds replayed from a captured HIP graph (the default)
+    give the same trajectories, bit for bit, as launching them one by one."""
+    spec = W.Problem(20, W.KIND_OCTANTS)
+    mu = W.sample_mu(spec, 0.01, 100.0, 6, 31)
+    P = rb.Problem(spec)
+    prec = rb.FP64 if precision == "fp64" else rb.FP32_IR
+    outs = []
+    for flags in (0, rb.FLAG_NO_GRAPH, 0):
+        u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mu))]
+        st = rb.solve([P], mu, rb.default_opts(tol=1e-10, precision=prec, flags=flags, check_every=3), u_out=u)
+        torch.cuda.synchronize()
+        outs.append(([(s["iters"], s["outer_iters"], s["final_rr"], s["status"]) for s in st],
+                     np.stack([t.cpu().numpy() for t in u])))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        assert np.array_equal(o[1], outs[0][1])
+    if precision == "fp64":
+        O = oracle.Problem(spec)
+        xo, so = O.cg_batch(mu, tol=1e-10)
+        assert [s["iters"] for s in so] == [t[0] for t in outs[0][0]]
+        assert np.array_equal(xo, outs[0][1])
+
+
+def test_autotune_keeps_results(rb):
+    wl = W.blocks3_16()
+    P = rb.Problem(wl.problem)
+    mu = W.sample_mu(wl.problem, wl.mu_lo, wl.mu_hi, wl.n_test, W.SEED_TEST)
+    try:
+        tz, ms = rb.autotune(P, len(mu), rb.FP64)
+        assert tz in (4, 8, 16) and tz in ms and all(v > 0 for v in ms.values())
+        O = oracle.Problem(wl.problem)
+        xo, so = O.cg_batch(mu, prec=1, tol=wl.tol)
+        xg, sg = run_gpu_cg(rb, wl.problem, mu, 1, wl.tol)
+        assert [s["iters"] for s in sg] == [s["iters"] for s in so]
+        assert np.array_equal(xg, xo)
+    finally:
+        rb.autotune_clear()
