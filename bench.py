@@ -92,6 +92,9 @@ def main():
     opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
                              eta_inner=args.eta, init=rbws.INIT_RB, lift=rbws.LIFT_MFMA,
                              ir_mode=rbws.IR_RELIABLE)
+    # tile depth for this grid size and batch (setup, like the offline stage)
+    tz, tz_ms = rbws.autotune(P, args.batch, rbws.FP32_IR)
+    log(f"autotuned tile depth {tz}: {tz_ms}")
     if args.counters:
         # rocprofv3 counter run: one step as timed below, then a plain copy of known size
         st = solve_step(rbws, P, basis, mu, opts)
@@ -174,9 +177,10 @@ def main():
         learned = learned_leg(rbws, W, wl, spec, P, basis, mu, args)
         log(f"learned start: {learned}")
 
-    # SpMV bandwidth (16 solves at 128^3, beyond the 256 MB infinity cache)
+    # SpMV bandwidth (64 solves at 128^3, well beyond the 256 MB infinity cache)
     spmv = {}
-    nb = 16
+    nb = 64
+    spmv_tz, _ = rbws.autotune(P, nb, rbws.FP32_IR)
     for name, dt, bpd, prec in (("fp32", torch.float32, 8, rbws.FP32_IR), ("fp64", torch.float64, 16, rbws.FP64)):
         x = torch.randn(nb, nd, dtype=dt, device="cuda")
         y = torch.empty_like(x)
@@ -224,6 +228,8 @@ def main():
         "latency_ms_p99": float(np.percentile(lat, 99)),
         "t_off_s": round(t_off, 2),
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
+        "spmv_batch": nb,
+        "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()}},
         "kernel_ms": {k: round(v, 2) for k, v in ms.items()},
         "copy_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -274,7 +280,7 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
             "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
 
 
-KERNEL_SOURCES = ("fast.hpp", "ir.hip", "solver.hpp", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
+KERNEL_SOURCES = ("fast.hpp", "ir.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_octants128_traffic.txt")
 
 
