@@ -18,6 +18,7 @@ _SRC = os.path.join(_HERE, "rbws_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 PREC_NONE, PREC_JACOBI = 0, 1
+MG_NU, MG_OMEGA = 1, 6.0 / 7.0   # V-cycle defaults: one damped-Jacobi sweep before and after
 CONVERGED, MAXITER, BREAKDOWN, NAN = 0, 1, 2, 3
 
 
@@ -67,6 +68,10 @@ def lib():
             "orc_rhs": (None, [pp, d, d]),
             "orc_cg": (i, [pp, d, d, d, i, C.c_double, i, d, C.POINTER(Stats), d]),
             "orc_cg_batch": (None, [pp, d, i, d, d, i, C.c_double, i, d, C.POINTER(Stats), i]),
+            "orc_mg_levels": (i, [i, C.POINTER(C.c_int)]),
+            "orc_mg_apply": (i, [pp, d, i, C.c_double, d, d]),
+            "orc_mgcg": (i, [pp, d, d, d, i, C.c_double, C.c_double, i, d, C.POINTER(Stats)]),
+            "orc_mgcg_batch": (None, [pp, d, i, d, d, i, C.c_double, C.c_double, i, d, C.POINTER(Stats), i]),
             "orc_rb_assemble": (None, [i, i, i, d, d, d]),
             "orc_chol_solve": (i, [i, d, d, d]),
             "orc_lift": (None, [i, l, d, d, d]),
@@ -184,6 +189,40 @@ class Problem:
         if hist:
             return x, st.as_dict(), h[: st.iters + 1]
         return x, st.as_dict()
+
+    # -- multigrid preconditioner (Alg. 2) and MGCG ----------------------
+    def mg_levels(self):
+        out = (C.c_int * 16)()
+        k = lib().orc_mg_levels(self.n, out)
+        return [out[i] for i in range(k)]
+
+    def mg_apply(self, mu, r, nu=MG_NU, omega=MG_OMEGA) -> np.ndarray:
+        """s = MG(r): one V-cycle (Alg. 2) with zero initial value."""
+        s = np.empty(self.ndof)
+        rc = lib().orc_mg_apply(self.ref, _dp(_f64(mu)), nu, omega, _dp(_f64(r)), _dp(s))
+        if rc != 0:
+            raise ArithmeticError("coarsest operator not positive definite")
+        return s
+
+    def mgcg(self, mu, f=None, u0=None, nu=MG_NU, omega=MG_OMEGA, tol=1e-10, maxit=50000):
+        """MGCG: Alg. 1 with the V-cycle of Alg. 2 as P; returns (x, stats)."""
+        mu = _f64(mu)
+        f = self.rhs(mu) if f is None else _f64(f)
+        x = np.empty(self.ndof)
+        st = Stats()
+        lib().orc_mgcg(self.ref, _dp(mu), _dp(f), _dp(None if u0 is None else _f64(u0)), nu, omega, tol, maxit,
+                       _dp(x), C.byref(st))
+        return x, st.as_dict()
+
+    def mgcg_batch(self, mu, u0=None, nu=MG_NU, omega=MG_OMEGA, tol=1e-10, maxit=50000, nthreads=None):
+        mu = _f64(mu)
+        B = mu.shape[0]
+        f = np.stack([self.rhs(m) for m in mu]) if B else np.zeros((0, self.ndof))
+        x = np.empty((B, self.ndof))
+        st = (Stats * max(B, 1))()
+        lib().orc_mgcg_batch(self.ref, _dp(mu), B, _dp(f), _dp(None if u0 is None else _f64(u0)), nu, omega,
+                             tol, maxit, _dp(x), st, nthreads or nthreads_default())
+        return x, [st[i].as_dict() for i in range(B)]
 
     def cg_batch(self, mu, u0=None, prec=PREC_JACOBI, tol=1e-10, maxit=50000, nthreads=None,
                  f=None):

@@ -414,15 +414,24 @@ static void precond_apply(int prec, const double *d, const double *r, double *s,
     else memcpy(s, r, sizeof(double) * m);
 }
 
-/* Residual history: hist[0] = ||r0||^2, hist[k] = recursive ||r||^2 after
- * iteration k (at most maxit+1 entries). */
-static int cg_faces(const faces *F, int n, const double *f, const double *u0, int prec,
+/* A preconditioner P(.) of Alg. 1: s = P(r). */
+typedef void (*precond_fn)(void *ctx, const double *r, double *s);
+
+typedef struct { int prec; const double *d; long m; } simple_prec;
+static void simple_prec_apply(void *ctx, const double *r, double *s) {
+    const simple_prec *c = ctx;
+    precond_apply(c->prec, c->d, r, s, c->m);
+}
+
+/* Alg. 1 with a generic preconditioner.  Residual history: hist[0] =
+ * ||r0||^2, hist[k] = recursive ||r||^2 after iteration k (at most maxit+1
+ * entries).  rho = r^T s is a correctly rounded dot (for P = identity it is
+ * ||r||^2). */
+static int pcg_core(const faces *F, int n, const double *f, const double *u0, precond_fn pre, void *ctx,
                     double tol, int maxit, double *x, orc_stats *st, double *hist) {
     long m = (long)n * n * n;
     double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * m);
     double *p = malloc(sizeof(double) * m), *q = malloc(sizeof(double) * m);
-    double *d = malloc(sizeof(double) * m);
-    diag_faces(F, n, d);
     memset(st, 0, sizeof *st);
     double ff = orc_exact_dot(f, f, m);
     double thr = (tol * tol) * ff;
@@ -440,8 +449,8 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
     if (!isfinite(rr)) { status = ORC_NAN; goto done; }
     if (rr <= thr) { status = ORC_CONVERGED; goto done; }
     /* Alg. 1 steps 3-4: s0 = P(r0), p0 = s0 */
-    precond_apply(prec, d, r, s, m);
-    rho = (prec == ORC_PREC_JACOBI) ? orc_exact_dot(r, s, m) : rr;
+    pre(ctx, r, s);
+    rho = orc_exact_dot(r, s, m);
     memcpy(p, s, sizeof(double) * m);
     for (;;) {
         if (k >= maxit) { status = ORC_MAXITER; break; }
@@ -458,8 +467,6 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
         rr = orc_exact_dot(r, r, m);
         if (hist) hist[k] = rr;
         if (!isfinite(rr)) { status = ORC_NAN; break; }
-        precond_apply(prec, d, r, s, m);
-        double rs = (prec == ORC_PREC_JACOBI) ? orc_exact_dot(r, s, m) : rr;
         if (rr <= thr) {
             /* recursive residual meets the tolerance: confirm with f - A x */
             apply_faces(F, n, x, q);
@@ -469,11 +476,13 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
             if (!isfinite(rr)) { status = ORC_NAN; break; }
             if (rr <= thr) { status = ORC_CONVERGED; break; }
             /* restart from the true residual */
-            precond_apply(prec, d, r, s, m);
-            rho = (prec == ORC_PREC_JACOBI) ? orc_exact_dot(r, s, m) : rr;
+            pre(ctx, r, s);
+            rho = orc_exact_dot(r, s, m);
             memcpy(p, s, sizeof(double) * m);
             continue;
         }
+        pre(ctx, r, s);
+        double rs = orc_exact_dot(r, s, m);
         double beta = rs / rho;
         for (long i = 0; i < m; i++) p[i] = fma(beta, p[i], s[i]);
         rho = rs;
@@ -483,8 +492,282 @@ done:
     st->extra_spmv = extra;
     st->status = status;
     st->final_rr = rr;
-    free(r); free(s); free(p); free(q); free(d);
+    free(r); free(s); free(p); free(q);
     return status;
+}
+
+static int cg_faces(const faces *F, int n, const double *f, const double *u0, int prec,
+                    double tol, int maxit, double *x, orc_stats *st, double *hist) {
+    long m = (long)n * n * n;
+    double *d = malloc(sizeof(double) * m);
+    diag_faces(F, n, d);
+    simple_prec c = {prec, d, m};
+    int rc = pcg_core(F, n, f, u0, simple_prec_apply, &c, tol, maxit, x, st, hist);
+    free(d);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Multigrid V-cycle preconditioner (Alg. 2) and MGCG                    */
+/* ------------------------------------------------------------------ */
+/* Levels: n_0 = n (finest), n_{l+1} = (n_l - 1) / 2 while n_l > 3.  Level
+ * operators are the same 7-point rule on the coarser grid (rediscretised;
+ * the paper forms P^T A P instead).  Vertex grids with n+1 intervals are not
+ * nested when n+1 is odd, so the prolongation P is trilinear interpolation
+ * between the grids: fine node i (at i/(nf+1)) lies in the coarse interval
+ * [I, I+1] with I = floor(i (nc+1) / (nf+1)) and weight
+ * w = (i (nc+1) - I (nf+1)) / (nf+1) on node I+1 (1 - w on node I); coarse
+ * nodes 0 and nc+1 are on the boundary (value 0).  Restriction is
+ * R = ((nc+1)/(nf+1)) P^T: with unscaled operators (A = h^2 L_h) this keeps
+ * the coarse right-hand side consistent with the coarse operator.  The
+ * coarsest level is solved exactly by a dense Cholesky factorisation.
+ * Smoother: damped Jacobi e <- e + omega (b - A e) / d, nu sweeps before and
+ * after the coarse correction, so the V-cycle is a symmetric operator.
+ *
+ * Fixed evaluation orders (the GPU follows the same ones):
+ *   Jacobi: q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
+ *   restriction: acc = 0, loop k, j, i ascending over the fine points whose
+ *     weight on the coarse node may be nonzero, acc = fma((px py) pz, r, acc),
+ *     then acc * ((nc+1)/(nf+1))
+ *   prolongation: v = 0, corners z, y, x in order 0, 1 (interior corners
+ *     only), v = fma((wx wy) wz, e_c, v), then e = e + v
+ *   coarse solve: Cholesky and the two triangular solves with sequential
+ *     fma accumulation in index order. */
+#define MG_MAXLEV 16
+typedef struct {
+    int nlev, nu;
+    double omega;
+    int n[MG_MAXLEV];
+    faces F[MG_MAXLEV];
+    double *d[MG_MAXLEV];
+    int *ci[MG_MAXLEV];      /* transfer l -> l+1: coarse interval of fine index i (1..n_l) */
+    double *cw[MG_MAXLEV];   /* its weight on the upper coarse node */
+    double *b[MG_MAXLEV], *e[MG_MAXLEV], *t[MG_MAXLEV];
+    double *L;               /* coarsest Cholesky factor (mc x mc, row-major) */
+    int mc;
+} mg_ctx;
+
+int orc_mg_levels(int n, int *out) {
+    int k = 0;
+    out[k++] = n;
+    while (out[k - 1] > 3 && k < MG_MAXLEV) { out[k] = (out[k - 1] - 1) / 2; k++; }
+    return k;
+}
+
+static void mg_transfer_table(int nf, int nc, int *ci, double *cw) {
+    for (int i = 1; i <= nf; i++) {
+        long I = ((long)i * (nc + 1)) / (nf + 1);
+        ci[i - 1] = (int)I;
+        cw[i - 1] = (double)((long)i * (nc + 1) - I * (nf + 1)) / (double)(nf + 1);
+    }
+}
+
+/* damped Jacobi sweep e_out = e_in + omega (b - A e_in) / d (e_in NULL = 0) */
+static void mg_jacobi(const mg_ctx *c, int l, const double *b, const double *ein, double *eout) {
+    int n = c->n[l];
+    long m = (long)n * n * n;
+    if (ein) apply_faces(&c->F[l], n, ein, c->t[l]);
+    for (long i = 0; i < m; i++) {
+        double q = ein ? c->t[l][i] : 0.0;
+        double t = b[i] - q;
+        t = t / c->d[l][i];
+        eout[i] = fma(c->omega, t, ein ? ein[i] : 0.0);
+    }
+}
+
+/* rc = ((nc+1)/(nf+1)) P^T rf */
+static void mg_restrict(const mg_ctx *c, int l, const double *rf, double *rc) {
+    int nf = c->n[l], nc = c->n[l + 1];
+    const int *ci = c->ci[l];
+    const double *cw = c->cw[l];
+    double scale = (double)(nc + 1) / (double)(nf + 1);
+    /* fine index ranges per coarse index: i with ci in {I-1, I} */
+    int *lo = malloc(sizeof(int) * (nc + 2)), *hi = malloc(sizeof(int) * (nc + 2));
+    for (int I = 1; I <= nc; I++) {
+        lo[I] = nf + 1; hi[I] = 0;
+        for (int i = 1; i <= nf; i++)
+            if (ci[i - 1] == I - 1 || ci[i - 1] == I) { if (i < lo[I]) lo[I] = i; if (i > hi[I]) hi[I] = i; }
+    }
+    for (int K = 1; K <= nc; K++)
+        for (int J = 1; J <= nc; J++)
+            for (int I = 1; I <= nc; I++) {
+                double acc = 0.0;
+                for (int k = lo[K]; k <= hi[K]; k++) {
+                    double pz = ci[k - 1] == K ? 1.0 - cw[k - 1] : cw[k - 1];
+                    for (int j = lo[J]; j <= hi[J]; j++) {
+                        double py = ci[j - 1] == J ? 1.0 - cw[j - 1] : cw[j - 1];
+                        for (int i = lo[I]; i <= hi[I]; i++) {
+                            double px = ci[i - 1] == I ? 1.0 - cw[i - 1] : cw[i - 1];
+                            long f = ((long)(k - 1) * nf + (j - 1)) * nf + (i - 1);
+                            acc = fma((px * py) * pz, rf[f], acc);
+                        }
+                    }
+                }
+                rc[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)] = acc * scale;
+            }
+    free(lo); free(hi);
+}
+
+/* ef += P ec */
+static void mg_prolong(const mg_ctx *c, int l, const double *ec, double *ef) {
+    int nf = c->n[l], nc = c->n[l + 1];
+    const int *ci = c->ci[l];
+    const double *cw = c->cw[l];
+    for (int k = 1; k <= nf; k++)
+        for (int j = 1; j <= nf; j++)
+            for (int i = 1; i <= nf; i++) {
+                double v = 0.0;
+                for (int cz = 0; cz < 2; cz++) {
+                    int K = ci[k - 1] + cz;
+                    if (K < 1 || K > nc) continue;
+                    double wz = cz ? cw[k - 1] : 1.0 - cw[k - 1];
+                    for (int cy = 0; cy < 2; cy++) {
+                        int J = ci[j - 1] + cy;
+                        if (J < 1 || J > nc) continue;
+                        double wy = cy ? cw[j - 1] : 1.0 - cw[j - 1];
+                        for (int cx = 0; cx < 2; cx++) {
+                            int I = ci[i - 1] + cx;
+                            if (I < 1 || I > nc) continue;
+                            double wx = cx ? cw[i - 1] : 1.0 - cw[i - 1];
+                            v = fma((wx * wy) * wz, ec[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+                        }
+                    }
+                }
+                long f = ((long)(k - 1) * nf + (j - 1)) * nf + (i - 1);
+                ef[f] = ef[f] + v;
+            }
+}
+
+/* dense Cholesky of the coarsest operator (mc <= 27), row-major lower factor */
+static int mg_factor(mg_ctx *c) {
+    int l = c->nlev - 1, n = c->n[l];
+    int mc = n * n * n;
+    c->mc = mc;
+    double *A = calloc((size_t)mc * mc, sizeof(double));
+    double *u = calloc(mc, sizeof(double)), *y = malloc(sizeof(double) * mc);
+    for (int j = 0; j < mc; j++) {            /* column j = A e_j */
+        u[j] = 1.0;
+        apply_faces(&c->F[l], n, u, y);
+        for (int i = 0; i < mc; i++) A[(long)i * mc + j] = y[i];
+        u[j] = 0.0;
+    }
+    double *L = calloc((size_t)mc * mc, sizeof(double));
+    int bad = 0;
+    for (int j = 0; j < mc && !bad; j++) {
+        double s = A[(long)j * mc + j];
+        for (int k = 0; k < j; k++) s = fma(-L[(long)j * mc + k], L[(long)j * mc + k], s);
+        if (!(s > 0.0)) { bad = 1; break; }
+        double ljj = sqrt(s);
+        L[(long)j * mc + j] = ljj;
+        for (int i = j + 1; i < mc; i++) {
+            double t = A[(long)i * mc + j];
+            for (int k = 0; k < j; k++) t = fma(-L[(long)i * mc + k], L[(long)j * mc + k], t);
+            L[(long)i * mc + j] = t / ljj;
+        }
+    }
+    free(A); free(u); free(y);
+    c->L = L;
+    return bad;
+}
+
+static void mg_coarse_solve(const mg_ctx *c, const double *b, double *x) {
+    int m = c->mc;
+    const double *L = c->L;
+    double *y = malloc(sizeof(double) * m);
+    for (int i = 0; i < m; i++) {
+        double s = b[i];
+        for (int k = 0; k < i; k++) s = fma(-L[(long)i * m + k], y[k], s);
+        y[i] = s / L[(long)i * m + i];
+    }
+    for (int i = m - 1; i >= 0; i--) {
+        double s = y[i];
+        for (int k = i + 1; k < m; k++) s = fma(-L[(long)k * m + i], x[k], s);
+        x[i] = s / L[(long)i * m + i];
+    }
+    free(y);
+}
+
+/* Alg. 2 at level l: e = MG(b) */
+static void mg_vcycle(const mg_ctx *c, int l, const double *b, double *e) {
+    if (l == c->nlev - 1) { mg_coarse_solve(c, b, e); return; }
+    int n = c->n[l];
+    long m = (long)n * n * n;
+    double *tmp = malloc(sizeof(double) * m);
+    /* pre-smoothing from zero */
+    mg_jacobi(c, l, b, NULL, e);
+    for (int s = 1; s < c->nu; s++) { mg_jacobi(c, l, b, e, tmp); memcpy(e, tmp, sizeof(double) * m); }
+    /* residual, restriction, coarse correction, prolongation */
+    apply_faces(&c->F[l], n, e, c->t[l]);
+    for (long i = 0; i < m; i++) tmp[i] = b[i] - c->t[l][i];
+    mg_restrict(c, l, tmp, c->b[l + 1]);
+    mg_vcycle(c, l + 1, c->b[l + 1], c->e[l + 1]);
+    mg_prolong(c, l, c->e[l + 1], e);
+    /* post-smoothing */
+    for (int s = 0; s < c->nu; s++) { mg_jacobi(c, l, b, e, tmp); memcpy(e, tmp, sizeof(double) * m); }
+    free(tmp);
+}
+
+static void mg_prec_apply(void *ctx, const double *r, double *s) { mg_vcycle(ctx, 0, r, s); }
+
+static int mg_setup(mg_ctx *c, const orc_problem *P, const double *mu, int nu, double omega) {
+    memset(c, 0, sizeof *c);
+    c->nu = nu;
+    c->omega = omega;
+    c->nlev = orc_mg_levels(P->n, c->n);
+    for (int l = 0; l < c->nlev; l++) {
+        orc_problem Pl = *P;
+        Pl.n = c->n[l];
+        c->F[l] = faces_for_mu(&Pl, mu);
+        long m = (long)c->n[l] * c->n[l] * c->n[l];
+        c->d[l] = malloc(sizeof(double) * m);
+        diag_faces(&c->F[l], c->n[l], c->d[l]);
+        c->b[l] = malloc(sizeof(double) * m);
+        c->e[l] = malloc(sizeof(double) * m);
+        c->t[l] = malloc(sizeof(double) * m);
+        if (l + 1 < c->nlev) {
+            c->ci[l] = malloc(sizeof(int) * c->n[l]);
+            c->cw[l] = malloc(sizeof(double) * c->n[l]);
+        }
+    }
+    for (int l = 0; l + 1 < c->nlev; l++) mg_transfer_table(c->n[l], c->n[l + 1], c->ci[l], c->cw[l]);
+    return mg_factor(c);
+}
+
+static void mg_free(mg_ctx *c) {
+    for (int l = 0; l < c->nlev; l++) {
+        faces_free(c->F[l]);
+        free(c->d[l]); free(c->b[l]); free(c->e[l]); free(c->t[l]);
+        free(c->ci[l]); free(c->cw[l]);
+    }
+    free(c->L);
+}
+
+/* s = MG(r) for one mu (the V-cycle as an operator, for tests) */
+int orc_mg_apply(const orc_problem *P, const double *mu, int nu, double omega, const double *r, double *s) {
+    mg_ctx c;
+    int bad = mg_setup(&c, P, mu, nu, omega);
+    if (!bad) mg_prec_apply(&c, r, s);
+    mg_free(&c);
+    return bad;
+}
+
+/* MGCG: Alg. 1 with s = MG(r) (Alg. 2), from u0 (NULL = 0) */
+int orc_mgcg(const orc_problem *P, const double *mu, const double *f, const double *u0, int nu, double omega,
+             double tol, int maxit, double *x, orc_stats *st) {
+    mg_ctx c;
+    if (mg_setup(&c, P, mu, nu, omega)) { mg_free(&c); memset(st, 0, sizeof *st); st->status = ORC_BREAKDOWN; return ORC_BREAKDOWN; }
+    int s = pcg_core(&c.F[0], P->n, f, u0, mg_prec_apply, &c, tol, maxit, x, st, NULL);
+    mg_free(&c);
+    return s;
+}
+
+void orc_mgcg_batch(const orc_problem *P, const double *mu, int nmu, const double *f, const double *u0, int nu,
+                    double omega, double tol, int maxit, double *x, orc_stats *st, int nthreads) {
+    long m = ndof_of(P);
+    int p = P->kind == ORC_BLOCKS ? P->nblocks : (P->kind == ORC_OCTANTS ? 8 : 24 + (P->f_kind == ORC_F_GAUSS ? 3 : 0));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int b = 0; b < nmu; b++)
+        orc_mgcg(P, mu + (long)b * p, f + b * m, u0 ? u0 + b * m : NULL, nu, omega, tol, maxit, x + b * m, st + b);
 }
 
 int orc_cg(const orc_problem *P, const double *mu, const double *f, const double *u0, int prec,
