@@ -66,7 +66,9 @@ enum {
 };
 enum { RBWS_INIT_ZERO = 0, RBWS_INIT_RB = 1, RBWS_INIT_LEARNED = 2 };
 enum { RBWS_FP64 = 0, RBWS_FP32_IR = 1 };
-enum { RBWS_PREC_NONE = 0, RBWS_PREC_JACOBI = 1 };
+/* the P of Alg. 1: identity, Jacobi (P r = r / diag A), or one multigrid
+ * V-cycle (Alg. 2; see rbws_solve_opts.mg_nu) */
+enum { RBWS_PREC_NONE = 0, RBWS_PREC_JACOBI = 1, RBWS_PREC_MG = 2 };
 enum {
   RBWS_SOLVE_CONVERGED = 0,
   RBWS_SOLVE_MAXITER = 1,   /* the iteration limit (L_max of Alg. 1) was reached */
@@ -99,7 +101,7 @@ typedef struct rbws_mlp rbws_mlp;
  * a sub-domain boundary along t axes it is the mean of the 2^t one-sided
  * values.  Copied during rbws_problem_create. */
 typedef struct {
-  int n;              /* interior points per axis, 2 <= n <= 1024 */
+  int n;              /* interior points per axis, 1 <= n <= 1024 */
   int kind;           /* RBWS_KIND_* */
   int nblocks;        /* RBWS_KIND_BLOCKS: number of blocks, 1..31 */
   const int* blocks;  /* host, [nblocks][6], RBWS_KIND_BLOCKS only */
@@ -136,14 +138,27 @@ typedef struct {
   int flags;         /* RBWS_FLAG_* */
   int check_every;   /* rounds between host checks for completion (0 = library default) */
   int ir_mode;       /* RBWS_IR_RESTART or RBWS_IR_RELIABLE (FP32_IR only) */
+  int mg_nu;         /* RBWS_PREC_MG: damped-Jacobi sweeps before and after the coarse
+                        correction on every level (1..8) */
+  double mg_omega;   /* RBWS_PREC_MG: Jacobi damping, in (0, 1] */
 } rbws_solve_opts;
+/* The multigrid preconditioner (Alg. 2, V-cycle from a zero initial value):
+ * levels n_0 = n, n_{l+1} = (n_l - 1) / 2 while n_l > 3; every level uses the
+ * same 7-point face rule on its own grid (rediscretised, not P^T A P);
+ * prolongation is trilinear interpolation between the vertex grids (which are
+ * not nested when n + 1 is odd), restriction ((n_c+1)/(n_f+1)) P^T; the
+ * coarsest level is solved exactly (dense Cholesky, at most 27 unknowns).
+ * The V-cycle is a fixed symmetric positive definite operator, so PCG applies;
+ * with RBWS_FP64 every step is evaluated in a fixed order and the trajectory
+ * is reproducible bit for bit. */
 
 /* ---- errors and defaults ------------------------------------------------ */
 const char* rbws_last_error(void);
 const char* rbws_version(void);
 /* Fill *o with defaults: tol 1e-10, max_iter 50000, Jacobi, FP64, zero start,
  * exact lift, eta_inner 0.1, max_outer 40, fallback 0, flags 0, reliable updates
- * (classic restarted refinement works best with eta_inner about 1e-4). */
+ * (classic restarted refinement works best with eta_inner about 1e-4),
+ * mg_nu 1, mg_omega 6/7. */
 void rbws_solve_opts_default(rbws_solve_opts* o);
 
 /* ---- operator setup (Eq. 1; Sec. 4 model PDE) ----------------------------
@@ -308,8 +323,9 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
  * thread, accumulated by kind: 0 A.p sweep (with the fused direction update),
  * 1 residual pass (initial / confirmation / refinement outer pass), 2 and 4
  * the per-solve scalar steps after each sweep, 3 update sweep (x, r and their
- * inner products), 5 SpMV, 6 MFMA lift, 7 reduced solves.  The call first
- * waits for recorded events and returns the totals so far (ms[8], launches[8],
+ * inner products), 5 SpMV, 6 MFMA lift, 7 reduced solves, 8 multigrid
+ * V-cycle with r^T s.  The call first
+ * waits for recorded events and returns the totals so far (ms[9], launches[9],
  * both nullable), then zeroes them if `reset`, then turns timing on or off. */
 rbws_status rbws_profile(int enable, double* ms, long long* launches, int reset);
 /* How often a correctly rounded inner product could not be certified from

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librbws.so")
 ARCH = os.environ.get("RBWS_ARCH", "gfx950")
 
-SOURCES = ["problem.cpp", "solver.hip", "rb.hip", "ir.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["problem.cpp", "solver.hip", "rb.hip", "ir.hip", "mg.hip", "mlp.hip", "capi.hip"]
 
 # -ffp-contract=off: every fused multiply-add in the FP64 path is explicit,
 # so results do not depend on the compiler's contraction choices.

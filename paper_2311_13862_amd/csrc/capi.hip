@@ -54,7 +54,8 @@ void collect_stats(Batch& B, unsigned long long t0, const std::vector<int>& init
     std::memset(&o, 0, sizeof o);
     o.iters = st[b].k;
     o.extra_spmv = st[b].extra;
-    o.outer_iters = outer_field_from_extra ? st[b].pad0 : 0;
+    o.outer_iters = 0;
+    (void)outer_field_from_extra;
     o.status = st[b].status < 0 ? RBWS_SOLVE_MAXITER : st[b].status;
     o.init_used = init_used[b];
     o.init_rr = st[b].init_rr;
@@ -184,6 +185,8 @@ void rbws_solve_opts_default(rbws_solve_opts* o) {
   o->flags = 0;
   o->check_every = 0;
   o->ir_mode = RBWS_IR_RELIABLE;
+  o->mg_nu = 1;
+  o->mg_omega = 6.0 / 7.0;
 }
 
 rbws_status rbws_problem_create(const rbws_problem_desc* desc, int device, rbws_problem** out) {
@@ -427,8 +430,12 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   RBWS_REQUIRE(opts != nullptr, RBWS_EINVAL, "opts is NULL");
   RBWS_REQUIRE(opts->tol >= 0.0 && std::isfinite(opts->tol), RBWS_EINVAL, "tol must be finite, >= 0");
   RBWS_REQUIRE(opts->max_iter >= 0, RBWS_EINVAL, "max_iter < 0");
-  RBWS_REQUIRE(opts->precond == RBWS_PREC_NONE || opts->precond == RBWS_PREC_JACOBI, RBWS_EINVAL,
-               "bad precond");
+  RBWS_REQUIRE(opts->precond == RBWS_PREC_NONE || opts->precond == RBWS_PREC_JACOBI ||
+                   opts->precond == RBWS_PREC_MG,
+               RBWS_EINVAL, "bad precond");
+  RBWS_REQUIRE(opts->precond != RBWS_PREC_MG ||
+                   (opts->mg_nu >= 1 && opts->mg_nu <= 8 && opts->mg_omega > 0.0 && opts->mg_omega <= 1.0),
+               RBWS_EINVAL, "bad multigrid settings (mg_nu in 1..8, mg_omega in (0, 1])");
   RBWS_REQUIRE(opts->precision == RBWS_FP64 || opts->precision == RBWS_FP32_IR, RBWS_EINVAL,
                "bad precision");
   RBWS_REQUIRE(opts->init >= RBWS_INIT_ZERO && opts->init <= RBWS_INIT_LEARNED, RBWS_EINVAL, "bad init");
@@ -488,7 +495,8 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
   std::vector<const double*> sol(nmu);
   std::vector<IrHost> ir;
   if (opts->precision == RBWS_FP64) {
-    CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every};
+    CgOpts co{opts->tol, opts->max_iter, opts->precond, opts->flags, opts->check_every, opts->mg_nu,
+              opts->mg_omega};
     cg_fp64_run(B, co, s);
     for (int b = 0; b < nmu; b++) sol[b] = x + B.sd_h[b].off;
   } else {
@@ -497,6 +505,7 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
     RBWS_REQUIRE(opts->max_iter >= 1, RBWS_EINVAL, "max_iter < 1 for refinement");
     RBWS_REQUIRE(opts->ir_mode == RBWS_IR_RESTART || opts->ir_mode == RBWS_IR_RELIABLE, RBWS_EINVAL,
                  "bad ir_mode");
+    RBWS_REQUIRE(opts->precond != RBWS_PREC_MG, RBWS_EINVAL, "multigrid inside refinement: not available");
     IrOpts io{opts->tol, opts->eta_inner, opts->precond, opts->max_iter, opts->max_outer, opts->flags,
               opts->check_every, opts->ir_mode == RBWS_IR_RELIABLE ? 1 : 0};
     ir_run(B, io, s, ir);

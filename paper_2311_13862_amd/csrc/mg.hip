@@ -1,0 +1,474 @@
+// mg.hip -- multigrid V-cycle preconditioner (the paper's Alg. 2) for the
+// batched PCG of Alg. 1 (MGCG), in FP64 (reproducible) or FP32 (refinement).
+//
+// Hierarchy: n_0 = n, n_{l+1} = (n_l - 1) / 2 while n_l > 3.  Every level is
+// the same 7-point face rule on its own grid (the paper forms P^T A P; the
+// rediscretised operator keeps the matrix-free class-table form on every
+// level).  Vertex grids with n+1 intervals are not nested when n+1 is odd, so
+// P is trilinear interpolation between them: fine node i (at i/(nf+1)) lies in
+// coarse interval I = floor(i (nc+1) / (nf+1)) with weight
+// w = (i (nc+1) - I (nf+1)) / (nf+1) on node I+1 and 1 - w on node I; coarse
+// boundary nodes carry 0.  R = ((nc+1)/(nf+1)) P^T keeps the coarse right-hand
+// side consistent with the unscaled coarse operator.  The coarsest level (at
+// most 27 unknowns) is solved by a per-solve dense Cholesky factorisation.
+// Smoother: damped Jacobi, nu sweeps before and after the coarse correction.
+//
+// Kernels are one thread per grid point (per coarse point for the
+// restriction, per solve for the coarsest solve), with a fixed evaluation
+// order for every value:
+//   Jacobi        q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
+//   restriction   acc = fma((px py) pz, r, acc) over k, j, i ascending, then acc * scale
+//   prolongation  v = fma((wx wy) wz, e_c, v) over corners z, y, x (interior ones), e + v
+//   coarsest      Cholesky and triangular solves with sequential fma accumulation
+// so that the FP64 V-cycle, and with it the whole MGCG trajectory, is
+// independent of the launch shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mg.hpp"
+#include "stencil.hpp"
+
+namespace rbws {
+
+Problem* problem_create(const rbws_problem_desc* d, int device);
+
+int mg_levels_of(int n, int* out) {
+  int k = 0;
+  out[k++] = n;
+  while (out[k - 1] > 3 && k < 16) {
+    out[k] = (out[k - 1] - 1) / 2;
+    k++;
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// device views
+// ---------------------------------------------------------------------------
+struct MgLv {
+  const ProbDev* pd;       // the level's grid
+  const SolveDev* sd;      // per group solve: offset of its coefficient table
+  const void* kap;         // coefficient tables (double or float)
+  const long long* voff;   // vector offset per group solve, or null: t * ndof
+  const int* sid;          // batch solve of each group solve
+  long long ndof;
+  int n, nsol;
+};
+
+template <typename T>
+__device__ __forceinline__ void kappa6(const GridDev& g, const T* kap, int i, int j, int k, T kk[6]) {
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  const T* kX = kap;
+  const T* kY = kap + (g.ndir == 3 ? g.nclass : 0);
+  const T* kZ = kap + (g.ndir == 3 ? 2 * g.nclass : 0);
+  const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+  const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+  const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+  kk[0] = kX[(cxm * N1 + cyn) * N2 + czn];
+  kk[1] = kX[(cxp * N1 + cyn) * N2 + czn];
+  kk[2] = kY[(cxn * N1 + cym) * N2 + czn];
+  kk[3] = kY[(cxn * N1 + cyp) * N2 + czn];
+  kk[4] = kZ[(cxn * N1 + cyn) * N2 + czm];
+  kk[5] = kZ[(cxn * N1 + cyn) * N2 + czp];
+}
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T stencilT(const T kk[6], T dg, const T* v, long long c, int n, int i, int j, int k) {
+  const long long n2 = (long long)n * n;
+  T acc = dg * v[c];
+  if (i > 1) acc = fmaT(-kk[0], v[c - 1], acc);
+  if (i < n) acc = fmaT(-kk[1], v[c + 1], acc);
+  if (j > 1) acc = fmaT(-kk[2], v[c - n], acc);
+  if (j < n) acc = fmaT(-kk[3], v[c + n], acc);
+  if (k > 1) acc = fmaT(-kk[4], v[c - n2], acc);
+  if (k < n) acc = fmaT(-kk[5], v[c + n2], acc);
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T diagT(const T kk[6]) {
+  return ((((kk[0] + kk[1]) + kk[2]) + kk[3]) + kk[4]) + kk[5];
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// e_out = e_in + omega (b - A e_in) / d  (e_in null: zero); RESID: t = b - A e_in
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_mg_point(MgLv L, const int* __restrict__ need, const T* __restrict__ b,
+                                                  const T* __restrict__ ein, T* __restrict__ out, T omega) {
+  const int t = blockIdx.y;
+  if (!need[L.sid[t]]) return;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L.ndof) return;
+  const int n = L.n;
+  const int i = (int)(c % n) + 1, j = (int)((c / n) % n) + 1, k = (int)(c / ((long long)n * n)) + 1;
+  const long long off = L.voff ? L.voff[t] : (long long)t * L.ndof;
+  T kk[6];
+  kappa6<T>(L.pd->g, (const T*)L.kap + L.sd[t].kap_off, i, j, k, kk);
+  const T dg = diagT(kk);
+  const T q = ein ? stencilT<T>(kk, dg, ein + off, c, n, i, j, k) : T(0);
+  T r = b[off + c] - q;
+  if (RESID) {
+    out[off + c] = r;
+  } else {
+    r = r / dg;
+    out[off + c] = fmaT(omega, r, ein ? ein[off + c] : T(0));
+  }
+}
+
+// b_c = scale P^T r_f, one thread per coarse point
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_restrict(MgLv F, MgLv C, const int* __restrict__ need,
+                                                     const int* __restrict__ ci, const T* __restrict__ cw,
+                                                     const int2* __restrict__ lohi, const T* __restrict__ rf,
+                                                     T* __restrict__ bc, T scale) {
+  const int t = blockIdx.y;
+  if (!need[C.sid[t]]) return;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C.ndof) return;
+  const int nc = C.n, nf = F.n;
+  const int I = (int)(c % nc) + 1, J = (int)((c / nc) % nc) + 1, K = (int)(c / ((long long)nc * nc)) + 1;
+  const T* r = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof);
+  const int2 xr = lohi[I], yr = lohi[J], zr = lohi[K];
+  T acc = T(0);
+  for (int k = zr.x; k <= zr.y; k++) {
+    const T pz = ci[k - 1] == K ? T(1) - cw[k - 1] : cw[k - 1];
+    for (int j = yr.x; j <= yr.y; j++) {
+      const T py = ci[j - 1] == J ? T(1) - cw[j - 1] : cw[j - 1];
+      const long long rowoff = ((long long)(k - 1) * nf + (j - 1)) * nf - 1;
+      for (int i = xr.x; i <= xr.y; i++) {
+        const T px = ci[i - 1] == I ? T(1) - cw[i - 1] : cw[i - 1];
+        acc = fmaT((px * py) * pz, r[rowoff + i], acc);
+      }
+    }
+  }
+  bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + c] = acc * scale;
+}
+
+// e_f += P e_c, one thread per fine point
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_prolong(MgLv F, MgLv C, const int* __restrict__ need,
+                                                    const int* __restrict__ ci, const T* __restrict__ cw,
+                                                    const T* __restrict__ ec, T* __restrict__ ef) {
+  const int t = blockIdx.y;
+  if (!need[F.sid[t]]) return;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= F.ndof) return;
+  const int nf = F.n, nc = C.n;
+  const int i = (int)(c % nf) + 1, j = (int)((c / nf) % nf) + 1, k = (int)(c / ((long long)nf * nf)) + 1;
+  const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
+  const int I0 = ci[i - 1], J0 = ci[j - 1], K0 = ci[k - 1];
+  const T wx1 = cw[i - 1], wy1 = cw[j - 1], wz1 = cw[k - 1];
+  T v = T(0);
+  for (int cz = 0; cz < 2; cz++) {
+    const int K = K0 + cz;
+    if (K < 1 || K > nc) continue;
+    const T wz = cz ? wz1 : T(1) - wz1;
+    for (int cy = 0; cy < 2; cy++) {
+      const int J = J0 + cy;
+      if (J < 1 || J > nc) continue;
+      const T wy = cy ? wy1 : T(1) - wy1;
+      for (int cx = 0; cx < 2; cx++) {
+        const int I = I0 + cx;
+        if (I < 1 || I > nc) continue;
+        const T wx = cx ? wx1 : T(1) - wx1;
+        v = fmaT((wx * wy) * wz, e[((long long)(K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+      }
+    }
+  }
+  T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof);
+  o[c] = o[c] + v;
+}
+
+// dense Cholesky of each solve's coarsest operator (FP64 tables), one thread
+// per solve; L (mc x mc, row-major lower) is assembled in place
+__global__ void k_mg_factor(MgLv C, double* __restrict__ Lall, int* __restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C.nsol) return;
+  const int n = C.n, mc = (int)C.ndof;
+  double* A = Lall + (long long)t * mc * mc;
+  for (int e = 0; e < mc * mc; e++) A[e] = 0.0;
+  const double* kap = (const double*)C.kap + C.sd[t].kap_off;
+  for (int r = 0; r < mc; r++) {
+    const int i = r % n + 1, j = (r / n) % n + 1, k = r / (n * n) + 1;
+    double kk[6];
+    kappa6<double>(C.pd->g, kap, i, j, k, kk);
+    A[r * mc + r] = diagT(kk);
+    if (i > 1) A[r * mc + r - 1] = -kk[0];
+    if (i < n) A[r * mc + r + 1] = -kk[1];
+    if (j > 1) A[r * mc + r - n] = -kk[2];
+    if (j < n) A[r * mc + r + n] = -kk[3];
+    if (k > 1) A[r * mc + r - n * n] = -kk[4];
+    if (k < n) A[r * mc + r + n * n] = -kk[5];
+  }
+  // in place: the strict upper triangle is never read again
+  for (int jj = 0; jj < mc; jj++) {
+    double s = A[jj * mc + jj];
+    for (int kq = 0; kq < jj; kq++) s = __fma_rn(-A[jj * mc + kq], A[jj * mc + kq], s);
+    if (!(s > 0.0)) {
+      atomicAdd(bad, 1);
+      return;
+    }
+    const double ljj = sqrt(s);
+    A[jj * mc + jj] = ljj;
+    for (int ii = jj + 1; ii < mc; ii++) {
+      double u = A[ii * mc + jj];
+      for (int kq = 0; kq < jj; kq++) u = __fma_rn(-A[ii * mc + kq], A[jj * mc + kq], u);
+      A[ii * mc + jj] = u / ljj;
+    }
+  }
+}
+
+// e = A_c^{-1} b by the stored factor (FP64 arithmetic), one thread per solve
+template <typename T>
+__global__ void k_mg_coarse(MgLv C, const int* __restrict__ need, const double* __restrict__ Lall,
+                            const T* __restrict__ b, T* __restrict__ e) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C.nsol || !need[C.sid[t]]) return;
+  const int mc = (int)C.ndof;
+  const double* L = Lall + (long long)t * mc * mc;
+  const long long off = C.voff ? C.voff[t] : (long long)t * C.ndof;
+  double y[27], x[27];
+  for (int i = 0; i < mc; i++) {
+    double s = (double)b[off + i];
+    for (int k = 0; k < i; k++) s = __fma_rn(-L[i * mc + k], y[k], s);
+    y[i] = s / L[i * mc + i];
+  }
+  for (int i = mc - 1; i >= 0; i--) {
+    double s = y[i];
+    for (int k = i + 1; k < mc; k++) s = __fma_rn(-L[k * mc + i], x[k], s);
+    x[i] = s / L[i * mc + i];
+  }
+  for (int i = 0; i < mc; i++) e[off + i] = (T)x[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct MgLevelHost {
+  const Problem* prob = nullptr;
+  Batch B;                 // the group's solves on this level's grid
+  int n = 0;
+  long long ndof = 0;
+  DevBuf ci, cwd, cwf, lohi;  // transfer to the next level
+  DevBuf vb, ve, ve2, vt;     // level vectors (levels >= 1), group-contiguous
+};
+
+struct MgGroup {
+  int q = 0;
+  std::vector<int> sol;
+  DevBuf sid, off0;
+  std::vector<MgLevelHost*> lv;
+  DevBuf L;
+  int mc = 0;
+  ~MgGroup() {
+    for (MgLevelHost* l : lv) delete l;
+  }
+};
+
+struct MgRun {
+  int nu = 1, device = 0;
+  double omega = 6.0 / 7.0;
+  bool fp32 = false;
+  std::vector<MgGroup*> g;
+  DevBuf x0, t0;  // level-0 scratch, laid out like the batch
+  ~MgRun() {
+    for (MgGroup* q : g) delete q;
+  }
+};
+
+// coarse problems, created once per (device, description, n) and kept
+static const Problem* coarse_problem(const Problem* P, int n) {
+  if (n == P->n) return P;
+  struct Ent {
+    int device, n, kind, f_kind;
+    double gw;
+    std::vector<int> blocks;
+    Problem* prob;
+  };
+  static std::vector<Ent*> cache;
+  for (Ent* e : cache)
+    if (e->device == P->device && e->n == n && e->kind == P->desc.kind && e->f_kind == P->desc.f_kind &&
+        e->gw == P->desc.gauss_width && e->blocks == P->blocks)
+      return e->prob;
+  rbws_problem_desc d = P->desc;
+  d.n = n;
+  d.blocks = P->blocks.empty() ? nullptr : P->blocks.data();
+  Ent* e = new Ent{P->device, n, P->desc.kind, P->desc.f_kind, P->desc.gauss_width, P->blocks, nullptr};
+  e->prob = problem_create(&d, P->device);
+  cache.push_back(e);
+  return e->prob;
+}
+
+static MgLv view(const MgLevelHost& l, const MgGroup& g, bool level0, bool fp32) {
+  MgLv v;
+  v.pd = (const ProbDev*)l.B.pd.ptr;
+  v.sd = (const SolveDev*)l.B.sd.ptr;
+  v.kap = fp32 ? l.B.kap32.ptr : l.B.kap64.ptr;
+  v.voff = level0 ? (const long long*)g.off0.ptr : nullptr;
+  v.sid = (const int*)g.sid.ptr;
+  v.ndof = l.ndof;
+  v.n = l.n;
+  v.nsol = (int)g.sol.size();
+  return v;
+}
+
+MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
+  static thread_local MgRun* run = nullptr;  // rebuilt per batch; never freed at exit
+  delete run;
+  run = new MgRun();
+  MgRun* m = run;
+  m->nu = nu;
+  m->omega = omega;
+  m->fp32 = fp32;
+  m->device = B.device;
+  const size_t el = fp32 ? sizeof(float) : sizeof(double);
+  m->x0.get(el * std::max<long long>(B.total, 1), B.device);
+  m->t0.get(el * std::max<long long>(B.total, 1), B.device);
+  for (int q = 0; q < B.nprob; q++) {
+    MgGroup* g = new MgGroup();
+    m->g.push_back(g);
+    g->q = q;
+    for (int b = 0; b < B.nsolve; b++)
+      if (B.sd_h[b].prob == q) g->sol.push_back(b);
+    if (g->sol.empty()) continue;
+    const int ns = (int)g->sol.size();
+    const Problem* P = B.probs[q];
+    std::vector<long long> off(ns);
+    std::vector<double> th((size_t)ns * P->Q);
+    for (int t = 0; t < ns; t++) {
+      off[t] = B.sd_h[g->sol[t]].off;
+      for (int k = 0; k < P->Q; k++) th[(size_t)t * P->Q + k] = B.theta_h[(size_t)g->sol[t] * kMaxQ + k];
+    }
+    RBWS_HIP(hipMemcpyAsync(g->sid.get(sizeof(int) * ns, B.device), g->sol.data(), sizeof(int) * ns,
+                            hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipMemcpyAsync(g->off0.get(sizeof(long long) * ns, B.device), off.data(), sizeof(long long) * ns,
+                            hipMemcpyHostToDevice, s));
+    int nl[16];
+    const int L = mg_levels_of(P->n, nl);
+    for (int l = 0; l < L; l++) {
+      MgLevelHost* lv = new MgLevelHost();
+      g->lv.push_back(lv);
+      lv->prob = coarse_problem(P, nl[l]);
+      lv->n = nl[l];
+      lv->ndof = (long long)nl[l] * nl[l] * nl[l];
+      std::vector<const Problem*> pl{lv->prob};
+      batch_setup(lv->B, pl, nullptr, ns, nullptr, P->p, s, th.data());
+      if (l > 0) {
+        lv->vb.get(el * ns * lv->ndof, B.device);
+        lv->ve.get(el * ns * lv->ndof, B.device);
+        lv->ve2.get(el * ns * lv->ndof, B.device);
+        lv->vt.get(el * ns * lv->ndof, B.device);
+      }
+    }
+    // transfer tables level l -> l+1
+    for (int l = 0; l + 1 < L; l++) {
+      const int nf = nl[l], nc = nl[l + 1];
+      std::vector<int> ci(nf);
+      std::vector<double> cw(nf);
+      std::vector<float> cwf(nf);
+      for (int i = 1; i <= nf; i++) {
+        const long long I = ((long long)i * (nc + 1)) / (nf + 1);
+        ci[i - 1] = (int)I;
+        cw[i - 1] = (double)((long long)i * (nc + 1) - I * (nf + 1)) / (double)(nf + 1);
+        cwf[i - 1] = (float)cw[i - 1];
+      }
+      std::vector<int2> lh(nc + 2, make_int2(1, 0));
+      for (int I = 1; I <= nc; I++) {
+        int lo = nf + 1, hi = 0;
+        for (int i = 1; i <= nf; i++)
+          if (ci[i - 1] == I - 1 || ci[i - 1] == I) {
+            lo = std::min(lo, i);
+            hi = std::max(hi, i);
+          }
+        lh[I] = make_int2(lo, hi);
+      }
+      MgLevelHost* lv = g->lv[l];
+      RBWS_HIP(hipMemcpyAsync(lv->ci.get(sizeof(int) * nf, B.device), ci.data(), sizeof(int) * nf,
+                              hipMemcpyHostToDevice, s));
+      RBWS_HIP(hipMemcpyAsync(lv->cwd.get(sizeof(double) * nf, B.device), cw.data(), sizeof(double) * nf,
+                              hipMemcpyHostToDevice, s));
+      RBWS_HIP(hipMemcpyAsync(lv->cwf.get(sizeof(float) * nf, B.device), cwf.data(), sizeof(float) * nf,
+                              hipMemcpyHostToDevice, s));
+      RBWS_HIP(hipMemcpyAsync(lv->lohi.get(sizeof(int2) * (nc + 2), B.device), lh.data(), sizeof(int2) * (nc + 2),
+                              hipMemcpyHostToDevice, s));
+      RBWS_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+    }
+    // coarsest factors
+    MgLevelHost* cl = g->lv[L - 1];
+    g->mc = (int)cl->ndof;
+    RBWS_REQUIRE(g->mc <= 27, RBWS_EINVAL, "coarsest multigrid level too large");
+    double* Lf = (double*)g->L.get(sizeof(double) * (size_t)ns * g->mc * g->mc, B.device);
+    RBWS_SCRATCH(badb);
+    int* bad = (int*)badb.get(sizeof(int), B.device);
+    RBWS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    MgLv cv = view(*cl, *g, L == 1, false);
+    hipLaunchKernelGGL(k_mg_factor, dim3((ns + 63) / 64), dim3(64), 0, s, cv, Lf, bad);
+    RBWS_HIP(hipGetLastError());
+    int hb = 0;
+    RBWS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    RBWS_HIP(hipStreamSynchronize(s));
+    RBWS_REQUIRE(hb == 0, RBWS_ENUMERIC, "coarsest multigrid operator not positive definite");
+  }
+  return m;
+}
+
+template <typename T>
+static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, const int* need,
+                   hipStream_t s) {
+  MgLevelHost& lv = *g.lv[l];
+  const int ns = (int)g.sol.size();
+  const bool l0 = l == 0;
+  const MgLv v = view(lv, g, l0, m->fp32);
+  if (l + 1 == (int)g.lv.size()) {
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3((ns + 63) / 64), dim3(64), 0, s, v, need, (const double*)g.L.ptr, b,
+                       e);
+    return;
+  }
+  const dim3 grid((unsigned)((lv.ndof + 255) / 256), ns);
+  const T om = (T)m->omega;
+  // 2 nu Jacobi writes alternate between `scratch` and `e`, the last one into e
+  T* w[2] = {scratch, e};
+  int wi = 0;
+  hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)nullptr, w[wi], om);
+  for (int it = 1; it < m->nu; it++) {
+    hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], w[wi ^ 1], om);
+    wi ^= 1;
+  }
+  hipLaunchKernelGGL((k_mg_point<T, true>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], tres, om);
+  MgLevelHost& cl = *g.lv[l + 1];
+  const MgLv cv = view(cl, g, false, m->fp32);
+  const T* cw = m->fp32 ? (const T*)lv.cwf.ptr : (const T*)lv.cwd.ptr;
+  const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
+  hipLaunchKernelGGL(k_mg_restrict<T>, dim3((unsigned)((cl.ndof + 255) / 256), ns), dim3(256), 0, s, v, cv, need,
+                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
+  vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, need, s);
+  hipLaunchKernelGGL(k_mg_prolong<T>, grid, dim3(256), 0, s, v, cv, need, (const int*)lv.ci.ptr, cw,
+                     (const T*)cl.ve.ptr, w[wi]);
+  for (int it = 0; it < m->nu; it++) {
+    hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], w[wi ^ 1], om);
+    wi ^= 1;
+  }
+  // 2 nu writes: the last one went to w[(2 nu - 1) & 1] = e
+}
+
+void mg_apply(MgRun* m, const void* r, void* sv, const int* need, hipStream_t st) {
+  for (MgGroup* g : m->g) {
+    if (g->sol.empty()) continue;
+    if (m->fp32)
+      vcycle<float>(m, *g, 0, (const float*)r, (float*)sv, (float*)m->x0.ptr, (float*)m->t0.ptr, need, st);
+    else
+      vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, need, st);
+  }
+  RBWS_HIP(hipGetLastError());
+}
+
+}  // namespace rbws

@@ -1,0 +1,24 @@
+// mg.hpp -- the multigrid V-cycle preconditioner (Alg. 2) for batched PCG.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "solver.hpp"
+
+namespace rbws {
+
+struct MgRun;
+
+// Levels of a grid: n_0 = n, n_{l+1} = (n_l - 1) / 2 while n_l > 3.
+int mg_levels_of(int n, int* out);
+
+// Hierarchy for every solve of batch B: per problem of the batch, the coarse
+// grids, each solve's face-coefficient tables on them, the transfer tables and
+// the coarsest-level Cholesky factors.  fp32 selects the vector type of
+// mg_apply.  The object is reused (and rebuilt) by the next call on this thread.
+MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s);
+
+// s_b = MG(r_b) (one V-cycle from zero) for every solve b with need[b] != 0;
+// r and s are device vectors laid out like the batch (double or float).
+void mg_apply(MgRun* m, const void* r, void* s, const int* need, hipStream_t st);
+
+}  // namespace rbws

@@ -168,7 +168,7 @@ void theta_host(const Problem& P, const double* mu, double* theta) {
 
 Problem* problem_create(const rbws_problem_desc* d, int device) {
   RBWS_REQUIRE(d != nullptr, RBWS_EINVAL, "desc is NULL");
-  RBWS_REQUIRE(d->n >= 2 && d->n <= 1024, RBWS_EINVAL, "n must be in [2, 1024]");
+  RBWS_REQUIRE(d->n >= 1 && d->n <= 1024, RBWS_EINVAL, "n must be in [1, 1024]");
   RBWS_REQUIRE(d->kind >= 0 && d->kind <= 2, RBWS_EINVAL, "unknown problem kind");
   RBWS_REQUIRE(d->f_kind == RBWS_F_ONE || d->f_kind == RBWS_F_GAUSS, RBWS_EINVAL, "unknown f kind");
   RBWS_REQUIRE(d->f_kind == RBWS_F_ONE || d->kind == RBWS_KIND_OCTANTS_ANISO, RBWS_EINVAL,

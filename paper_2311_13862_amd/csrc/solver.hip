@@ -24,11 +24,12 @@
 #include <cstring>
 
 #include "fast.hpp"
+#include "mg.hpp"
 
 namespace rbws {
 
 enum { OP_AP = 1, OP_RNORM = 3 };
-enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3, DOT_RESID = 4 };
+enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3, DOT_RESID = 4, DOT_RSV = 5 };
 constexpr int kSlots = 3;  // partial accumulators per work item
 
 // exact-path fallbacks taken by this translation unit's kernels (diagnostics)
@@ -474,6 +475,8 @@ __device__ double exact_solve_dot(FinShared& sh, int which, const ProbDev& P, co
       xa_add_prod(&sh.xa, Pv[c], stencil(kk, diag6(kk), Pv, c, n, i, j, k));
     } else if (which == DOT_RR) {
       xa_add_prod(&sh.xa, R[c], R[c]);
+    } else if (which == DOT_RSV) {
+      xa_add_prod(&sh.xa, R[c], Pv[c]);
     } else if (which == DOT_RESID) {
       double kk[6];
       point_kappa(g, kt, i, j, k, kk);
@@ -571,7 +574,7 @@ __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
     else if (rr <= s.thr) mark_done(s, RBWS_SOLVE_CONVERGED, active);
     else if (s.k >= s.maxit) mark_done(s, RBWS_SOLVE_MAXITER, active);
     else {
-      s.rho = rs;
+      if (!s.mg) s.rho = rs;  // with a V-cycle, rho = r^T s follows the preconditioner step
       s.restart = 1;
       s.mode = MODE_ITER;
       s.skip2 = 1;  // no update this round: the next round starts with p = s
@@ -585,11 +588,12 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
                                               const double* __restrict__ kap, const double* x,
                                               const double* r, const double* p,
                                               const CrAcc* __restrict__ part, int* active,
-                                              int force_exact, Lists L) {
+                                              int force_exact, Lists L, int* need) {
   __shared__ FinShared sh;
   const int b = blockIdx.x;
   if (b == 0 && threadIdx.x == 0) L.cnt[WL_UP] = 0;  // the up sweep of this round is done
   const int mode = st[b].mode;
+  if (need && threadIdx.x == 0) need[b] = 0;
   if (mode == MODE_DONE) return;
   const SolveDev S = sd[b];
   if (mode == MODE_RESID) {
@@ -598,7 +602,10 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
   }
   CgState s = st[b];
   if (s.skip2) {
-    if (threadIdx.x == 0) st[b].skip2 = 0;
+    if (threadIdx.x == 0) {
+      st[b].skip2 = 0;
+      if (need) need[b] = 1;  // the V-cycle on the (re)started residual
+    }
     list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &sh.slot);
     return;
   }
@@ -613,7 +620,10 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
       s.mode = MODE_RESID;
       s.extra += 1;
     } else if (s.k >= s.maxit) mark_done(s, RBWS_SOLVE_MAXITER, active);
-    else {
+    else if (s.mg) {
+      s.restart = 0;  // beta and rho follow the V-cycle (k_fin_mg)
+      need[b] = 1;
+    } else {
       s.beta = rs / s.rho;
       s.rho = rs;
       s.restart = 0;
@@ -625,6 +635,61 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
   const int nm = sh.flag;
   if (nm == MODE_ITER) list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &sh.slot);
   else if (nm == MODE_RESID) list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &sh.slot);
+}
+
+// r^T s over the tiles of the solves on a list (s from the V-cycle), into partial slot 1
+__device__ __forceinline__ void k_dot_rs_item(int item, const int2* __restrict__ items,
+                                              const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                              const double* __restrict__ r, const double* __restrict__ sv,
+                                              CrAcc* __restrict__ part) {
+  __shared__ CrAcc red[4];
+  __syncthreads();
+  const int2 it = items[item];
+  const SolveDev S = sd[it.x];
+  const ProbDev& P = pd[S.prob];
+  QuadGeo G;
+  quad_geo(G, P, it.y);
+  const int n = P.g.n;
+  CrAcc a = cr_zero();
+  for (int k = G.kb; k <= G.ke; k++) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (e >= G.nv) continue;
+      const long long c = S.off + vidx(n, G.i + e, G.j, k);
+      cr_add_prod(a, r[c], sv[c]);
+    }
+  }
+  a = cr_block_reduce(a, red);
+  if (threadIdx.x == 0) part[(long long)item * kSlots + 1] = a;
+}
+
+__global__ __launch_bounds__(256) void k_dot_rs(const int2* __restrict__ items, const int* __restrict__ list,
+                                                const int* __restrict__ cnt, int nitems,
+                                                const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                const double* __restrict__ r, const double* __restrict__ sv,
+                                                CrAcc* __restrict__ part) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step) k_dot_rs_item(list ? list[w] : w, items, sd, pd, r, sv, part);
+}
+
+// after the V-cycle: rho' = r^T s, then beta = rho' / rho (or a restart: p = s)
+__global__ __launch_bounds__(256) void k_fin_mg(const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                CgState* st, const double* __restrict__ kap, const double* x,
+                                                const double* r, const double* sv,
+                                                const CrAcc* __restrict__ part, const int* __restrict__ need,
+                                                int force_exact) {
+  __shared__ FinShared sh;
+  const int b = blockIdx.x;
+  if (!need[b]) return;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const double rs = solve_dot(sh, 1, DOT_RSV, P, S, kap, x, r, sv, part, force_exact);
+  if (threadIdx.x == 0) {
+    CgState s = st[b];
+    if (!s.restart) s.beta = rs / s.rho;
+    s.rho = rs;
+    st[b] = s;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fin_rnorm(const SolveDev* __restrict__ sd,
@@ -762,7 +827,8 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
   }
   B.sd_h.assign(nsolve, SolveDev{});
   B.items_h.clear();
-  std::vector<double> theta((size_t)std::max(nsolve, 1) * kMaxQ, 0.0);
+  std::vector<double>& theta = B.theta_h;  // kept: the copy below is asynchronous
+  theta.assign((size_t)std::max(nsolve, 1) * kMaxQ, 0.0);
   long long off = 0, koff = 0;
   B.kap_max = 0;
   for (int b = 0; b < nsolve; b++) {
@@ -842,6 +908,12 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
     c.prec = o.prec;
     c.first = 1;
   }
+  const bool mg = o.prec == RBWS_PREC_MG;
+  if (mg)
+    for (CgState& c : init) {
+      c.prec = 0;  // the sweeps form ||r||^2 only; s and r^T s come from the V-cycle
+      c.mg = 1;
+    }
   CgState* st = (CgState*)B.state.get(sizeof(CgState) * ns, B.device);
   RBWS_HIP(hipMemcpyAsync(st, init.data(), sizeof(CgState) * ns, hipMemcpyHostToDevice, s));
   int* active = (int*)B.active.get(sizeof(int), B.device);
@@ -870,12 +942,24 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
   const unsigned g_up = persistent_grid((const void*)up, lds_fast, ni, B.device);
   const unsigned g_res = persistent_grid((const void*)res, lds, ni, B.device);
   const Lists L = lists_init(B, s);
+  MgRun* mgr = nullptr;
+  double* sv = r;  // the vector the direction update reads: r (P = I, Jacobi in-kernel) or s
+  int* need = nullptr;
+  if (mg) {
+    mgr = mg_prepare(B, o.mg_nu, o.mg_omega, false, s);
+    sv = (double*)B.sv.get(sizeof(double) * B.total, B.device);
+    need = (int*)B.need.get(sizeof(int) * ns, B.device);
+    std::vector<int> z(ns, 0);
+    RBWS_HIP(hipMemcpyAsync(need, z.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipStreamSynchronize(s));
+  }
+  const unsigned g_dot = mg ? persistent_grid((const void*)k_dot_rs, 0, ni, B.device) : 0;
   KernelTimer& kt = ktimer();
   const bool graph = !(o.flags & RBWS_FLAG_NO_GRAPH) && !kt.on;
   run_rounds(B, active, max_rounds, check, graph, s, [&](hipStream_t q) {
     kt.begin(q, KK_AP);
     hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, q, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, kap,
-                       x, r, p, p1, part, ktab);
+                       x, sv, p, p1, part, ktab);
     kt.end(q);
     kt.begin(q, KK_RESID);
     hipLaunchKernelGGL(res, dim3(g_res), dim3(256), lds, q, items, L.res, L.cnt + WL_RES, ni, sd, pd, st, kap, x,
@@ -889,8 +973,17 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
                        x, r, p, p1, part, ktab);
     kt.end(q);
     kt.begin(q, KK_FIN2);
-    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, x, r, p, part, active, fe, L);
+    hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, x, r, p, part, active, fe, L, need);
     kt.end(q);
+    if (mg) {
+      kt.begin(q, KK_MG);
+      mg_apply(mgr, r, sv, need, q);
+      hipLaunchKernelGGL(k_dot_rs, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
+                         (const int*)(L.cnt + WL_AP), ni, sd, pd, (const double*)r, (const double*)sv, part);
+      hipLaunchKernelGGL(k_fin_mg, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, (const double*)x, (const double*)r,
+                         (const double*)sv, (const CrAcc*)part, (const int*)need, fe);
+      kt.end(q);
+    }
   });
 }
 

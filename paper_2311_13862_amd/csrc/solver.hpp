@@ -76,10 +76,11 @@ struct Batch {
   std::vector<ProbDev> pd_h;
   std::vector<SolveDev> sd_h;
   std::vector<int2> items_h;
+  std::vector<double> theta_h;  // nsolve x kMaxQ
   DevBuf pd, sd, items, kap64, kap32, theta, ncorner, thidx, state, part, active, lists;
   std::vector<int> lists_h;  // initial list image: counts, then res = all items
-  // FP64 CG vectors
-  DevBuf x, r, p, p2;
+  // FP64 CG vectors (sv: the preconditioned residual s when P is a V-cycle)
+  DevBuf x, r, p, p2, sv, need;
   // FP32 inner vectors (refinement)
   DevBuf d32, r32, p32, p32b;
   int* active_host = nullptr;  // pinned
@@ -121,6 +122,8 @@ void resid_norms(Batch& B, const double* x, double* rel, double* rr, double* ff,
 struct CgOpts {
   double tol;
   int maxit, prec, flags, check_every;
+  int mg_nu = 1;
+  double mg_omega = 6.0 / 7.0;
 };
 void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s);
 void states_to_host(Batch& B, std::vector<CgState>& out, hipStream_t s);
@@ -207,7 +210,7 @@ double wall_clock_khz(int device);
 
 // Opt-in HIP-event timing of every launch of the solver's kernels, by kind.
 enum KernelKind { KK_AP = 0, KK_RESID = 1, KK_FIN1 = 2, KK_UP2 = 3, KK_FIN2 = 4, KK_SPMV = 5, KK_LIFT = 6,
-                  KK_COEF = 7, KK_COUNT = 8 };
+                  KK_COEF = 7, KK_MG = 8, KK_COUNT = 9 };
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;

@@ -21,7 +21,7 @@ KIND_BLOCKS, KIND_OCTANTS, KIND_OCTANTS_ANISO = 0, 1, 2
 F_ONE, F_GAUSS = 0, 1
 INIT_ZERO, INIT_RB, INIT_LEARNED = 0, 1, 2
 FP64, FP32_IR = 0, 1
-PREC_NONE, PREC_JACOBI = 0, 1
+PREC_NONE, PREC_JACOBI, PREC_MG = 0, 1, 2
 SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 LIFT_EXACT, LIFT_MFMA = 0, 1
 IR_RESTART, IR_RELIABLE = 0, 1
@@ -51,7 +51,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precond", C.c_int),
                 ("precision", C.c_int), ("init", C.c_int), ("lift", C.c_int),
                 ("eta_inner", C.c_double), ("max_outer", C.c_int), ("fallback", C.c_int),
-                ("flags", C.c_int), ("check_every", C.c_int), ("ir_mode", C.c_int)]
+                ("flags", C.c_int), ("check_every", C.c_int), ("ir_mode", C.c_int),
+                ("mg_nu", C.c_int), ("mg_omega", C.c_double)]
 
 
 class MlpDesc(C.Structure):
@@ -430,7 +431,7 @@ def pack_params(layers) -> np.ndarray:
     return np.concatenate([np.concatenate([np.asarray(W).ravel(), np.asarray(b).ravel()]) for W, b in layers])
 
 
-KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs")
+KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs", "mg_vcycle")
 
 
 def profile(enable: bool, reset: bool = True):
@@ -438,8 +439,8 @@ def profile(enable: bool, reset: bool = True):
     fn = getattr(_L, "rbws_profile")
     fn.restype = C.c_int
     fn.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
-    ms = (C.c_double * 8)()
-    n = (C.c_longlong * 8)()
+    ms = (C.c_double * len(KERNEL_KINDS))()
+    n = (C.c_longlong * len(KERNEL_KINDS))()
     _check(fn(1 if enable else 0, ms, n, 1 if reset else 0))
     return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
 
