@@ -505,9 +505,9 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
     RBWS_REQUIRE(opts->max_iter >= 1, RBWS_EINVAL, "max_iter < 1 for refinement");
     RBWS_REQUIRE(opts->ir_mode == RBWS_IR_RESTART || opts->ir_mode == RBWS_IR_RELIABLE, RBWS_EINVAL,
                  "bad ir_mode");
-    RBWS_REQUIRE(opts->precond != RBWS_PREC_MG, RBWS_EINVAL, "multigrid inside refinement: not available");
-    IrOpts io{opts->tol, opts->eta_inner, opts->precond, opts->max_iter, opts->max_outer, opts->flags,
-              opts->check_every, opts->ir_mode == RBWS_IR_RELIABLE ? 1 : 0};
+    IrOpts io{opts->tol,         opts->eta_inner,  opts->precond,
+              opts->max_iter,    opts->max_outer,  opts->flags,
+              opts->check_every, opts->ir_mode == RBWS_IR_RELIABLE ? 1 : 0, opts->mg_nu, opts->mg_omega};
     ir_run(B, io, s, ir);
     for (int b = 0; b < nmu; b++) sol[b] = (ir[b].cur ? (const double*)B.r.ptr : x) + B.sd_h[b].off;
   }

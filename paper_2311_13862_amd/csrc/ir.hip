@@ -22,6 +22,7 @@
 #include <cstring>
 
 #include "fast.hpp"
+#include "mg.hpp"
 
 namespace rbws {
 
@@ -272,14 +273,16 @@ __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd
         s.skip2 = 1;
         s.bb = g0;
         s.thr_in = s.eta2 * g0;
-        if (s.reliable && s.dir_ok && s.rho > 0.0) {
+        if (s.mg) {
+          // beta, restart and rho follow the V-cycle on the new right-hand side (k_ir_fin_mg)
+        } else if (s.reliable && s.dir_ok && s.rho > 0.0) {
           // continue CG with the true residual: p <- s + beta p, p rescaled by s.rescale
           s.beta = (double)(float)(rho_new / (s.rescale * s.rho));
           s.restart = 0;
         } else {
           s.restart = 1;
         }
-        s.rho = rho_new;
+        if (!s.mg) s.rho = rho_new;
       }
     }
     st[b] = s;
@@ -290,12 +293,13 @@ __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd
 }
 
 __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd, IrState* st,
-                                                 const IrPart* __restrict__ part, Lists L) {
+                                                 const IrPart* __restrict__ part, Lists L, int* need) {
   __shared__ double red[4][2];
   __shared__ int flag, slot;
   const int b = blockIdx.x;
   if (b == 0 && threadIdx.x == 0) L.cnt[WL_UP] = 0;  // the up sweep of this round is done
   const int mode = st[b].mode;
+  if (need && threadIdx.x == 0) need[b] = 0;
   if (mode == MODE_DONE) return;
   const SolveDev S = sd[b];
   if (mode == MODE_RESID) {
@@ -304,7 +308,10 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
   }
   IrState s = st[b];
   if (s.skip2) {
-    if (threadIdx.x == 0) st[b].skip2 = 0;
+    if (threadIdx.x == 0) {
+      st[b].skip2 = 0;
+      if (need) need[b] = 1;  // the V-cycle on the new right-hand side
+    }
     list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &slot);
     return;
   }
@@ -334,6 +341,9 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
     s.k_total += 1;
     if (!__builtin_isfinite(rr) || rr <= s.thr_in || s.k_in >= s.inner_max) {
       ir_end_inner(s, rr, __builtin_isfinite(rr) ? 1 : 0);
+    } else if (s.mg) {
+      s.restart = 0;  // beta and rho follow the V-cycle (k_ir_fin_mg)
+      need[b] = 1;
     } else {
       s.beta = (double)(float)(rs / s.rho);
       s.rho = rs;
@@ -345,6 +355,74 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
   __syncthreads();
   if (flag == MODE_ITER) list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &slot);
   else list_push(L.res, L.cnt + WL_RES, S.item0, S.ntiles, &slot);
+}
+
+// r^T s of the inner solve (FP32 vectors, FP64 accumulation) over listed tiles, into g[2]
+__device__ __forceinline__ void k_dot_rs32_item(int item, const int2* __restrict__ items,
+                                                const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                const float* __restrict__ r, const float* __restrict__ sv,
+                                                IrPart* __restrict__ part) {
+  __shared__ double red[4];
+  __syncthreads();
+  const int2 it = items[item];
+  const SolveDev S = sd[it.x];
+  const ProbDev& P = pd[S.prob];
+  QuadGeo G;
+  quad_geo(G, P, it.y);
+  const int n = P.g.n;
+  double a = 0.0;
+  for (int k = G.kb; k <= G.ke; k++) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (e >= G.nv) continue;
+      const long long c = S.off + vidx(n, G.i + e, G.j, k);
+      a = __fma_rn((double)r[c], (double)sv[c], a);
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[item].g[2] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_dot_rs32(const int2* __restrict__ items, const int* __restrict__ list,
+                                                  const int* __restrict__ cnt, int nitems,
+                                                  const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                                  const float* __restrict__ r, const float* __restrict__ sv,
+                                                  IrPart* __restrict__ part) {
+  const WorkRange R = work_range(cnt ? *cnt : nitems);
+  for (int w = R.w; w < R.w1; w += R.step) k_dot_rs32_item(list ? list[w] : w, items, sd, pd, r, sv, part);
+}
+
+// after the V-cycle: rho' = r^T s; beta = rho' / rho, or after an outer step the
+// reliable-update continuation beta = rho' / (rescale rho) (or a restart)
+__global__ __launch_bounds__(256) void k_ir_fin_mg(const SolveDev* __restrict__ sd, IrState* st,
+                                                   const IrPart* __restrict__ part, const int* __restrict__ need) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  if (!need[b]) return;
+  const SolveDev S = sd[b];
+  double g = 0.0;
+  for (int t = threadIdx.x; t < S.ntiles; t += blockDim.x) g += part[S.item0 + t].g[2];
+  for (int m = 32; m >= 1; m >>= 1) g += __shfl_xor(g, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  g = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); q++) g += red[q];
+  IrState s = st[b];
+  if (s.k_in == 0) {
+    if (s.reliable && s.dir_ok && s.rho > 0.0) {
+      s.beta = (double)(float)(g / (s.rescale * s.rho));
+      s.restart = 0;
+    } else {
+      s.restart = 1;
+    }
+  } else {
+    s.beta = (double)(float)(g / s.rho);
+  }
+  s.rho = g;
+  st[b] = s;
 }
 
 // bit 0: A.p sweep with register-cached coefficients; bit 1: the same for the
@@ -380,6 +458,10 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     c.prec = o.prec;
     c.reliable = o.reliable;
     c.rescale = 1.0;
+    if (o.prec == RBWS_PREC_MG) {
+      c.prec = 0;  // the sweeps form ||r||^2 only; s and r^T s come from the V-cycle
+      c.mg = 1;
+    }
   }
   IrState* st = (IrState*)B.state.get(sizeof(IrState) * ns, B.device);
   RBWS_HIP(hipMemcpyAsync(st, init.data(), sizeof(IrState) * ns, hipMemcpyHostToDevice, s));
@@ -413,6 +495,19 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   const unsigned g_up = persistent_grid((const void*)up, lds_fast, ni, B.device);
   const unsigned g_res = persistent_grid((const void*)outer, lds_outer, ni, B.device);
   const Lists L = lists_init(B, s);
+  const bool mg = o.prec == RBWS_PREC_MG;
+  MgRun* mgr = nullptr;
+  float* sv = r;  // the vector the direction update reads: r (P = I, Jacobi in-kernel) or s
+  int* need = nullptr;
+  if (mg) {
+    mgr = mg_prepare(B, o.mg_nu, o.mg_omega, true, s);
+    sv = (float*)B.sv32.get(sizeof(float) * B.total, B.device);
+    need = (int*)B.need.get(sizeof(int) * ns, B.device);
+    std::vector<int> z(ns, 0);
+    RBWS_HIP(hipMemcpyAsync(need, z.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    RBWS_HIP(hipStreamSynchronize(s));
+  }
+  const unsigned g_dot = mg ? persistent_grid((const void*)k_dot_rs32, 0, ni, B.device) : 0;
   const int check = o.check_every > 0 ? o.check_every : 8;
   const long long max_rounds = (long long)(o.inner_max + 2) * (o.max_outer + 1) + 16;
   KernelTimer& kt = ktimer();
@@ -420,7 +515,7 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   run_rounds(B, active, max_rounds, check, graph, s, [&](hipStream_t q) {
     kt.begin(q, KK_AP);
     hipLaunchKernelGGL(ap, dim3(g_ap), dim3(256), lds_fast, q, items, L.ap, L.cnt + WL_AP, ni, sd, pd, st, k32, d,
-                       r, p, p1, part, ktab);
+                       sv, p, p1, part, ktab);
     kt.end(q);
     kt.begin(q, KK_RESID);
     hipLaunchKernelGGL(outer, dim3(g_res), dim3(256), lds_outer, q, items, L.res, L.cnt + WL_RES, ni, sd, pd, st,
@@ -434,8 +529,16 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
                        r, p, p1, part, ktab);
     kt.end(q);
     kt.begin(q, KK_FIN2);
-    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, L);
+    hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, L, need);
     kt.end(q);
+    if (mg) {
+      kt.begin(q, KK_MG);
+      mg_apply(mgr, r, sv, need, q);
+      hipLaunchKernelGGL(k_dot_rs32, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
+                         (const int*)(L.cnt + WL_AP), ni, sd, pd, (const float*)r, (const float*)sv, part);
+      hipLaunchKernelGGL(k_ir_fin_mg, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, (const int*)need);
+      kt.end(q);
+    }
   });
   std::vector<IrState> h(ns);
   RBWS_HIP(hipMemcpyAsync(h.data(), st, sizeof(IrState) * ns, hipMemcpyDeviceToHost, s));

@@ -33,6 +33,8 @@ struct IrState {
   double rescale;  // scale after / scale before the last outer correction (a power of two)
   int reliable;    // keep the search direction across outer corrections
   int dir_ok;      // the last inner solve ended with a usable direction
+  int mg;          // the inner preconditioner is a V-cycle (s, r^T s follow the sweeps)
+  int pad;
 };
 
 // device arrays of a batch (grow-only allocations, reused across calls)
@@ -81,8 +83,8 @@ struct Batch {
   std::vector<int> lists_h;  // initial list image: counts, then res = all items
   // FP64 CG vectors (sv: the preconditioned residual s when P is a V-cycle)
   DevBuf x, r, p, p2, sv, need;
-  // FP32 inner vectors (refinement)
-  DevBuf d32, r32, p32, p32b;
+  // FP32 inner vectors (refinement; sv32: s from the V-cycle)
+  DevBuf d32, r32, p32, p32b, sv32;
   int* active_host = nullptr;  // pinned
   ~Batch();
 };
@@ -135,6 +137,8 @@ void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s);
 struct IrOpts {
   double tol, eta;
   int prec, inner_max, max_outer, flags, check_every, reliable;
+  int mg_nu = 1;
+  double mg_omega = 6.0 / 7.0;
 };
 struct IrHost {
   int iters, outer, status, cur;

@@ -101,3 +101,27 @@ def test_mgcg_64_sample(rb):
     for b in (0, 5):
         xo, so = O.mgcg(mu[b], tol=1e-10)
         assert sg[b]["iters"] == so["iters"] and np.array_equal(xg[b], xo)
+
+
+@pytest.mark.parametrize("spec", [W.Problem(20, W.KIND_OCTANTS), W.Problem(33, W.KIND_BLOCKS, W.BLOCKS4)],
+                         ids=["oct20", "blk33"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_refinement_with_multigrid(rb, spec, mode):
+    """FP32 MGCG inside FP64 refinement: the solution matches the oracle's FP64
+    reference to 1e-8, in about as many inner iterations as FP64 MGCG needs."""
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 6, 60 + spec.n)
+    u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mu))]
+    opts = rb.default_opts(tol=1e-10, precision=rb.FP32_IR, precond=rb.PREC_MG, ir_mode=mode,
+                           eta_inner=0.1 if mode == rb.IR_RELIABLE else 1e-4)
+    st = rb.solve([P], mu, opts, u_out=u)
+    torch.cuda.synchronize()
+    ref, _ = O.cg_batch(mu, tol=1e-12, maxit=20000)
+    _, so = O.mgcg_batch(mu, tol=1e-10)
+    for b in range(len(mu)):
+        assert st[b]["status"] == rb.SOLVE_CONVERGED
+        assert st[b]["final_rr"] <= 1e-20 * st[b]["ff"]
+        ub = u[b].cpu().numpy()
+        assert np.linalg.norm(ub - ref[b]) <= 1e-8 * np.linalg.norm(ref[b])
+        assert st[b]["iters"] <= 2 * so[b]["iters"] + 10, (st[b]["iters"], so[b]["iters"])
