@@ -5,9 +5,10 @@ Workload: the 3D diffusion problem on a 128^3 interior grid (2,097,152
 unknowns) with a piecewise-constant coefficient on the 2x2x2 octant split
 (8 parameters, log-uniform in [0.01, 100]); a greedy reduced basis of
 dimension 40 from 1024 seeded training parameters; 1024 seeded test
-parameters solved in one batch to relative residual 1e-10 with Jacobi-PCG in
-FP32 inside FP64 iterative refinement, started from the RB solution (the
-paper's Alg. 5) and, for comparison, from zero.
+parameters solved in one batch to relative residual 1e-10 with PCG in FP32
+(preconditioned by the multigrid V-cycle of Alg. 2, i.e. MGCG; --precond
+jacobi for Jacobi-PCG) inside FP64 iterative refinement, started from the RB
+solution (the paper's Alg. 5) and, for comparison, from zero.
 
 One step = the whole online path over the batch: reduced assembly and
 Cholesky, MFMA lift u0 = V c, the refined Krylov solve.  The offline greedy
@@ -33,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+PRECOND = 2            # RBWS_PREC_MG
 
 
 def parse():
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--ntrain", type=int, default=1024)
     ap.add_argument("--N", type=int, default=40)
     ap.add_argument("--eta", type=float, default=0.1)
+    ap.add_argument("--precond", choices=("mg", "jacobi"), default="mg",
+                    help="P of Alg. 1: the multigrid V-cycle of Alg. 2 (default) or Jacobi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-zero", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
@@ -65,6 +69,8 @@ def solve_step(rb, P, basis, mu, opts):
 
 def main():
     args = parse()
+    global PRECOND
+    PRECOND = {"mg": 2, "jacobi": 1}[args.precond]
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(solves are independent per parameter; see the design notes for sharding)",
@@ -89,7 +95,7 @@ def main():
     t_off = time.perf_counter() - t
     log(f"offline done in {t_off:.1f} s, N={basis.N}, max training indicator {basis.final_max:.3g}")
 
-    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
+    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                              eta_inner=args.eta, init=rbws.INIT_RB, lift=rbws.LIFT_MFMA,
                              ir_mode=rbws.IR_RELIABLE)
     # tile depth for this grid size and batch (setup, like the offline stage)
@@ -147,12 +153,15 @@ def main():
 
     # roofline of the dominant kernel, from the events recorded over the timed steps
     nd = P.ndof
-    up_bytes = args.steps * float(np.sum(iters * 20 - outer * 4)) * nd   # R p, d, r; W d, r (FP32)
-    ap_bytes = args.steps * float(np.sum(iters * 12 - outer * 4)) * nd   # R r, p_old; W p_new
+    alg = {"up2_sweep": args.steps * float(np.sum(iters * 20 - outer * 4)) * nd,  # R p, d, r; W d, r (FP32)
+           "ap_sweep": args.steps * float(np.sum(iters * 12 - outer * 4)) * nd,   # R s, p_old; W p_new
+           # one V-cycle per inner iteration: on every level read b, write e (pre-smoothing), read e, b
+           # (residual, restriction), read e, b, write s (correction, post-smoothing) = 7 FP32 vectors
+           "mg_vcycle": args.steps * float(np.sum(iters)) * 28.0 * mg_points(spec.n) if PRECOND == 2 else 0.0}
     ms = {k: v[0] for k, v in kern.items()}
     n_launch = {k: v[1] for k, v in kern.items()}
-    dom = "up2_sweep" if ms["up2_sweep"] >= ms["ap_sweep"] else "ap_sweep"
-    dom_bytes = up_bytes if dom == "up2_sweep" else ap_bytes
+    dom = max(alg, key=lambda k: ms.get(k, 0.0))
+    dom_bytes = alg[dom]
     achieved = dom_bytes / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
     per_launch_bytes = dom_bytes / max(n_launch[dom], 1)
     per_launch_ms = ms[dom] / max(n_launch[dom], 1)
@@ -161,7 +170,7 @@ def main():
     zero_value = None
     zero_iters = None
     if not args.no_zero:
-        zopts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
+        zopts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                                   eta_inner=args.eta, init=rbws.INIT_ZERO, ir_mode=rbws.IR_RELIABLE)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -213,7 +222,7 @@ def main():
         "dtype": "f32 inner / f64 outer",
         "data": "synthetic (seeded parameters)",
         "config": {"workload": "octants8-128^3-fp32ir-rbws", "n": spec.n, "batch": args.batch,
-                   "rb_dim": basis.N, "n_train": args.ntrain, "tol": wl.tol, "precond": "jacobi",
+                   "rb_dim": basis.N, "n_train": args.ntrain, "tol": wl.tol, "precond": "mg-vcycle" if args.precond == "mg" else "jacobi",
                    "eta_inner": args.eta, "refinement": "reliable-update", "init": "rb",
                    "lift": "mfma", "parallelism": "none"},
         "all_converged": bool(ok),
@@ -260,7 +269,7 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
     c_rb = basis.coeffs(mu)
     c_nn = net.predict(mu)
     cerr = np.linalg.norm(c_nn - c_rb, axis=1) / np.linalg.norm(c_rb, axis=1)
-    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=rbws.PREC_JACOBI,
+    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                              eta_inner=args.eta, init=rbws.INIT_LEARNED, lift=rbws.LIFT_MFMA,
                              ir_mode=rbws.IR_RELIABLE, fallback=0)
     torch.cuda.synchronize()
@@ -278,6 +287,16 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
             "train_pairs": args.mlp_pairs, "train_epochs": args.mlp_epochs, "t_pairs_s": round(t_pairs, 3),
             "t_train_s": round(t_train, 3), "final_loss": float(np.mean(hist[-32:])),
             "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
+
+
+def mg_points(n):
+    """Grid points per solve over all multigrid levels (n, (n-1)//2, ... while > 3)."""
+    tot, m = 0, n
+    while True:
+        tot += m ** 3
+        if m <= 3:
+            return tot
+        m = (m - 1) // 2
 
 
 KERNEL_SOURCES = ("fast.hpp", "ir.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
@@ -310,31 +329,39 @@ def traffic_per_launch(kernel):
 
 
 def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s):
-    """The oracle's own refinement solver on the host cores, on a bounded sample:
-    `cores` parameters in parallel (one per thread), each allowed one refinement
-    step of a capped number of inner iterations; the per-solve cost is scaled to
-    the GPU's mean inner iteration count."""
+    """The oracle's own solver for the same method on the host cores, on a
+    bounded sample: `cores` parameters in parallel (one per thread), each for a
+    capped number of iterations; the per-solve cost is scaled to the GPU's mean
+    inner iteration count.  With the multigrid preconditioner the oracle runs
+    MGCG in FP64 (it has no FP32 inner solver for it), with Jacobi its FP32
+    refinement solver."""
     import oracle
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     O = oracle.Problem(spec)
     sample = mu[:cores]
-    # probe the cost of a few inner iterations, then size the sample to the budget
+    mg = PRECOND == 2
+
+    def run(ms, cap, threads):
+        if mg:
+            O.mgcg_batch(ms, tol=1e-30, maxit=cap, nthreads=threads)
+        else:
+            O.ir_batch(ms, prec=oracle.PREC_JACOBI, tol=1e-10, eta=1e-30, kin_max=cap, max_outer=1,
+                       nthreads=threads, reliable=True)
+
+    # probe the cost of a few iterations, then size the sample to the budget
     t = time.perf_counter()
-    O.ir_batch(sample[:1], prec=oracle.PREC_JACOBI, tol=1e-10, eta=1e-30, kin_max=3, max_outer=1,
-               nthreads=1, reliable=True)
+    run(sample[:1], 3, 1)
     per_it = max((time.perf_counter() - t) / 5.0, 1e-3)
-    cap = int(max(5, min(400, budget_s / per_it / 2.0)))
+    cap = int(max(3, min(400, budget_s / per_it / 2.0)))
     t = time.perf_counter()
-    O.ir_batch(sample, prec=oracle.PREC_JACOBI, tol=1e-10, eta=1e-30, kin_max=cap, max_outer=1,
-               nthreads=cores, reliable=True)
+    run(sample, cap, cores)
     wall = time.perf_counter() - t
-    per_solve = wall / cap * (gpu_inner_mean + 2 * gpu_outer_mean)
+    per_solve = wall / cap * (gpu_inner_mean + (0 if mg else 2 * gpu_outer_mean))
+    what = "FP64 MGCG iterations" if mg else "FP32 inner iterations (+2 outer residuals)"
     return {"value": round(cores / per_solve, 5), "unit": "mu-solves/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{cores} parameters of the batch, one per thread, {cap} FP32 inner iterations "
-                      f"each (+2 outer residuals); wall {wall:.1f} s, scaled to the GPU's mean "
-                      f"{gpu_inner_mean:.0f} inner iterations per solve"}
-
+            "sample": f"{cores} parameters of the batch, one per thread, {cap} {what} each; "
+                      f"wall {wall:.1f} s, scaled to the GPU's mean {gpu_inner_mean:.0f} inner iterations per solve"}
 
 if __name__ == "__main__":
     main()
