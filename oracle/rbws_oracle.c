@@ -526,9 +526,10 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
  *
  * Fixed evaluation orders (the GPU follows the same ones):
  *   Jacobi: q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
- *   restriction: acc = 0, loop k, j, i ascending over the fine points whose
- *     weight on the coarse node may be nonzero, acc = fma((px py) pz, r, acc),
- *     then acc * ((nc+1)/(nf+1))
+ *   restriction, separable: ax = sum over i of px r (fma chain from 0, i
+ *     ascending over the fine points whose weight on the coarse node may be
+ *     nonzero), ay = sum over j of py ax, az = sum over k of pz ay, then
+ *     az * ((nc+1)/(nf+1))
  *   prolongation: v = 0, corners z, y, x in order 0, 1 (interior corners
  *     only), v = fma((wx wy) wz, e_c, v), then e = e + v
  *   coarse solve: Cholesky and the two triangular solves with sequential
@@ -591,19 +592,22 @@ static void mg_restrict(const mg_ctx *c, int l, const double *rf, double *rc) {
     for (int K = 1; K <= nc; K++)
         for (int J = 1; J <= nc; J++)
             for (int I = 1; I <= nc; I++) {
-                double acc = 0.0;
+                double az = 0.0;
                 for (int k = lo[K]; k <= hi[K]; k++) {
                     double pz = ci[k - 1] == K ? 1.0 - cw[k - 1] : cw[k - 1];
+                    double ay = 0.0;
                     for (int j = lo[J]; j <= hi[J]; j++) {
                         double py = ci[j - 1] == J ? 1.0 - cw[j - 1] : cw[j - 1];
+                        double ax = 0.0;
                         for (int i = lo[I]; i <= hi[I]; i++) {
                             double px = ci[i - 1] == I ? 1.0 - cw[i - 1] : cw[i - 1];
-                            long f = ((long)(k - 1) * nf + (j - 1)) * nf + (i - 1);
-                            acc = fma((px * py) * pz, rf[f], acc);
+                            ax = fma(px, rf[((long)(k - 1) * nf + (j - 1)) * nf + (i - 1)], ax);
                         }
+                        ay = fma(py, ax, ay);
                     }
+                    az = fma(pz, ay, az);
                 }
-                rc[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)] = acc * scale;
+                rc[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)] = az * scale;
             }
     free(lo); free(hi);
 }

@@ -202,9 +202,10 @@ __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd
   __shared__ CrAcc redc[4];
   __shared__ int flag, slot;
   const int b = blockIdx.x;
-  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps of this round are done
+  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps and the last V-cycle are done
     L.cnt[WL_AP] = 0;
     L.cnt[WL_RES] = 0;
+    for (int q = 0; q < WL_MAXPROB; q++) L.cnt[WL_MG + q] = 0;
   }
   const int mode = st[b].mode;
   if (mode == MODE_DONE) return;
@@ -310,7 +311,11 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
   if (s.skip2) {
     if (threadIdx.x == 0) {
       st[b].skip2 = 0;
-      if (need) need[b] = 1;  // the V-cycle on the new right-hand side
+      if (need) {  // the V-cycle on the new right-hand side
+        need[b] = 1;
+        const int q = sd[b].prob;
+        L.mg[L.cnt[WL_SEG + q] + atomicAdd(&L.cnt[WL_MG + q], 1)] = L.gidx[b];
+      }
     }
     list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &slot);
     return;
@@ -344,6 +349,7 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
     } else if (s.mg) {
       s.restart = 0;  // beta and rho follow the V-cycle (k_ir_fin_mg)
       need[b] = 1;
+      L.mg[L.cnt[WL_SEG + S.prob] + atomicAdd(&L.cnt[WL_MG + S.prob], 1)] = L.gidx[b];
     } else {
       s.beta = (double)(float)(rs / s.rho);
       s.rho = rs;
@@ -533,7 +539,7 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     kt.end(q);
     if (mg) {
       kt.begin(q, KK_MG);
-      mg_apply(mgr, r, sv, need, q);
+      mg_apply(mgr, r, sv, L, q);
       hipLaunchKernelGGL(k_dot_rs32, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
                          (const int*)(L.cnt + WL_AP), ni, sd, pd, (const float*)r, (const float*)sv, part);
       hipLaunchKernelGGL(k_ir_fin_mg, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, (const int*)need);

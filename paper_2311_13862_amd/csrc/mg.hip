@@ -17,7 +17,8 @@
 // restriction, per solve for the coarsest solve), with a fixed evaluation
 // order for every value:
 //   Jacobi        q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
-//   restriction   acc = fma((px py) pz, r, acc) over k, j, i ascending, then acc * scale
+//   restriction   ax = fma(px, r, ax) over i, ay = fma(py, ax, ay) over j,
+//                 az = fma(pz, ay, az) over k (ascending, from 0), then az * scale
 //   prolongation  v = fma((wx wy) wz, e_c, v) over corners z, y, x (interior ones), e + v
 //   coarsest      Cholesky and triangular solves with sequential fma accumulation
 // so that the FP64 V-cycle, and with it the whole MGCG trajectory, is
@@ -98,94 +99,308 @@ __device__ __forceinline__ T diagT(const T kk[6]) {
 }
 
 // ---------------------------------------------------------------------------
-// kernels
+// kernels: a grid of workgroups walks the (listed solve, chunk of 256 points)
+// items; XCD x (blocks b with b % 8 == x) takes a contiguous eighth of them, so
+// the chunks of one solve, which read each other's halo planes, share an L2
 // ---------------------------------------------------------------------------
+struct MgList {
+  const int* list;  // group-local solve indices
+  const int* cnt;   // their number
+};
+
+// (all index arithmetic below is 32-bit: a level has at most 2^30 points and a
+// list at most 2^31 items; 64-bit division would dominate these kernels)
+struct ItemRange {
+  int w, w1, step;
+};
+__device__ __forceinline__ ItemRange item_range(int total) {
+  const int x = blockIdx.x & 7;
+  const int nx = gridDim.x >> 3;
+  const int per = (total + 7) >> 3;
+  const int w0 = x * per;
+  return ItemRange{w0 + (int)(blockIdx.x >> 3), min(total, w0 + per), nx};
+}
 // e_out = e_in + omega (b - A e_in) / d  (e_in null: zero); RESID: t = b - A e_in
 template <typename T, bool RESID>
-__global__ __launch_bounds__(256) void k_mg_point(MgLv L, const int* __restrict__ need, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void k_mg_point(MgLv L, MgList ml, const T* __restrict__ b,
                                                   const T* __restrict__ ein, T* __restrict__ out, T omega) {
-  const int t = blockIdx.y;
-  if (!need[L.sid[t]]) return;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= L.ndof) return;
+  const int chunks = (int)((L.ndof + 255) >> 8), nd = (int)L.ndof;
+  const ItemRange R = item_range(*ml.cnt * chunks);
   const int n = L.n;
-  const int i = (int)(c % n) + 1, j = (int)((c / n) % n) + 1, k = (int)(c / ((long long)n * n)) + 1;
-  const long long off = L.voff ? L.voff[t] : (long long)t * L.ndof;
-  T kk[6];
-  kappa6<T>(L.pd->g, (const T*)L.kap + L.sd[t].kap_off, i, j, k, kk);
-  const T dg = diagT(kk);
-  const T q = ein ? stencilT<T>(kk, dg, ein + off, c, n, i, j, k) : T(0);
-  T r = b[off + c] - q;
-  if (RESID) {
-    out[off + c] = r;
-  } else {
-    r = r / dg;
-    out[off + c] = fmaT(omega, r, ein ? ein[off + c] : T(0));
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int c = (w % chunks) * 256 + (int)threadIdx.x;
+    if (c >= nd) continue;
+    const int ij = c % (n * n);
+    const int i = ij % n + 1, j = ij / n + 1, k = c / (n * n) + 1;
+    const long long off = L.voff ? L.voff[t] : (long long)t * L.ndof;
+    T kk[6];
+    kappa6<T>(L.pd->g, (const T*)L.kap + L.sd[t].kap_off, i, j, k, kk);
+    const T dg = diagT(kk);
+    const T q = ein ? stencilT<T>(kk, dg, ein + off, c, n, i, j, k) : T(0);
+    T r = b[off + c] - q;
+    if (RESID) {
+      out[off + c] = r;
+    } else {
+      r = r / dg;
+      out[off + c] = fmaT(omega, r, ein ? ein[off + c] : T(0));
+    }
   }
 }
 
-// b_c = scale P^T r_f, one thread per coarse point
+// Restriction b_c = scale P^T r_f, separable: the x-pass forms, for every fine
+// (k, j) row and coarse column I, ax = sum_i px r (fma chain from 0, i ascending);
+// the yz-pass forms az = sum_k pz (sum_j py ax) per coarse point, times scale.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_restrict(MgLv F, MgLv C, const int* __restrict__ need,
-                                                     const int* __restrict__ ci, const T* __restrict__ cw,
-                                                     const int2* __restrict__ lohi, const T* __restrict__ rf,
-                                                     T* __restrict__ bc, T scale) {
-  const int t = blockIdx.y;
-  if (!need[C.sid[t]]) return;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C.ndof) return;
+__global__ __launch_bounds__(256) void k_mg_rx(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                               const T* __restrict__ cw, const int2* __restrict__ lohi,
+                                               const T* __restrict__ rf, T* __restrict__ tx) {
   const int nc = C.n, nf = F.n;
-  const int I = (int)(c % nc) + 1, J = (int)((c / nc) % nc) + 1, K = (int)(c / ((long long)nc * nc)) + 1;
-  const T* r = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof);
-  const int2 xr = lohi[I], yr = lohi[J], zr = lohi[K];
-  T acc = T(0);
-  for (int k = zr.x; k <= zr.y; k++) {
-    const T pz = ci[k - 1] == K ? T(1) - cw[k - 1] : cw[k - 1];
-    for (int j = yr.x; j <= yr.y; j++) {
-      const T py = ci[j - 1] == J ? T(1) - cw[j - 1] : cw[j - 1];
-      const long long rowoff = ((long long)(k - 1) * nf + (j - 1)) * nf - 1;
-      for (int i = xr.x; i <= xr.y; i++) {
-        const T px = ci[i - 1] == I ? T(1) - cw[i - 1] : cw[i - 1];
-        acc = fmaT((px * py) * pz, r[rowoff + i], acc);
+  const int per = nf * nf * nc;  // outputs per solve
+  const int chunks = (per + 255) >> 8;
+  const ItemRange R = item_range(*ml.cnt * chunks);
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int o = (w % chunks) * 256 + (int)threadIdx.x;
+    if (o >= per) continue;
+    const int I = o % nc + 1, row = o / nc;  // row = (k-1) nf + (j-1)
+    const T* r = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof) + (long long)row * nf - 1;
+    const int2 xr = lohi[I];
+    T ax = T(0);
+    for (int i = xr.x; i <= xr.y; i++) {
+      const T px = ci[i - 1] == I ? T(1) - cw[i - 1] : cw[i - 1];
+      ax = fmaT(px, r[i], ax);
+    }
+    tx[(long long)t * per + o] = ax;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                const T* __restrict__ cw, const int2* __restrict__ lohi,
+                                                const T* __restrict__ tx, T* __restrict__ bc, T scale) {
+  const int nc = C.n, nf = F.n, nd = (int)C.ndof;
+  const int chunks = (nd + 255) >> 8;
+  const ItemRange R = item_range(*ml.cnt * chunks);
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int c = (w % chunks) * 256 + (int)threadIdx.x;
+    if (c >= nd) continue;
+    const int IJ = c % (nc * nc);
+    const int I = IJ % nc + 1, J = IJ / nc + 1, K = c / (nc * nc) + 1;
+    const T* a = tx + (long long)t * nf * nf * nc + (I - 1);
+    const int2 yr = lohi[J], zr = lohi[K];
+    T az = T(0);
+    for (int k = zr.x; k <= zr.y; k++) {
+      const T pz = ci[k - 1] == K ? T(1) - cw[k - 1] : cw[k - 1];
+      T ay = T(0);
+      for (int j = yr.x; j <= yr.y; j++) {
+        const T py = ci[j - 1] == J ? T(1) - cw[j - 1] : cw[j - 1];
+        ay = fmaT(py, a[((k - 1) * nf + (j - 1)) * nc], ay);
+      }
+      az = fmaT(pz, ay, az);
+    }
+    bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + c] = az * scale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the same point operations on quads of 4 x-consecutive points (n % 4 == 0,
+// 16-byte aligned vectors): one vector load per neighbour plane or row
+// instead of four scalar ones.  Out-of-grid neighbours enter as +0, which
+// leaves the fma chain bit-identical to skipping them.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct V4 {
+  T v[4];
+};
+template <typename T>
+__device__ __forceinline__ V4<T> ld4q(const T* p) {
+  V4<T> r;
+  if (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    r.v[0] = f.x;
+    r.v[1] = f.y;
+    r.v[2] = f.z;
+    r.v[3] = f.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = a.x;
+    r.v[1] = a.y;
+    r.v[2] = b.x;
+    r.v[3] = b.y;
+  }
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ void st4q(T* p, const T v[4]) {
+  if (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+  }
+}
+template <typename T>
+__device__ __forceinline__ V4<T> zero4() {
+  V4<T> r;
+  r.v[0] = r.v[1] = r.v[2] = r.v[3] = T(0);
+  return r;
+}
+
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_mg_quad(MgLv L, MgList ml, const T* __restrict__ b,
+                                                 const T* __restrict__ ein, T* __restrict__ out, T omega) {
+  const int n = L.n, nd = (int)L.ndof, nq = nd >> 2;
+  const int chunks = (nq + 255) >> 8;
+  const ItemRange R = item_range(*ml.cnt * chunks);
+  const GridDev& g = L.pd->g;
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int q = (w % chunks) * 256 + (int)threadIdx.x;
+    if (q >= nq) continue;
+    const int c = q * 4;
+    const int ij = c % (n * n);
+    const int i0 = ij % n + 1, j = ij / n + 1, k = c / (n * n) + 1;
+    const long long off = L.voff ? L.voff[t] : (long long)t * L.ndof;
+    const T* kX = (const T*)L.kap + L.sd[t].kap_off;
+    const T* kY = kX + (g.ndir == 3 ? g.nclass : 0);
+    const T* kZ = kX + (g.ndir == 3 ? 2 * g.nclass : 0);
+    const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+    const V4<T> B = ld4q(b + off + c);
+    V4<T> E = zero4<T>(), YM = zero4<T>(), YP = zero4<T>(), ZM = zero4<T>(), ZP = zero4<T>();
+    T xm = T(0), xp = T(0);
+    if (ein) {
+      const T* e = ein + off;
+      E = ld4q(e + c);
+      if (i0 > 1) xm = e[c - 1];
+      if (i0 + 3 < n) xp = e[c + 4];
+      if (j > 1) YM = ld4q(e + c - n);
+      if (j < n) YP = ld4q(e + c + n);
+      if (k > 1) ZM = ld4q(e + c - n * n);
+      if (k < n) ZP = ld4q(e + c + n * n);
+    }
+    T o[4];
+#pragma unroll
+    for (int el = 0; el < 4; el++) {
+      const int i = i0 + el;
+      const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+      T kk[6];
+      kk[0] = kX[(cxm * N1 + cyn) * N2 + czn];
+      kk[1] = kX[(cxp * N1 + cyn) * N2 + czn];
+      kk[2] = kY[(cxn * N1 + cym) * N2 + czn];
+      kk[3] = kY[(cxn * N1 + cyp) * N2 + czn];
+      kk[4] = kZ[(cxn * N1 + cyn) * N2 + czm];
+      kk[5] = kZ[(cxn * N1 + cyn) * N2 + czp];
+      const T dg = diagT(kk);
+      T qv = T(0);
+      if (ein) {
+        qv = dg * E.v[el];
+        qv = fmaT(-kk[0], el > 0 ? E.v[el - 1] : xm, qv);
+        qv = fmaT(-kk[1], el < 3 ? E.v[el + 1] : xp, qv);
+        qv = fmaT(-kk[2], YM.v[el], qv);
+        qv = fmaT(-kk[3], YP.v[el], qv);
+        qv = fmaT(-kk[4], ZM.v[el], qv);
+        qv = fmaT(-kk[5], ZP.v[el], qv);
+      }
+      T r = B.v[el] - qv;
+      if (RESID) {
+        o[el] = r;
+      } else {
+        r = r / dg;
+        o[el] = fmaT(omega, r, ein ? E.v[el] : T(0));
       }
     }
+    st4q(out + off + c, o);
   }
-  bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + c] = acc * scale;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_prolong_quad(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                         const T* __restrict__ cw, const T* __restrict__ ec,
+                                                         T* __restrict__ ef) {
+  const int nf = F.n, nc = C.n, nd = (int)F.ndof, nq = nd >> 2;
+  const int chunks = (nq + 255) >> 8;
+  const ItemRange R = item_range(*ml.cnt * chunks);
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int q = (w % chunks) * 256 + (int)threadIdx.x;
+    if (q >= nq) continue;
+    const int c = q * 4;
+    const int ij = c % (nf * nf);
+    const int i0 = ij % nf + 1, j = ij / nf + 1, k = c / (nf * nf) + 1;
+    const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
+    T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof) + c;
+    V4<T> X = ld4q(o);
+    const int J0 = ci[j - 1], K0 = ci[k - 1];
+    const T wy1 = cw[j - 1], wz1 = cw[k - 1];
+#pragma unroll
+    for (int el = 0; el < 4; el++) {
+      const int I0 = ci[i0 + el - 1];
+      const T wx1 = cw[i0 + el - 1];
+      T v = T(0);
+      for (int cz = 0; cz < 2; cz++) {
+        const int K = K0 + cz;
+        if (K < 1 || K > nc) continue;
+        const T wz = cz ? wz1 : T(1) - wz1;
+        for (int cy = 0; cy < 2; cy++) {
+          const int J = J0 + cy;
+          if (J < 1 || J > nc) continue;
+          const T wy = cy ? wy1 : T(1) - wy1;
+          for (int cx = 0; cx < 2; cx++) {
+            const int I = I0 + cx;
+            if (I < 1 || I > nc) continue;
+            const T wx = cx ? wx1 : T(1) - wx1;
+            v = fmaT((wx * wy) * wz, e[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+          }
+        }
+      }
+      X.v[el] = X.v[el] + v;
+    }
+    st4q(o, X.v);
+  }
 }
 
 // e_f += P e_c, one thread per fine point
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_prolong(MgLv F, MgLv C, const int* __restrict__ need,
-                                                    const int* __restrict__ ci, const T* __restrict__ cw,
-                                                    const T* __restrict__ ec, T* __restrict__ ef) {
-  const int t = blockIdx.y;
-  if (!need[F.sid[t]]) return;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= F.ndof) return;
+__global__ __launch_bounds__(256) void k_mg_prolong(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                    const T* __restrict__ cw, const T* __restrict__ ec,
+                                                    T* __restrict__ ef) {
+  const int chunks = (int)((F.ndof + 255) >> 8), nd = (int)F.ndof;
+  const ItemRange R = item_range(*ml.cnt * chunks);
   const int nf = F.n, nc = C.n;
-  const int i = (int)(c % nf) + 1, j = (int)((c / nf) % nf) + 1, k = (int)(c / ((long long)nf * nf)) + 1;
-  const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
-  const int I0 = ci[i - 1], J0 = ci[j - 1], K0 = ci[k - 1];
-  const T wx1 = cw[i - 1], wy1 = cw[j - 1], wz1 = cw[k - 1];
-  T v = T(0);
-  for (int cz = 0; cz < 2; cz++) {
-    const int K = K0 + cz;
-    if (K < 1 || K > nc) continue;
-    const T wz = cz ? wz1 : T(1) - wz1;
-    for (int cy = 0; cy < 2; cy++) {
-      const int J = J0 + cy;
-      if (J < 1 || J > nc) continue;
-      const T wy = cy ? wy1 : T(1) - wy1;
-      for (int cx = 0; cx < 2; cx++) {
-        const int I = I0 + cx;
-        if (I < 1 || I > nc) continue;
-        const T wx = cx ? wx1 : T(1) - wx1;
-        v = fmaT((wx * wy) * wz, e[((long long)(K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int c = (w % chunks) * 256 + (int)threadIdx.x;
+    if (c >= nd) continue;
+    const int ij = c % (nf * nf);
+    const int i = ij % nf + 1, j = ij / nf + 1, k = c / (nf * nf) + 1;
+    const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
+    const int I0 = ci[i - 1], J0 = ci[j - 1], K0 = ci[k - 1];
+    const T wx1 = cw[i - 1], wy1 = cw[j - 1], wz1 = cw[k - 1];
+    T v = T(0);
+    for (int cz = 0; cz < 2; cz++) {
+      const int K = K0 + cz;
+      if (K < 1 || K > nc) continue;
+      const T wz = cz ? wz1 : T(1) - wz1;
+      for (int cy = 0; cy < 2; cy++) {
+        const int J = J0 + cy;
+        if (J < 1 || J > nc) continue;
+        const T wy = cy ? wy1 : T(1) - wy1;
+        for (int cx = 0; cx < 2; cx++) {
+          const int I = I0 + cx;
+          if (I < 1 || I > nc) continue;
+          const T wx = cx ? wx1 : T(1) - wx1;
+          v = fmaT((wx * wy) * wz, e[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+        }
       }
     }
+    T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof);
+    o[c] = o[c] + v;
   }
-  T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof);
-  o[c] = o[c] + v;
 }
 
 // dense Cholesky of each solve's coarsest operator (FP64 tables), one thread
@@ -227,12 +442,13 @@ __global__ void k_mg_factor(MgLv C, double* __restrict__ Lall, int* __restrict__
   }
 }
 
-// e = A_c^{-1} b by the stored factor (FP64 arithmetic), one thread per solve
+// e = A_c^{-1} b by the stored factor (FP64 arithmetic), one thread per listed solve
 template <typename T>
-__global__ void k_mg_coarse(MgLv C, const int* __restrict__ need, const double* __restrict__ Lall,
-                            const T* __restrict__ b, T* __restrict__ e) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= C.nsol || !need[C.sid[t]]) return;
+__global__ void k_mg_coarse(MgLv C, MgList ml, const double* __restrict__ Lall, const T* __restrict__ b,
+                            T* __restrict__ e) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= *ml.cnt) return;
+  const int t = ml.list[w];
   const int mc = (int)C.ndof;
   const double* L = Lall + (long long)t * mc * mc;
   const long long off = C.voff ? C.voff[t] : (long long)t * C.ndof;
@@ -260,10 +476,12 @@ struct MgLevelHost {
   long long ndof = 0;
   DevBuf ci, cwd, cwf, lohi;  // transfer to the next level
   DevBuf vb, ve, ve2, vt;     // level vectors (levels >= 1), group-contiguous
+  DevBuf vtx;                 // x-restricted residual (fine rows x coarse columns)
+  bool quad = false;          // n % 4 == 0 and every vector offset a multiple of 4
 };
 
 struct MgGroup {
-  int q = 0;
+  int q = 0, seg = 0;  // problem index; its segment in the V-cycle solve list
   std::vector<int> sol;
   DevBuf sid, off0;
   std::vector<MgLevelHost*> lv;
@@ -337,8 +555,11 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     MgGroup* g = new MgGroup();
     m->g.push_back(g);
     g->q = q;
-    for (int b = 0; b < B.nsolve; b++)
+    g->seg = 0;
+    for (int b = 0; b < B.nsolve; b++) {
       if (B.sd_h[b].prob == q) g->sol.push_back(b);
+      if (B.sd_h[b].prob < q) g->seg++;
+    }
     if (g->sol.empty()) continue;
     const int ns = (int)g->sol.size();
     const Problem* P = B.probs[q];
@@ -368,6 +589,10 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
         lv->ve2.get(el * ns * lv->ndof, B.device);
         lv->vt.get(el * ns * lv->ndof, B.device);
       }
+      if (l + 1 < L) lv->vtx.get(el * ns * (size_t)nl[l] * nl[l] * nl[l + 1], B.device);
+      lv->quad = nl[l] % 4 == 0;
+      if (l == 0)
+        for (long long o : off) lv->quad = lv->quad && o % 4 == 0;
     }
     // transfer tables level l -> l+1
     for (int l = 0; l + 1 < L; l++) {
@@ -410,7 +635,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     RBWS_SCRATCH(badb);
     int* bad = (int*)badb.get(sizeof(int), B.device);
     RBWS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-    MgLv cv = view(*cl, *g, L == 1, false);
+    MgLv cv = view(*cl, *g, L == 1, false);  // (the factor kernel reads only tables)
     hipLaunchKernelGGL(k_mg_factor, dim3((ns + 63) / 64), dim3(64), 0, s, cv, Lf, bad);
     RBWS_HIP(hipGetLastError());
     int hb = 0;
@@ -421,52 +646,71 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   return m;
 }
 
+static unsigned grid_for(long long items) {
+  const long long g = std::min<long long>(std::max<long long>(items, 1), 16384);
+  return (unsigned)((g + 7) & ~7LL);
+}
+
 template <typename T>
-static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, const int* need,
-                   hipStream_t s) {
+static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, MgList ml, hipStream_t s) {
   MgLevelHost& lv = *g.lv[l];
   const int ns = (int)g.sol.size();
   const bool l0 = l == 0;
   const MgLv v = view(lv, g, l0, m->fp32);
   if (l + 1 == (int)g.lv.size()) {
-    hipLaunchKernelGGL(k_mg_coarse<T>, dim3((ns + 63) / 64), dim3(64), 0, s, v, need, (const double*)g.L.ptr, b,
-                       e);
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3((ns + 63) / 64), dim3(64), 0, s, v, ml, (const double*)g.L.ptr, b, e);
     return;
   }
-  const dim3 grid((unsigned)((lv.ndof + 255) / 256), ns);
+  const dim3 grid(grid_for((long long)ns * ((lv.ndof + 255) / 256)));
+  const dim3 gq(grid_for((long long)ns * ((lv.ndof / 4 + 255) / 256)));
   const T om = (T)m->omega;
+  auto smooth = [&](const T* ein, T* out) {
+    if (lv.quad) hipLaunchKernelGGL((k_mg_quad<T, false>), gq, dim3(256), 0, s, v, ml, b, ein, out, om);
+    else hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, ml, b, ein, out, om);
+  };
   // 2 nu Jacobi writes alternate between `scratch` and `e`, the last one into e
   T* w[2] = {scratch, e};
   int wi = 0;
-  hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)nullptr, w[wi], om);
+  smooth(nullptr, w[wi]);
   for (int it = 1; it < m->nu; it++) {
-    hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], w[wi ^ 1], om);
+    smooth(w[wi], w[wi ^ 1]);
     wi ^= 1;
   }
-  hipLaunchKernelGGL((k_mg_point<T, true>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], tres, om);
+  if (lv.quad) hipLaunchKernelGGL((k_mg_quad<T, true>), gq, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
+  else hipLaunchKernelGGL((k_mg_point<T, true>), grid, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
   MgLevelHost& cl = *g.lv[l + 1];
   const MgLv cv = view(cl, g, false, m->fp32);
   const T* cw = m->fp32 ? (const T*)lv.cwf.ptr : (const T*)lv.cwd.ptr;
   const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
-  hipLaunchKernelGGL(k_mg_restrict<T>, dim3((unsigned)((cl.ndof + 255) / 256), ns), dim3(256), 0, s, v, cv, need,
-                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
-  vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, need, s);
-  hipLaunchKernelGGL(k_mg_prolong<T>, grid, dim3(256), 0, s, v, cv, need, (const int*)lv.ci.ptr, cw,
-                     (const T*)cl.ve.ptr, w[wi]);
+  const long long nx = (long long)lv.n * lv.n * cl.n;
+  hipLaunchKernelGGL(k_mg_rx<T>, dim3(grid_for((long long)ns * ((nx + 255) / 256))), dim3(256), 0, s, v, cv, ml,
+                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)lv.vtx.ptr);
+  hipLaunchKernelGGL(k_mg_ryz<T>, dim3(grid_for((long long)ns * ((cl.ndof + 255) / 256))), dim3(256), 0, s, v,
+                     cv, ml, (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr,
+                     (T*)cl.vb.ptr, scale);
+  vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
+  if (lv.quad)
+    hipLaunchKernelGGL(k_mg_prolong_quad<T>, gq, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
+                       (const T*)cl.ve.ptr, w[wi]);
+  else
+    hipLaunchKernelGGL(k_mg_prolong<T>, grid, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
+                       (const T*)cl.ve.ptr, w[wi]);
   for (int it = 0; it < m->nu; it++) {
-    hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, need, b, (const T*)w[wi], w[wi ^ 1], om);
+    smooth(w[wi], w[wi ^ 1]);
     wi ^= 1;
   }
   // 2 nu writes: the last one went to w[(2 nu - 1) & 1] = e
 }
 
-void mg_apply(MgRun* m, const void* r, void* sv, const int* need, hipStream_t st) {
+void mg_apply(MgRun* m, const void* r, void* sv, const Lists& L, hipStream_t st) {
   for (MgGroup* g : m->g) {
     if (g->sol.empty()) continue;
+    RBWS_REQUIRE(g->q < WL_MAXPROB, RBWS_EINVAL, "too many problems in one multigrid batch");
+    const MgList ml{L.mg + g->seg, L.cnt + WL_MG + g->q};
     if (m->fp32)
-      vcycle<float>(m, *g, 0, (const float*)r, (float*)sv, (float*)m->x0.ptr, (float*)m->t0.ptr, need, st);
+      vcycle<float>(m, *g, 0, (const float*)r, (float*)sv, (float*)m->x0.ptr, (float*)m->t0.ptr, ml, st);
     else
-      vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, need, st);
+      vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, ml, st);
   }
   RBWS_HIP(hipGetLastError());
 }

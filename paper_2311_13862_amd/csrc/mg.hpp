@@ -17,8 +17,9 @@ int mg_levels_of(int n, int* out);
 // mg_apply.  The object is reused (and rebuilt) by the next call on this thread.
 MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s);
 
-// s_b = MG(r_b) (one V-cycle from zero) for every solve b with need[b] != 0;
-// r and s are device vectors laid out like the batch (double or float).
-void mg_apply(MgRun* m, const void* r, void* s, const int* need, hipStream_t st);
+// s_b = MG(r_b) (one V-cycle from zero) for every solve on the V-cycle lists
+// of L (Lists::mg, filled by the per-solve finalisers); r and s are device
+// vectors laid out like the batch (double or float).
+void mg_apply(MgRun* m, const void* r, void* s, const Lists& L, hipStream_t st);
 
 }  // namespace rbws

@@ -78,14 +78,22 @@ RoundStreams& round_streams(int device) {
 }
 
 Lists lists_init(Batch& B, hipStream_t s) {
-  const int ni = B.nitems;
-  const size_t head = 64;  // counters, padded
-  int* base = (int*)B.lists.get(sizeof(int) * (head + 3 * (size_t)ni), B.device);
+  const int ni = B.nitems, ns = B.nsolve;
+  const size_t head = 64;  // counters and segment offsets, padded
+  int* base = (int*)B.lists.get(sizeof(int) * (head + 3 * (size_t)ni + 2 * (size_t)ns), B.device);
+  // host image: head, res = all items, then (after ap and up, not copied) mg and gidx
   B.lists_h.assign(head + ni, 0);
   B.lists_h[WL_RES] = ni;
   for (int t = 0; t < ni; t++) B.lists_h[head + t] = t;
-  RBWS_HIP(hipMemcpyAsync(base, B.lists_h.data(), sizeof(int) * B.lists_h.size(), hipMemcpyHostToDevice, s));
-  return Lists{base, base + head, base + head + ni, base + head + 2 * (size_t)ni};
+  std::vector<int> gidx(ns), seg(B.nprob + 1, 0);
+  for (int b = 0; b < ns; b++) gidx[b] = seg[B.sd_h[b].prob + 1]++;
+  for (int q = 0; q < B.nprob; q++) seg[q + 1] += seg[q];
+  for (int q = 0; q < B.nprob && q < WL_MAXPROB; q++) B.lists_h[WL_SEG + q] = seg[q];
+  B.lists_h.insert(B.lists_h.end(), gidx.begin(), gidx.end());  // kept: the copies are asynchronous
+  int* mg = base + head + 3 * (size_t)ni;
+  RBWS_HIP(hipMemcpyAsync(base, B.lists_h.data(), sizeof(int) * (head + ni), hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipMemcpyAsync(mg + ns, B.lists_h.data() + head + ni, sizeof(int) * ns, hipMemcpyHostToDevice, s));
+  return Lists{base, base + head, base + head + ni, base + head + 2 * (size_t)ni, mg, mg + ns};
 }
 
 static int g_grid_mode = -1;
@@ -534,9 +542,10 @@ __global__ __launch_bounds__(256) void k_fin1(const SolveDev* __restrict__ sd,
                                               int force_exact, Lists L) {
   __shared__ FinShared sh;
   const int b = blockIdx.x;
-  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps of this round are done
+  if (b == 0 && threadIdx.x == 0) {  // the ap and res sweeps and the last V-cycle are done
     L.cnt[WL_AP] = 0;
     L.cnt[WL_RES] = 0;
+    for (int q = 0; q < WL_MAXPROB; q++) L.cnt[WL_MG + q] = 0;
   }
   const int mode = st[b].mode;
   if (mode == MODE_DONE) return;
@@ -604,7 +613,11 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
   if (s.skip2) {
     if (threadIdx.x == 0) {
       st[b].skip2 = 0;
-      if (need) need[b] = 1;  // the V-cycle on the (re)started residual
+      if (need) {  // the V-cycle on the (re)started residual
+        need[b] = 1;
+        const int q = sd[b].prob;
+        L.mg[L.cnt[WL_SEG + q] + atomicAdd(&L.cnt[WL_MG + q], 1)] = L.gidx[b];
+      }
     }
     list_push(L.ap, L.cnt + WL_AP, S.item0, S.ntiles, &sh.slot);
     return;
@@ -623,6 +636,7 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
     else if (s.mg) {
       s.restart = 0;  // beta and rho follow the V-cycle (k_fin_mg)
       need[b] = 1;
+      L.mg[L.cnt[WL_SEG + S.prob] + atomicAdd(&L.cnt[WL_MG + S.prob], 1)] = L.gidx[b];
     } else {
       s.beta = rs / s.rho;
       s.rho = rs;
@@ -977,7 +991,7 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
     kt.end(q);
     if (mg) {
       kt.begin(q, KK_MG);
-      mg_apply(mgr, r, sv, need, q);
+      mg_apply(mgr, r, sv, L, q);
       hipLaunchKernelGGL(k_dot_rs, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
                          (const int*)(L.cnt + WL_AP), ni, sd, pd, (const double*)r, (const double*)sv, part);
       hipLaunchKernelGGL(k_fin_mg, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, (const double*)x, (const double*)r,

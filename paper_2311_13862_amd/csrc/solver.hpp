@@ -59,12 +59,18 @@ void fill64(double* x, long long n, double v, hipStream_t s);
 // per-solve finalisers append each unfinished solve's tiles to the list of the
 // sweep it needs next, so a sweep touches active tiles only and the work of a
 // shrinking batch stays spread over all XCDs.  cnt[WL_*] holds the lengths.
-enum { WL_AP = 0, WL_RES = 1, WL_UP = 2 };
+// The V-cycle of a multigrid-preconditioned solve runs over a list of the
+// solves that need it this round, one segment per problem of the batch:
+// mg[seg[q] ...] holds group-local indices (gidx[b] is solve b's index within
+// its problem's group) and cnt[WL_MG + q] their number.
+enum { WL_AP = 0, WL_RES = 1, WL_UP = 2, WL_MG = 8, WL_SEG = 32, WL_MAXPROB = 24 };
 struct Lists {
   int* cnt;
   int* res;
   int* ap;
   int* up;
+  int* mg;
+  int* gidx;
 };
 
 struct Batch {
