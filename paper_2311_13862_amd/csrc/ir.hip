@@ -26,12 +26,6 @@
 
 namespace rbws {
 
-struct IrPart {
-  CrAcc rr, ff;
-  double g[3];
-  double pad;
-};
-
 // Outer pass (FP64) of every solve whose mode is RESID (fast.hpp, outer_body)
 template <bool VEC>
 __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict__ items,
@@ -539,9 +533,9 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     kt.end(q);
     if (mg) {
       kt.begin(q, KK_MG);
-      mg_apply(mgr, r, sv, L, q);
-      hipLaunchKernelGGL(k_dot_rs32, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
-                         (const int*)(L.cnt + WL_AP), ni, sd, pd, (const float*)r, (const float*)sv, part);
+      if (!mg_apply(mgr, B, r, sv, L, part, q))
+        hipLaunchKernelGGL(k_dot_rs32, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
+                           (const int*)(L.cnt + WL_AP), ni, sd, pd, (const float*)r, (const float*)sv, part);
       hipLaunchKernelGGL(k_ir_fin_mg, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, (const int*)need);
       kt.end(q);
     }

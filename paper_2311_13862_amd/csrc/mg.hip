@@ -30,8 +30,8 @@
 #include <cstring>
 #include <vector>
 
+#include "fast.hpp"
 #include "mg.hpp"
-#include "stencil.hpp"
 
 namespace rbws {
 
@@ -76,9 +76,6 @@ __device__ __forceinline__ void kappa6(const GridDev& g, const T* kap, int i, in
   kk[4] = kZ[(cxn * N1 + cyn) * N2 + czm];
   kk[5] = kZ[(cxn * N1 + cyn) * N2 + czp];
 }
-
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __fma_rn(a, b, c); }
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 
 template <typename T>
 __device__ __forceinline__ T stencilT(const T kk[6], T dg, const T* v, long long c, int n, int i, int j, int k) {
@@ -467,6 +464,186 @@ __global__ void k_mg_coarse(MgLv C, MgList ml, const double* __restrict__ Lall, 
 }
 
 // ---------------------------------------------------------------------------
+// Level 0, after the coarse correction (nu = 1): one z-march over each tile of
+// the batch (the CG work items) forms e2 = e1 + P e_c at the tile's points and
+// halo, keeps the current plane in LDS, and writes the post-smoothed
+//   s = e2 + omega (r - A e2) / d
+// with the r^T s partial of the tile (CrAcc slot 1 in FP64, IrPart.g[2] in
+// FP32).  e2 never goes to memory: 12 bytes per point (FP32) instead of the 28
+// of separate prolongation, smoothing and dot passes.
+// ---------------------------------------------------------------------------
+struct MgFine {           // per problem: its level-1 correction and level-0 transfer tables
+  const void* ec;         // coarse e, group layout (t * ndof_c)
+  const int* ci;
+  const void* cw;
+  long long ndof_c;
+  int nc, pad;
+};
+
+template <typename T>
+__device__ __forceinline__ T prolong_at(const MgFine& F, const T* ec, int I0, T wx1, int J0, T wy1, int K0, T wz1) {
+  const int nc = F.nc;
+  T v = T(0);
+  for (int cz = 0; cz < 2; cz++) {
+    const int K = K0 + cz;
+    if (K < 1 || K > nc) continue;
+    const T wz = cz ? wz1 : T(1) - wz1;
+    for (int cy = 0; cy < 2; cy++) {
+      const int J = J0 + cy;
+      if (J < 1 || J > nc) continue;
+      const T wy = cy ? wy1 : T(1) - wy1;
+      for (int cx = 0; cx < 2; cx++) {
+        const int I = I0 + cx;
+        if (I < 1 || I > nc) continue;
+        const T wx = cx ? wx1 : T(1) - wx1;
+        v = fmaT((wx * wy) * wz, ec[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+      }
+    }
+  }
+  return v;
+}
+
+template <typename T> struct PostPart;
+template <> struct PostPart<double> {
+  static __device__ __forceinline__ void put(void* part, int item, DotAcc<double>& a, CrAcc* red) {
+    const CrAcc t = cr_block_reduce(a.a, red);
+    if (threadIdx.x == 0) ((CrAcc*)part)[(long long)item * kSlots + 1] = t;
+  }
+};
+template <> struct PostPart<float> {
+  static __device__ __forceinline__ void put(void* part, int item, DotAcc<float>& a, CrAcc* red) {
+    double g = a.a;
+    for (int m = 32; m >= 1; m >>= 1) g += __shfl_xor(g, m, 64);
+    double* rd = reinterpret_cast<double*>(red);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) rd[threadIdx.x >> 6] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) ((IrPart*)part)[item].g[2] = rd[0] + rd[1] + rd[2] + rd[3];
+  }
+};
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items, const int* __restrict__ list,
+                                                  const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                  const ProbDev* __restrict__ pd, const T* __restrict__ kap,
+                                                  const MgFine* __restrict__ mf, const int* __restrict__ gidx,
+                                                  const T* __restrict__ e1, const T* __restrict__ r,
+                                                  T* __restrict__ sout, void* part, T omega, int ktab) {
+  extern __shared__ double smem_raw[];
+  T* kt = reinterpret_cast<T*>(smem_raw);
+  T* plane = kt + ktab;
+  __shared__ CrAcc red[4];
+  const WorkRange WR = work_range(*cnt);
+  for (int w = WR.w; w < WR.w1; w += WR.step) {
+    const int item = list[w];
+    __syncthreads();  // LDS of the previous item is free
+    const int2 it = items[item];
+    const int b = it.x;
+    const SolveDev S = sd[b];
+    const ProbDev& P = pd[S.prob];
+    const GridDev& g = P.g;
+    const MgFine F = mf[S.prob];
+    const T* ec = (const T*)F.ec + (long long)gidx[b] * F.ndof_c;
+    const T* cw = (const T*)F.cw;
+    const int ntab = g.ndir * g.nclass;
+    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+    __syncthreads();
+    QuadGeo G;
+    quad_geo(G, P, it.y);
+    const int n = g.n, nv = G.nv;
+    const long long n2 = (long long)n * n;
+    const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
+    const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
+    const bool hin = G.hi != 0;
+    const T* E1 = e1 + S.off;
+    const T* R = r + S.off;
+    T* SO = sout + S.off;
+    // transfer weights of the quad's x points, its row and the halo point
+    int I0[4];
+    T wx[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int i = min(G.i + e, n);
+      I0[e] = F.ci[i - 1];
+      wx[e] = cw[i - 1];
+    }
+    const int jj = min(G.j, n);
+    const int J0 = F.ci[jj - 1];
+    const T wy = cw[jj - 1];
+    const int hI0 = hin ? F.ci[G.hi - 1] : 0, hJ0 = hin ? F.ci[G.hj - 1] : 0;
+    const T hwx = hin ? cw[G.hi - 1] : T(0), hwy = hin ? cw[G.hj - 1] : T(0);
+    auto quad_e2 = [&](int k, T out[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = T(0);
+      if (nv == 0 || k < 1 || k > n) return;
+      const long long c = (long long)(k - 1) * n2 + rowoff;
+      ld4<T, VEC>(E1, c, nv, out);
+      const int K0 = F.ci[k - 1];
+      const T wz = cw[k - 1];
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (e < nv) out[e] = out[e] + prolong_at<T>(F, ec, I0[e], wx[e], J0, wy, K0, wz);
+    };
+    auto halo_e2 = [&](int k) __attribute__((always_inline)) -> T {
+      if (!hin || k < 1 || k > n) return T(0);
+      const long long c = (long long)(k - 1) * n2 + hoff;
+      return E1[c] + prolong_at<T>(F, ec, hI0, hwx, hJ0, hwy, F.ci[k - 1], cw[k - 1]);
+    };
+    T um[4], uc[4], un[4];
+    quad_e2(G.kb - 1, um);
+    quad_e2(G.kb, uc);
+    DotAcc<T> acc;
+    acc.zero();
+    int buf = 0;
+    const int mrow = (G.ly + 1) * QS + 4 * G.lx;
+    const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+    for (int k = G.kb; k <= G.ke; k++) {
+      quad_e2(k + 1, un);
+      const T hv = halo_e2(k);
+      T* pl = plane + buf * QPLANE;
+#pragma unroll
+      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      if (G.hslot >= 0) pl[G.hslot] = hv;
+      __syncthreads();
+      if (nv > 0) {
+        const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+        const long long c = (long long)(k - 1) * n2 + rowoff;
+        T rv[4];
+        ld4<T, VEC>(R, c, nv, rv);
+        const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
+        const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+        T so[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          T kk[6];
+          quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
+          const T dg = diag6T<T>(kk);
+          T q = dg * uc[e];
+          q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
+          q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
+          q = fmaT(-kk[2], pl[mrow - QS + e], q);
+          q = fmaT(-kk[3], pl[mrow + QS + e], q);
+          q = fmaT(-kk[4], um[e], q);
+          q = fmaT(-kk[5], un[e], q);
+          T t = rv[e] - q;
+          t = t / dg;
+          so[e] = fmaT(omega, t, uc[e]);
+          if (e < nv) acc.add(rv[e], so[e]);
+        }
+        st4<T, VEC>(SO, c, nv, so);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        um[e] = uc[e];
+        uc[e] = un[e];
+      }
+      buf ^= 1;
+    }
+    PostPart<T>::put(part, item, acc, red);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct MgLevelHost {
@@ -496,7 +673,9 @@ struct MgRun {
   int nu = 1, device = 0;
   double omega = 6.0 / 7.0;
   bool fp32 = false;
+  bool fused = false;  // level-0 correction + post-smoothing + r^T s in one tile kernel
   std::vector<MgGroup*> g;
+  DevBuf fine;    // MgFine per problem
   DevBuf x0, t0;  // level-0 scratch, laid out like the batch
   ~MgRun() {
     for (MgGroup* q : g) delete q;
@@ -643,6 +822,26 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     RBWS_HIP(hipStreamSynchronize(s));
     RBWS_REQUIRE(hb == 0, RBWS_ENUMERIC, "coarsest multigrid operator not positive definite");
   }
+  // the fused level-0 post step needs nu = 1 and a coarse level for every problem
+  m->fused = nu == 1;
+  std::vector<MgFine> fh(B.nprob);
+  for (MgGroup* g : m->g) {
+    if (g->sol.empty()) continue;
+    if (g->lv.size() < 2) {
+      m->fused = false;
+      continue;
+    }
+    MgFine& f = fh[g->q];
+    f.ec = g->lv[1]->ve.ptr;
+    f.ci = (const int*)g->lv[0]->ci.ptr;
+    f.cw = fp32 ? g->lv[0]->cwf.ptr : g->lv[0]->cwd.ptr;
+    f.ndof_c = g->lv[1]->ndof;
+    f.nc = g->lv[1]->n;
+    f.pad = 0;
+  }
+  RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
+                          hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipStreamSynchronize(s));
   return m;
 }
 
@@ -651,8 +850,11 @@ static unsigned grid_for(long long items) {
   return (unsigned)((g + 7) & ~7LL);
 }
 
+// one V-cycle at level l of group g; with `pre_only` (level 0 of the fused
+// path, nu = 1) it stops after the coarse correction, e1 in `scratch`
 template <typename T>
-static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, MgList ml, hipStream_t s) {
+static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, MgList ml, hipStream_t s,
+                   bool pre_only = false) {
   MgLevelHost& lv = *g.lv[l];
   const int ns = (int)g.sol.size();
   const bool l0 = l == 0;
@@ -689,6 +891,7 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
                      cv, ml, (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr,
                      (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
+  if (pre_only) return;
   if (lv.quad)
     hipLaunchKernelGGL(k_mg_prolong_quad<T>, gq, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
                        (const T*)cl.ve.ptr, w[wi]);
@@ -702,17 +905,38 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   // 2 nu writes: the last one went to w[(2 nu - 1) & 1] = e
 }
 
-void mg_apply(MgRun* m, const void* r, void* sv, const Lists& L, hipStream_t st) {
+bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void* part, hipStream_t st) {
   for (MgGroup* g : m->g) {
     if (g->sol.empty()) continue;
     RBWS_REQUIRE(g->q < WL_MAXPROB, RBWS_EINVAL, "too many problems in one multigrid batch");
     const MgList ml{L.mg + g->seg, L.cnt + WL_MG + g->q};
     if (m->fp32)
-      vcycle<float>(m, *g, 0, (const float*)r, (float*)sv, (float*)m->x0.ptr, (float*)m->t0.ptr, ml, st);
+      vcycle<float>(m, *g, 0, (const float*)r, (float*)sv, (float*)m->x0.ptr, (float*)m->t0.ptr, ml, st, m->fused);
     else
-      vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, ml, st);
+      vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, ml, st,
+                     m->fused);
+  }
+  if (m->fused) {  // e1 is in x0; the tiles of the listed solves are the CG work list L.ap
+    const int ktab = (B.kap_max + 3) & ~3;
+    const unsigned grid = 8u * (unsigned)((B.nitems + 7) / 8);
+    if (m->fp32) {
+      auto k = B.vec ? k_mg_post0<float, true> : k_mg_post0<float, false>;
+      hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
+                         (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
+                         (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr,
+                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const float*)m->x0.ptr, (const float*)r,
+                         (float*)sv, part, (float)m->omega, ktab);
+    } else {
+      auto k = B.vec ? k_mg_post0<double, true> : k_mg_post0<double, false>;
+      hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
+                         (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
+                         (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
+                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const double*)m->x0.ptr,
+                         (const double*)r, (double*)sv, part, m->omega, ktab);
+    }
   }
   RBWS_HIP(hipGetLastError());
+  return m->fused;
 }
 
 }  // namespace rbws

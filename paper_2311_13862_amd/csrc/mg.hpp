@@ -20,6 +20,8 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s);
 // s_b = MG(r_b) (one V-cycle from zero) for every solve on the V-cycle lists
 // of L (Lists::mg, filled by the per-solve finalisers); r and s are device
 // vectors laid out like the batch (double or float).
-void mg_apply(MgRun* m, const void* r, void* s, const Lists& L, hipStream_t st);
+// Returns true when the level-0 post-smoothing also wrote the r^T s partials
+// of every listed tile (partial slot 1 in FP64, IrPart.g[2] in FP32).
+bool mg_apply(MgRun* m, Batch& B, const void* r, void* s, const Lists& L, void* part, hipStream_t st);
 
 }  // namespace rbws

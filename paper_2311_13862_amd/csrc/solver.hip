@@ -30,7 +30,6 @@ namespace rbws {
 
 enum { OP_AP = 1, OP_RNORM = 3 };
 enum { DOT_PAP = 0, DOT_RR = 1, DOT_RS = 2, DOT_FF = 3, DOT_RESID = 4, DOT_RSV = 5 };
-constexpr int kSlots = 3;  // partial accumulators per work item
 
 // exact-path fallbacks taken by this translation unit's kernels (diagnostics)
 __device__ unsigned long long g_fallback_solver;
@@ -991,9 +990,9 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
     kt.end(q);
     if (mg) {
       kt.begin(q, KK_MG);
-      mg_apply(mgr, r, sv, L, q);
-      hipLaunchKernelGGL(k_dot_rs, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
-                         (const int*)(L.cnt + WL_AP), ni, sd, pd, (const double*)r, (const double*)sv, part);
+      if (!mg_apply(mgr, B, r, sv, L, part, q))
+        hipLaunchKernelGGL(k_dot_rs, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
+                           (const int*)(L.cnt + WL_AP), ni, sd, pd, (const double*)r, (const double*)sv, part);
       hipLaunchKernelGGL(k_fin_mg, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, (const double*)x, (const double*)r,
                          (const double*)sv, (const CrAcc*)part, (const int*)need, fe);
       kt.end(q);

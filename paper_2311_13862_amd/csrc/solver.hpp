@@ -37,6 +37,15 @@ struct IrState {
   int pad;
 };
 
+// partial results of a work item: FP64 path kSlots correctly rounded
+// accumulators; refinement: IrPart (slot use documented at the kernels)
+constexpr int kSlots = 3;
+struct IrPart {
+  CrAcc rr, ff;
+  double g[3];
+  double pad;
+};
+
 // device arrays of a batch (grow-only allocations, reused across calls)
 struct DevBuf {
   void* ptr = nullptr;
