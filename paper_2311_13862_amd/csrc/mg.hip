@@ -503,6 +503,122 @@ __device__ __forceinline__ T prolong_at(const MgFine& F, const T* ec, int I0, T 
   return v;
 }
 
+// Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
+// Jacobi sweep from zero) and t = b - A e1, one z-march per tile; e1 of the
+// current plane and its halo (whose diagonal comes from the halo point's own
+// coefficients) sit in LDS.  Writes e1 and t: 12 bytes per point in FP32
+// instead of the 20 of separate smoothing and residual passes.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items, const int* __restrict__ list,
+                                                 const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                 const ProbDev* __restrict__ pd, const T* __restrict__ kap,
+                                                 const T* __restrict__ b, T* __restrict__ e1out,
+                                                 T* __restrict__ tout, T omega, int ktab) {
+  extern __shared__ double smem_raw[];
+  T* kt = reinterpret_cast<T*>(smem_raw);
+  T* plane = kt + ktab;
+  const WorkRange WR = work_range(*cnt);
+  for (int w = WR.w; w < WR.w1; w += WR.step) {
+    const int item = list[w];
+    __syncthreads();  // LDS of the previous item is free
+    const int2 it = items[item];
+    const SolveDev S = sd[it.x];
+    const ProbDev& P = pd[S.prob];
+    const GridDev& g = P.g;
+    const int ntab = g.ndir * g.nclass;
+    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+    __syncthreads();
+    QuadGeo G;
+    quad_geo(G, P, it.y);
+    const int n = g.n, nv = G.nv;
+    const long long n2 = (long long)n * n;
+    const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
+    const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
+    const bool hin = G.hi != 0;
+    const T* Bv = b + S.off;
+    T* E1 = e1out + S.off;
+    T* TO = tout + S.off;
+    // e1 of the own quad at plane k (b there returned in bq)
+    auto quad_e1 = [&](int k, T out[4], T bq[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = bq[e] = T(0);
+      if (nv == 0 || k < 1 || k > n) return;
+      const long long c = (long long)(k - 1) * n2 + rowoff;
+      ld4<T, VEC>(Bv, c, nv, bq);
+      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        T kk[6];
+        quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
+        const T dg = diag6T<T>(kk);
+        T t = bq[e] - T(0);
+        t = t / dg;
+        out[e] = e < nv ? fmaT(omega, t, T(0)) : T(0);
+      }
+    };
+    auto halo_e1 = [&](int k) __attribute__((always_inline)) -> T {
+      if (!hin || k < 1 || k > n) return T(0);
+      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      T kk[6];
+      kk[0] = kt[G.hb[0] + czn];
+      kk[1] = kt[G.hb[1] + czn];
+      kk[2] = kt[G.hb[2] + czn];
+      kk[3] = kt[G.hb[3] + czn];
+      kk[4] = kt[G.hb[4] + czm];
+      kk[5] = kt[G.hb[4] + czp];
+      const T dg = diag6T<T>(kk);
+      T t = Bv[(long long)(k - 1) * n2 + hoff] - T(0);
+      t = t / dg;
+      return fmaT(omega, t, T(0));
+    };
+    T um[4], uc[4], un[4], bm[4], bc[4], bn[4];
+    quad_e1(G.kb - 1, um, bm);
+    quad_e1(G.kb, uc, bc);
+    int buf = 0;
+    const int mrow = (G.ly + 1) * QS + 4 * G.lx;
+    const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+    for (int k = G.kb; k <= G.ke; k++) {
+      quad_e1(k + 1, un, bn);
+      const T hv = halo_e1(k);
+      T* pl = plane + buf * QPLANE;
+#pragma unroll
+      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      if (G.hslot >= 0) pl[G.hslot] = hv;
+      __syncthreads();
+      if (nv > 0) {
+        const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+        const long long c = (long long)(k - 1) * n2 + rowoff;
+        const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
+        const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+        T to[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          T kk[6];
+          quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
+          const T dg = diag6T<T>(kk);
+          T q = dg * uc[e];
+          q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
+          q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
+          q = fmaT(-kk[2], pl[mrow - QS + e], q);
+          q = fmaT(-kk[3], pl[mrow + QS + e], q);
+          q = fmaT(-kk[4], um[e], q);
+          q = fmaT(-kk[5], un[e], q);
+          to[e] = bc[e] - q;
+        }
+        st4<T, VEC>(E1, c, nv, uc);
+        st4<T, VEC>(TO, c, nv, to);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        um[e] = uc[e];
+        uc[e] = un[e];
+        bc[e] = bn[e];
+      }
+      buf ^= 1;
+    }
+  }
+}
+
 template <typename T> struct PostPart;
 template <> struct PostPart<double> {
   static __device__ __forceinline__ void put(void* part, int item, DotAcc<double>& a, CrAcc* red) {
@@ -852,9 +968,12 @@ static unsigned grid_for(long long items) {
 
 // one V-cycle at level l of group g; with `pre_only` (level 0 of the fused
 // path, nu = 1) it stops after the coarse correction, e1 in `scratch`
+// (level 0 of the fused path: the pre-smoothing and the residual are already in
+// scratch and tres, written by k_mg_pre0)
 template <typename T>
 static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, MgList ml, hipStream_t s,
                    bool pre_only = false) {
+  const bool pre_done = pre_only && l == 0;
   MgLevelHost& lv = *g.lv[l];
   const int ns = (int)g.sol.size();
   const bool l0 = l == 0;
@@ -873,13 +992,15 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   // 2 nu Jacobi writes alternate between `scratch` and `e`, the last one into e
   T* w[2] = {scratch, e};
   int wi = 0;
-  smooth(nullptr, w[wi]);
-  for (int it = 1; it < m->nu; it++) {
-    smooth(w[wi], w[wi ^ 1]);
-    wi ^= 1;
+  if (!pre_done) {
+    smooth(nullptr, w[wi]);
+    for (int it = 1; it < m->nu; it++) {
+      smooth(w[wi], w[wi ^ 1]);
+      wi ^= 1;
+    }
+    if (lv.quad) hipLaunchKernelGGL((k_mg_quad<T, true>), gq, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
+    else hipLaunchKernelGGL((k_mg_point<T, true>), grid, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
   }
-  if (lv.quad) hipLaunchKernelGGL((k_mg_quad<T, true>), gq, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
-  else hipLaunchKernelGGL((k_mg_point<T, true>), grid, dim3(256), 0, s, v, ml, b, (const T*)w[wi], tres, om);
   MgLevelHost& cl = *g.lv[l + 1];
   const MgLv cv = view(cl, g, false, m->fp32);
   const T* cw = m->fp32 ? (const T*)lv.cwf.ptr : (const T*)lv.cwd.ptr;
@@ -906,6 +1027,23 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
 }
 
 bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void* part, hipStream_t st) {
+  const int ktab = (B.kap_max + 3) & ~3;
+  const unsigned tgrid = 8u * (unsigned)((B.nitems + 7) / 8);
+  if (m->fused) {  // level 0: e1 into x0 and the residual into t0, over the tiles of the listed solves
+    if (m->fp32) {
+      auto k = B.vec ? k_mg_pre0<float, true> : k_mg_pre0<float, false>;
+      hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
+                         (const int*)L.ap, (const int*)(L.cnt + WL_AP), (const SolveDev*)B.sd.ptr,
+                         (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r, (float*)m->x0.ptr,
+                         (float*)m->t0.ptr, (float)m->omega, ktab);
+    } else {
+      auto k = B.vec ? k_mg_pre0<double, true> : k_mg_pre0<double, false>;
+      hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
+                         (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
+                         (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
+                         (const double*)r, (double*)m->x0.ptr, (double*)m->t0.ptr, m->omega, ktab);
+    }
+  }
   for (MgGroup* g : m->g) {
     if (g->sol.empty()) continue;
     RBWS_REQUIRE(g->q < WL_MAXPROB, RBWS_EINVAL, "too many problems in one multigrid batch");
@@ -917,8 +1055,7 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
                      m->fused);
   }
   if (m->fused) {  // e1 is in x0; the tiles of the listed solves are the CG work list L.ap
-    const int ktab = (B.kap_max + 3) & ~3;
-    const unsigned grid = 8u * (unsigned)((B.nitems + 7) / 8);
+    const unsigned grid = tgrid;
     if (m->fp32) {
       auto k = B.vec ? k_mg_post0<float, true> : k_mg_post0<float, false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
