@@ -530,8 +530,10 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
  *     ascending over the fine points whose weight on the coarse node may be
  *     nonzero), ay = sum over j of py ax, az = sum over k of pz ay, then
  *     az * ((nc+1)/(nf+1))
- *   prolongation: v = 0, corners z, y, x in order 0, 1 (interior corners
- *     only), v = fma((wx wy) wz, e_c, v), then e = e + v
+ *   prolongation, separable (interior corners only, each sum an fma chain
+ *     from 0 over corner 0 then 1): az = sum over the z corners of wz e_c,
+ *     ay = sum over the y corners of wy az, v = sum over the x corners of
+ *     wx ay, then e = e + v
  *   coarse solve: Cholesky and the two triangular solves with sequential
  *     fma accumulation in index order. */
 #define MG_MAXLEV 16
@@ -621,21 +623,25 @@ static void mg_prolong(const mg_ctx *c, int l, const double *ec, double *ef) {
         for (int j = 1; j <= nf; j++)
             for (int i = 1; i <= nf; i++) {
                 double v = 0.0;
-                for (int cz = 0; cz < 2; cz++) {
-                    int K = ci[k - 1] + cz;
-                    if (K < 1 || K > nc) continue;
-                    double wz = cz ? cw[k - 1] : 1.0 - cw[k - 1];
+                for (int cx = 0; cx < 2; cx++) {
+                    int I = ci[i - 1] + cx;
+                    if (I < 1 || I > nc) continue;
+                    double wx = cx ? cw[i - 1] : 1.0 - cw[i - 1];
+                    double ay = 0.0;
                     for (int cy = 0; cy < 2; cy++) {
                         int J = ci[j - 1] + cy;
                         if (J < 1 || J > nc) continue;
                         double wy = cy ? cw[j - 1] : 1.0 - cw[j - 1];
-                        for (int cx = 0; cx < 2; cx++) {
-                            int I = ci[i - 1] + cx;
-                            if (I < 1 || I > nc) continue;
-                            double wx = cx ? cw[i - 1] : 1.0 - cw[i - 1];
-                            v = fma((wx * wy) * wz, ec[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
+                        double az = 0.0;
+                        for (int cz = 0; cz < 2; cz++) {
+                            int K = ci[k - 1] + cz;
+                            if (K < 1 || K > nc) continue;
+                            double wz = cz ? cw[k - 1] : 1.0 - cw[k - 1];
+                            az = fma(wz, ec[((long)(K - 1) * nc + (J - 1)) * nc + (I - 1)], az);
                         }
+                        ay = fma(wy, az, ay);
                     }
+                    v = fma(wx, ay, v);
                 }
                 long f = ((long)(k - 1) * nf + (j - 1)) * nf + (i - 1);
                 ef[f] = ef[f] + v;

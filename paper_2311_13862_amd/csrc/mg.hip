@@ -19,7 +19,9 @@
 //   Jacobi        q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
 //   restriction   ax = fma(px, r, ax) over i, ay = fma(py, ax, ay) over j,
 //                 az = fma(pz, ay, az) over k (ascending, from 0), then az * scale
-//   prolongation  v = fma((wx wy) wz, e_c, v) over corners z, y, x (interior ones), e + v
+//   prolongation  az = fma(wz, e_c, az) over z corners, ay = fma(wy, az, ay) over
+//                 y corners, v = fma(wx, ay, v) over x corners (interior ones,
+//                 corner 0 then 1, from 0), then e + v
 //   coarsest      Cholesky and triangular solves with sequential fma accumulation
 // so that the FP64 V-cycle, and with it the whole MGCG trajectory, is
 // independent of the launch shape.
@@ -201,6 +203,55 @@ __global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const
   }
 }
 
+// Prolongation, separable: first the coarse values are interpolated in z and y
+// onto the fine (k, j) rows at every coarse column I,
+//   ezy[k][j][I] = sum_cy wy (sum_cz wz e_c[K][J][I])    (fma chains from 0),
+// then each fine point takes v = sum_cx wx ezy[k][j][I0 + cx].  Out-of-grid
+// coarse nodes (value 0) are skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_pyz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                const T* __restrict__ cw, const T* __restrict__ ec,
+                                                T* __restrict__ ezy) {
+  const int nc = C.n, nf = F.n;
+  const int per = nf * nf * nc;
+  const int chunks = (per + 255) >> 8;
+  const ItemRange R = item_range(*ml.cnt * chunks);
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / chunks];
+    const int o = (w % chunks) * 256 + (int)threadIdx.x;
+    if (o >= per) continue;
+    const int I = o % nc + 1, row = o / nc;
+    const int j = row % nf + 1, k = row / nf + 1;
+    const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (I - 1);
+    const int J0 = ci[j - 1], K0 = ci[k - 1];
+    const T wy1 = cw[j - 1], wz1 = cw[k - 1];
+    T ay = T(0);
+    for (int cy = 0; cy < 2; cy++) {
+      const int J = J0 + cy;
+      if (J < 1 || J > nc) continue;
+      const T wy = cy ? wy1 : T(1) - wy1;
+      T az = T(0);
+      for (int cz = 0; cz < 2; cz++) {
+        const int K = K0 + cz;
+        if (K < 1 || K > nc) continue;
+        const T wz = cz ? wz1 : T(1) - wz1;
+        az = fmaT(wz, e[((K - 1) * nc + (J - 1)) * nc], az);
+      }
+      ay = fmaT(wy, az, ay);
+    }
+    ezy[(long long)t * per + o] = ay;
+  }
+}
+
+// v = sum over the x corners of wx ezy (row pointer at coarse column 1)
+template <typename T>
+__device__ __forceinline__ T prolong_x(const T* __restrict__ row, int nc, int I0, T wx1) {
+  T v = T(0);
+  if (I0 >= 1) v = fmaT(T(1) - wx1, row[I0 - 1], v);
+  if (I0 + 1 <= nc) v = fmaT(wx1, row[I0], v);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // the same point operations on quads of 4 x-consecutive points (n % 4 == 0,
 // 16-byte aligned vectors): one vector load per neighbour plane or row
@@ -317,7 +368,7 @@ __global__ __launch_bounds__(256) void k_mg_quad(MgLv L, MgList ml, const T* __r
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_prolong_quad(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
-                                                         const T* __restrict__ cw, const T* __restrict__ ec,
+                                                         const T* __restrict__ cw, const T* __restrict__ ezy,
                                                          T* __restrict__ ef) {
   const int nf = F.n, nc = C.n, nd = (int)F.ndof, nq = nd >> 2;
   const int chunks = (nq + 255) >> 8;
@@ -327,76 +378,32 @@ __global__ __launch_bounds__(256) void k_mg_prolong_quad(MgLv F, MgLv C, MgList 
     const int q = (w % chunks) * 256 + (int)threadIdx.x;
     if (q >= nq) continue;
     const int c = q * 4;
-    const int ij = c % (nf * nf);
-    const int i0 = ij % nf + 1, j = ij / nf + 1, k = c / (nf * nf) + 1;
-    const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
+    const int i0 = c % nf + 1, row = c / nf;
+    const T* zr = ezy + (long long)t * nf * nf * nc + (long long)row * nc;
     T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof) + c;
     V4<T> X = ld4q(o);
-    const int J0 = ci[j - 1], K0 = ci[k - 1];
-    const T wy1 = cw[j - 1], wz1 = cw[k - 1];
 #pragma unroll
-    for (int el = 0; el < 4; el++) {
-      const int I0 = ci[i0 + el - 1];
-      const T wx1 = cw[i0 + el - 1];
-      T v = T(0);
-      for (int cz = 0; cz < 2; cz++) {
-        const int K = K0 + cz;
-        if (K < 1 || K > nc) continue;
-        const T wz = cz ? wz1 : T(1) - wz1;
-        for (int cy = 0; cy < 2; cy++) {
-          const int J = J0 + cy;
-          if (J < 1 || J > nc) continue;
-          const T wy = cy ? wy1 : T(1) - wy1;
-          for (int cx = 0; cx < 2; cx++) {
-            const int I = I0 + cx;
-            if (I < 1 || I > nc) continue;
-            const T wx = cx ? wx1 : T(1) - wx1;
-            v = fmaT((wx * wy) * wz, e[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
-          }
-        }
-      }
-      X.v[el] = X.v[el] + v;
-    }
+    for (int el = 0; el < 4; el++) X.v[el] = X.v[el] + prolong_x(zr, nc, ci[i0 + el - 1], cw[i0 + el - 1]);
     st4q(o, X.v);
   }
 }
 
-// e_f += P e_c, one thread per fine point
+// e_f += P e_c, one thread per fine point (from the z/y-interpolated ezy)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_prolong(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
-                                                    const T* __restrict__ cw, const T* __restrict__ ec,
+                                                    const T* __restrict__ cw, const T* __restrict__ ezy,
                                                     T* __restrict__ ef) {
-  const int chunks = (int)((F.ndof + 255) >> 8), nd = (int)F.ndof;
+  const int nf = F.n, nc = C.n, nd = (int)F.ndof;
+  const int chunks = (nd + 255) >> 8;
   const ItemRange R = item_range(*ml.cnt * chunks);
-  const int nf = F.n, nc = C.n;
   for (int w = R.w; w < R.w1; w += R.step) {
     const int t = ml.list[w / chunks];
     const int c = (w % chunks) * 256 + (int)threadIdx.x;
     if (c >= nd) continue;
-    const int ij = c % (nf * nf);
-    const int i = ij % nf + 1, j = ij / nf + 1, k = c / (nf * nf) + 1;
-    const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof);
-    const int I0 = ci[i - 1], J0 = ci[j - 1], K0 = ci[k - 1];
-    const T wx1 = cw[i - 1], wy1 = cw[j - 1], wz1 = cw[k - 1];
-    T v = T(0);
-    for (int cz = 0; cz < 2; cz++) {
-      const int K = K0 + cz;
-      if (K < 1 || K > nc) continue;
-      const T wz = cz ? wz1 : T(1) - wz1;
-      for (int cy = 0; cy < 2; cy++) {
-        const int J = J0 + cy;
-        if (J < 1 || J > nc) continue;
-        const T wy = cy ? wy1 : T(1) - wy1;
-        for (int cx = 0; cx < 2; cx++) {
-          const int I = I0 + cx;
-          if (I < 1 || I > nc) continue;
-          const T wx = cx ? wx1 : T(1) - wx1;
-          v = fmaT((wx * wy) * wz, e[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
-        }
-      }
-    }
+    const int i = c % nf + 1, row = c / nf;  // row = (k-1) nf + (j-1)
+    const T* zr = ezy + (long long)t * nf * nf * nc + (long long)row * nc;
     T* o = ef + (F.voff ? F.voff[t] : (long long)t * F.ndof);
-    o[c] = o[c] + v;
+    o[c] = o[c] + prolong_x(zr, nc, ci[i - 1], cw[i - 1]);
   }
 }
 
@@ -472,36 +479,13 @@ __global__ void k_mg_coarse(MgLv C, MgList ml, const double* __restrict__ Lall, 
 // FP32).  e2 never goes to memory: 12 bytes per point (FP32) instead of the 28
 // of separate prolongation, smoothing and dot passes.
 // ---------------------------------------------------------------------------
-struct MgFine {           // per problem: its level-1 correction and level-0 transfer tables
-  const void* ec;         // coarse e, group layout (t * ndof_c)
+struct MgFine {           // per problem: the z/y-interpolated level-1 correction and transfer tables
+  const void* ezy;        // group layout, t * nf * nf * nc
   const int* ci;
   const void* cw;
-  long long ndof_c;
+  long long per;          // nf * nf * nc
   int nc, pad;
 };
-
-template <typename T>
-__device__ __forceinline__ T prolong_at(const MgFine& F, const T* ec, int I0, T wx1, int J0, T wy1, int K0, T wz1) {
-  const int nc = F.nc;
-  T v = T(0);
-  for (int cz = 0; cz < 2; cz++) {
-    const int K = K0 + cz;
-    if (K < 1 || K > nc) continue;
-    const T wz = cz ? wz1 : T(1) - wz1;
-    for (int cy = 0; cy < 2; cy++) {
-      const int J = J0 + cy;
-      if (J < 1 || J > nc) continue;
-      const T wy = cy ? wy1 : T(1) - wy1;
-      for (int cx = 0; cx < 2; cx++) {
-        const int I = I0 + cx;
-        if (I < 1 || I > nc) continue;
-        const T wx = cx ? wx1 : T(1) - wx1;
-        v = fmaT((wx * wy) * wz, ec[((K - 1) * nc + (J - 1)) * nc + (I - 1)], v);
-      }
-    }
-  }
-  return v;
-}
 
 // Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
 // Jacobi sweep from zero) and t = b - A e1, one z-march per tile; e1 of the
@@ -659,7 +643,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     const ProbDev& P = pd[S.prob];
     const GridDev& g = P.g;
     const MgFine F = mf[S.prob];
-    const T* ec = (const T*)F.ec + (long long)gidx[b] * F.ndof_c;
+    const T* ezy = (const T*)F.ezy + (long long)gidx[b] * F.per;
     const T* cw = (const T*)F.cw;
     const int ntab = g.ndir * g.nclass;
     for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
@@ -683,27 +667,26 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       I0[e] = F.ci[i - 1];
       wx[e] = cw[i - 1];
     }
+    const int nc = F.nc;
     const int jj = min(G.j, n);
-    const int J0 = F.ci[jj - 1];
-    const T wy = cw[jj - 1];
-    const int hI0 = hin ? F.ci[G.hi - 1] : 0, hJ0 = hin ? F.ci[G.hj - 1] : 0;
-    const T hwx = hin ? cw[G.hi - 1] : T(0), hwy = hin ? cw[G.hj - 1] : T(0);
+    const int hI0 = hin ? F.ci[G.hi - 1] : 0;
+    const T hwx = hin ? cw[G.hi - 1] : T(0);
     auto quad_e2 = [&](int k, T out[4]) __attribute__((always_inline)) {
 #pragma unroll
       for (int e = 0; e < 4; e++) out[e] = T(0);
       if (nv == 0 || k < 1 || k > n) return;
       const long long c = (long long)(k - 1) * n2 + rowoff;
       ld4<T, VEC>(E1, c, nv, out);
-      const int K0 = F.ci[k - 1];
-      const T wz = cw[k - 1];
+      const T* zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc;
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        if (e < nv) out[e] = out[e] + prolong_at<T>(F, ec, I0[e], wx[e], J0, wy, K0, wz);
+        if (e < nv) out[e] = out[e] + prolong_x(zr, nc, I0[e], wx[e]);
     };
     auto halo_e2 = [&](int k) __attribute__((always_inline)) -> T {
       if (!hin || k < 1 || k > n) return T(0);
       const long long c = (long long)(k - 1) * n2 + hoff;
-      return E1[c] + prolong_at<T>(F, ec, hI0, hwx, hJ0, hwy, F.ci[k - 1], cw[k - 1]);
+      const T* zr = ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc;
+      return E1[c] + prolong_x(zr, nc, hI0, hwx);
     };
     T um[4], uc[4], un[4];
     quad_e2(G.kb - 1, um);
@@ -948,10 +931,10 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
       continue;
     }
     MgFine& f = fh[g->q];
-    f.ec = g->lv[1]->ve.ptr;
+    f.ezy = g->lv[0]->vtx.ptr;
     f.ci = (const int*)g->lv[0]->ci.ptr;
     f.cw = fp32 ? g->lv[0]->cwf.ptr : g->lv[0]->cwd.ptr;
-    f.ndof_c = g->lv[1]->ndof;
+    f.per = (long long)g->lv[0]->n * g->lv[0]->n * g->lv[1]->n;
     f.nc = g->lv[1]->n;
     f.pad = 0;
   }
@@ -1012,13 +995,16 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
                      cv, ml, (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr,
                      (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
+  // z/y interpolation of the coarse correction (into vtx, free again after the restriction)
+  hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * ((nx + 255) / 256))), dim3(256), 0, s, v, cv, ml,
+                     (const int*)lv.ci.ptr, cw, (const T*)cl.ve.ptr, (T*)lv.vtx.ptr);
   if (pre_only) return;
   if (lv.quad)
     hipLaunchKernelGGL(k_mg_prolong_quad<T>, gq, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
-                       (const T*)cl.ve.ptr, w[wi]);
+                       (const T*)lv.vtx.ptr, w[wi]);
   else
     hipLaunchKernelGGL(k_mg_prolong<T>, grid, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
-                       (const T*)cl.ve.ptr, w[wi]);
+                       (const T*)lv.vtx.ptr, w[wi]);
   for (int it = 0; it < m->nu; it++) {
     smooth(w[wi], w[wi ^ 1]);
     wi ^= 1;
