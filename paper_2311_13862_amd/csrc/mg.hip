@@ -147,30 +147,56 @@ __global__ __launch_bounds__(256) void k_mg_point(MgLv L, MgList ml, const T* __
   }
 }
 
+// Transfers between levels.  A wave takes a row of 64 coarse columns I (lane =
+// column) and walks several fine or coarse rows with the per-column weights
+// held in registers, so the index arithmetic is paid once per wave item.
+//
 // Restriction b_c = scale P^T r_f, separable: the x-pass forms, for every fine
 // (k, j) row and coarse column I, ax = sum_i px r (fma chain from 0, i ascending);
 // the yz-pass forms az = sum_k pz (sum_j py ax) per coarse point, times scale.
+constexpr int kSpan = 6;  // fine points per coarse node and axis: 2 (nf+1)/(nc+1) + 1 <= 6
+constexpr int kRxRows = 32;
+
+template <typename T>
+__device__ __forceinline__ int fine_weights(int I, const int* __restrict__ ci, const T* __restrict__ cw,
+                                            const int2* __restrict__ lohi, T wts[kSpan]) {
+  const int2 r = lohi[I];
+#pragma unroll
+  for (int u = 0; u < kSpan; u++) {
+    const int i = r.x + u;
+    wts[u] = i <= r.y ? (ci[i - 1] == I ? T(1) - cw[i - 1] : cw[i - 1]) : T(0);
+  }
+  return r.x;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_rx(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
                                                const T* __restrict__ cw, const int2* __restrict__ lohi,
                                                const T* __restrict__ rf, T* __restrict__ tx) {
-  const int nc = C.n, nf = F.n;
-  const int per = nf * nf * nc;  // outputs per solve
-  const int chunks = (per + 255) >> 8;
-  const ItemRange R = item_range(*ml.cnt * chunks);
+  const int nc = C.n, nf = F.n, rows = nf * nf;
+  const int ich = (nc + 63) >> 6, rblk = (rows + kRxRows - 1) / kRxRows;
+  const int per = ich * rblk;
+  const ItemRange R = item_range(*ml.cnt * per);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int w = R.w; w < R.w1; w += R.step) {
-    const int t = ml.list[w / chunks];
-    const int o = (w % chunks) * 256 + (int)threadIdx.x;
-    if (o >= per) continue;
-    const int I = o % nc + 1, row = o / nc;  // row = (k-1) nf + (j-1)
-    const T* r = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof) + (long long)row * nf - 1;
-    const int2 xr = lohi[I];
-    T ax = T(0);
-    for (int i = xr.x; i <= xr.y; i++) {
-      const T px = ci[i - 1] == I ? T(1) - cw[i - 1] : cw[i - 1];
-      ax = fmaT(px, r[i], ax);
+    const int t = ml.list[w / per];
+    const int rem = w % per, rb = rem / ich, I = (rem % ich) * 64 + lane + 1;
+    if (I > nc) continue;
+    T wts[kSpan];
+    const int lo = fine_weights(I, ci, cw, lohi, wts);
+    const int2 span = lohi[I];
+    const T* r0 = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof) + (lo - 1);
+    T* out = tx + (long long)t * rows * nc + (I - 1);
+    for (int m = wv; m < kRxRows; m += 4) {
+      const int row = rb * kRxRows + m;
+      if (row >= rows) break;
+      const T* rr = r0 + (long long)row * nf;
+      T ax = T(0);
+#pragma unroll
+      for (int u = 0; u < kSpan; u++)
+        if (lo + u <= span.y) ax = fmaT(wts[u], rr[u], ax);
+      out[(long long)row * nc] = ax;
     }
-    tx[(long long)t * per + o] = ax;
   }
 }
 
@@ -178,28 +204,35 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
                                                 const T* __restrict__ cw, const int2* __restrict__ lohi,
                                                 const T* __restrict__ tx, T* __restrict__ bc, T scale) {
-  const int nc = C.n, nf = F.n, nd = (int)C.ndof;
-  const int chunks = (nd + 255) >> 8;
-  const ItemRange R = item_range(*ml.cnt * chunks);
+  const int nc = C.n, nf = F.n;
+  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2;
+  const int per = nc * jq * ich;  // (K, J quad, I chunk) items per solve
+  const ItemRange R = item_range(*ml.cnt * per);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int w = R.w; w < R.w1; w += R.step) {
-    const int t = ml.list[w / chunks];
-    const int c = (w % chunks) * 256 + (int)threadIdx.x;
-    if (c >= nd) continue;
-    const int IJ = c % (nc * nc);
-    const int I = IJ % nc + 1, J = IJ / nc + 1, K = c / (nc * nc) + 1;
+    const int t = ml.list[w / per];
+    const int rem = w % per;
+    const int K = rem / (jq * ich) + 1, J = ((rem / ich) % jq) * 4 + wv + 1, I = (rem % ich) * 64 + lane + 1;
+    if (J > nc || I > nc) continue;
+    T wy[kSpan], wz[kSpan];
+    const int jlo = fine_weights(J, ci, cw, lohi, wy);
+    const int klo = fine_weights(K, ci, cw, lohi, wz);
+    const int jhi = lohi[J].y, khi = lohi[K].y;
     const T* a = tx + (long long)t * nf * nf * nc + (I - 1);
-    const int2 yr = lohi[J], zr = lohi[K];
     T az = T(0);
-    for (int k = zr.x; k <= zr.y; k++) {
-      const T pz = ci[k - 1] == K ? T(1) - cw[k - 1] : cw[k - 1];
+#pragma unroll
+    for (int uk = 0; uk < kSpan; uk++) {
+      const int k = klo + uk;
+      if (k > khi) continue;
       T ay = T(0);
-      for (int j = yr.x; j <= yr.y; j++) {
-        const T py = ci[j - 1] == J ? T(1) - cw[j - 1] : cw[j - 1];
-        ay = fmaT(py, a[((k - 1) * nf + (j - 1)) * nc], ay);
+#pragma unroll
+      for (int uj = 0; uj < kSpan; uj++) {
+        const int j = jlo + uj;
+        if (j <= jhi) ay = fmaT(wy[uj], a[((long long)(k - 1) * nf + (j - 1)) * nc], ay);
       }
-      az = fmaT(pz, ay, az);
+      az = fmaT(wz[uk], ay, az);
     }
-    bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + c] = az * scale;
+    bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + ((K - 1) * nc + (J - 1)) * nc + (I - 1)] = az * scale;
   }
 }
 
@@ -207,20 +240,21 @@ __global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const
 // onto the fine (k, j) rows at every coarse column I,
 //   ezy[k][j][I] = sum_cy wy (sum_cz wz e_c[K][J][I])    (fma chains from 0),
 // then each fine point takes v = sum_cx wx ezy[k][j][I0 + cx].  Out-of-grid
-// coarse nodes (value 0) are skipped.
+// coarse nodes (value 0) are skipped.  A wave takes one fine row and 64 I.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_pyz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
                                                 const T* __restrict__ cw, const T* __restrict__ ec,
                                                 T* __restrict__ ezy) {
   const int nc = C.n, nf = F.n;
-  const int per = nf * nf * nc;
-  const int chunks = (per + 255) >> 8;
-  const ItemRange R = item_range(*ml.cnt * chunks);
+  const int ich = (nc + 63) >> 6, rq = (nf * nf + 3) >> 2;
+  const int per = rq * ich;
+  const ItemRange R = item_range(*ml.cnt * per);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int w = R.w; w < R.w1; w += R.step) {
-    const int t = ml.list[w / chunks];
-    const int o = (w % chunks) * 256 + (int)threadIdx.x;
-    if (o >= per) continue;
-    const int I = o % nc + 1, row = o / nc;
+    const int t = ml.list[w / per];
+    const int rem = w % per;
+    const int row = (rem / ich) * 4 + wv, I = (rem % ich) * 64 + lane + 1;
+    if (row >= nf * nf || I > nc) continue;
     const int j = row % nf + 1, k = row / nf + 1;
     const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (I - 1);
     const int J0 = ci[j - 1], K0 = ci[k - 1];
@@ -239,7 +273,7 @@ __global__ __launch_bounds__(256) void k_mg_pyz(MgLv F, MgLv C, MgList ml, const
       }
       ay = fmaT(wy, az, ay);
     }
-    ezy[(long long)t * per + o] = ay;
+    ezy[(long long)t * nf * nf * nc + (long long)row * nc + (I - 1)] = ay;
   }
 }
 
@@ -893,6 +927,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
             hi = std::max(hi, i);
           }
         lh[I] = make_int2(lo, hi);
+        RBWS_REQUIRE(hi - lo + 1 <= kSpan, RBWS_EINVAL, "multigrid transfer wider than expected");
       }
       MgLevelHost* lv = g->lv[l];
       RBWS_HIP(hipMemcpyAsync(lv->ci.get(sizeof(int) * nf, B.device), ci.data(), sizeof(int) * nf,
@@ -989,14 +1024,17 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const T* cw = m->fp32 ? (const T*)lv.cwf.ptr : (const T*)lv.cwd.ptr;
   const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
   const long long nx = (long long)lv.n * lv.n * cl.n;
-  hipLaunchKernelGGL(k_mg_rx<T>, dim3(grid_for((long long)ns * ((nx + 255) / 256))), dim3(256), 0, s, v, cv, ml,
+  const long long nrx = ((long long)lv.n * lv.n + kRxRows - 1) / kRxRows * ((cl.n + 63) / 64);
+  const long long nryz = (long long)cl.n * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
+  const long long npyz = ((long long)lv.n * lv.n + 3) / 4 * ((cl.n + 63) / 64);
+  hipLaunchKernelGGL(k_mg_rx<T>, dim3(grid_for((long long)ns * nrx)), dim3(256), 0, s, v, cv, ml,
                      (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)lv.vtx.ptr);
-  hipLaunchKernelGGL(k_mg_ryz<T>, dim3(grid_for((long long)ns * ((cl.ndof + 255) / 256))), dim3(256), 0, s, v,
+  hipLaunchKernelGGL(k_mg_ryz<T>, dim3(grid_for((long long)ns * nryz)), dim3(256), 0, s, v,
                      cv, ml, (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr,
                      (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
   // z/y interpolation of the coarse correction (into vtx, free again after the restriction)
-  hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * ((nx + 255) / 256))), dim3(256), 0, s, v, cv, ml,
+  hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
                      (const int*)lv.ci.ptr, cw, (const T*)cl.ve.ptr, (T*)lv.vtx.ptr);
   if (pre_only) return;
   if (lv.quad)
