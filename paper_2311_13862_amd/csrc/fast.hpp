@@ -91,7 +91,14 @@ struct QuadGeo {
   // halo point of this thread (threads 0..127), -1 when none / outside
   int hslot, hi, hj;
   int hb[6];                // the halo point's six face bases (x-,x+,y-,y+ with node z code, z)
+  // packed z class codes czn | czm << 8 | czp << 16 of the planes kb-1 .. ke+1
+  // (index k - kb + 1), staged in LDS by zk_stage
+  const int* zk;
 };
+
+// Deepest tile (planes per z-march) and the length of its staged z codes.
+constexpr int kTzMax = 64;
+constexpr int kZkLen = kTzMax + 4;
 
 __device__ __forceinline__ void quad_geo(QuadGeo& G, const ProbDev& P, int tile) {
   const GridDev& g = P.g;
@@ -218,7 +225,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
       for (int e = 0; e < 4; e++) out[e] = ra[e];
       return;
     }
-    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+    const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       T sv = ra[e];
@@ -245,7 +252,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
     if (OP != FOP_AP || !hin) return ha;
     T sv = ha;
     if (prec) {
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
       T kk[6] = {kt[G.hb[0] + czn], kt[G.hb[1] + czn], kt[G.hb[2] + czn],
                  kt[G.hb[3] + czn], kt[G.hb[4] + czm], kt[G.hb[4] + czp]};
       sv = ha / diag6T<T>(kk);
@@ -296,7 +303,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
     if (G.hslot >= 0) pl[G.hslot] = halo_finish(k, ha, hb);
     __syncthreads();
     if (nv > 0) {
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
       const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
       const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
       T qo[4];
@@ -367,6 +374,18 @@ __device__ __forceinline__ int zkey(const GridDev& g, int k) {
   return g.code[2][0][k - 1] | (g.code[2][1][k - 1] << 8) | (g.code[2][1][k] << 16);
 }
 
+// Stages the tile's z codes in LDS (zk[kZkLen], before the barrier that
+// publishes the class table).  The z-march then reads them from LDS: a global
+// load of a code inside the march would make the wait for it also drain the
+// loads issued ahead for later planes.
+__device__ __forceinline__ void zk_stage(int* zk, const GridDev& g, QuadGeo& G) {
+  for (int t = threadIdx.x; t < G.ke - G.kb + 3; t += blockDim.x) {
+    const int k = G.kb - 1 + t;
+    zk[t] = (k >= 1 && k <= g.n) ? zkey(g, k) : 0;
+  }
+  G.zk = zk;
+}
+
 __device__ __forceinline__ void kc_fill(KCache32& C, const QuadGeo& G, const float* kt, int key) {
   const int czn = key & 255, czm = (key >> 8) & 255, czp = key >> 16;
 #pragma unroll
@@ -418,7 +437,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
   };
   // reciprocal diagonal of the own quad at plane k (from the cache when the codes match)
   auto quad_inv = [&](int k, float inv[4]) __attribute__((always_inline)) {
-    const int key = zkey(g, k);
+    const int key = G.zk[k - G.kb + 1];
     if (key == C.key) {
 #pragma unroll
       for (int e = 0; e < 4; e++) inv[e] = C.inv[e];
@@ -490,7 +509,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
 #pragma unroll
     for (int e = 0; e < 4; e++) xo2[e] = ro2[e] = 0.0f;
     xr_load(k + 1, xo2, ro2);
-    const int key = zkey(g, k);
+    const int key = G.zk[k - G.kb + 1];
     if (key != C.key) kc_fill(C, G, kt, key);
     float* pl = plane + buf * QPLANE;
 #pragma unroll
@@ -608,7 +627,7 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
     if (G.hslot >= 0) pl[G.hslot] = hv;
     __syncthreads();
     if (nv > 0) {
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
       const double left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
       const double right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
       float ro[4];

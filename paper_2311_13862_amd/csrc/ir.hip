@@ -37,6 +37,7 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   extern __shared__ double lds[];
   __shared__ double redd[4][2];
   __shared__ CrAcc redc[4];
+  __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
@@ -48,13 +49,14 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   double* k64 = lds;
   float* k32 = reinterpret_cast<float*>(lds + ktab);
   double* plane = lds + ktab + (ktab + 1) / 2;
+  QuadGeo G;
+  quad_geo(G, P, it.y);
   for (int e = threadIdx.x; e < ntab; e += blockDim.x) {
     k32[e] = kap32[S.kap_off + e];
     k64[e] = kap64[S.kap_off + e];
   }
+  zk_stage(zk, g, G);
   __syncthreads();
-  QuadGeo G;
-  quad_geo(G, P, it.y);
   const IrState& s = st[b];
   const int first = s.first;
   double g0 = 0.0, g1 = 0.0;
@@ -109,6 +111,7 @@ __device__ __forceinline__ void k_fast32_item(int item, const int2* __restrict__
   extern __shared__ double smem_raw[];
   float* smem = reinterpret_cast<float*>(smem_raw);
   __shared__ double red[4][2];
+  __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
@@ -118,10 +121,11 @@ __device__ __forceinline__ void k_fast32_item(int item, const int2* __restrict__
   const SolveDev S = sd[b];
   const ProbDev& P = pd[S.prob];
   const int ntab = P.g.ndir * P.g.nclass;
-  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
-  __syncthreads();
   QuadGeo G;
   quad_geo(G, P, it.y);
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
+  zk_stage(zk, P.g, G);
+  __syncthreads();
   const int par = s.k_total & 1;
   const float* Pold = (par ? p1 : p0) + S.off;
   float* Pn = (par ? p0 : p1) + S.off;

@@ -524,17 +524,19 @@ struct MgFine {           // per problem: the z/y-interpolated level-1 correctio
 // Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
 // Jacobi sweep from zero) and t = b - A e1, one z-march per tile; e1 of the
 // current plane and its halo (whose diagonal comes from the halo point's own
-// coefficients) sit in LDS.  Writes e1 and t: 12 bytes per point in FP32
-// instead of the 20 of separate smoothing and residual passes.
+// coefficients) sit in LDS.  Only t is written (8 bytes per point in FP32
+// instead of the 20 of separate smoothing and residual passes): the
+// post-smoothing forms e1 again from b, with the same operations.
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items, const int* __restrict__ list,
                                                  const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
                                                  const ProbDev* __restrict__ pd, const T* __restrict__ kap,
-                                                 const T* __restrict__ b, T* __restrict__ e1out,
-                                                 T* __restrict__ tout, T omega, int ktab) {
+                                                 const T* __restrict__ b, T* __restrict__ tout, T omega,
+                                                 int ktab) {
   extern __shared__ double smem_raw[];
   T* kt = reinterpret_cast<T*>(smem_raw);
   T* plane = kt + ktab;
+  __shared__ int zk[kZkLen];
   const WorkRange WR = work_range(*cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     const int item = list[w];
@@ -544,26 +546,34 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
     const ProbDev& P = pd[S.prob];
     const GridDev& g = P.g;
     const int ntab = g.ndir * g.nclass;
-    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
-    __syncthreads();
     QuadGeo G;
     quad_geo(G, P, it.y);
+    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+    zk_stage(zk, g, G);
+    __syncthreads();
     const int n = g.n, nv = G.nv;
     const long long n2 = (long long)n * n;
     const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
     const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
     const bool hin = G.hi != 0;
     const T* Bv = b + S.off;
-    T* E1 = e1out + S.off;
     T* TO = tout + S.off;
-    // e1 of the own quad at plane k (b there returned in bq)
-    auto quad_e1 = [&](int k, T out[4], T bq[4]) __attribute__((always_inline)) {
+    // raw loads of b (own quad at plane k, halo point at plane k), issued one
+    // or two planes ahead of their use; e1 = omega b / d formed from them later
+    auto load_b = [&](int k, T bq[4]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int e = 0; e < 4; e++) out[e] = bq[e] = T(0);
+      for (int e = 0; e < 4; e++) bq[e] = T(0);
       if (nv == 0 || k < 1 || k > n) return;
-      const long long c = (long long)(k - 1) * n2 + rowoff;
-      ld4<T, VEC>(Bv, c, nv, bq);
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      ld4<T, VEC>(Bv, (long long)(k - 1) * n2 + rowoff, nv, bq);
+    };
+    auto load_hb = [&](int k) __attribute__((always_inline)) -> T {
+      return (!hin || k < 1 || k > n) ? T(0) : Bv[(long long)(k - 1) * n2 + hoff];
+    };
+    auto quad_e1 = [&](int k, const T bq[4], T out[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = T(0);
+      if (nv == 0 || k < 1 || k > n) return;
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         T kk[6];
@@ -574,9 +584,9 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
         out[e] = e < nv ? fmaT(omega, t, T(0)) : T(0);
       }
     };
-    auto halo_e1 = [&](int k) __attribute__((always_inline)) -> T {
+    auto halo_e1 = [&](int k, T braw) __attribute__((always_inline)) -> T {
       if (!hin || k < 1 || k > n) return T(0);
-      const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
       T kk[6];
       kk[0] = kt[G.hb[0] + czn];
       kk[1] = kt[G.hb[1] + czn];
@@ -585,26 +595,32 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
       kk[4] = kt[G.hb[4] + czm];
       kk[5] = kt[G.hb[4] + czp];
       const T dg = diag6T<T>(kk);
-      T t = Bv[(long long)(k - 1) * n2 + hoff] - T(0);
+      T t = braw - T(0);
       t = t / dg;
       return fmaT(omega, t, T(0));
     };
-    T um[4], uc[4], un[4], bm[4], bc[4], bn[4];
-    quad_e1(G.kb - 1, um, bm);
-    quad_e1(G.kb, uc, bc);
+    T um[4], uc[4], un[4], bm[4], bc[4], bn[4], bnn[4];
+    load_b(G.kb - 1, bm);
+    load_b(G.kb, bc);
+    load_b(G.kb + 1, bn);
+    T hbc = load_hb(G.kb);
+    quad_e1(G.kb - 1, bm, um);
+    quad_e1(G.kb, bc, uc);
     int buf = 0;
     const int mrow = (G.ly + 1) * QS + 4 * G.lx;
     const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
     for (int k = G.kb; k <= G.ke; k++) {
-      quad_e1(k + 1, un, bn);
-      const T hv = halo_e1(k);
+      load_b(k + 2, bnn);
+      const T hbn = load_hb(k + 1);
+      quad_e1(k + 1, bn, un);
+      const T hv = halo_e1(k, hbc);
       T* pl = plane + buf * QPLANE;
 #pragma unroll
       for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
       if (G.hslot >= 0) pl[G.hslot] = hv;
       __syncthreads();
       if (nv > 0) {
-        const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+        const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
         const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
         const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
@@ -623,7 +639,6 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
           q = fmaT(-kk[5], un[e], q);
           to[e] = bc[e] - q;
         }
-        st4<T, VEC>(E1, c, nv, uc);
         st4<T, VEC>(TO, c, nv, to);
       }
 #pragma unroll
@@ -631,7 +646,9 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
         um[e] = uc[e];
         uc[e] = un[e];
         bc[e] = bn[e];
+        bn[e] = bnn[e];
       }
+      hbc = hbn;
       buf ^= 1;
     }
   }
@@ -661,12 +678,13 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
                                                   const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
                                                   const ProbDev* __restrict__ pd, const T* __restrict__ kap,
                                                   const MgFine* __restrict__ mf, const int* __restrict__ gidx,
-                                                  const T* __restrict__ e1, const T* __restrict__ r,
-                                                  T* __restrict__ sout, void* part, T omega, int ktab) {
+                                                  const T* __restrict__ r, T* __restrict__ sout, void* part,
+                                                  T omega, int ktab) {
   extern __shared__ double smem_raw[];
   T* kt = reinterpret_cast<T*>(smem_raw);
   T* plane = kt + ktab;
   __shared__ CrAcc red[4];
+  __shared__ int zk[kZkLen];
   const WorkRange WR = work_range(*cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     const int item = list[w];
@@ -680,16 +698,16 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     const T* ezy = (const T*)F.ezy + (long long)gidx[b] * F.per;
     const T* cw = (const T*)F.cw;
     const int ntab = g.ndir * g.nclass;
-    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
-    __syncthreads();
     QuadGeo G;
     quad_geo(G, P, it.y);
+    for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+    zk_stage(zk, g, G);
+    __syncthreads();
     const int n = g.n, nv = G.nv;
     const long long n2 = (long long)n * n;
     const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);
     const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);
     const bool hin = G.hi != 0;
-    const T* E1 = e1 + S.off;
     const T* R = r + S.off;
     T* SO = sout + S.off;
     // transfer weights of the quad's x points, its row and the halo point
@@ -705,44 +723,105 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     const int jj = min(G.j, n);
     const int hI0 = hin ? F.ci[G.hi - 1] : 0;
     const T hwx = hin ? cw[G.hi - 1] : T(0);
-    auto quad_e2 = [&](int k, T out[4]) __attribute__((always_inline)) {
+    // raw loads (r and the two x taps of ezy) for the own quad and the halo
+    // point, issued ahead of their use; then e2 = e1 + P_x ezy with e1 the
+    // pre-smoothing omega r / d, formed as the pre-smoothing forms it
+    auto taps = [&](const T* zr, int i0, T& za, T& zb) __attribute__((always_inline)) {
+      za = i0 >= 1 ? zr[i0 - 1] : T(0);
+      zb = i0 + 1 <= nc ? zr[i0] : T(0);
+    };
+    auto join = [&](int i0, T w, T za, T zb) __attribute__((always_inline)) -> T {
+      T v = T(0);
+      if (i0 >= 1) v = fmaT(T(1) - w, za, v);
+      if (i0 + 1 <= nc) v = fmaT(w, zb, v);
+      return v;
+    };
+    auto jac = [&](T rv, T dg) __attribute__((always_inline)) -> T {
+      T t = rv - T(0);
+      t = t / dg;
+      return fmaT(omega, t, T(0));
+    };
+    struct Raw {
+      T r[4], za[4], zb[4];
+    };
+    auto load_q = [&](int k, Raw& q) __attribute__((always_inline)) {
 #pragma unroll
-      for (int e = 0; e < 4; e++) out[e] = T(0);
+      for (int e = 0; e < 4; e++) q.r[e] = q.za[e] = q.zb[e] = T(0);
       if (nv == 0 || k < 1 || k > n) return;
-      const long long c = (long long)(k - 1) * n2 + rowoff;
-      ld4<T, VEC>(E1, c, nv, out);
+      ld4<T, VEC>(R, (long long)(k - 1) * n2 + rowoff, nv, q.r);
       const T* zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc;
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        if (e < nv) out[e] = out[e] + prolong_x(zr, nc, I0[e], wx[e]);
+        if (e < nv) taps(zr, I0[e], q.za[e], q.zb[e]);
     };
-    auto halo_e2 = [&](int k) __attribute__((always_inline)) -> T {
+    auto fin_q = [&](int k, const Raw& q, T out[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = T(0);
+      if (nv == 0 || k < 1 || k > n) return;
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        T kk[6];
+        quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
+        const T dg = diag6T<T>(kk);
+        out[e] = e < nv ? jac(q.r[e], dg) + join(I0[e], wx[e], q.za[e], q.zb[e]) : T(0);
+      }
+    };
+    struct RawH {
+      T r, za, zb;
+    };
+    auto load_h = [&](int k, RawH& h) __attribute__((always_inline)) {
+      h.r = h.za = h.zb = T(0);
+      if (!hin || k < 1 || k > n) return;
+      h.r = R[(long long)(k - 1) * n2 + hoff];
+      taps(ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc, hI0, h.za, h.zb);
+    };
+    auto fin_h = [&](int k, const RawH& h) __attribute__((always_inline)) -> T {
       if (!hin || k < 1 || k > n) return T(0);
-      const long long c = (long long)(k - 1) * n2 + hoff;
-      const T* zr = ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc;
-      return E1[c] + prolong_x(zr, nc, hI0, hwx);
+      const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
+      T kk[6];
+      kk[0] = kt[G.hb[0] + czn];
+      kk[1] = kt[G.hb[1] + czn];
+      kk[2] = kt[G.hb[2] + czn];
+      kk[3] = kt[G.hb[3] + czn];
+      kk[4] = kt[G.hb[4] + czm];
+      kk[5] = kt[G.hb[4] + czp];
+      const T dg = diag6T<T>(kk);
+      return jac(h.r, dg) + join(hI0, hwx, h.za, h.zb);
     };
-    T um[4], uc[4], un[4];
-    quad_e2(G.kb - 1, um);
-    quad_e2(G.kb, uc);
+    T um[4], uc[4], un[4], rc[4];
+    Raw qn, qnn;
+    {
+      Raw qm, qc;
+      load_q(G.kb - 1, qm);
+      load_q(G.kb, qc);
+      load_q(G.kb + 1, qn);
+      fin_q(G.kb - 1, qm, um);
+      fin_q(G.kb, qc, uc);
+#pragma unroll
+      for (int e = 0; e < 4; e++) rc[e] = qc.r[e];
+    }
+    RawH hc;
+    load_h(G.kb, hc);
     DotAcc<T> acc;
     acc.zero();
     int buf = 0;
     const int mrow = (G.ly + 1) * QS + 4 * G.lx;
     const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
     for (int k = G.kb; k <= G.ke; k++) {
-      quad_e2(k + 1, un);
-      const T hv = halo_e2(k);
+      load_q(k + 2, qnn);
+      RawH hn;
+      load_h(k + 1, hn);
+      fin_q(k + 1, qn, un);
+      const T hv = fin_h(k, hc);
       T* pl = plane + buf * QPLANE;
 #pragma unroll
       for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
       if (G.hslot >= 0) pl[G.hslot] = hv;
       __syncthreads();
       if (nv > 0) {
-        const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+        const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
-        T rv[4];
-        ld4<T, VEC>(R, c, nv, rv);
         const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
         const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
         T so[4];
@@ -758,10 +837,10 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
           q = fmaT(-kk[3], pl[mrow + QS + e], q);
           q = fmaT(-kk[4], um[e], q);
           q = fmaT(-kk[5], un[e], q);
-          T t = rv[e] - q;
+          T t = rc[e] - q;
           t = t / dg;
           so[e] = fmaT(omega, t, uc[e]);
-          if (e < nv) acc.add(rv[e], so[e]);
+          if (e < nv) acc.add(rc[e], so[e]);
         }
         st4<T, VEC>(SO, c, nv, so);
       }
@@ -769,7 +848,10 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       for (int e = 0; e < 4; e++) {
         um[e] = uc[e];
         uc[e] = un[e];
+        rc[e] = qn.r[e];
       }
+      qn = qnn;
+      hc = hn;
       buf ^= 1;
     }
     PostPart<T>::put(part, item, acc, red);
@@ -809,7 +891,7 @@ struct MgRun {
   bool fused = false;  // level-0 correction + post-smoothing + r^T s in one tile kernel
   std::vector<MgGroup*> g;
   DevBuf fine;    // MgFine per problem
-  DevBuf x0, t0;  // level-0 scratch, laid out like the batch
+  DevBuf x0, t0;  // level-0 scratch, laid out like the batch (x0 only without the fused kernels)
   ~MgRun() {
     for (MgGroup* q : g) delete q;
   }
@@ -861,7 +943,6 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   m->fp32 = fp32;
   m->device = B.device;
   const size_t el = fp32 ? sizeof(float) : sizeof(double);
-  m->x0.get(el * std::max<long long>(B.total, 1), B.device);
   m->t0.get(el * std::max<long long>(B.total, 1), B.device);
   for (int q = 0; q < B.nprob; q++) {
     MgGroup* g = new MgGroup();
@@ -975,6 +1056,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   }
   RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
                           hipMemcpyHostToDevice, s));
+  if (!m->fused) m->x0.get(el * std::max<long long>(B.total, 1), B.device);
   RBWS_HIP(hipStreamSynchronize(s));
   return m;
 }
@@ -984,10 +1066,10 @@ static unsigned grid_for(long long items) {
   return (unsigned)((g + 7) & ~7LL);
 }
 
-// one V-cycle at level l of group g; with `pre_only` (level 0 of the fused
-// path, nu = 1) it stops after the coarse correction, e1 in `scratch`
-// (level 0 of the fused path: the pre-smoothing and the residual are already in
-// scratch and tres, written by k_mg_pre0)
+// one V-cycle at level l of group g.  With `pre_only` (level 0 of the fused
+// path, nu = 1) the residual after pre-smoothing is already in tres (written
+// by k_mg_pre0, `scratch` unused) and the cycle stops once the z/y-interpolated
+// coarse correction is in the level's vtx; k_mg_post0 finishes it.
 template <typename T>
 static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T* tres, MgList ml, hipStream_t s,
                    bool pre_only = false) {
@@ -1053,19 +1135,19 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
 bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void* part, hipStream_t st) {
   const int ktab = (B.kap_max + 3) & ~3;
   const unsigned tgrid = 8u * (unsigned)((B.nitems + 7) / 8);
-  if (m->fused) {  // level 0: e1 into x0 and the residual into t0, over the tiles of the listed solves
+  if (m->fused) {  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
     if (m->fp32) {
       auto k = B.vec ? k_mg_pre0<float, true> : k_mg_pre0<float, false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
                          (const int*)L.ap, (const int*)(L.cnt + WL_AP), (const SolveDev*)B.sd.ptr,
-                         (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r, (float*)m->x0.ptr,
+                         (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r,
                          (float*)m->t0.ptr, (float)m->omega, ktab);
     } else {
       auto k = B.vec ? k_mg_pre0<double, true> : k_mg_pre0<double, false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
-                         (const double*)r, (double*)m->x0.ptr, (double*)m->t0.ptr, m->omega, ktab);
+                         (const double*)r, (double*)m->t0.ptr, m->omega, ktab);
     }
   }
   for (MgGroup* g : m->g) {
@@ -1078,22 +1160,21 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
       vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, ml, st,
                      m->fused);
   }
-  if (m->fused) {  // e1 is in x0; the tiles of the listed solves are the CG work list L.ap
+  if (m->fused) {  // e1 formed again from r; the tiles of the listed solves are the CG work list L.ap
     const unsigned grid = tgrid;
     if (m->fp32) {
       auto k = B.vec ? k_mg_post0<float, true> : k_mg_post0<float, false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr,
-                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const float*)m->x0.ptr, (const float*)r,
+                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const float*)r,
                          (float*)sv, part, (float)m->omega, ktab);
     } else {
       auto k = B.vec ? k_mg_post0<double, true> : k_mg_post0<double, false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
-                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const double*)m->x0.ptr,
-                         (const double*)r, (double*)sv, part, m->omega, ktab);
+                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const double*)r, (double*)sv, part, m->omega, ktab);
     }
   }
   RBWS_HIP(hipGetLastError());

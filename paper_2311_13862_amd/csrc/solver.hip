@@ -329,6 +329,7 @@ __device__ __forceinline__ void k_sweep64_item(int item, const int2* __restrict_
                                                  CrAcc* __restrict__ part) {
   extern __shared__ double kl[];
   __shared__ CrAcc red[4];
+  __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x, tile = it.y;
@@ -337,17 +338,18 @@ __device__ __forceinline__ void k_sweep64_item(int item, const int2* __restrict_
   const ProbDev& P = pd[S.prob];
   const GridDev& g = P.g;
   const int ntab = g.ndir * g.nclass;
-  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
-  __syncthreads();
-  const int prec = OP == OP_AP ? st[b].prec : 0, first = OP == OP_AP ? st[b].first : 1;
   QuadGeo G;
   quad_geo(G, P, tile);
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kl[e] = kap[S.kap_off + e];
+  zk_stage(zk, g, G);
+  __syncthreads();
+  const int prec = OP == OP_AP ? st[b].prec : 0, first = OP == OP_AP ? st[b].first : 1;
   const int n = g.n;
   CrAcc a0 = cr_zero(), a1 = cr_zero(), a2 = cr_zero();
   double* X = x + S.off;
   double* R = r + S.off;
   for (int k = G.kb; k <= G.ke; k++) {
-    const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+    const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       if (e >= G.nv) continue;
@@ -406,6 +408,7 @@ __device__ __forceinline__ void k_fast64_item(int item, const int2* __restrict__
                                                 int ktab) {
   extern __shared__ double smem[];
   __shared__ CrAcc red[4];
+  __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const int b = it.x;
@@ -416,10 +419,11 @@ __device__ __forceinline__ void k_fast64_item(int item, const int2* __restrict__
   const ProbDev& P = pd[S.prob];
   const int ntab = P.g.ndir * P.g.nclass;
   double* kt = smem;
-  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
-  __syncthreads();
   QuadGeo G;
   quad_geo(G, P, it.y);
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];
+  zk_stage(zk, P.g, G);
+  __syncthreads();
   const int par = s.k & 1;
   const double* Pold = (par ? p1 : p0) + S.off;
   double* Pn = (par ? p0 : p1) + S.off;
@@ -734,15 +738,17 @@ __device__ __forceinline__ void k_spmv_item(int item, const int2* __restrict__ i
                                               T* __restrict__ y, int ktab) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
+  __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
   const int2 it = items[item];
   const SolveDev S = sd[it.x];
   const ProbDev& P = pd[S.prob];
   const int ntab = P.g.ndir * P.g.nclass;
-  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
-  __syncthreads();
   QuadGeo G;
   quad_geo(G, P, it.y);
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) smem[e] = kap[S.kap_off + e];
+  zk_stage(zk, P.g, G);
+  __syncthreads();
   DotAcc<T> a0, a1;
   fast_body<T, VEC, FOP_SPMV>(G, P.g, smem, smem + ktab, nullptr, nullptr, nullptr,
                               const_cast<T*>(x) + S.off, y + S.off, T(0), T(0), 0, 0, 0, a0, a1);
@@ -827,6 +833,7 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
     long long cnt = 0;
     for (int b = 0; b < nsolve; b++) cnt += (prob_of ? prob_of[b] : 0) == q;
     choose_tile(P->n, cnt, &d.TX, &d.TY, &d.TZ);
+    RBWS_REQUIRE(d.TZ >= 1 && d.TZ <= kTzMax, RBWS_EINVAL, "tile depth out of range");
     d.ntx = (P->n + d.TX - 1) / d.TX;
     d.nty = (P->n + d.TY - 1) / d.TY;
     d.ntz = (P->n + d.TZ - 1) / d.TZ;

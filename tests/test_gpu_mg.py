@@ -125,3 +125,27 @@ def test_refinement_with_multigrid(rb, spec, mode):
         ub = u[b].cpu().numpy()
         assert np.linalg.norm(ub - ref[b]) <= 1e-8 * np.linalg.norm(ref[b])
         assert st[b]["iters"] <= 2 * so[b]["iters"] + 10, (st[b]["iters"], so[b]["iters"])
+
+
+def test_refinement_with_multigrid_full_size_sample(rb):
+    """The bench's configuration (128^3, FP32 MGCG inside FP64 refinement,
+    reliable updates) on 64 solves; two sampled solutions against the oracle's
+    FP64 MGCG solved to 1e-12."""
+    wl = W.octants_128()
+    spec = wl.problem
+    P = rb.Problem(spec)
+    mu = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, 64, W.SEED_TEST)
+    picks = (0, 37)
+    u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") if b in picks else None for b in range(len(mu))]
+    opts = rb.default_opts(tol=wl.tol, precision=rb.FP32_IR, precond=rb.PREC_MG, ir_mode=rb.IR_RELIABLE,
+                           eta_inner=0.1)
+    st = rb.solve([P], mu, opts, u_out=u)
+    torch.cuda.synchronize()
+    assert all(s["status"] == rb.SOLVE_CONVERGED for s in st)
+    assert all(s["final_rr"] <= wl.tol ** 2 * s["ff"] for s in st)
+    O = oracle.Problem(spec)
+    for b in picks:
+        ref, so = O.mgcg(mu[b], tol=1e-12)
+        assert so["status"] == oracle.CONVERGED
+        ub = u[b].cpu().numpy()
+        assert np.linalg.norm(ub - ref) <= 1e-8 * np.linalg.norm(ref)
