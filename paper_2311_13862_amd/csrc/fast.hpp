@@ -79,6 +79,17 @@ __device__ __forceinline__ void st4(T* __restrict__ a, long long c, int nv, cons
   }
 }
 
+// A pointer known to address global memory: loads through it are global_load,
+// not flat loads (which also count against the LDS wait counter, so that every
+// LDS wait would drain them).  For pointers read from memory, whose address
+// space the compiler cannot infer.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __fma_rn(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
 

@@ -200,39 +200,58 @@ __global__ __launch_bounds__(256) void k_mg_rx(MgLv F, MgLv C, MgList ml, const 
   }
 }
 
+// The yz-pass is a z-march: a thread owns a coarse column (J, I) and a
+// segment of kRzSeg coarse planes.  Each fine plane k forms ay(k) = sum_j py
+// ax[k][j][I] once and adds it to the two coarse planes whose spans hold k,
+// K = ci(k) (weight 1 - cw) and ci(k) + 1 (weight cw), in ascending k: the
+// order of the fma chains over k.  With (nc+1)/(nf+1) <= 1/2, ci grows by at
+// most one per fine plane, so two accumulators (K = Kc, Kc + 1) suffice and Kc
+// is complete when ci moves past it.
+constexpr int kRzSeg = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
                                                 const T* __restrict__ cw, const int2* __restrict__ lohi,
                                                 const T* __restrict__ tx, T* __restrict__ bc, T scale) {
   const int nc = C.n, nf = F.n;
-  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2;
-  const int per = nc * jq * ich;  // (K, J quad, I chunk) items per solve
+  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2, nseg = (nc + kRzSeg - 1) / kRzSeg;
+  const int cols = jq * ich, per = nseg * cols;  // (segment, J quad, I chunk) items per solve
   const ItemRange R = item_range(*ml.cnt * per);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nc2 = (long long)nc * nc, fplane = (long long)nf * nc;
   for (int w = R.w; w < R.w1; w += R.step) {
     const int t = ml.list[w / per];
-    const int rem = w % per;
-    const int K = rem / (jq * ich) + 1, J = ((rem / ich) % jq) * 4 + wv + 1, I = (rem % ich) * 64 + lane + 1;
+    const int rem = w % per, sg = rem / cols, rc = rem % cols;
+    const int J = (rc / ich) * 4 + wv + 1, I = (rc % ich) * 64 + lane + 1;
     if (J > nc || I > nc) continue;
-    T wy[kSpan], wz[kSpan];
+    const int Ks = sg * kRzSeg + 1, Ke = min(nc, Ks + kRzSeg - 1);
+    T wy[kSpan];
     const int jlo = fine_weights(J, ci, cw, lohi, wy);
-    const int klo = fine_weights(K, ci, cw, lohi, wz);
-    const int jhi = lohi[J].y, khi = lohi[K].y;
-    const T* a = tx + (long long)t * nf * nf * nc + (I - 1);
-    T az = T(0);
-#pragma unroll
-    for (int uk = 0; uk < kSpan; uk++) {
-      const int k = klo + uk;
-      if (k > khi) continue;
+    const int jn = lohi[J].y - jlo + 1;
+    const int k0 = lohi[Ks].x, k1 = lohi[Ke].y;
+    const T* a = tx + (long long)t * nf * fplane + (long long)(jlo - 1) * nc + (I - 1);
+    T* out = bc + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (long long)(J - 1) * nc + (I - 1);
+    int Kc = ci[k0 - 1];
+    T accA = T(0), accB = T(0);
+    for (int k = k0; k <= k1; k++) {
+      const int K0 = ci[k - 1];
+      const T wz = cw[k - 1];
+      if (K0 != Kc) {
+        if (Kc >= Ks) out[(Kc - 1) * nc2] = accA * scale;
+        accA = accB;
+        accB = T(0);
+        Kc = K0;
+      }
+      const T* ak = a + (long long)(k - 1) * fplane;
       T ay = T(0);
 #pragma unroll
-      for (int uj = 0; uj < kSpan; uj++) {
-        const int j = jlo + uj;
-        if (j <= jhi) ay = fmaT(wy[uj], a[((long long)(k - 1) * nf + (j - 1)) * nc], ay);
-      }
-      az = fmaT(wz[uk], ay, az);
+      for (int u = 0; u < kSpan; u++)
+        if (u < jn) ay = fmaT(wy[u], ak[(long long)u * nc], ay);
+      if (K0 >= 1) accA = fmaT(T(1) - wz, ay, accA);
+      if (K0 + 1 <= nc) accB = fmaT(wz, ay, accB);
     }
-    bc[(C.voff ? C.voff[t] : (long long)t * C.ndof) + ((K - 1) * nc + (J - 1)) * nc + (I - 1)] = az * scale;
+    if (Kc >= Ks && Kc <= Ke) out[(Kc - 1) * nc2] = accA * scale;
+    if (Kc + 1 >= Ks && Kc + 1 <= Ke) out[Kc * nc2] = accB * scale;
   }
 }
 
@@ -240,40 +259,68 @@ __global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const
 // onto the fine (k, j) rows at every coarse column I,
 //   ezy[k][j][I] = sum_cy wy (sum_cz wz e_c[K][J][I])    (fma chains from 0),
 // then each fine point takes v = sum_cx wx ezy[k][j][I0 + cx].  Out-of-grid
-// coarse nodes (value 0) are skipped.  A wave takes one fine row and 64 I.
+// coarse nodes (value 0) are skipped.  The z/y pass is a z-march: a thread owns
+// a fine (j, I) column and a segment of kPzSeg fine planes, and keeps the four
+// coarse values at (K0, K0 + 1) x (J0, J0 + 1) in registers; when K0 = ci(k)
+// advances, the old upper plane becomes the lower one and one plane is loaded.
+constexpr int kPzSeg = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_pyz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
                                                 const T* __restrict__ cw, const T* __restrict__ ec,
                                                 T* __restrict__ ezy) {
   const int nc = C.n, nf = F.n;
-  const int ich = (nc + 63) >> 6, rq = (nf * nf + 3) >> 2;
-  const int per = rq * ich;
+  const int ich = (nc + 63) >> 6, jq = (nf + 3) >> 2, nseg = (nf + kPzSeg - 1) / kPzSeg;
+  const int cols = jq * ich, per = nseg * cols;  // (segment, j quad, I chunk) items per solve
   const ItemRange R = item_range(*ml.cnt * per);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nc2 = (long long)nc * nc, fplane = (long long)nf * nc;
   for (int w = R.w; w < R.w1; w += R.step) {
     const int t = ml.list[w / per];
-    const int rem = w % per;
-    const int row = (rem / ich) * 4 + wv, I = (rem % ich) * 64 + lane + 1;
-    if (row >= nf * nf || I > nc) continue;
-    const int j = row % nf + 1, k = row / nf + 1;
+    const int rem = w % per, sg = rem / cols, rc = rem % cols;
+    const int j = (rc / ich) * 4 + wv + 1, I = (rc % ich) * 64 + lane + 1;
+    if (j > nf || I > nc) continue;
+    const int kA = sg * kPzSeg + 1, kB = min(nf, kA + kPzSeg - 1);
+    const int J0 = ci[j - 1];
+    const T wy1 = cw[j - 1];
+    const bool y0 = J0 >= 1, y1 = J0 + 1 <= nc;
     const T* e = ec + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (I - 1);
-    const int J0 = ci[j - 1], K0 = ci[k - 1];
-    const T wy1 = cw[j - 1], wz1 = cw[k - 1];
-    T ay = T(0);
-    for (int cy = 0; cy < 2; cy++) {
-      const int J = J0 + cy;
-      if (J < 1 || J > nc) continue;
-      const T wy = cy ? wy1 : T(1) - wy1;
-      T az = T(0);
-      for (int cz = 0; cz < 2; cz++) {
-        const int K = K0 + cz;
-        if (K < 1 || K > nc) continue;
-        const T wz = cz ? wz1 : T(1) - wz1;
-        az = fmaT(wz, e[((K - 1) * nc + (J - 1)) * nc], az);
+    T* o = ezy + (long long)t * nf * fplane + (long long)(j - 1) * nc + (I - 1);
+    auto plane = [&](int K, T& v0, T& v1) __attribute__((always_inline)) {
+      v0 = v1 = T(0);
+      if (K < 1 || K > nc) return;
+      const T* eK = e + (long long)(K - 1) * nc2;
+      if (y0) v0 = eK[(long long)(J0 - 1) * nc];
+      if (y1) v1 = eK[(long long)J0 * nc];
+    };
+    int Kc = ci[kA - 1];
+    T a0, a1, b0, b1;  // coarse plane Kc at rows J0, J0 + 1; plane Kc + 1
+    plane(Kc, a0, a1);
+    plane(Kc + 1, b0, b1);
+    for (int k = kA; k <= kB; k++) {
+      const int K0 = ci[k - 1];
+      if (K0 != Kc) {
+        a0 = b0;
+        a1 = b1;
+        Kc = K0;
+        plane(Kc + 1, b0, b1);
       }
-      ay = fmaT(wy, az, ay);
+      const T wz1 = cw[k - 1];
+      T ay = T(0);
+      if (y0) {
+        T az = T(0);
+        if (K0 >= 1) az = fmaT(T(1) - wz1, a0, az);
+        if (K0 + 1 <= nc) az = fmaT(wz1, b0, az);
+        ay = fmaT(T(1) - wy1, az, ay);
+      }
+      if (y1) {
+        T az = T(0);
+        if (K0 >= 1) az = fmaT(T(1) - wz1, a1, az);
+        if (K0 + 1 <= nc) az = fmaT(wz1, b1, az);
+        ay = fmaT(wy1, az, ay);
+      }
+      o[(long long)(k - 1) * fplane] = ay;
     }
-    ezy[(long long)t * nf * nf * nc + (long long)row * nc + (I - 1)] = ay;
   }
 }
 
@@ -695,8 +742,8 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     const ProbDev& P = pd[S.prob];
     const GridDev& g = P.g;
     const MgFine F = mf[S.prob];
-    const T* ezy = (const T*)F.ezy + (long long)gidx[b] * F.per;
-    const T* cw = (const T*)F.cw;
+    const gptr<T> ezy = as_global((const T*)F.ezy) + (long long)gidx[b] * F.per;
+    const gptr<T> cw = as_global((const T*)F.cw);
     const int ntab = g.ndir * g.nclass;
     QuadGeo G;
     quad_geo(G, P, it.y);
@@ -726,7 +773,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     // raw loads (r and the two x taps of ezy) for the own quad and the halo
     // point, issued ahead of their use; then e2 = e1 + P_x ezy with e1 the
     // pre-smoothing omega r / d, formed as the pre-smoothing forms it
-    auto taps = [&](const T* zr, int i0, T& za, T& zb) __attribute__((always_inline)) {
+    auto taps = [&](gptr<T> zr, int i0, T& za, T& zb) __attribute__((always_inline)) {
       za = i0 >= 1 ? zr[i0 - 1] : T(0);
       zb = i0 + 1 <= nc ? zr[i0] : T(0);
     };
@@ -749,7 +796,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       for (int e = 0; e < 4; e++) q.r[e] = q.za[e] = q.zb[e] = T(0);
       if (nv == 0 || k < 1 || k > n) return;
       ld4<T, VEC>(R, (long long)(k - 1) * n2 + rowoff, nv, q.r);
-      const T* zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc;
+      const gptr<T> zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc;
 #pragma unroll
       for (int e = 0; e < 4; e++)
         if (e < nv) taps(zr, I0[e], q.za[e], q.zb[e]);
@@ -857,6 +904,302 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     PostPart<T>::put(part, item, acc, red);
   }
 }
+
+// FP32 level-0 kernels.  The own quad's face coefficients, diagonal and
+// reciprocal diagonal, and the halo point's reciprocal diagonal, sit in
+// registers (KCache32, refreshed only when the plane's z codes change), so a
+// plane costs no class-table reads and no division: Jacobi is
+// omega (r (1/d)).  e1 of plane k+1, needed by the stencil of plane k, takes
+// its reciprocals from a second cache keyed by plane k+1.  The pre- and
+// post-smoothing form e1 with the same operations.
+struct InvCache32 {
+  int key;
+  float inv[4];
+};
+__device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const float* kt, int key) {
+  const int czn = key & 255, czm = (key >> 8) & 255, czp = key >> 16;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    float kk[6];
+    quad_kappa<float>(G, kt, e, czn, czm, czp, kk);
+    C.inv[e] = 1.0f / diag6T<float>(kk);
+  }
+  C.key = key;
+}
+
+// shared set-up of an item of the FP32 level-0 kernels
+#define MG0_ITEM_SETUP()                                                                \
+  const int item = list[w];                                                             \
+  __syncthreads(); /* LDS of the previous item is free */                               \
+  const int2 it = items[item];                                                          \
+  const SolveDev S = sd[it.x];                                                          \
+  const ProbDev& P = pd[S.prob];                                                        \
+  const GridDev& g = P.g;                                                               \
+  const int ntab = g.ndir * g.nclass;                                                   \
+  QuadGeo G;                                                                            \
+  quad_geo(G, P, it.y);                                                                 \
+  for (int e = threadIdx.x; e < ntab; e += blockDim.x) kt[e] = kap[S.kap_off + e];      \
+  zk_stage(zk, g, G);                                                                   \
+  __syncthreads();                                                                      \
+  const int n = g.n, nv = G.nv;                                                         \
+  const long long n2 = (long long)n * n;                                                \
+  const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);                      \
+  const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);                      \
+  const bool hin = G.hi != 0;                                                           \
+  const int mrow = (G.ly + 1) * QS + 4 * G.lx;                                          \
+  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;             \
+  auto zkey_at = [&](int k) __attribute__((always_inline)) { return G.zk[k - G.kb + 1]; };
+
+// q = A u at the own quad of plane k (u of plane k in registers and LDS; the
+// planes k-1, k+1 in um, un), coefficients from the cache
+#define MG0_STENCIL(C, um, uc, un, pl, q)                                               \
+  {                                                                                     \
+    const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];                                \
+    const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];                               \
+    _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
+      float a = C.dg[e] * uc[e];                                                        \
+      a = fmaf(-C.kx[e], e > 0 ? uc[e - 1] : left, a);                                  \
+      a = fmaf(-C.kx[e + 1], e < 3 ? uc[e + 1] : right, a);                             \
+      a = fmaf(-C.kym[e], pl[mrow - QS + e], a);                                        \
+      a = fmaf(-C.kyp[e], pl[mrow + QS + e], a);                                        \
+      a = fmaf(-C.kzm[e], um[e], a);                                                    \
+      a = fmaf(-C.kzp[e], un[e], a);                                                    \
+      q[e] = a;                                                                         \
+    }                                                                                   \
+  }
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
+                                                    const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                    const ProbDev* __restrict__ pd, const float* __restrict__ kap,
+                                                    const float* __restrict__ b, float* __restrict__ tout,
+                                                    float omega, int ktab) {
+  extern __shared__ double smem_raw[];
+  float* kt = reinterpret_cast<float*>(smem_raw);
+  float* plane = kt + ktab;
+  __shared__ int zk[kZkLen];
+  const WorkRange WR = work_range(*cnt);
+  for (int w = WR.w; w < WR.w1; w += WR.step) {
+    MG0_ITEM_SETUP()
+    const float* Bv = b + S.off;
+    float* TO = tout + S.off;
+    auto load_b = [&](int k, float bq[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) bq[e] = 0.0f;
+      if (nv == 0 || k < 1 || k > n) return;
+      ld4<float, VEC>(Bv, (long long)(k - 1) * n2 + rowoff, nv, bq);
+    };
+    auto load_hb = [&](int k) __attribute__((always_inline)) -> float {
+      return (!hin || k < 1 || k > n) ? 0.0f : Bv[(long long)(k - 1) * n2 + hoff];
+    };
+    KCache32 C;
+    InvCache32 Ci;
+    C.key = Ci.key = -1;
+    auto e1_quad = [&](int k, const float bq[4], float out[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = 0.0f;
+      if (nv == 0 || k < 1 || k > n) return;
+      const int key = zkey_at(k);
+      if (key != Ci.key) inv_fill(Ci, G, kt, key);
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = e < nv ? omega * (bq[e] * Ci.inv[e]) : 0.0f;
+    };
+    float um[4], uc[4], un[4], bm[4], bc[4], bn[4], bnn[4];
+    load_b(G.kb - 1, bm);
+    load_b(G.kb, bc);
+    load_b(G.kb + 1, bn);
+    float hbc = load_hb(G.kb);
+    e1_quad(G.kb - 1, bm, um);
+    e1_quad(G.kb, bc, uc);
+    int buf = 0;
+    for (int k = G.kb; k <= G.ke; k++) {
+      load_b(k + 2, bnn);
+      const float hbn = load_hb(k + 1);
+      const int key = zkey_at(k);
+      if (key != C.key) kc_fill(C, G, kt, key);
+      e1_quad(k + 1, bn, un);
+      float* pl = plane + buf * QPLANE;
+#pragma unroll
+      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hbc * C.hinv) : 0.0f;
+      __syncthreads();
+      if (nv > 0) {
+        float q[4], to[4];
+        MG0_STENCIL(C, um, uc, un, pl, q)
+#pragma unroll
+        for (int e = 0; e < 4; e++) to[e] = bc[e] - q[e];
+        st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        um[e] = uc[e];
+        uc[e] = un[e];
+        bc[e] = bn[e];
+        bn[e] = bnn[e];
+      }
+      hbc = hbn;
+      buf ^= 1;
+    }
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ items, const int* __restrict__ list,
+                                                     const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                     const ProbDev* __restrict__ pd, const float* __restrict__ kap,
+                                                     const MgFine* __restrict__ mf, const int* __restrict__ gidx,
+                                                     const float* __restrict__ r, float* __restrict__ sout,
+                                                     IrPart* __restrict__ part, float omega, int ktab) {
+  extern __shared__ double smem_raw[];
+  float* kt = reinterpret_cast<float*>(smem_raw);
+  float* plane = kt + ktab;
+  __shared__ double red[4];
+  __shared__ int zk[kZkLen];
+  const WorkRange WR = work_range(*cnt);
+  for (int w = WR.w; w < WR.w1; w += WR.step) {
+    MG0_ITEM_SETUP()
+    const MgFine F = mf[S.prob];
+    const gptr<float> ezy = as_global((const float*)F.ezy) + (long long)gidx[it.x] * F.per;
+    const gptr<float> cw = as_global((const float*)F.cw);
+    const float* R = r + S.off;
+    float* SO = sout + S.off;
+    // the quad's x points take their two coarse taps from the window of four
+    // coarse columns W0 .. W0+3 (W0 = I0 of the first point, minus one): with
+    // (nc+1)/(nf+1) <= 1/2, I0 grows by at most 2 over the quad
+    int dI[4];
+    bool ta[4], tb[4];
+    float wx[4];
+    const int nc = F.nc;
+    const int W0 = F.ci[min(G.i, n) - 1] - 1;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int i = min(G.i + e, n);
+      const int I0 = F.ci[i - 1];
+      dI[e] = I0 - 1 - W0;
+      ta[e] = I0 >= 1;
+      tb[e] = I0 + 1 <= nc;
+      wx[e] = cw[i - 1];
+    }
+    bool wv[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) wv[m] = W0 + m >= 0 && W0 + m < nc;
+    const int jj = min(G.j, n);
+    const int hI0 = hin ? F.ci[G.hi - 1] : 0;
+    const float hwx = hin ? cw[G.hi - 1] : 0.0f;
+    auto taps = [&](gptr<float> zr, int i0, float& za, float& zb) __attribute__((always_inline)) {
+      za = i0 >= 1 ? zr[i0 - 1] : 0.0f;
+      zb = i0 + 1 <= nc ? zr[i0] : 0.0f;
+    };
+    auto join = [&](int i0, float wgt, float za, float zb) __attribute__((always_inline)) -> float {
+      float v = 0.0f;
+      if (i0 >= 1) v = fmaf(1.0f - wgt, za, v);
+      if (i0 + 1 <= nc) v = fmaf(wgt, zb, v);
+      return v;
+    };
+    auto join2 = [&](bool a, bool bb, float wgt, float za, float zb) __attribute__((always_inline)) -> float {
+      float v = 0.0f;
+      if (a) v = fmaf(1.0f - wgt, za, v);
+      if (bb) v = fmaf(wgt, zb, v);
+      return v;
+    };
+    struct Raw {
+      float r[4], z[4];
+    };
+    auto load_q = [&](int k, Raw& q) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) q.r[e] = q.z[e] = 0.0f;
+      if (nv == 0 || k < 1 || k > n) return;
+      ld4<float, VEC>(R, (long long)(k - 1) * n2 + rowoff, nv, q.r);
+      const gptr<float> zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc + W0;
+#pragma unroll
+      for (int m = 0; m < 4; m++)
+        if (wv[m]) q.z[m] = zr[m];
+    };
+    // tap m of the window (m = dI, dI + 1 in 0..3)
+    auto pick = [&](const float z[4], int m) __attribute__((always_inline)) -> float {
+      return m == 0 ? z[0] : m == 1 ? z[1] : m == 2 ? z[2] : z[3];
+    };
+    struct RawH {
+      float r, za, zb;
+    };
+    auto load_h = [&](int k, RawH& h) __attribute__((always_inline)) {
+      h.r = h.za = h.zb = 0.0f;
+      if (!hin || k < 1 || k > n) return;
+      h.r = R[(long long)(k - 1) * n2 + hoff];
+      taps(ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc, hI0, h.za, h.zb);
+    };
+    KCache32 C;
+    InvCache32 Ci;
+    C.key = Ci.key = -1;
+    // e2 = e1 + P_x ezy of the own quad at plane k (e1 = omega r (1/d))
+    auto e2_quad = [&](int k, const Raw& q, float out[4]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int e = 0; e < 4; e++) out[e] = 0.0f;
+      if (nv == 0 || k < 1 || k > n) return;
+      const int key = zkey_at(k);
+      if (key != Ci.key) inv_fill(Ci, G, kt, key);
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + join2(ta[e], tb[e], wx[e], pick(q.z, dI[e]), pick(q.z, dI[e] + 1))
+                        : 0.0f;
+    };
+    float um[4], uc[4], un[4], rc[4];
+    Raw qn, qnn;
+    {
+      Raw qm, qc;
+      load_q(G.kb - 1, qm);
+      load_q(G.kb, qc);
+      load_q(G.kb + 1, qn);
+      e2_quad(G.kb - 1, qm, um);
+      e2_quad(G.kb, qc, uc);
+#pragma unroll
+      for (int e = 0; e < 4; e++) rc[e] = qc.r[e];
+    }
+    RawH hc;
+    load_h(G.kb, hc);
+    double acc = 0.0;
+    int buf = 0;
+    for (int k = G.kb; k <= G.ke; k++) {
+      load_q(k + 2, qnn);
+      RawH hn;
+      load_h(k + 1, hn);
+      const int key = zkey_at(k);
+      if (key != C.key) kc_fill(C, G, kt, key);
+      e2_quad(k + 1, qn, un);
+      float* pl = plane + buf * QPLANE;
+#pragma unroll
+      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hc.r * C.hinv) + join(hI0, hwx, hc.za, hc.zb) : 0.0f;
+      __syncthreads();
+      if (nv > 0) {
+        float q[4], so[4];
+        MG0_STENCIL(C, um, uc, un, pl, q)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);
+          if (e < nv) acc = __fma_rn((double)rc[e], (double)so[e], acc);
+        }
+        st4<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        um[e] = uc[e];
+        uc[e] = un[e];
+        rc[e] = qn.r[e];
+      }
+      qn = qnn;
+      hc = hn;
+      buf ^= 1;
+    }
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[item].g[2] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+#undef MG0_STENCIL
+#undef MG0_ITEM_SETUP
 
 // ---------------------------------------------------------------------------
 // host side
@@ -990,6 +1333,9 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     // transfer tables level l -> l+1
     for (int l = 0; l + 1 < L; l++) {
       const int nf = nl[l], nc = nl[l + 1];
+      // the z-marching transfers and the FP32 post-smoothing's tap window assume
+      // that ci grows by at most one per fine point
+      RBWS_REQUIRE(2 * (nc + 1) <= nf + 1, RBWS_EINVAL, "multigrid coarsening ratio above 1/2");
       std::vector<int> ci(nf);
       std::vector<double> cw(nf);
       std::vector<float> cwf(nf);
@@ -1062,7 +1408,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
 }
 
 static unsigned grid_for(long long items) {
-  const long long g = std::min<long long>(std::max<long long>(items, 1), 16384);
+  const long long g = std::min<long long>(std::max<long long>(items, 1), 65536);
   return (unsigned)((g + 7) & ~7LL);
 }
 
@@ -1107,8 +1453,8 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
   const long long nx = (long long)lv.n * lv.n * cl.n;
   const long long nrx = ((long long)lv.n * lv.n + kRxRows - 1) / kRxRows * ((cl.n + 63) / 64);
-  const long long nryz = (long long)cl.n * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
-  const long long npyz = ((long long)lv.n * lv.n + 3) / 4 * ((cl.n + 63) / 64);
+  const long long nryz = (long long)((cl.n + kRzSeg - 1) / kRzSeg) * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
+  const long long npyz = (long long)((lv.n + kPzSeg - 1) / kPzSeg) * ((lv.n + 3) / 4) * ((cl.n + 63) / 64);
   hipLaunchKernelGGL(k_mg_rx<T>, dim3(grid_for((long long)ns * nrx)), dim3(256), 0, s, v, cv, ml,
                      (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)lv.vtx.ptr);
   hipLaunchKernelGGL(k_mg_ryz<T>, dim3(grid_for((long long)ns * nryz)), dim3(256), 0, s, v,
@@ -1137,7 +1483,7 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   const unsigned tgrid = 8u * (unsigned)((B.nitems + 7) / 8);
   if (m->fused) {  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
     if (m->fp32) {
-      auto k = B.vec ? k_mg_pre0<float, true> : k_mg_pre0<float, false>;
+      auto k = B.vec ? k_mg_pre0_32<true> : k_mg_pre0_32<false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
                          (const int*)L.ap, (const int*)(L.cnt + WL_AP), (const SolveDev*)B.sd.ptr,
                          (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r,
@@ -1163,12 +1509,12 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   if (m->fused) {  // e1 formed again from r; the tiles of the listed solves are the CG work list L.ap
     const unsigned grid = tgrid;
     if (m->fp32) {
-      auto k = B.vec ? k_mg_post0<float, true> : k_mg_post0<float, false>;
+      auto k = B.vec ? k_mg_post0_32<true> : k_mg_post0_32<false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr,
                          (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const float*)r,
-                         (float*)sv, part, (float)m->omega, ktab);
+                         (float*)sv, (IrPart*)part, (float)m->omega, ktab);
     } else {
       auto k = B.vec ? k_mg_post0<double, true> : k_mg_post0<double, false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
