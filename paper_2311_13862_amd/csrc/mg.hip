@@ -147,15 +147,13 @@ __global__ __launch_bounds__(256) void k_mg_point(MgLv L, MgList ml, const T* __
   }
 }
 
-// Transfers between levels.  A wave takes a row of 64 coarse columns I (lane =
-// column) and walks several fine or coarse rows with the per-column weights
-// held in registers, so the index arithmetic is paid once per wave item.
+// Transfers between levels, weights from the tables ci (coarse node left of a
+// fine point), cw (its offset) and lohi (fine span of a coarse node).
 //
-// Restriction b_c = scale P^T r_f, separable: the x-pass forms, for every fine
-// (k, j) row and coarse column I, ax = sum_i px r (fma chain from 0, i ascending);
-// the yz-pass forms az = sum_k pz (sum_j py ax) per coarse point, times scale.
+// Restriction b_c = scale P^T r_f, separable as
+//   ax[k][j][I] = sum_i px r[k][j][i],  ay = sum_j py ax,  az = sum_k pz ay,
+// each an fma chain from 0 over ascending fine index, then b_c = az * scale.
 constexpr int kSpan = 6;  // fine points per coarse node and axis: 2 (nf+1)/(nc+1) + 1 <= 6
-constexpr int kRxRows = 32;
 
 template <typename T>
 __device__ __forceinline__ int fine_weights(int I, const int* __restrict__ ci, const T* __restrict__ cw,
@@ -169,89 +167,105 @@ __device__ __forceinline__ int fine_weights(int I, const int* __restrict__ ci, c
   return r.x;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_rx(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
-                                               const T* __restrict__ cw, const int2* __restrict__ lohi,
-                                               const T* __restrict__ rf, T* __restrict__ tx) {
-  const int nc = C.n, nf = F.n, rows = nf * nf;
-  const int ich = (nc + 63) >> 6, rblk = (rows + kRxRows - 1) / kRxRows;
-  const int per = ich * rblk;
-  const ItemRange R = item_range(*ml.cnt * per);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int w = R.w; w < R.w1; w += R.step) {
-    const int t = ml.list[w / per];
-    const int rem = w % per, rb = rem / ich, I = (rem % ich) * 64 + lane + 1;
-    if (I > nc) continue;
-    T wts[kSpan];
-    const int lo = fine_weights(I, ci, cw, lohi, wts);
-    const int2 span = lohi[I];
-    const T* r0 = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof) + (lo - 1);
-    T* out = tx + (long long)t * rows * nc + (I - 1);
-    for (int m = wv; m < kRxRows; m += 4) {
-      const int row = rb * kRxRows + m;
-      if (row >= rows) break;
-      const T* rr = r0 + (long long)row * nf;
-      T ax = T(0);
-#pragma unroll
-      for (int u = 0; u < kSpan; u++)
-        if (lo + u <= span.y) ax = fmaT(wts[u], rr[u], ax);
-      out[(long long)row * nc] = ax;
-    }
-  }
-}
-
-// The yz-pass is a z-march: a thread owns a coarse column (J, I) and a
-// segment of kRzSeg coarse planes.  Each fine plane k forms ay(k) = sum_j py
-// ax[k][j][I] once and adds it to the two coarse planes whose spans hold k,
-// K = ci(k) (weight 1 - cw) and ci(k) + 1 (weight cw), in ascending k: the
-// order of the fma chains over k.  With (nc+1)/(nf+1) <= 1/2, ci grows by at
+// One pass, a z-march: a block owns a quad of coarse rows J (a wave each), a
+// chunk of 64 coarse columns I (a lane each) and a segment of kRsSeg coarse
+// planes, and walks the fine planes k that feed them.  Per plane the fine
+// block (rows in the quad's span) x (columns in the chunk's span) is staged in
+// LDS (loaded one plane ahead into registers), the x-sums ax[j][I] are formed
+// there, and each thread forms ay(k) for its (J, I) and adds it to the coarse
+// planes K = ci(k) (weight 1 - cw) and ci(k) + 1 (weight cw), in ascending k:
+// the order of the chains over k.  With (nc+1)/(nf+1) <= 1/2, ci grows by at
 // most one per fine plane, so two accumulators (K = Kc, Kc + 1) suffice and Kc
-// is complete when ci moves past it.
-constexpr int kRzSeg = 8;
+// is complete once ci has moved past it.
+constexpr int kRsSeg = 16;
+constexpr int kRsRows = 16;   // fine rows of a J quad's span (checked at set-up)
+constexpr int kRsCols = 144;  // fine columns of an I chunk's span (checked at set-up)
+constexpr int kRsQ = (kRsCols + 63) / 64;
+constexpr int kRsPer = (kRsRows / 4) * kRsQ;  // staged values per thread
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_ryz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
-                                                const T* __restrict__ cw, const int2* __restrict__ lohi,
-                                                const T* __restrict__ tx, T* __restrict__ bc, T scale) {
+__global__ __launch_bounds__(256) void k_mg_restrict(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                     const T* __restrict__ cw, const int2* __restrict__ lohi,
+                                                     const T* __restrict__ rf, T* __restrict__ bc, T scale) {
+  __shared__ T tile[2][kRsRows][kRsCols];
+  __shared__ T axs[2][kRsRows][64];
   const int nc = C.n, nf = F.n;
-  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2, nseg = (nc + kRzSeg - 1) / kRzSeg;
+  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2, nseg = (nc + kRsSeg - 1) / kRsSeg;
   const int cols = jq * ich, per = nseg * cols;  // (segment, J quad, I chunk) items per solve
   const ItemRange R = item_range(*ml.cnt * per);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const long long nc2 = (long long)nc * nc, fplane = (long long)nf * nc;
+  const long long nc2 = (long long)nc * nc, nf2 = (long long)nf * nf;
   for (int w = R.w; w < R.w1; w += R.step) {
     const int t = ml.list[w / per];
     const int rem = w % per, sg = rem / cols, rc = rem % cols;
-    const int J = (rc / ich) * 4 + wv + 1, I = (rc % ich) * 64 + lane + 1;
-    if (J > nc || I > nc) continue;
-    const int Ks = sg * kRzSeg + 1, Ke = min(nc, Ks + kRzSeg - 1);
-    T wy[kSpan];
-    const int jlo = fine_weights(J, ci, cw, lohi, wy);
-    const int jn = lohi[J].y - jlo + 1;
+    const int Jq0 = (rc / ich) * 4 + 1, Iq0 = (rc % ich) * 64 + 1;
+    const int J = Jq0 + wv, I = Iq0 + lane;
+    const bool act = J <= nc && I <= nc;
+    const int Jl = min(Jq0 + 3, nc), Il = min(Iq0 + 63, nc);
+    const int jr0 = lohi[Jq0].x, nr = lohi[Jl].y - jr0 + 1;  // staged fine rows
+    const int ic0 = lohi[Iq0].x, ncl = lohi[Il].y - ic0 + 1;  // staged fine columns
+    const int Ks = sg * kRsSeg + 1, Ke = min(nc, Ks + kRsSeg - 1);
     const int k0 = lohi[Ks].x, k1 = lohi[Ke].y;
-    const T* a = tx + (long long)t * nf * fplane + (long long)(jlo - 1) * nc + (I - 1);
-    T* out = bc + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (long long)(J - 1) * nc + (I - 1);
+    // per-thread weights: x for column I, y for row J
+    T wx[kSpan], wy[kSpan];
+    const int Ic = min(I, nc), Jc = min(J, nc);
+    const int xo = fine_weights(Ic, ci, cw, lohi, wx) - ic0, xn = lohi[Ic].y - lohi[Ic].x + 1;
+    const int yo = fine_weights(Jc, ci, cw, lohi, wy) - jr0, yn = lohi[Jc].y - lohi[Jc].x + 1;
+    const T* src = rf + (F.voff ? F.voff[t] : (long long)t * F.ndof) + (long long)(jr0 - 1) * nf + (ic0 - 1);
+    T* out = bc + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (long long)(Jc - 1) * nc + (Ic - 1);
+    T st[kRsPer];
+    auto load = [&](int k) __attribute__((always_inline)) {
+      const T* p = src + (long long)(k - 1) * nf2;
+#pragma unroll
+      for (int m = 0; m < kRsRows / 4; m++)
+#pragma unroll
+        for (int q = 0; q < kRsQ; q++) {
+          const int r = wv + 4 * m, c = lane + 64 * q;
+          st[m * kRsQ + q] = (r < nr && c < ncl) ? p[(long long)r * nf + c] : T(0);
+        }
+    };
     int Kc = ci[k0 - 1];
     T accA = T(0), accB = T(0);
+    load(k0);
+    int buf = 0;
     for (int k = k0; k <= k1; k++) {
+#pragma unroll
+      for (int m = 0; m < kRsRows / 4; m++)
+#pragma unroll
+        for (int q = 0; q < kRsQ; q++)
+          if (lane + 64 * q < kRsCols) tile[buf][wv + 4 * m][lane + 64 * q] = st[m * kRsQ + q];
+      if (k < k1) load(k + 1);
+      __syncthreads();
+      // x-sums of the staged rows at this lane's column I
+#pragma unroll
+      for (int m = 0; m < kRsRows / 4; m++) {
+        const int r = wv + 4 * m;
+        T ax = T(0);
+#pragma unroll
+        for (int u = 0; u < kSpan; u++)
+          if (u < xn) ax = fmaT(wx[u], tile[buf][r][xo + u], ax);
+        axs[buf][r][lane] = ax;
+      }
+      __syncthreads();
       const int K0 = ci[k - 1];
       const T wz = cw[k - 1];
       if (K0 != Kc) {
-        if (Kc >= Ks) out[(Kc - 1) * nc2] = accA * scale;
+        if (act && Kc >= Ks) out[(Kc - 1) * nc2] = accA * scale;
         accA = accB;
         accB = T(0);
         Kc = K0;
       }
-      const T* ak = a + (long long)(k - 1) * fplane;
       T ay = T(0);
 #pragma unroll
       for (int u = 0; u < kSpan; u++)
-        if (u < jn) ay = fmaT(wy[u], ak[(long long)u * nc], ay);
+        if (u < yn) ay = fmaT(wy[u], axs[buf][yo + u][lane], ay);
       if (K0 >= 1) accA = fmaT(T(1) - wz, ay, accA);
       if (K0 + 1 <= nc) accB = fmaT(wz, ay, accB);
+      buf ^= 1;
     }
-    if (Kc >= Ks && Kc <= Ke) out[(Kc - 1) * nc2] = accA * scale;
-    if (Kc + 1 >= Ks && Kc + 1 <= Ke) out[Kc * nc2] = accB * scale;
+    if (act && Kc >= Ks && Kc <= Ke) out[(Kc - 1) * nc2] = accA * scale;
+    if (act && Kc + 1 >= Ks && Kc + 1 <= Ke) out[Kc * nc2] = accB * scale;
+    __syncthreads();  // LDS of this item is free
   }
 }
 
@@ -1356,6 +1370,12 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
         lh[I] = make_int2(lo, hi);
         RBWS_REQUIRE(hi - lo + 1 <= kSpan, RBWS_EINVAL, "multigrid transfer wider than expected");
       }
+      // the restriction stages the fine span of 4 coarse rows and of 64 coarse columns
+      for (int I = 1; I <= nc; I++) {
+        RBWS_REQUIRE(lh[std::min(I + 3, nc)].y - lh[I].x + 1 <= kRsRows &&
+                         lh[std::min(I + 63, nc)].y - lh[I].x + 1 <= kRsCols,
+                     RBWS_EINVAL, "multigrid restriction block wider than expected");
+      }
       MgLevelHost* lv = g->lv[l];
       RBWS_HIP(hipMemcpyAsync(lv->ci.get(sizeof(int) * nf, B.device), ci.data(), sizeof(int) * nf,
                               hipMemcpyHostToDevice, s));
@@ -1451,15 +1471,10 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const MgLv cv = view(cl, g, false, m->fp32);
   const T* cw = m->fp32 ? (const T*)lv.cwf.ptr : (const T*)lv.cwd.ptr;
   const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
-  const long long nx = (long long)lv.n * lv.n * cl.n;
-  const long long nrx = ((long long)lv.n * lv.n + kRxRows - 1) / kRxRows * ((cl.n + 63) / 64);
-  const long long nryz = (long long)((cl.n + kRzSeg - 1) / kRzSeg) * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
+  const long long nrs = (long long)((cl.n + kRsSeg - 1) / kRsSeg) * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
   const long long npyz = (long long)((lv.n + kPzSeg - 1) / kPzSeg) * ((lv.n + 3) / 4) * ((cl.n + 63) / 64);
-  hipLaunchKernelGGL(k_mg_rx<T>, dim3(grid_for((long long)ns * nrx)), dim3(256), 0, s, v, cv, ml,
-                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)lv.vtx.ptr);
-  hipLaunchKernelGGL(k_mg_ryz<T>, dim3(grid_for((long long)ns * nryz)), dim3(256), 0, s, v,
-                     cv, ml, (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr,
-                     (T*)cl.vb.ptr, scale);
+  hipLaunchKernelGGL(k_mg_restrict<T>, dim3(grid_for((long long)ns * nrs)), dim3(256), 0, s, v, cv, ml,
+                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
   // z/y interpolation of the coarse correction (into vtx, free again after the restriction)
   hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
