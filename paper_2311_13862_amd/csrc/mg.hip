@@ -919,13 +919,17 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
   }
 }
 
-// FP32 level-0 kernels.  The own quad's face coefficients, diagonal and
-// reciprocal diagonal, and the halo point's reciprocal diagonal, sit in
-// registers (KCache32, refreshed only when the plane's z codes change), so a
-// plane costs no class-table reads and no division: Jacobi is
-// omega (r (1/d)).  e1 of plane k+1, needed by the stencil of plane k, takes
-// its reciprocals from a second cache keyed by plane k+1.  The pre- and
-// post-smoothing form e1 with the same operations.
+// FP32 fused smoothing kernels of a level (nu = 1), tile z-marches like the
+// FP64 ones above.  The own quad's face coefficients, diagonal and reciprocal
+// diagonal, and the halo point's reciprocal diagonal, sit in registers
+// (KCache32, refreshed only when the plane's z codes change), so a plane costs
+// no class-table reads and no division: Jacobi is omega (r (1/d)).  e1 of plane
+// k+1, needed by the stencil of plane k, takes its reciprocals from a second
+// cache keyed by plane k+1.  The pre- and post-smoothing form e1 with the same
+// operations.  Items: with ML false, the tiles on a work list (level 0, the
+// CG's list of the listed solves); with ML true, every tile of the solves on a
+// V-cycle list (item = list[w / ntiles] * ntiles + w % ntiles, levels >= 1,
+// whose batches hold ntiles tiles per solve, solve-major).
 struct InvCache32 {
   int key;
   float inv[4];
@@ -943,7 +947,7 @@ __device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const 
 
 // shared set-up of an item of the FP32 level-0 kernels
 #define MG0_ITEM_SETUP()                                                                \
-  const int item = list[w];                                                             \
+  const int item = ML ? list[w / ntiles] * ntiles + w % ntiles : list[w];              \
   __syncthreads(); /* LDS of the previous item is free */                               \
   const int2 it = items[item];                                                          \
   const SolveDev S = sd[it.x];                                                          \
@@ -982,9 +986,10 @@ __device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const 
     }                                                                                   \
   }
 
-template <bool VEC>
+template <bool VEC, bool ML>
 __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
-                                                    const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                    const int* __restrict__ cnt, int ntiles,
+                                                    const SolveDev* __restrict__ sd,
                                                     const ProbDev* __restrict__ pd, const float* __restrict__ kap,
                                                     const float* __restrict__ b, float* __restrict__ tout,
                                                     float omega, int ktab) {
@@ -992,7 +997,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
   float* kt = reinterpret_cast<float*>(smem_raw);
   float* plane = kt + ktab;
   __shared__ int zk[kZkLen];
-  const WorkRange WR = work_range(*cnt);
+  const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
     const float* Bv = b + S.off;
@@ -1057,9 +1062,10 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
   }
 }
 
-template <bool VEC>
+template <bool VEC, bool ML>
 __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ items, const int* __restrict__ list,
-                                                     const int* __restrict__ cnt, const SolveDev* __restrict__ sd,
+                                                     const int* __restrict__ cnt, int ntiles,
+                                                     const SolveDev* __restrict__ sd,
                                                      const ProbDev* __restrict__ pd, const float* __restrict__ kap,
                                                      const MgFine* __restrict__ mf, const int* __restrict__ gidx,
                                                      const float* __restrict__ r, float* __restrict__ sout,
@@ -1069,11 +1075,11 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
   float* plane = kt + ktab;
   __shared__ double red[4];
   __shared__ int zk[kZkLen];
-  const WorkRange WR = work_range(*cnt);
+  const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
     const MgFine F = mf[S.prob];
-    const gptr<float> ezy = as_global((const float*)F.ezy) + (long long)gidx[it.x] * F.per;
+    const gptr<float> ezy = as_global((const float*)F.ezy) + (long long)(ML ? it.x : gidx[it.x]) * F.per;
     const gptr<float> cw = as_global((const float*)F.cw);
     const float* R = r + S.off;
     float* SO = sout + S.off;
@@ -1191,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);
-          if (e < nv) acc = __fma_rn((double)rc[e], (double)so[e], acc);
+          if (!ML && e < nv) acc = __fma_rn((double)rc[e], (double)so[e], acc);
         }
         st4<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
       }
@@ -1205,11 +1211,13 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
       hc = hn;
       buf ^= 1;
     }
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) part[item].g[2] = red[0] + red[1] + red[2] + red[3];
+    if (!ML) {  // r^T s partial of the tile
+      for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) part[item].g[2] = red[0] + red[1] + red[2] + red[3];
+    }
   }
 }
 #undef MG0_STENCIL
@@ -1225,7 +1233,8 @@ struct MgLevelHost {
   long long ndof = 0;
   DevBuf ci, cwd, cwf, lohi;  // transfer to the next level
   DevBuf vb, ve, ve2, vt;     // level vectors (levels >= 1), group-contiguous
-  DevBuf vtx;                 // x-restricted residual (fine rows x coarse columns)
+  DevBuf vtx;                 // z/y-interpolated coarse correction (fine rows x coarse columns)
+  DevBuf fine;                // MgFine of this level (levels >= 1 with a coarser level)
   bool quad = false;          // n % 4 == 0 and every vector offset a multiple of 4
 };
 
@@ -1419,6 +1428,13 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     f.per = (long long)g->lv[0]->n * g->lv[0]->n * g->lv[1]->n;
     f.nc = g->lv[1]->n;
     f.pad = 0;
+    // the same for the levels >= 1 that have a coarser level (FP32 fused path)
+    for (size_t l = 1; fp32 && l + 1 < g->lv.size(); l++) {
+      MgLevelHost& lv = *g->lv[l];
+      MgFine fl{lv.vtx.ptr, (const int*)lv.ci.ptr, lv.cwf.ptr, (long long)lv.n * lv.n * g->lv[l + 1]->n,
+                g->lv[l + 1]->n, 0};
+      RBWS_HIP(hipMemcpy(lv.fine.get(sizeof(MgFine), B.device), &fl, sizeof(MgFine), hipMemcpyHostToDevice));
+    }
   }
   RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
                           hipMemcpyHostToDevice, s));
@@ -1451,6 +1467,12 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const dim3 grid(grid_for((long long)ns * ((lv.ndof + 255) / 256)));
   const dim3 gq(grid_for((long long)ns * ((lv.ndof / 4 + 255) / 256)));
   const T om = (T)m->omega;
+  // FP32, nu = 1, levels >= 1: fused tile kernels over every tile of the listed solves
+  const bool tiles = m->fp32 && m->nu == 1 && l >= 1;
+  const int ntiles = lv.B.nsolve > 0 ? lv.B.sd_h[0].ntiles : 0;
+  const int ktab = (lv.B.kap_max + 3) & ~3;
+  const dim3 tgrid(8u * (unsigned)(((long long)ns * ntiles + 7) / 8));
+  const size_t tlds = sizeof(float) * (ktab + 2 * QPLANE);
   auto smooth = [&](const T* ein, T* out) {
     if (lv.quad) hipLaunchKernelGGL((k_mg_quad<T, false>), gq, dim3(256), 0, s, v, ml, b, ein, out, om);
     else hipLaunchKernelGGL((k_mg_point<T, false>), grid, dim3(256), 0, s, v, ml, b, ein, out, om);
@@ -1458,7 +1480,12 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   // 2 nu Jacobi writes alternate between `scratch` and `e`, the last one into e
   T* w[2] = {scratch, e};
   int wi = 0;
-  if (!pre_done) {
+  if (tiles) {
+    auto k = lv.B.vec ? k_mg_pre0_32<true, true> : k_mg_pre0_32<false, true>;
+    hipLaunchKernelGGL(k, tgrid, dim3(256), tlds, s, (const int2*)lv.B.items.ptr, ml.list, ml.cnt, ntiles,
+                       (const SolveDev*)lv.B.sd.ptr, (const ProbDev*)lv.B.pd.ptr, (const float*)lv.B.kap32.ptr,
+                       (const float*)b, (float*)tres, (float)m->omega, ktab);
+  } else if (!pre_done) {
     smooth(nullptr, w[wi]);
     for (int it = 1; it < m->nu; it++) {
       smooth(w[wi], w[wi ^ 1]);
@@ -1480,6 +1507,14 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
                      (const int*)lv.ci.ptr, cw, (const T*)cl.ve.ptr, (T*)lv.vtx.ptr);
   if (pre_only) return;
+  if (tiles) {
+    auto k = lv.B.vec ? k_mg_post0_32<true, true> : k_mg_post0_32<false, true>;
+    hipLaunchKernelGGL(k, tgrid, dim3(256), tlds, s, (const int2*)lv.B.items.ptr, ml.list, ml.cnt, ntiles,
+                       (const SolveDev*)lv.B.sd.ptr, (const ProbDev*)lv.B.pd.ptr, (const float*)lv.B.kap32.ptr,
+                       (const MgFine*)lv.fine.ptr, nullptr, (const float*)b, (float*)e, nullptr, (float)m->omega,
+                       ktab);
+    return;
+  }
   if (lv.quad)
     hipLaunchKernelGGL(k_mg_prolong_quad<T>, gq, dim3(256), 0, s, v, cv, ml, (const int*)lv.ci.ptr, cw,
                        (const T*)lv.vtx.ptr, w[wi]);
@@ -1498,9 +1533,9 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   const unsigned tgrid = 8u * (unsigned)((B.nitems + 7) / 8);
   if (m->fused) {  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
     if (m->fp32) {
-      auto k = B.vec ? k_mg_pre0_32<true> : k_mg_pre0_32<false>;
+      auto k = B.vec ? k_mg_pre0_32<true, false> : k_mg_pre0_32<false, false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
-                         (const int*)L.ap, (const int*)(L.cnt + WL_AP), (const SolveDev*)B.sd.ptr,
+                         (const int*)L.ap, (const int*)(L.cnt + WL_AP), 0, (const SolveDev*)B.sd.ptr,
                          (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r,
                          (float*)m->t0.ptr, (float)m->omega, ktab);
     } else {
@@ -1524,9 +1559,9 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   if (m->fused) {  // e1 formed again from r; the tiles of the listed solves are the CG work list L.ap
     const unsigned grid = tgrid;
     if (m->fp32) {
-      auto k = B.vec ? k_mg_post0_32<true> : k_mg_post0_32<false>;
+      auto k = B.vec ? k_mg_post0_32<true, false> : k_mg_post0_32<false, false>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
-                         (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
+                         (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP), 0,
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr,
                          (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const float*)r,
                          (float*)sv, (IrPart*)part, (float)m->omega, ktab);
