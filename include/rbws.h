@@ -179,6 +179,19 @@ rbws_status rbws_theta(const rbws_problem* p, const double* mu, int nmu, double*
 rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x, void* y,
                       int precision, void* stream);
 
+/* s_b = MG(r_b) for b < nmu: one V-cycle from zero (Alg. 2 with nu damped
+ * Jacobi sweeps of weight omega before and after the coarse correction; the
+ * levels, transfers and coarsest solve of RBWS_PREC_MG), the preconditioner of
+ * the multigrid path as an operator.  r, s: device, nmu*ndof values of type
+ * double (RBWS_FP64: each step in a fixed order, bitwise reproducible) or
+ * float (RBWS_FP32_IR: float coefficients and vectors; with nu = 1 the
+ * smoothing multiplies by a float reciprocal of the diagonal).  r and s must
+ * not overlap.  Blocks until done.  Errors: EINVAL (NULL, bad precision,
+ * nu outside 1..8, omega outside (0, 1]), ENUMERIC (coarsest matrix not
+ * positive definite), EDEVICE. */
+rbws_status rbws_mg_apply(rbws_problem* p, const double* mu, int nmu, int nu, double omega, const void* r,
+                          void* s, int precision, void* stream);
+
 /* Correctly rounded dot products out[b] = sum_i x[b*len+i] y[b*len+i]
  * (exact sum of exact products rounded once to nearest-even), b < count.
  * x, y device (double); out host.  Used by every FP64 inner product. */

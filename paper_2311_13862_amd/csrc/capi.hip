@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "mg.hpp"
 #include "mlp.hpp"
 #include "rb.hpp"
 
@@ -235,6 +236,24 @@ rbws_status rbws_spmv(rbws_problem* p, const double* mu, int nmu, const void* x,
   batch_setup(B, probs, nullptr, nmu, mu, PP(p)->p, s);
   spmv_batch(B, x, y, precision == RBWS_FP32_IR, s);
   RBWS_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+rbws_status rbws_mg_apply(rbws_problem* p, const double* mu, int nmu, int nu, double omega, const void* r,
+                          void* s, int precision, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(p != nullptr, RBWS_EINVAL, "problem is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  RBWS_REQUIRE(precision == RBWS_FP64 || precision == RBWS_FP32_IR, RBWS_EINVAL, "bad precision");
+  RBWS_REQUIRE(nu >= 1 && nu <= 8 && omega > 0.0 && omega <= 1.0, RBWS_EINVAL,
+               "bad multigrid settings (nu in 1..8, omega in (0, 1])");
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(mu && r && s, RBWS_EINVAL, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  static thread_local Batch& B = *new Batch();
+  std::vector<const Problem*> probs{PP(p)};
+  batch_setup(B, probs, nullptr, nmu, mu, PP(p)->p, st);
+  mg_apply_all(B, nu, omega, precision == RBWS_FP32_IR, r, s, st);
   API_END
 }
 

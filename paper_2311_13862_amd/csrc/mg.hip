@@ -1577,4 +1577,35 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   return m->fused;
 }
 
+void mg_apply_all(Batch& B, int nu, double omega, bool fp32, const void* r, void* sv, hipStream_t st) {
+  if (B.nsolve == 0) return;
+  RBWS_REQUIRE(B.nprob <= WL_MAXPROB, RBWS_EINVAL, "too many problems in one multigrid batch");
+  Lists L = lists_init(B, st);
+  // every tile on the ap list, every solve on its problem's V-cycle list
+  const int ni = B.nitems, ns = B.nsolve;
+  static thread_local std::vector<int> head, ap, mg;  // kept until the stream is synchronised below
+  head.assign(64, 0);
+  head[WL_AP] = ni;
+  std::vector<int> seg(B.nprob + 1, 0);
+  for (int b = 0; b < ns; b++) seg[B.sd_h[b].prob + 1]++;
+  for (int q = 0; q < B.nprob; q++) {
+    head[WL_MG + q] = seg[q + 1];
+    seg[q + 1] += seg[q];
+    head[WL_SEG + q] = seg[q];
+  }
+  ap.resize(ni);
+  for (int t = 0; t < ni; t++) ap[t] = t;
+  mg.resize(ns);
+  for (int q = 0; q < B.nprob; q++)
+    for (int i = 0; i < seg[q + 1] - seg[q]; i++) mg[seg[q] + i] = i;
+  RBWS_HIP(hipMemcpyAsync(L.cnt, head.data(), sizeof(int) * head.size(), hipMemcpyHostToDevice, st));
+  RBWS_HIP(hipMemcpyAsync(L.ap, ap.data(), sizeof(int) * ni, hipMemcpyHostToDevice, st));
+  RBWS_HIP(hipMemcpyAsync(L.mg, mg.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+  MgRun* m = mg_prepare(B, nu, omega, fp32, st);
+  RBWS_SCRATCH(part);
+  void* pp = part.get(std::max(sizeof(CrAcc) * kSlots, sizeof(IrPart)) * (size_t)ni, B.device);
+  mg_apply(m, B, r, sv, L, pp, st);
+  RBWS_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace rbws

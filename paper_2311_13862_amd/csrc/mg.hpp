@@ -24,4 +24,8 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s);
 // of every listed tile (partial slot 1 in FP64, IrPart.g[2] in FP32).
 bool mg_apply(MgRun* m, Batch& B, const void* r, void* s, const Lists& L, void* part, hipStream_t st);
 
+// s_b = MG(r_b) for every solve of B, outside a solve: every tile and every
+// solve listed, then one V-cycle.  Synchronises the stream.
+void mg_apply_all(Batch& B, int nu, double omega, bool fp32, const void* r, void* s, hipStream_t st);
+
 }  // namespace rbws

@@ -78,6 +78,7 @@ def _load():
         "rbws_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
         "rbws_problem_create": (i, [C.POINTER(ProblemDesc), i, C.POINTER(vp)]),
         "rbws_problem_destroy": (None, [vp]),
+        "rbws_mg_apply": (i, [vp, dp, i, i, d, vp, vp, i, vp]),
         "rbws_problem_info": (i, [vp, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(ll)]),
         "rbws_theta": (i, [vp, dp, i, dp]),
         "rbws_spmv": (i, [vp, dp, i, vp, vp, i, vp]),
@@ -199,6 +200,13 @@ class Problem:
         mu = _f64(mu).reshape(-1, self.p)
         _check(_L.rbws_spmv(self.handle, _dp(mu), mu.shape[0], C.c_void_p(x.data_ptr()),
                             C.c_void_p(y.data_ptr()), precision, _stream(stream)))
+
+    def mg_apply(self, mu, r, s, nu=1, omega=6.0 / 7.0, precision=FP64, stream=None):
+        """s[b] = MG(r[b]), one V-cycle; r, s torch device tensors (nmu, ndof) of
+        float64 (FP64) or float32 (FP32_IR)."""
+        mu = _f64(mu).reshape(-1, self.p)
+        _check(_L.rbws_mg_apply(self.handle, _dp(mu), mu.shape[0], nu, float(omega), C.c_void_p(r.data_ptr()),
+                                C.c_void_p(s.data_ptr()), precision, _stream(stream)))
 
 
 def exact_dots(x, y, flags: int = 0, stream=None) -> np.ndarray:

@@ -53,6 +53,53 @@ def test_mgcg_parity(rb, spec, nu, omega):
         assert sg[0]["iters"] * 2 < sj[0]["iters"]
 
 
+@pytest.mark.parametrize("spec", CASES, ids=lambda s: f"k{s.kind}n{s.n}")
+@pytest.mark.parametrize("nu,omega", [(1, 6.0 / 7.0), (2, 0.8)])
+def test_vcycle_operator_fp64(rb, spec, nu, omega):
+    """rbws_mg_apply in FP64 is the oracle's V-cycle bit for bit."""
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 3, 80 + spec.n)
+    rhs = np.random.default_rng(spec.n).standard_normal((3, O.ndof))
+    r = torch.tensor(rhs, device="cuda")
+    s = torch.empty_like(r)
+    P.mg_apply(mu, r, s, nu=nu, omega=omega)
+    sg = s.cpu().numpy()
+    for b in range(len(mu)):
+        assert np.array_equal(sg[b], O.mg_apply(mu[b], rhs[b], nu, omega)), b
+
+
+@pytest.mark.parametrize("spec", [W.Problem(64, W.KIND_OCTANTS), W.Problem(33, W.KIND_BLOCKS, W.BLOCKS4),
+                                  W.Problem(20, W.KIND_OCTANTS_ANISO)], ids=["oct64", "blk33", "aniso20"])
+def test_vcycle_operator_fp32(rb, spec):
+    """The FP32 V-cycle (float coefficients and vectors, reciprocal-diagonal
+    Jacobi on the fused levels) against the oracle's FP64 one: relative 2-norm
+    error within 2e-5, about 100 float roundings of accumulated error; a wrong
+    weight, index or sign gives errors of order 1e-2 or more."""
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 4, 90 + spec.n)
+    rhs = np.random.default_rng(spec.n + 1).standard_normal((4, O.ndof))
+    r = torch.tensor(rhs, device="cuda", dtype=torch.float32)
+    s = torch.empty_like(r)
+    P.mg_apply(mu, r, s, precision=rb.FP32_IR)
+    sg = s.double().cpu().numpy()
+    for b in range(len(mu)):
+        ref = O.mg_apply(mu[b], r[b].double().cpu().numpy(), 1, 6.0 / 7.0)
+        err = np.linalg.norm(sg[b] - ref) / np.linalg.norm(ref)
+        assert err <= 2e-5, (b, err)
+
+
+def test_vcycle_operator_errors(rb):
+    spec = W.Problem(8, W.KIND_OCTANTS)
+    P = rb.Problem(spec)
+    mu = W.sample_mu(spec, 0.1, 10.0, 1, 1)
+    r = torch.zeros((1, P.ndof), dtype=torch.float64, device="cuda")
+    for kw in ({"nu": 0}, {"nu": 9}, {"omega": 0.0}, {"omega": 1.5}):
+        with pytest.raises(rb.RbwsError):
+            P.mg_apply(mu, r, torch.empty_like(r), **kw)
+
+
 def test_mgcg_forced_exact_dots_and_launches(rb):
     spec = W.Problem(15, W.KIND_OCTANTS)
     P = rb.Problem(spec)
