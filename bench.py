@@ -106,6 +106,7 @@ def main():
         st = solve_step(rbws, P, basis, mu, opts)
         it = np.array([s["iters"] for s in st])
         ou = np.array([s["outer_iters"] for s in st])
+        vc = float(np.sum([s["vcycles"] for s in st]))
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
         b.copy_(a)
@@ -114,6 +115,8 @@ def main():
                           "copy_bytes_written": b.numel() * 8,
                           "up2_algorithmic_bytes": float(np.sum(it * 20 - ou * 4)) * P.ndof,
                           "ap_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
+                          "mg_pre0_algorithmic_bytes": vc * MG_PRE0_BYTES * P.ndof,
+                          "mg_post0_algorithmic_bytes": vc * mg_post0_bytes(spec.n) * P.ndof,
                           "sources_sha256": kernel_sources_hash()}), flush=True)
         return
 
@@ -151,13 +154,15 @@ def main():
     copy_gbs = 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
 
-    # roofline of the dominant kernel, from the events recorded over the timed steps
+    # roofline of the dominant kernel (the single kernel with the most time over the timed
+    # steps, from its HIP events), priced at its algorithmic bytes
     nd = P.ndof
+    vcyc = np.array([s["vcycles"] for s in stats])
     alg = {"up2_sweep": args.steps * float(np.sum(iters * 20 - outer * 4)) * nd,  # R p, d, r; W d, r (FP32)
            "ap_sweep": args.steps * float(np.sum(iters * 12 - outer * 4)) * nd,   # R s, p_old; W p_new
-           # one V-cycle per inner iteration: on every level read b, write e (pre-smoothing), read e, b
-           # (residual, restriction), read e, b, write s (correction, post-smoothing) = 7 FP32 vectors
-           "mg_vcycle": args.steps * float(np.sum(iters)) * 28.0 * mg_points(spec.n) if PRECOND == 2 else 0.0}
+           # V-cycle, finest level (FP32): R b, W t; and R r, R ezy, W s
+           "mg_pre0": args.steps * float(np.sum(vcyc)) * MG_PRE0_BYTES * nd,
+           "mg_post0": args.steps * float(np.sum(vcyc)) * mg_post0_bytes(spec.n) * nd}
     ms = {k: v[0] for k, v in kern.items()}
     n_launch = {k: v[1] for k, v in kern.items()}
     dom = max(alg, key=lambda k: ms.get(k, 0.0))
@@ -229,6 +234,7 @@ def main():
         "max_final_relres": float(relres.max()),
         "inner_iters_mean": float(iters.mean()),
         "outer_iters_mean": float(outer.mean()),
+        "vcycles_mean": float(vcyc.mean()),
         "zero_start_value": None if zero_value is None else round(zero_value, 3),
         "zero_start_inner_iters_mean": zero_iters,
         "rb_over_zero": None if zero_value is None else round(value / zero_value, 4),
@@ -289,17 +295,16 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
             "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
 
 
-def mg_points(n):
-    """Grid points per solve over all multigrid levels (n, (n-1)//2, ... while > 3)."""
-    tot, m = 0, n
-    while True:
-        tot += m ** 3
-        if m <= 3:
-            return tot
-        m = (m - 1) // 2
+MG_PRE0_BYTES = 8.0  # per finest-level point: read b, write t = b - A e1 (FP32)
 
 
-KERNEL_SOURCES = ("fast.hpp", "ir.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
+def mg_post0_bytes(n):
+    """Per finest-level point: read r, write s (FP32), and the z/y-interpolated
+    coarse correction ezy (n x n rows of nc = (n-1)//2 values per solve)."""
+    return 8.0 + 4.0 * ((n - 1) // 2) / n
+
+
+KERNEL_SOURCES = ("fast.hpp", "ir.hip", "mg.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_octants128_traffic.txt")
 
 

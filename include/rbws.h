@@ -116,7 +116,7 @@ typedef struct {
   int extra_spmv;    /* true-residual evaluations beyond the initial one */
   int status;        /* RBWS_SOLVE_* */
   int init_used;     /* RBWS_INIT_* actually used (learned start may fall back to RB) */
-  int pad;
+  int vcycles;       /* V-cycles applied (RBWS_PREC_MG), else 0 */
   double init_rr;    /* ||f - A u0||^2 */
   double final_rr;   /* ||f - A u||^2 at exit (the true residual when converged) */
   double ff;         /* ||f||^2 */
@@ -337,9 +337,12 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
  * 1 residual pass (initial / confirmation / refinement outer pass), 2 and 4
  * the per-solve scalar steps after each sweep, 3 update sweep (x, r and their
  * inner products), 5 SpMV, 6 MFMA lift, 7 reduced solves, 8 multigrid
- * V-cycle with r^T s.  The call first
- * waits for recorded events and returns the totals so far (ms[9], launches[9],
- * both nullable), then zeroes them if `reset`, then turns timing on or off. */
+ * V-cycle except its fused finest-level kernels (coarser levels, transfers,
+ * the per-solve step after it), 9 the finest level's fused pre-smoothing and
+ * residual, 10 its fused coarse correction, post-smoothing and r^T s.  The
+ * call first waits for recorded events and returns the totals so far
+ * (ms[11], launches[11], both nullable), then zeroes them if `reset`, then
+ * turns timing on or off. */
 rbws_status rbws_profile(int enable, double* ms, long long* launches, int reset);
 /* How often a correctly rounded inner product could not be certified from
  * its double-double value and was recomputed exactly (current device):

@@ -59,6 +59,7 @@ void collect_stats(Batch& B, unsigned long long t0, const std::vector<int>& init
     (void)outer_field_from_extra;
     o.status = st[b].status < 0 ? RBWS_SOLVE_MAXITER : st[b].status;
     o.init_used = init_used[b];
+    o.vcycles = st[b].nvc;
     o.init_rr = st[b].init_rr;
     o.final_rr = st[b].rr;
     o.ff = st[b].ff;
@@ -552,6 +553,7 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
         o.extra_spmv = ir[b].outer;
         o.status = ir[b].status;
         o.init_used = used[b];
+        o.vcycles = ir[b].nvc;
         o.init_rr = ir[b].init_rr;
         o.final_rr = ir[b].rr;
         o.ff = ir[b].ff;

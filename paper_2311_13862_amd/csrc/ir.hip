@@ -311,6 +311,7 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
       st[b].skip2 = 0;
       if (need) {  // the V-cycle on the new right-hand side
         need[b] = 1;
+        st[b].nvc += 1;
         const int q = sd[b].prob;
         L.mg[L.cnt[WL_SEG + q] + atomicAdd(&L.cnt[WL_MG + q], 1)] = L.gidx[b];
       }
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(256) void k_ir_fin2(const SolveDev* __restrict__ sd
       ir_end_inner(s, rr, __builtin_isfinite(rr) ? 1 : 0);
     } else if (s.mg) {
       s.restart = 0;  // beta and rho follow the V-cycle (k_ir_fin_mg)
+      s.nvc += 1;
       need[b] = 1;
       L.mg[L.cnt[WL_SEG + S.prob] + atomicAdd(&L.cnt[WL_MG + S.prob], 1)] = L.gidx[b];
     } else {
@@ -536,8 +538,9 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     hipLaunchKernelGGL(k_ir_fin2, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, L, need);
     kt.end(q);
     if (mg) {
+      const bool fused = mg_apply(mgr, B, r, sv, L, part, q);  // times its own kernels
       kt.begin(q, KK_MG);
-      if (!mg_apply(mgr, B, r, sv, L, part, q))
+      if (!fused)
         hipLaunchKernelGGL(k_dot_rs32, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
                            (const int*)(L.cnt + WL_AP), ni, sd, pd, (const float*)r, (const float*)sv, part);
       hipLaunchKernelGGL(k_ir_fin_mg, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, (const int*)need);
@@ -553,6 +556,7 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     q.outer = h[b].outer;
     q.status = h[b].status < 0 ? RBWS_SOLVE_MAXITER : h[b].status;
     q.cur = h[b].cur;
+    q.nvc = h[b].nvc;
     q.init_rr = h[b].init_rr;
     q.rr = h[b].rr;
     q.ff = h[b].ff;

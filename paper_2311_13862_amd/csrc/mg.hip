@@ -1531,7 +1531,9 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
 bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void* part, hipStream_t st) {
   const int ktab = (B.kap_max + 3) & ~3;
   const unsigned tgrid = 8u * (unsigned)((B.nitems + 7) / 8);
-  if (m->fused) {  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
+  KernelTimer& kt = ktimer();
+  if (m->fused) {
+    kt.begin(st, KK_MG_PRE);  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
     if (m->fp32) {
       auto k = B.vec ? k_mg_pre0_32<true, false> : k_mg_pre0_32<false, false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
@@ -1545,7 +1547,9 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
                          (const double*)r, (double*)m->t0.ptr, m->omega, ktab);
     }
+    kt.end(st);
   }
+  kt.begin(st, KK_MG);
   for (MgGroup* g : m->g) {
     if (g->sol.empty()) continue;
     RBWS_REQUIRE(g->q < WL_MAXPROB, RBWS_EINVAL, "too many problems in one multigrid batch");
@@ -1556,7 +1560,9 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
       vcycle<double>(m, *g, 0, (const double*)r, (double*)sv, (double*)m->x0.ptr, (double*)m->t0.ptr, ml, st,
                      m->fused);
   }
+  kt.end(st);
   if (m->fused) {  // e1 formed again from r; the tiles of the listed solves are the CG work list L.ap
+    kt.begin(st, KK_MG_POST);
     const unsigned grid = tgrid;
     if (m->fp32) {
       auto k = B.vec ? k_mg_post0_32<true, false> : k_mg_post0_32<false, false>;
@@ -1570,8 +1576,10 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP),
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const double*)B.kap64.ptr,
-                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const double*)r, (double*)sv, part, m->omega, ktab);
+                         (const MgFine*)m->fine.ptr, (const int*)L.gidx, (const double*)r, (double*)sv, part,
+                         m->omega, ktab);
     }
+    kt.end(st);
   }
   RBWS_HIP(hipGetLastError());
   return m->fused;

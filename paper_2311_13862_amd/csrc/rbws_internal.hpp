@@ -82,6 +82,7 @@ enum SolveMode : int { MODE_RESID = 0, MODE_ITER = 1, MODE_DONE = 2 };
 struct CgState {
   double rho, alpha, beta, rr, thr, ff, init_rr, tol2;
   int k, extra, status, mode, restart, skip2, maxit, prec, first, mg;  // mg: P is a V-cycle
+  int nvc;                                                             // V-cycles applied
   unsigned long long t_done;
 };
 

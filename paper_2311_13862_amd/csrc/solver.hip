@@ -618,6 +618,7 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
       st[b].skip2 = 0;
       if (need) {  // the V-cycle on the (re)started residual
         need[b] = 1;
+        st[b].nvc += 1;
         const int q = sd[b].prob;
         L.mg[L.cnt[WL_SEG + q] + atomicAdd(&L.cnt[WL_MG + q], 1)] = L.gidx[b];
       }
@@ -638,6 +639,7 @@ __global__ __launch_bounds__(256) void k_fin2(const SolveDev* __restrict__ sd,
     } else if (s.k >= s.maxit) mark_done(s, RBWS_SOLVE_MAXITER, active);
     else if (s.mg) {
       s.restart = 0;  // beta and rho follow the V-cycle (k_fin_mg)
+      s.nvc += 1;
       need[b] = 1;
       L.mg[L.cnt[WL_SEG + S.prob] + atomicAdd(&L.cnt[WL_MG + S.prob], 1)] = L.gidx[b];
     } else {
@@ -996,8 +998,9 @@ void cg_fp64_run(Batch& B, const CgOpts& o, hipStream_t s) {
     hipLaunchKernelGGL(k_fin2, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, x, r, p, part, active, fe, L, need);
     kt.end(q);
     if (mg) {
+      const bool fused = mg_apply(mgr, B, r, sv, L, part, q);  // times its own kernels
       kt.begin(q, KK_MG);
-      if (!mg_apply(mgr, B, r, sv, L, part, q))
+      if (!fused)
         hipLaunchKernelGGL(k_dot_rs, dim3(g_dot), dim3(256), 0, q, items, (const int*)L.ap,
                            (const int*)(L.cnt + WL_AP), ni, sd, pd, (const double*)r, (const double*)sv, part);
       hipLaunchKernelGGL(k_fin_mg, dim3(ns), dim3(256), 0, q, sd, pd, st, kap, (const double*)x, (const double*)r,

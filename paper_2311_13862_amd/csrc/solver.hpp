@@ -34,7 +34,7 @@ struct IrState {
   int reliable;    // keep the search direction across outer corrections
   int dir_ok;      // the last inner solve ended with a usable direction
   int mg;          // the inner preconditioner is a V-cycle (s, r^T s follow the sweeps)
-  int pad;
+  int nvc;         // V-cycles applied
 };
 
 // partial results of a work item: FP64 path kSlots correctly rounded
@@ -156,7 +156,7 @@ struct IrOpts {
   double mg_omega = 6.0 / 7.0;
 };
 struct IrHost {
-  int iters, outer, status, cur;
+  int iters, outer, status, cur, nvc, pad;
   double init_rr, rr, ff;
   unsigned long long t_done;
 };
@@ -229,7 +229,7 @@ double wall_clock_khz(int device);
 
 // Opt-in HIP-event timing of every launch of the solver's kernels, by kind.
 enum KernelKind { KK_AP = 0, KK_RESID = 1, KK_FIN1 = 2, KK_UP2 = 3, KK_FIN2 = 4, KK_SPMV = 5, KK_LIFT = 6,
-                  KK_COEF = 7, KK_MG = 8, KK_COUNT = 9 };
+                  KK_COEF = 7, KK_MG = 8, KK_MG_PRE = 9, KK_MG_POST = 10, KK_COUNT = 11 };
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;

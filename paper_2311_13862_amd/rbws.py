@@ -42,7 +42,7 @@ class ProblemDesc(C.Structure):
 
 class SolveStat(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer_iters", C.c_int), ("extra_spmv", C.c_int),
-                ("status", C.c_int), ("init_used", C.c_int), ("pad", C.c_int),
+                ("status", C.c_int), ("init_used", C.c_int), ("vcycles", C.c_int),
                 ("init_rr", C.c_double), ("final_rr", C.c_double), ("ff", C.c_double),
                 ("t_done_ms", C.c_double)]
 
@@ -219,7 +219,7 @@ def exact_dots(x, y, flags: int = 0, stream=None) -> np.ndarray:
 
 
 def stats_to_dicts(st, n: int) -> List[dict]:
-    return [{k: getattr(st[i], k) for k, _ in SolveStat._fields_ if k != "pad"} for i in range(n)]
+    return [{k: getattr(st[i], k) for k, _ in SolveStat._fields_} for i in range(n)]
 
 
 def solve(problems: Sequence[Problem], mu, opts: SolveOpts, problem_of=None, bases=None,
@@ -439,7 +439,8 @@ def pack_params(layers) -> np.ndarray:
     return np.concatenate([np.concatenate([np.asarray(W).ravel(), np.asarray(b).ravel()]) for W, b in layers])
 
 
-KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs", "mg_vcycle")
+KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs", "mg_vcycle",
+                "mg_pre0", "mg_post0")
 
 
 def profile(enable: bool, reset: bool = True):
