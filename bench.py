@@ -305,7 +305,7 @@ def mg_post0_bytes(n):
 
 
 KERNEL_SOURCES = ("fast.hpp", "ir.hip", "mg.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweeps_octants128_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp32ir_mg_kernels_octants128_traffic.txt")
 
 
 def kernel_sources_hash():
