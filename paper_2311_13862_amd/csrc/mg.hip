@@ -986,6 +986,52 @@ __device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const 
     }                                                                                   \
   }
 
+// The post-smoothing keeps fewer registers (four waves per SIMD instead of
+// three): only d, 1/d and the z codes are cached; the face coefficients of
+// the stencil come from the class table in LDS.  The values are the same.
+struct DCache32 {
+  int key, czn, czm, czp;
+  float dg[4], inv[4];
+  float hinv;
+};
+__device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const float* kt, int key) {
+  C.czn = key & 255;
+  C.czm = (key >> 8) & 255;
+  C.czp = key >> 16;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    float kk[6];
+    quad_kappa<float>(G, kt, e, C.czn, C.czm, C.czp, kk);
+    C.dg[e] = diag6T<float>(kk);
+    C.inv[e] = 1.0f / C.dg[e];
+  }
+  C.hinv = 1.0f;
+  if (G.hi != 0) {
+    const float hd = ((((kt[G.hb[0] + C.czn] + kt[G.hb[1] + C.czn]) + kt[G.hb[2] + C.czn]) + kt[G.hb[3] + C.czn]) +
+                      kt[G.hb[4] + C.czm]) +
+                     kt[G.hb[4] + C.czp];
+    C.hinv = 1.0f / hd;
+  }
+  C.key = key;
+}
+#define MG0_STENCIL_LDS(C, um, uc, un, pl, q)                                           \
+  {                                                                                     \
+    const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];                                \
+    const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];                               \
+    _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
+      float kk[6];                                                                      \
+      quad_kappa<float>(G, kt, e, C.czn, C.czm, C.czp, kk);                             \
+      float a = C.dg[e] * uc[e];                                                        \
+      a = fmaf(-kk[0], e > 0 ? uc[e - 1] : left, a);                                    \
+      a = fmaf(-kk[1], e < 3 ? uc[e + 1] : right, a);                                   \
+      a = fmaf(-kk[2], pl[mrow - QS + e], a);                                           \
+      a = fmaf(-kk[3], pl[mrow + QS + e], a);                                           \
+      a = fmaf(-kk[4], um[e], a);                                                       \
+      a = fmaf(-kk[5], un[e], a);                                                       \
+      q[e] = a;                                                                         \
+    }                                                                                   \
+  }
+
 template <bool VEC, bool ML>
 __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                     const int* __restrict__ cnt, int ntiles,
@@ -1063,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
 }
 
 template <bool VEC, bool ML>
-__global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ items, const int* __restrict__ list,
+__global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                      const int* __restrict__ cnt, int ntiles,
                                                      const SolveDev* __restrict__ sd,
                                                      const ProbDev* __restrict__ pd, const float* __restrict__ kap,
@@ -1148,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
       h.r = R[(long long)(k - 1) * n2 + hoff];
       taps(ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc, hI0, h.za, h.zb);
     };
-    KCache32 C;
+    DCache32 C;
     InvCache32 Ci;
     C.key = Ci.key = -1;
     // e2 = e1 + P_x ezy of the own quad at plane k (e1 = omega r (1/d))
@@ -1184,7 +1230,7 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
       RawH hn;
       load_h(k + 1, hn);
       const int key = zkey_at(k);
-      if (key != C.key) kc_fill(C, G, kt, key);
+      if (key != C.key) dc_fill(C, G, kt, key);
       e2_quad(k + 1, qn, un);
       float* pl = plane + buf * QPLANE;
 #pragma unroll
@@ -1193,7 +1239,7 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
       __syncthreads();
       if (nv > 0) {
         float q[4], so[4];
-        MG0_STENCIL(C, um, uc, un, pl, q)
+        MG0_STENCIL_LDS(C, um, uc, un, pl, q)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);
@@ -1221,6 +1267,7 @@ __global__ __launch_bounds__(256) void k_mg_post0_32(const int2* __restrict__ it
   }
 }
 #undef MG0_STENCIL
+#undef MG0_STENCIL_LDS
 #undef MG0_ITEM_SETUP
 
 // ---------------------------------------------------------------------------
