@@ -541,28 +541,47 @@ __global__ void k_mg_factor(MgLv C, double* __restrict__ Lall, int* __restrict__
   }
 }
 
-// e = A_c^{-1} b by the stored factor (FP64 arithmetic), one thread per listed solve
+// e = A_c^{-1} b by the stored factor (FP64 arithmetic), one wave per listed
+// solve.  The factor is staged in LDS; lane i holds unknown i, and the chains
+// of the two triangular solves (fma over ascending k, then the division) run
+// on values broadcast from the lanes that own them, in the same order as a
+// sequential solve.
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+
 template <typename T>
-__global__ void k_mg_coarse(MgLv C, MgList ml, const double* __restrict__ Lall, const T* __restrict__ b,
-                            T* __restrict__ e) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= *ml.cnt) return;
-  const int t = ml.list[w];
+__global__ __launch_bounds__(64) void k_mg_coarse(MgLv C, MgList ml, const double* __restrict__ Lall,
+                                                  const T* __restrict__ b, T* __restrict__ e) {
+  __shared__ double Ls[27 * 27];
+  if ((int)blockIdx.x >= *ml.cnt) return;  // uniform over the block
+  const int lane = threadIdx.x;
+  const int t = ml.list[blockIdx.x];
   const int mc = (int)C.ndof;
   const double* L = Lall + (long long)t * mc * mc;
   const long long off = C.voff ? C.voff[t] : (long long)t * C.ndof;
-  double y[27], x[27];
+  for (int x = lane; x < mc * mc; x += 64) Ls[x] = L[x];
+  const double bl = lane < mc ? (double)b[off + lane] : 0.0;
+  __syncthreads();
+  double yv = 0.0;  // y[lane]
   for (int i = 0; i < mc; i++) {
-    double s = (double)b[off + i];
-    for (int k = 0; k < i; k++) s = __fma_rn(-L[i * mc + k], y[k], s);
-    y[i] = s / L[i * mc + i];
+    const double Li = lane < mc ? Ls[i * mc + lane] : 0.0;  // row i: L[i][lane]
+    double sacc = lane_bcast(bl, i);
+    for (int k = 0; k < i; k++) sacc = __fma_rn(-lane_bcast(Li, k), lane_bcast(yv, k), sacc);
+    const double yi = sacc / lane_bcast(Li, i);
+    if (lane == i) yv = yi;
   }
+  double xv = 0.0;  // x[lane]
   for (int i = mc - 1; i >= 0; i--) {
-    double s = y[i];
-    for (int k = i + 1; k < mc; k++) s = __fma_rn(-L[k * mc + i], x[k], s);
-    x[i] = s / L[i * mc + i];
+    const double Lc = lane < mc ? Ls[lane * mc + i] : 0.0;  // column i: L[lane][i]
+    double sacc = lane_bcast(yv, i);
+    for (int k = i + 1; k < mc; k++) sacc = __fma_rn(-lane_bcast(Lc, k), lane_bcast(xv, k), sacc);
+    const double xi = sacc / lane_bcast(Lc, i);
+    if (lane == i) xv = xi;
   }
-  for (int i = 0; i < mc; i++) e[off + i] = (T)x[i];
+  if (lane < mc) e[off + lane] = (T)xv;
 }
 
 // ---------------------------------------------------------------------------
@@ -1508,7 +1527,7 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const bool l0 = l == 0;
   const MgLv v = view(lv, g, l0, m->fp32);
   if (l + 1 == (int)g.lv.size()) {
-    hipLaunchKernelGGL(k_mg_coarse<T>, dim3((ns + 63) / 64), dim3(64), 0, s, v, ml, (const double*)g.L.ptr, b, e);
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(ns), dim3(64), 0, s, v, ml, (const double*)g.L.ptr, b, e);
     return;
   }
   const dim3 grid(grid_for((long long)ns * ((lv.ndof + 255) / 256)));
