@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--ntrain", type=int, default=1024)
     ap.add_argument("--N", type=int, default=40)
     ap.add_argument("--eta", type=float, default=0.1)
+    ap.add_argument("--mg-omega", type=float, default=0.9,
+                    help="Jacobi weight of the V-cycle's smoother (0.9: fewest iterations at 128^3)")
     ap.add_argument("--precond", choices=("mg", "jacobi"), default="mg",
                     help="P of Alg. 1: the multigrid V-cycle of Alg. 2 (default) or Jacobi")
     ap.add_argument("--no-cpu", action="store_true")
@@ -97,7 +99,7 @@ def main():
 
     opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                              eta_inner=args.eta, init=rbws.INIT_RB, lift=rbws.LIFT_MFMA,
-                             ir_mode=rbws.IR_RELIABLE)
+                             ir_mode=rbws.IR_RELIABLE, mg_omega=args.mg_omega)
     # tile depth for this grid size and batch (setup, like the offline stage)
     tz, tz_ms = rbws.autotune(P, args.batch, rbws.FP32_IR)
     log(f"autotuned tile depth {tz}: {tz_ms}")
@@ -176,7 +178,8 @@ def main():
     zero_iters = None
     if not args.no_zero:
         zopts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
-                                  eta_inner=args.eta, init=rbws.INIT_ZERO, ir_mode=rbws.IR_RELIABLE)
+                                  eta_inner=args.eta, init=rbws.INIT_ZERO, ir_mode=rbws.IR_RELIABLE,
+                                  mg_omega=args.mg_omega)
         torch.cuda.synchronize()
         t = time.perf_counter()
         zst = rbws.solve([P], mu, zopts)
@@ -210,7 +213,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(spec, mu, float(np.mean(iters)), float(np.mean(outer)), args.cpu_seconds)
+        cpu = cpu_baseline(spec, mu, float(np.mean(iters)), float(np.mean(outer)), args.cpu_seconds, args.mg_omega)
         log(f"cpu baseline: {cpu}")
 
     line = {
@@ -228,7 +231,7 @@ def main():
         "data": "synthetic (seeded parameters)",
         "config": {"workload": "octants8-128^3-fp32ir-rbws", "n": spec.n, "batch": args.batch,
                    "rb_dim": basis.N, "n_train": args.ntrain, "tol": wl.tol, "precond": "mg-vcycle" if args.precond == "mg" else "jacobi",
-                   "eta_inner": args.eta, "refinement": "reliable-update", "init": "rb",
+                   "eta_inner": args.eta, "mg_omega": args.mg_omega, "refinement": "reliable-update", "init": "rb",
                    "lift": "mfma", "parallelism": "none"},
         "all_converged": bool(ok),
         "max_final_relres": float(relres.max()),
@@ -277,7 +280,7 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
     cerr = np.linalg.norm(c_nn - c_rb, axis=1) / np.linalg.norm(c_rb, axis=1)
     opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                              eta_inner=args.eta, init=rbws.INIT_LEARNED, lift=rbws.LIFT_MFMA,
-                             ir_mode=rbws.IR_RELIABLE, fallback=0)
+                             ir_mode=rbws.IR_RELIABLE, fallback=0, mg_omega=args.mg_omega)
     torch.cuda.synchronize()
     t = time.perf_counter()
     st = rbws.solve([P], mu, opts, bases=[basis], mlps=[net])
@@ -333,7 +336,7 @@ def traffic_per_launch(kernel):
     return float(v) if v else None
 
 
-def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s):
+def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s, omega):
     """The oracle's own solver for the same method on the host cores, on a
     bounded sample: `cores` parameters in parallel (one per thread), each for a
     capped number of iterations; the per-solve cost is scaled to the GPU's mean
@@ -348,7 +351,7 @@ def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s):
 
     def run(ms, cap, threads):
         if mg:
-            O.mgcg_batch(ms, tol=1e-30, maxit=cap, nthreads=threads)
+            O.mgcg_batch(ms, tol=1e-30, maxit=cap, nthreads=threads, omega=omega)
         else:
             O.ir_batch(ms, prec=oracle.PREC_JACOBI, tol=1e-10, eta=1e-30, kin_max=cap, max_outer=1,
                        nthreads=threads, reliable=True)
