@@ -353,10 +353,13 @@ rbws_status rbws_exact_fallbacks(long long* counts, int reset);
  * RBWS_TUNE_SWEEP32, value bit 0 / bit 1: the FP32 A.p / update sweeps keep
  * their face coefficients in registers (1) or look them up per plane (0).
  * RBWS_TUNE_GRID: the sweeps launch one workgroup per work item (0, default)
- * or a persistent grid of one full occupancy that loops over the items (1). */
-enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1 };
+ * or a persistent grid of one full occupancy that loops over the items (1).
+ * RBWS_TUNE_TZ: tile depth of every later batch, a power of two in [4, 64],
+ * or 0 (default) for the autotuner's choice or the built-in rule. */
+enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1, RBWS_TUNE_TZ = 2 };
 rbws_status rbws_set_tuning(int key, int value);
-/* Tile autotuner.  Work items are 32 x 32 grid columns by TZ planes; a
+/* Tile autotuner.  Work items are tiles of 1024 grid columns (32 x 32, or a
+ * whole row when 32 < n <= 128) by TZ planes; a
  * deeper tile re-reads fewer halo planes, a shallower one gives more items
  * to spread over the 256 compute units.  Times y = A(mu) x for `nsolve` solves
  * of problem p (precision RBWS_FP64 or RBWS_FP32_IR) at TZ = 4, 8, ..., 64 and

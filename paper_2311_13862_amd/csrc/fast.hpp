@@ -19,10 +19,14 @@
 
 namespace rbws {
 
-constexpr int QX = 32, QY = 32;                 // tile columns (x, y)
-constexpr int QS = 36;                          // LDS row stride (elements)
-constexpr int QROWS = QY + 2;                   // rows with the two halo rows
-constexpr int QPLANE = QROWS * QS + 2 * QROWS;  // plane buffer: rows + left/right halo columns
+// Tile shapes: 4 x-points per thread, TPR threads per row, 256 / TPR rows.
+// TPR = 8 (32 x 32 columns, halo on all four sides) in general; when one
+// tile spans a whole row (32 < n <= 128: TPR 16 or 32, 64 x 16 or 128 x 8
+// columns) there is no x-halo and the y-halo rows are contiguous.
+constexpr int QX = 32, QY = 32;  // the general shape
+// LDS plane: (rows + 2) rows of stride TX + 4, then the left and right halo
+// columns; sized for the largest shape (128 x 8: 10 * 132 + 20).
+constexpr int QPLANE = 1340;
 
 // Persistent grid over a work list: blocks are dealt round-robin to the 8
 // XCDs, so every XCD takes a contiguous share of the list and the tiles of
@@ -102,6 +106,10 @@ struct QuadGeo {
   // halo point of this thread (threads 0..127), -1 when none / outside
   int hslot, hi, hj;
   int hb[6];                // the halo point's six face bases (x-,x+,y-,y+ with node z code, z)
+  // LDS plane layout: row stride, this thread's quad, the left/right halo
+  // slots of its row, the last lane of a row, whether x-halo columns exist
+  int qs, mrow, hl, hr, lxm;
+  bool hx;
   // packed z class codes czn | czm << 8 | czp << 16 of the planes kb-1 .. ke+1
   // (index k - kb + 1), staged in LDS by zk_stage
   const int* zk;
@@ -117,9 +125,16 @@ __device__ __forceinline__ void quad_geo(QuadGeo& G, const ProbDev& P, int tile)
   G.n = n;
   const int tx = tile % P.ntx, ty = (tile / P.ntx) % P.nty, tz = tile / (P.ntx * P.nty);
   const int t = threadIdx.x;
-  G.lx = t & 7;
-  G.ly = t >> 3;
-  const int i0 = tx * QX + 1, j0 = ty * QY + 1;
+  const int TX = P.TX, TY = P.TY, tpr = TX >> 2, rows = TY + 2;
+  G.lx = t & (tpr - 1);
+  G.ly = t / tpr;
+  G.lxm = tpr - 1;
+  G.qs = TX + 4;
+  G.mrow = (G.ly + 1) * G.qs + 4 * G.lx;
+  G.hl = rows * G.qs + G.ly + 1;
+  G.hr = rows * G.qs + rows + G.ly + 1;
+  G.hx = P.ntx > 1 || TX == QX;
+  const int i0 = tx * TX + 1, j0 = ty * TY + 1;
   G.i = i0 + 4 * G.lx;
   G.j = j0 + G.ly;
   G.nv = G.j <= n ? max(0, min(4, n - G.i + 1)) : 0;
@@ -142,16 +157,27 @@ __device__ __forceinline__ void quad_geo(QuadGeo& G, const ProbDev& P, int tile)
     G.byp[e] = oY + (cxn * N1 + cyp) * N2;
     G.bz[e] = oZ + (cxn * N1 + cyn) * N2;
   }
-  // halo: threads 0-31 row j0-1, 32-63 row j0+QY, 64-95 column i0-1, 96-127 column i0+QX
+  // halo.  32 x 32: threads 0-31 row j0-1, 32-63 row j0+TY, 64-95 column i0-1,
+  // 96-127 column i0+TX.  Whole-row tiles: threads 0..TX-1 row j0-1, TX..2TX-1
+  // row j0+TY (the x-halo lies outside the grid and is never read).
   G.hslot = -1;
   G.hi = G.hj = 0;
-  if (t < 128) {
-    const int side = t >> 5, o = t & 31;
-    int hi, hj, slot;
-    if (side == 0) { hi = i0 + o; hj = j0 - 1; slot = o; }
-    else if (side == 1) { hi = i0 + o; hj = j0 + QY; slot = (QROWS - 1) * QS + o; }
-    else if (side == 2) { hi = i0 - 1; hj = j0 + o; slot = QROWS * QS + 1 + o; }
-    else { hi = i0 + QX; hj = j0 + o; slot = QROWS * QS + QROWS + 1 + o; }
+  int hi = 0, hj = 0, slot = -1;
+  if (TX == QX) {
+    if (t < 128) {
+      const int side = t >> 5, o = t & 31;
+      if (side == 0) { hi = i0 + o; hj = j0 - 1; slot = o; }
+      else if (side == 1) { hi = i0 + o; hj = j0 + TY; slot = (rows - 1) * G.qs + o; }
+      else if (side == 2) { hi = i0 - 1; hj = j0 + o; slot = rows * G.qs + 1 + o; }
+      else { hi = i0 + TX; hj = j0 + o; slot = rows * G.qs + rows + 1 + o; }
+    }
+  } else if (t < 2 * TX) {
+    const int o = t % TX;
+    hi = i0 + o;
+    if (t < TX) { hj = j0 - 1; slot = o; }
+    else { hj = j0 + TY; slot = (rows - 1) * G.qs + o; }
+  }
+  if (slot >= 0) {
     // points outside the grid keep the value 0; the slot is still written
     G.hslot = slot;
     if (hi >= 1 && hi <= n && hj >= 1 && hj <= n) {
@@ -297,8 +323,8 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
   for (int e = 0; e < 4; e++) xo[e] = ro[e] = T(0);
   xr_load(G.kb, xo, ro);
   int buf = 0;
-  const int mrow = (G.ly + 1) * QS + 4 * G.lx;
-  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+  const int mrow = G.mrow;
+  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     // issue the next loads
     quad_load(k + 2, ra, rb);
@@ -315,8 +341,8 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
     __syncthreads();
     if (nv > 0) {
       const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
-      const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
-      const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+      const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
+      const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
       T qo[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
@@ -325,7 +351,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         const T dg = diag6T<T>(kk);
         const T xm = e > 0 ? pc[e - 1] : left;
         const T xp = e < 3 ? pc[e + 1] : right;
-        const T ym = pl[mrow - QS + e], yp = pl[mrow + QS + e];
+        const T ym = pl[mrow - G.qs + e], yp = pl[mrow + G.qs + e];
         T q = dg * pc[e];
         q = fmaT(-kk[0], xm, q);
         q = fmaT(-kk[1], xp, q);
@@ -511,8 +537,8 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
   for (int e = 0; e < 4; e++) xo[e] = ro[e] = 0.0f;
   xr_load(G.kb, xo, ro);
   int buf = 0;
-  const int mrow = (G.ly + 1) * QS + 4 * G.lx;
-  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+  const int mrow = G.mrow;
+  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     quad_load(k + 2, ra, rb);
     float ha2, hb2, xo2[4], ro2[4];
@@ -535,14 +561,14 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
     }
     __syncthreads();
     if (nv > 0) {
-      const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
-      const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+      const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
+      const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
       float qo[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         const float xm = e > 0 ? pc[e - 1] : left;
         const float xp = e < 3 ? pc[e + 1] : right;
-        const float ym = pl[mrow - QS + e], yp = pl[mrow + QS + e];
+        const float ym = pl[mrow - G.qs + e], yp = pl[mrow + G.qs + e];
         float q = C.dg[e] * pc[e];
         q = fmaf(-C.kx[e], xm, q);
         q = fmaf(-C.kx[e + 1], xp, q);
@@ -627,8 +653,8 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
   quad_u(G.kb, uc);
   double hv = halo_u(G.kb);
   int buf = 0;
-  const int mrow = (G.ly + 1) * QS + 4 * G.lx;
-  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+  const int mrow = G.mrow;
+  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     quad_u(k + 1, un);
     const double hv2 = halo_u(k + 1);
@@ -639,8 +665,8 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
     __syncthreads();
     if (nv > 0) {
       const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
-      const double left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
-      const double right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+      const double left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
+      const double right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
       float ro[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
@@ -651,8 +677,8 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
         double q = diag6T<double>(kk) * uc[e];
         q = __fma_rn(-kk[0], xm, q);
         q = __fma_rn(-kk[1], xp, q);
-        q = __fma_rn(-kk[2], pl[mrow - QS + e], q);
-        q = __fma_rn(-kk[3], pl[mrow + QS + e], q);
+        q = __fma_rn(-kk[2], pl[mrow - G.qs + e], q);
+        q = __fma_rn(-kk[3], pl[mrow + G.qs + e], q);
         q = __fma_rn(-kk[4], um[e], q);
         q = __fma_rn(-kk[5], un[e], q);
         ro[e] = 0.0f;

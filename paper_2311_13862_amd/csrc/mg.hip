@@ -687,8 +687,8 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
     quad_e1(G.kb - 1, bm, um);
     quad_e1(G.kb, bc, uc);
     int buf = 0;
-    const int mrow = (G.ly + 1) * QS + 4 * G.lx;
-    const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+    const int mrow = G.mrow;
+    const int hl = G.hl, hr = G.hr;
     for (int k = G.kb; k <= G.ke; k++) {
       load_b(k + 2, bnn);
       const T hbn = load_hb(k + 1);
@@ -702,8 +702,8 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
       if (nv > 0) {
         const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
-        const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
-        const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+        const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
+        const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
         T to[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -713,8 +713,8 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
           T q = dg * uc[e];
           q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
           q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
-          q = fmaT(-kk[2], pl[mrow - QS + e], q);
-          q = fmaT(-kk[3], pl[mrow + QS + e], q);
+          q = fmaT(-kk[2], pl[mrow - G.qs + e], q);
+          q = fmaT(-kk[3], pl[mrow + G.qs + e], q);
           q = fmaT(-kk[4], um[e], q);
           q = fmaT(-kk[5], un[e], q);
           to[e] = bc[e] - q;
@@ -886,8 +886,8 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     DotAcc<T> acc;
     acc.zero();
     int buf = 0;
-    const int mrow = (G.ly + 1) * QS + 4 * G.lx;
-    const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;
+    const int mrow = G.mrow;
+    const int hl = G.hl, hr = G.hr;
     for (int k = G.kb; k <= G.ke; k++) {
       load_q(k + 2, qnn);
       RawH hn;
@@ -902,8 +902,8 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       if (nv > 0) {
         const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
-        const T left = G.lx > 0 ? pl[mrow - 1] : pl[hl];
-        const T right = G.lx < 7 ? pl[mrow + 4] : pl[hr];
+        const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
+        const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
         T so[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -913,8 +913,8 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
           T q = dg * uc[e];
           q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
           q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
-          q = fmaT(-kk[2], pl[mrow - QS + e], q);
-          q = fmaT(-kk[3], pl[mrow + QS + e], q);
+          q = fmaT(-kk[2], pl[mrow - G.qs + e], q);
+          q = fmaT(-kk[3], pl[mrow + G.qs + e], q);
           q = fmaT(-kk[4], um[e], q);
           q = fmaT(-kk[5], un[e], q);
           T t = rc[e] - q;
@@ -983,22 +983,22 @@ __device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const 
   const long long rowoff = ((long long)(G.j - 1)) * n + (G.i - 1);                      \
   const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);                      \
   const bool hin = G.hi != 0;                                                           \
-  const int mrow = (G.ly + 1) * QS + 4 * G.lx;                                          \
-  const int hl = QROWS * QS + G.ly + 1, hr = QROWS * QS + QROWS + G.ly + 1;             \
+  const int mrow = G.mrow;                                          \
+  const int hl = G.hl, hr = G.hr;             \
   auto zkey_at = [&](int k) __attribute__((always_inline)) { return G.zk[k - G.kb + 1]; };
 
 // q = A u at the own quad of plane k (u of plane k in registers and LDS; the
 // planes k-1, k+1 in um, un), coefficients from the cache
 #define MG0_STENCIL(C, um, uc, un, pl, q)                                               \
   {                                                                                     \
-    const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];                                \
-    const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];                               \
+    const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);                                \
+    const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);                               \
     _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
       float a = C.dg[e] * uc[e];                                                        \
       a = fmaf(-C.kx[e], e > 0 ? uc[e - 1] : left, a);                                  \
       a = fmaf(-C.kx[e + 1], e < 3 ? uc[e + 1] : right, a);                             \
-      a = fmaf(-C.kym[e], pl[mrow - QS + e], a);                                        \
-      a = fmaf(-C.kyp[e], pl[mrow + QS + e], a);                                        \
+      a = fmaf(-C.kym[e], pl[mrow - G.qs + e], a);                                        \
+      a = fmaf(-C.kyp[e], pl[mrow + G.qs + e], a);                                        \
       a = fmaf(-C.kzm[e], um[e], a);                                                    \
       a = fmaf(-C.kzp[e], un[e], a);                                                    \
       q[e] = a;                                                                         \
@@ -1035,16 +1035,16 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
 }
 #define MG0_STENCIL_LDS(C, um, uc, un, pl, q)                                           \
   {                                                                                     \
-    const float left = G.lx > 0 ? pl[mrow - 1] : pl[hl];                                \
-    const float right = G.lx < 7 ? pl[mrow + 4] : pl[hr];                               \
+    const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);                                \
+    const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);                               \
     _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
       float kk[6];                                                                      \
       quad_kappa<float>(G, kt, e, C.czn, C.czm, C.czp, kk);                             \
       float a = C.dg[e] * uc[e];                                                        \
       a = fmaf(-kk[0], e > 0 ? uc[e - 1] : left, a);                                    \
       a = fmaf(-kk[1], e < 3 ? uc[e + 1] : right, a);                                   \
-      a = fmaf(-kk[2], pl[mrow - QS + e], a);                                           \
-      a = fmaf(-kk[3], pl[mrow + QS + e], a);                                           \
+      a = fmaf(-kk[2], pl[mrow - G.qs + e], a);                                           \
+      a = fmaf(-kk[3], pl[mrow + G.qs + e], a);                                           \
       a = fmaf(-kk[4], um[e], a);                                                       \
       a = fmaf(-kk[5], un[e], a);                                                       \
       q[e] = a;                                                                         \

@@ -137,7 +137,9 @@ struct TileEntry {
   int n, bucket, tz;
 };
 static std::vector<TileEntry> g_tiles;
-static int g_force_tz = 0;
+static int g_force_tz = 0;  // set by the autotuner while it times a candidate
+static int g_user_tz = 0;   // set by the caller (RBWS_TUNE_TZ); 0: automatic
+void set_tile_depth(int tz) { g_user_tz = tz; }
 static int count_bucket(long long c) {
   int b = 0;
   while ((2LL << b) <= std::max(1LL, c)) b++;
@@ -145,10 +147,11 @@ static int count_bucket(long long c) {
 }
 
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ) {
-  *TX = QX;
-  *TY = QY;
-  if (g_force_tz > 0) {
-    *TZ = std::min(g_force_tz, n);
+  // one tile spans the whole row when 32 < n <= 128 (no x-halo, contiguous y-halo rows)
+  *TX = n > 128 || n <= 32 ? QX : (n > 64 ? 128 : 64);
+  *TY = 1024 / *TX;
+  if (g_force_tz > 0 || g_user_tz > 0) {
+    *TZ = std::min(g_force_tz > 0 ? g_force_tz : g_user_tz, n);
     return;
   }
   const int bk = count_bucket(nsolve_of_this_size);
@@ -157,7 +160,7 @@ void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ
       *TZ = std::min(e.tz, n);
       return;
     }
-  const long long cols = (long long)((n + QX - 1) / QX) * ((n + QY - 1) / QY) * std::max(1LL, nsolve_of_this_size);
+  const long long cols = (long long)((n + *TX - 1) / *TX) * ((n + *TY - 1) / *TY) * std::max(1LL, nsolve_of_this_size);
   int tz = 64;
   while (tz > 4 && cols * ((n + tz - 1) / tz) < 4096) tz /= 2;
   *TZ = std::min(tz, n);

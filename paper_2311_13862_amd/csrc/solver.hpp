@@ -104,12 +104,15 @@ struct Batch {
   ~Batch();
 };
 
-// tiles: 32 x 32 grid columns (256 threads, 4 points each) by TZ planes; TZ
-// is the largest power of two in [4, 64] that still gives >= 4096 work items
+// tiles: 256 threads of 4 x-points each, 32 x 32 grid columns, or a whole row
+// (64 x 16, 128 x 8) when 32 < n <= 128, by TZ planes; TZ is the largest power
+// of two in [4, 64] that still gives >= 4096 work items
 void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ);
 // autotuner of the tile depth (see solver.hip); its choices override the rule above
 int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, double* ms);
 void clear_tile_table();
+// fixed tile depth for every later batch (a power of two in [4, 64]), 0: automatic
+void set_tile_depth(int tz);
 
 // Lists with every item on the residual list and the others empty (stream-ordered)
 Lists lists_init(Batch& B, hipStream_t s);
