@@ -100,12 +100,17 @@ def main():
     opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
                              eta_inner=args.eta, init=rbws.INIT_RB, lift=rbws.LIFT_MFMA,
                              ir_mode=rbws.IR_RELIABLE, mg_omega=args.mg_omega)
+    # launches are counted by kind from here on, so that a profiler's per-dispatch
+    # records of the timed step can be told apart from those of the set-up below
+    rbws.profile(True, reset=True)
     # tile depth for this grid size and batch (setup, like the offline stage)
     tz, tz_ms = pick_tile_depth(rbws, torch, P, mu, args)
     log(f"tile depth {tz}: {tz_ms}")
     if args.counters:
         # rocprofv3 counter run: one step as timed below, then a plain copy of known size
+        pre = rbws.profile(True, reset=True)
         st = solve_step(rbws, P, basis, mu, opts)
+        stp = rbws.profile(False, reset=True)
         it = np.array([s["iters"] for s in st])
         ou = np.array([s["outer_iters"] for s in st])
         vc = float(np.sum([s["vcycles"] for s in st]))
@@ -119,13 +124,15 @@ def main():
                           "ap_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
                           "mg_pre0_algorithmic_bytes": vc * MG_PRE0_BYTES * P.ndof,
                           "mg_post0_algorithmic_bytes": vc * mg_post0_bytes(spec.n) * P.ndof,
+                          "launches_before_step": {k: v[1] for k, v in pre.items()},
+                          "launches_step": {k: v[1] for k, v in stp.items()},
                           "sources_sha256": kernel_sources_hash()}), flush=True)
         return
 
     for w in range(args.warmup):
         solve_step(rbws, P, basis, mu, opts)
         log(f"warmup step {w + 1} done")
-    rbws.profile(True, reset=True)
+    pre = rbws.profile(True, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
@@ -251,6 +258,8 @@ def main():
         "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()},
                        "picked_by": "short solves of half the batch at each depth"},
         "kernel_ms": {k: round(v, 2) for k, v in ms.items()},
+        "kernel_launches": n_launch,
+        "launches_before_timed_step": {k: v[1] for k, v in pre.items()},
         "copy_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
