@@ -122,7 +122,7 @@ def main():
                           "copy_bytes_written": b.numel() * 8,
                           "up2_algorithmic_bytes": float(np.sum(it * 20 - ou * 4)) * P.ndof,
                           "ap_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
-                          "mg_pre0_algorithmic_bytes": vc * MG_PRE0_BYTES * P.ndof,
+                          "mg_pre0_algorithmic_bytes": vc * mg_pre0_bytes(spec.n) * P.ndof,
                           "mg_post0_algorithmic_bytes": vc * mg_post0_bytes(spec.n) * P.ndof,
                           "launches_before_step": {k: v[1] for k, v in pre.items()},
                           "launches_step": {k: v[1] for k, v in stp.items()},
@@ -169,8 +169,8 @@ def main():
     vcyc = np.array([s["vcycles"] for s in stats])
     alg = {"up2_sweep": args.steps * float(np.sum(iters * 20 - outer * 4)) * nd,  # R p, d, r; W d, r (FP32)
            "ap_sweep": args.steps * float(np.sum(iters * 12 - outer * 4)) * nd,   # R s, p_old; W p_new
-           # V-cycle, finest level (FP32): R b, W t; and R r, R ezy, W s
-           "mg_pre0": args.steps * float(np.sum(vcyc)) * MG_PRE0_BYTES * nd,
+           # V-cycle, finest level (FP32): R b, W x-sums of t; and R r, R ezy, W s
+           "mg_pre0": args.steps * float(np.sum(vcyc)) * mg_pre0_bytes(spec.n) * nd,
            "mg_post0": args.steps * float(np.sum(vcyc)) * mg_post0_bytes(spec.n) * nd}
     ms = {k: v[0] for k, v in kern.items()}
     n_launch = {k: v[1] for k, v in kern.items()}
@@ -331,7 +331,11 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
             "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
 
 
-MG_PRE0_BYTES = 8.0  # per finest-level point: read b, write t = b - A e1 (FP32)
+def mg_pre0_bytes(n):
+    """Per finest-level point: read b (FP32) and write the restriction's x-sums
+    of t = b - A e1 (n x n rows of nc = (n-1)//2 values per solve): the path
+    for tiles that span whole rows (n <= 128)."""
+    return 4.0 + 4.0 * ((n - 1) // 2) / n
 
 
 def mg_post0_bytes(n):

@@ -269,6 +269,76 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgLv F, MgLv C, MgList ml, 
   }
 }
 
+// The y/z part alone, when the fine level's pre-smoothing has already formed
+// the x-sums ax[k][j][I] (fine rows of n_c values, group layout): per fine
+// plane the rows of the quad's y-span go to LDS (loaded one plane ahead), then
+// the same y and z chains as above.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_restrict_yz(MgLv F, MgLv C, MgList ml, const int* __restrict__ ci,
+                                                        const T* __restrict__ cw, const int2* __restrict__ lohi,
+                                                        const T* __restrict__ tx, T* __restrict__ bc, T scale) {
+  __shared__ T axs[2][kRsRows][64];
+  const int nc = C.n, nf = F.n;
+  const int ich = (nc + 63) >> 6, jq = (nc + 3) >> 2, nseg = (nc + kRsSeg - 1) / kRsSeg;
+  const int cols = jq * ich, per = nseg * cols;  // (segment, J quad, I chunk) items per solve
+  const ItemRange R = item_range(*ml.cnt * per);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long nc2 = (long long)nc * nc, fplane = (long long)nf * nc;
+  for (int w = R.w; w < R.w1; w += R.step) {
+    const int t = ml.list[w / per];
+    const int rem = w % per, sg = rem / cols, rc = rem % cols;
+    const int Jq0 = (rc / ich) * 4 + 1, Iq0 = (rc % ich) * 64 + 1;
+    const int J = Jq0 + wv, I = Iq0 + lane;
+    const bool act = J <= nc && I <= nc;
+    const int Jl = min(Jq0 + 3, nc);
+    const int jr0 = lohi[Jq0].x, nr = lohi[Jl].y - jr0 + 1;  // staged fine rows
+    const int Ks = sg * kRsSeg + 1, Ke = min(nc, Ks + kRsSeg - 1);
+    const int k0 = lohi[Ks].x, k1 = lohi[Ke].y;
+    T wy[kSpan];
+    const int Ic = min(I, nc), Jc = min(J, nc);
+    const int yo = fine_weights(Jc, ci, cw, lohi, wy) - jr0, yn = lohi[Jc].y - lohi[Jc].x + 1;
+    const T* src = tx + (long long)t * nf * fplane + (long long)(jr0 - 1) * nc + (Ic - 1);
+    T* out = bc + (C.voff ? C.voff[t] : (long long)t * C.ndof) + (long long)(Jc - 1) * nc + (Ic - 1);
+    T st[kRsRows / 4];
+    auto load = [&](int k) __attribute__((always_inline)) {
+      const T* p = src + (long long)(k - 1) * fplane;
+#pragma unroll
+      for (int m = 0; m < kRsRows / 4; m++) {
+        const int r = wv + 4 * m;
+        st[m] = (r < nr && I <= nc) ? p[(long long)r * nc] : T(0);
+      }
+    };
+    int Kc = ci[k0 - 1];
+    T accA = T(0), accB = T(0);
+    load(k0);
+    int buf = 0;
+    for (int k = k0; k <= k1; k++) {
+#pragma unroll
+      for (int m = 0; m < kRsRows / 4; m++) axs[buf][wv + 4 * m][lane] = st[m];
+      if (k < k1) load(k + 1);
+      __syncthreads();
+      const int K0 = ci[k - 1];
+      const T wz = cw[k - 1];
+      if (K0 != Kc) {
+        if (act && Kc >= Ks) out[(Kc - 1) * nc2] = accA * scale;
+        accA = accB;
+        accB = T(0);
+        Kc = K0;
+      }
+      T ay = T(0);
+#pragma unroll
+      for (int u = 0; u < kSpan; u++)
+        if (u < yn) ay = fmaT(wy[u], axs[buf][yo + u][lane], ay);
+      if (K0 >= 1) accA = fmaT(T(1) - wz, ay, accA);
+      if (K0 + 1 <= nc) accB = fmaT(wz, ay, accB);
+      buf ^= 1;
+    }
+    if (act && Kc >= Ks && Kc <= Ke) out[(Kc - 1) * nc2] = accA * scale;
+    if (act && Kc + 1 >= Ks && Kc + 1 <= Ke) out[Kc * nc2] = accB * scale;
+    __syncthreads();  // LDS of this item is free
+  }
+}
+
 // Prolongation, separable: first the coarse values are interpolated in z and y
 // onto the fine (k, j) rows at every coarse column I,
 //   ezy[k][j][I] = sum_cy wy (sum_cz wz e_c[K][J][I])    (fma chains from 0),
@@ -594,11 +664,12 @@ __global__ __launch_bounds__(64) void k_mg_coarse(MgLv C, MgList ml, const doubl
 // of separate prolongation, smoothing and dot passes.
 // ---------------------------------------------------------------------------
 struct MgFine {           // per problem: the z/y-interpolated level-1 correction and transfer tables
-  const void* ezy;        // group layout, t * nf * nf * nc
+  const void* ezy;        // group layout, t * nf * nf * nc (before it: the x-sums of the restriction)
   const int* ci;
   const void* cw;
   long long per;          // nf * nf * nc
   int nc, pad;
+  const int2* lohi;       // fine span of each coarse node
 };
 
 // Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
@@ -1051,22 +1122,50 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
     }                                                                                   \
   }
 
-template <bool VEC, bool ML>
+// With RX (tiles that span the whole row) the residual t is not written:
+// each fine row of it goes through LDS and the kernel writes the restriction's
+// x-sums ax[k][j][I] = sum_i px t (fma chain from 0, ascending i) into the
+// level's MgFine buffer, n_c values per row instead of n.
+template <bool VEC, bool ML, bool RX>
 __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                     const int* __restrict__ cnt, int ntiles,
                                                     const SolveDev* __restrict__ sd,
                                                     const ProbDev* __restrict__ pd, const float* __restrict__ kap,
                                                     const float* __restrict__ b, float* __restrict__ tout,
+                                                    const MgFine* __restrict__ mf, const int* __restrict__ gidx,
                                                     float omega, int ktab) {
   extern __shared__ double smem_raw[];
   float* kt = reinterpret_cast<float*>(smem_raw);
   float* plane = kt + ktab;
   __shared__ int zk[kZkLen];
+  __shared__ float trow[RX ? 2048 : 1];          // the tile's t of two planes (rows of TX)
+  __shared__ float xw[RX ? 64 : 1][kSpan];       // x weights per coarse column
+  __shared__ int xlo[RX ? 64 : 1], xnn[RX ? 64 : 1];
   const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
     const float* Bv = b + S.off;
     float* TO = tout + S.off;
+    float* txo = nullptr;
+    int nc = 0;
+    const int txw = 4 * (G.lxm + 1);  // row length of trow (the tile spans the row)
+    if constexpr (RX) {
+      const MgFine F = mf[S.prob];
+      nc = F.nc;
+      txo = (float*)F.ezy + (long long)(ML ? it.x : gidx[it.x]) * F.per;
+      const float* cw = (const float*)F.cw;
+      for (int I = threadIdx.x + 1; I <= nc; I += blockDim.x) {
+        const int2 r = F.lohi[I];
+        xlo[I - 1] = r.x;
+        xnn[I - 1] = r.y - r.x + 1;
+#pragma unroll
+        for (int u = 0; u < kSpan; u++) {
+          const int i = r.x + u;
+          xw[I - 1][u] = i <= r.y ? (F.ci[i - 1] == I ? 1.0f - cw[i - 1] : cw[i - 1]) : 0.0f;
+        }
+      }
+      __syncthreads();
+    }
     auto load_b = [&](int k, float bq[4]) __attribute__((always_inline)) {
 #pragma unroll
       for (int e = 0; e < 4; e++) bq[e] = 0.0f;
@@ -1088,6 +1187,24 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
 #pragma unroll
       for (int e = 0; e < 4; e++) out[e] = e < nv ? omega * (bq[e] * Ci.inv[e]) : 0.0f;
     };
+    // x-sums of plane k's rows from trow (buffer tb); the writes of that plane
+    // are ordered before these reads by the next plane's barrier
+    auto xsums = [&](int k, int tb) __attribute__((always_inline)) {
+      if constexpr (RX) {
+        if (G.j <= n) {
+          float* o = txo + ((long long)(k - 1) * n + (G.j - 1)) * nc;
+          const float* tr = trow + tb * 1024 + G.ly * txw - 1;
+          for (int I = G.lx + 1; I <= nc; I += G.lxm + 1) {
+            const int lo = xlo[I - 1], nn = xnn[I - 1];
+            float ax = 0.0f;
+#pragma unroll
+            for (int u = 0; u < kSpan; u++)
+              if (u < nn) ax = fmaf(xw[I - 1][u], tr[lo + u], ax);
+            o[I - 1] = ax;
+          }
+        }
+      }
+    };
     float um[4], uc[4], un[4], bm[4], bc[4], bn[4], bnn[4];
     load_b(G.kb - 1, bm);
     load_b(G.kb, bc);
@@ -1107,13 +1224,21 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
       if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hbc * C.hinv) : 0.0f;
       __syncthreads();
+      if (k > G.kb) xsums(k - 1, buf ^ 1);
       if (nv > 0) {
         float q[4], to[4];
         MG0_STENCIL(C, um, uc, un, pl, q)
 #pragma unroll
         for (int e = 0; e < 4; e++) to[e] = bc[e] - q[e];
-        st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
+        if constexpr (RX) {
+#pragma unroll
+          for (int e = 0; e < 4; e++)
+            if (e < nv) trow[buf * 1024 + G.ly * txw + 4 * G.lx + e] = to[e];
+        } else {
+          st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
+        }
       }
+
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         um[e] = uc[e];
@@ -1123,6 +1248,10 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       }
       hbc = hbn;
       buf ^= 1;
+    }
+    if constexpr (RX) {
+      __syncthreads();
+      xsums(G.ke, buf ^ 1);
     }
   }
 }
@@ -1302,6 +1431,7 @@ struct MgLevelHost {
   DevBuf vtx;                 // z/y-interpolated coarse correction (fine rows x coarse columns)
   DevBuf fine;                // MgFine of this level (levels >= 1 with a coarser level)
   bool quad = false;          // n % 4 == 0 and every vector offset a multiple of 4
+  bool rows = false;          // the level's tiles span whole rows
 };
 
 struct MgGroup {
@@ -1321,6 +1451,7 @@ struct MgRun {
   double omega = 6.0 / 7.0;
   bool fp32 = false;
   bool fused = false;  // level-0 correction + post-smoothing + r^T s in one tile kernel
+  bool rx0 = false;    // FP32 fused: level-0 tiles span whole rows, the pre-smoothing forms the x-sums
   std::vector<MgGroup*> g;
   DevBuf fine;    // MgFine per problem
   DevBuf x0, t0;  // level-0 scratch, laid out like the batch (x0 only without the fused kernels)
@@ -1494,16 +1625,23 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     f.per = (long long)g->lv[0]->n * g->lv[0]->n * g->lv[1]->n;
     f.nc = g->lv[1]->n;
     f.pad = 0;
+    f.lohi = (const int2*)g->lv[0]->lohi.ptr;
     // the same for the levels >= 1 that have a coarser level (FP32 fused path)
     for (size_t l = 1; fp32 && l + 1 < g->lv.size(); l++) {
       MgLevelHost& lv = *g->lv[l];
       MgFine fl{lv.vtx.ptr, (const int*)lv.ci.ptr, lv.cwf.ptr, (long long)lv.n * lv.n * g->lv[l + 1]->n,
-                g->lv[l + 1]->n, 0};
+                g->lv[l + 1]->n, 0, (const int2*)lv.lohi.ptr};
       RBWS_HIP(hipMemcpy(lv.fine.get(sizeof(MgFine), B.device), &fl, sizeof(MgFine), hipMemcpyHostToDevice));
     }
   }
   RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
                           hipMemcpyHostToDevice, s));
+  // tiles that span whole rows (at most 128 points, so n_c <= 63): the FP32
+  // pre-smoothing forms the restriction's x-sums itself
+  m->rx0 = fp32 && m->fused;
+  for (int q = 0; q < B.nprob; q++) m->rx0 = m->rx0 && B.pd_h[q].ntx == 1 && B.probs[q]->n <= 128;
+  for (MgGroup* g : m->g)
+    for (MgLevelHost* lv : g->lv) lv->rows = lv->B.nsolve > 0 && lv->B.pd_h[0].ntx == 1 && lv->n <= 128;
   if (!m->fused) m->x0.get(el * std::max<long long>(B.total, 1), B.device);
   RBWS_HIP(hipStreamSynchronize(s));
   return m;
@@ -1535,6 +1673,8 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const T om = (T)m->omega;
   // FP32, nu = 1, levels >= 1: fused tile kernels over every tile of the listed solves
   const bool tiles = m->fp32 && m->nu == 1 && l >= 1;
+  // the pre-smoothing kernel forms the restriction's x-sums (whole-row tiles)
+  const bool rx = l == 0 ? pre_only && m->rx0 : tiles && lv.rows;
   const int ntiles = lv.B.nsolve > 0 ? lv.B.sd_h[0].ntiles : 0;
   const int ktab = (lv.B.kap_max + 3) & ~3;
   const dim3 tgrid(8u * (unsigned)(((long long)ns * ntiles + 7) / 8));
@@ -1547,10 +1687,11 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   T* w[2] = {scratch, e};
   int wi = 0;
   if (tiles) {
-    auto k = lv.B.vec ? k_mg_pre0_32<true, true> : k_mg_pre0_32<false, true>;
+    auto k = rx ? (lv.B.vec ? k_mg_pre0_32<true, true, true> : k_mg_pre0_32<false, true, true>)
+                : (lv.B.vec ? k_mg_pre0_32<true, true, false> : k_mg_pre0_32<false, true, false>);
     hipLaunchKernelGGL(k, tgrid, dim3(256), tlds, s, (const int2*)lv.B.items.ptr, ml.list, ml.cnt, ntiles,
                        (const SolveDev*)lv.B.sd.ptr, (const ProbDev*)lv.B.pd.ptr, (const float*)lv.B.kap32.ptr,
-                       (const float*)b, (float*)tres, (float)m->omega, ktab);
+                       (const float*)b, (float*)tres, (const MgFine*)lv.fine.ptr, nullptr, (float)m->omega, ktab);
   } else if (!pre_done) {
     smooth(nullptr, w[wi]);
     for (int it = 1; it < m->nu; it++) {
@@ -1566,8 +1707,13 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const T scale = (T)((double)(cl.n + 1) / (double)(lv.n + 1));
   const long long nrs = (long long)((cl.n + kRsSeg - 1) / kRsSeg) * ((cl.n + 3) / 4) * ((cl.n + 63) / 64);
   const long long npyz = (long long)((lv.n + kPzSeg - 1) / kPzSeg) * ((lv.n + 3) / 4) * ((cl.n + 63) / 64);
-  hipLaunchKernelGGL(k_mg_restrict<T>, dim3(grid_for((long long)ns * nrs)), dim3(256), 0, s, v, cv, ml,
-                     (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
+  if (rx)
+    hipLaunchKernelGGL(k_mg_restrict_yz<T>, dim3(grid_for((long long)ns * nrs)), dim3(256), 0, s, v, cv, ml,
+                       (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)lv.vtx.ptr, (T*)cl.vb.ptr,
+                       scale);
+  else
+    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(grid_for((long long)ns * nrs)), dim3(256), 0, s, v, cv, ml,
+                       (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
   // z/y interpolation of the coarse correction (into vtx, free again after the restriction)
   hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
@@ -1601,11 +1747,12 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
   if (m->fused) {
     kt.begin(st, KK_MG_PRE);  // level 0: the residual after pre-smoothing into t0, over the tiles of the listed solves
     if (m->fp32) {
-      auto k = B.vec ? k_mg_pre0_32<true, false> : k_mg_pre0_32<false, false>;
+      auto k = m->rx0 ? (B.vec ? k_mg_pre0_32<true, false, true> : k_mg_pre0_32<false, false, true>)
+                      : (B.vec ? k_mg_pre0_32<true, false, false> : k_mg_pre0_32<false, false, false>);
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st, (const int2*)B.items.ptr,
                          (const int*)L.ap, (const int*)(L.cnt + WL_AP), 0, (const SolveDev*)B.sd.ptr,
                          (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr, (const float*)r,
-                         (float*)m->t0.ptr, (float)m->omega, ktab);
+                         (float*)m->t0.ptr, (const MgFine*)m->fine.ptr, (const int*)L.gidx, (float)m->omega, ktab);
     } else {
       auto k = B.vec ? k_mg_pre0<double, true> : k_mg_pre0<double, false>;
       hipLaunchKernelGGL(k, dim3(tgrid), dim3(256), sizeof(double) * (ktab + 2 * QPLANE), st,
