@@ -33,3 +33,14 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     lib.rbws_version.restype = ctypes.c_char_p
     assert b"gfx950" in lib.rbws_version()
+
+
+def test_tuning_knobs_validate_without_a_gpu():
+    """rbws_set_tuning checks its arguments on the host (no device call)."""
+    lib = ctypes.CDLL(LIB)
+    RBWS_TUNE_TZ, EINVAL = 2, -1
+    assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 12) == EINVAL
+    assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 128) == EINVAL
+    assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 32) == 0
+    assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 0) == 0
+    assert lib.rbws_set_tuning(99, 0) == EINVAL

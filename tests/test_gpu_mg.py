@@ -150,6 +150,42 @@ def test_mgcg_64_sample(rb):
         assert sg[b]["iters"] == so["iters"] and np.array_equal(xg[b], xo)
 
 
+@pytest.mark.parametrize("n", [72, 70])
+def test_mgcg_whole_row_tiles(rb, n):
+    """Grids with 64 < n <= 128 run on 128 x 8 tiles that span the row (vector
+    loads at n = 72, scalar row ends at n = 70; the coarse levels 35 and 34 on
+    64 x 16 tiles): FP64 MGCG trajectories bitwise equal to the oracle's."""
+    spec = W.Problem(n, W.KIND_OCTANTS)
+    P = rb.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 3, 70 + n)
+    xg, sg = gpu_mgcg(rb, [P], mu, 1e-10)
+    O = oracle.Problem(spec)
+    xo, so = O.mgcg_batch(mu, tol=1e-10)
+    for b in range(len(mu)):
+        assert sg[b]["iters"] == so[b]["iters"] and sg[b]["final_rr"] == so[b]["final_rr"]
+        assert np.array_equal(xg[b], xo[b])
+
+
+def test_tile_depth_does_not_change_results(rb):
+    """RBWS_TUNE_TZ fixes the tile depth; FP64 trajectories do not depend on it."""
+    spec = W.Problem(40, W.KIND_BLOCKS, W.BLOCKS3)
+    P = rb.Problem(spec)
+    mu = W.sample_mu(spec, 0.1, 10.0, 3, 5)
+    out = []
+    try:
+        for tz in (4, 16, 64, 0):
+            rb.set_tuning(rb.TUNE_TZ, tz)
+            out.append(gpu_mgcg(rb, [P], mu, 1e-10))
+    finally:
+        rb.set_tuning(rb.TUNE_TZ, 0)
+    x0, s0 = out[0]
+    for x, st in out[1:]:
+        assert [a["iters"] for a in st] == [a["iters"] for a in s0]
+        assert all(np.array_equal(a, b) for a, b in zip(x, x0))
+    with pytest.raises(rb.RbwsError):
+        rb.set_tuning(rb.TUNE_TZ, 12)
+
+
 @pytest.mark.parametrize("spec", [W.Problem(20, W.KIND_OCTANTS), W.Problem(33, W.KIND_BLOCKS, W.BLOCKS4)],
                          ids=["oct20", "blk33"])
 @pytest.mark.parametrize("mode", [0, 1])
