@@ -201,9 +201,10 @@ def main():
         learned = learned_leg(rbws, W, wl, spec, P, basis, mu, args)
         log(f"learned start: {learned}")
 
-    # SpMV bandwidth (64 solves at 128^3, well beyond the 256 MB infinity cache)
+    # SpMV bandwidth: 256 solves at 128^3 (2.1 GB per FP32 vector, far beyond the 256 MB
+    # last-level cache); smaller batches leave the last round of workgroups part-empty
     spmv = {}
-    nb = 64
+    nb = 256
     rbws.set_tuning(rbws.TUNE_TZ, 0)  # the SpMV takes its own autotuned depth
     spmv_tz, _ = rbws.autotune(P, nb, rbws.FP32_IR)
     for name, dt, bpd, prec in (("fp32", torch.float32, 8, rbws.FP32_IR), ("fp64", torch.float64, 16, rbws.FP64)):

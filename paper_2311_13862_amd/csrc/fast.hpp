@@ -70,6 +70,27 @@ __device__ __forceinline__ void ld4(const T* __restrict__ a, long long c, int nv
   }
 }
 
+// store of a value that is not read again soon (streamed past the caches)
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+template <typename T, bool VEC>
+__device__ __forceinline__ void st4_stream(T* __restrict__ a, long long c, int nv, const T v[4]) {
+  if (VEC && nv == 4) {
+    if constexpr (sizeof(T) == 4) {
+      const nt_f4 q = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(q, reinterpret_cast<nt_f4*>(a + c));
+    } else {
+      const nt_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+      __builtin_nontemporal_store(q0, reinterpret_cast<nt_d2*>(a + c));
+      __builtin_nontemporal_store(q1, reinterpret_cast<nt_d2*>(a + c + 2));
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      if (e < nv) __builtin_nontemporal_store(v[e], a + c + e);
+  }
+}
+
 template <typename T, bool VEC>
 __device__ __forceinline__ void st4(T* __restrict__ a, long long c, int nv, const T v[4]) {
   if (VEC && nv == 4) {
@@ -377,7 +398,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         st4<T, VEC>(X, c, nv, xo);
         st4<T, VEC>(R, c, nv, ro);
       }
-      if (OP == FOP_SPMV) st4<T, VEC>(X, c, nv, qo);
+      if (OP == FOP_SPMV) st4_stream<T, VEC>(X, c, nv, qo);
     }
     // rotate; finish p_new of plane k+2 and store it when it is ours
 #pragma unroll
@@ -594,7 +615,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
         st4<float, VEC>(X, c, nv, xo);
         st4<float, VEC>(R, c, nv, ro);
       }
-      if (OP == FOP_SPMV) st4<float, VEC>(X, c, nv, qo);
+      if (OP == FOP_SPMV) st4_stream<float, VEC>(X, c, nv, qo);
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
