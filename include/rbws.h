@@ -85,6 +85,9 @@ enum { RBWS_IR_RESTART = 0, RBWS_IR_RELIABLE = 1 };
 enum {
   RBWS_FLAG_FORCE_EXACT_DOTS = 1, /* take the exact integer path for every inner product
                                      (results are identical; for testing the fallback) */
+  RBWS_FLAG_EXPLICIT_FALLBACK = 4, /* learned start, strict rule: compare explicit FP64
+                                     residuals of both starts instead of the basis's
+                                     residual decomposition */
   RBWS_FLAG_NO_GRAPH = 2          /* launch the iteration rounds one by one instead of
                                      replaying a captured HIP graph of them (results are
                                      identical; the graph is also skipped while kernel
@@ -235,6 +238,18 @@ rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, doubl
  * mode RBWS_LIFT_EXACT: every entry a correctly rounded N-term dot;
  * RBWS_LIFT_MFMA: FP64 matrix cores (rounding depends on the blocking). */
 rbws_status rbws_rb_lift(const rbws_basis* b, const double* c, int nmu, double* u, int mode, void* stream);
+/* rel_b = ||f - A_h(mu_b) V c_b|| / ||f|| for b < nmu without forming V c_b: the
+ * affine decomposition of the residual norm (Sec. 2.3's offline/online split
+ * applied to r = f - sum_q theta_q(mu) A_q V c).  rbws_rb_build stores, for
+ * f = 1 and when the Q N vectors A_q v_i fit in 8 GB, the correctly rounded
+ * dots G = (A_q v_i)^T (A_q' v_j), g = (A_q v_i)^T f and f^T f; online,
+ * ||r||^2 = f^T f - 2 y^T g + y^T G y with y = theta(mu) (x) c, O(Q^2 N^2) per
+ * parameter.  mu host (nmu x p), c host (nmu x N), rel host (nmu).  Accurate
+ * while ||r||^2 is not far below the terms' magnitude (relative residuals above
+ * about 1e-4 of ||A V c|| / ||f||).  Errors: ESTATE when the basis has no
+ * decomposition (Gaussian source, too large, or loaded from a file). */
+rbws_status rbws_rb_residual_estimate(const rbws_basis* b, const double* mu, int nmu, const double* c, double* rel,
+                                      void* stream);
 /* Checkpoint: the basis, reduced matrices, selection and indicator history.
  * Loading checks that the file belongs to problem p. */
 rbws_status rbws_basis_save(const rbws_basis* b, const char* path);

@@ -1081,7 +1081,11 @@ int orc_ir_solve2(const orc_problem *P, const double *mu, const double *f, const
         for (long i = 0; i < m; i++) { ri[i] = (float)(r[i] * sc); d[i] = 0.0f; }
         double bb = 0.0;
         for (long i = 0; i < m; i++) bb += (double)ri[i] * (double)ri[i];
-        double thr_in = (eta * eta) * bb;
+        /* the inner solve reduces the residual by eta, and at least to eta ||f||
+         * (in the scaled units): a start whose residual exceeds ||f|| (a reduced
+         * basis start with a small error but a large residual) then needs no
+         * more outer steps than the zero start */
+        double thr_in = (eta * eta) * fmin(bb, ff * sc * sc);
         for (long i = 0; i < m; i++) s[i] = (prec == ORC_PREC_JACOBI) ? ri[i] / dg[i] : ri[i];
         double rho_new = 0.0;
         for (long i = 0; i < m; i++) rho_new += (double)ri[i] * (double)s[i];

@@ -37,6 +37,12 @@ __global__ void k_pick(double* __restrict__ x, const double* __restrict__ src, c
     x[o + i] = src[o + i];
 }
 
+// c[b] = cr[b] (both stride 64) for the solves with pick[b]
+__global__ void k_pick_rows(double* __restrict__ c, const double* __restrict__ cr, const int* __restrict__ pick) {
+  const int b = blockIdx.x;
+  if (pick[b]) c[(long long)b * 64 + threadIdx.x] = cr[(long long)b * 64 + threadIdx.x];
+}
+
 void fill64(double* x, long long n, double v, hipStream_t s) {
   if (n <= 0) return;
   long long blocks = std::min<long long>((n + 255) / 256, 65536);
@@ -73,8 +79,8 @@ void collect_stats(Batch& B, unsigned long long t0, const std::vector<int>& init
 // greedy indicator).  `used` receives RBWS_INIT_LEARNED or RBWS_INIT_RB.
 template <class Lift>
 void learned_start(Batch& B, const std::vector<const Basis*>& bl, const std::vector<Mlp*>& ml,
-                   const int* problem_of, const double* mu, int fallback, int fe, hipStream_t s, Lift lift,
-                   std::vector<int>& used) {
+                   const int* problem_of, const double* mu, int fallback, int fe, bool allow_est, hipStream_t s,
+                   Lift lift, std::vector<int>& used) {
   const int ns = B.nsolve, nprob = B.nprob, p = B.probs[0]->p;
   RBWS_SCRATCH(cm_b);
   RBWS_SCRATCH(cr_b);
@@ -100,8 +106,29 @@ void learned_start(Batch& B, const std::vector<const Basis*>& bl, const std::vec
     mlp_predict_dev(ml[q], mq.data(), (int)rows.size(), rd, cm, 64, s);
     RBWS_HIP(hipStreamSynchronize(s));  // rows_b is reused by the next problem
   }
-  lift(cm, x);
   std::vector<double> rel_m(ns), rel_r(ns);
+  // strict rule from the residual decomposition: both residual norms in
+  // O(Q^2 N^2) per solve, then one lift of the chosen coefficients
+  bool est = fallback == 0 && allow_est;
+  for (const Basis* b : bl) est = est && b != nullptr && b->est;
+  if (est) {
+    double* cr = (double*)cr_b.get(sizeof(double) * 64 * ns, B.device);
+    RBWS_REQUIRE(rb_coeffs(B, bl, cr, 64, fe, s) == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
+    const int bad = rb_resid_estimate(B, bl, cm, 64, rel_m.data(), s) + rb_resid_estimate(B, bl, cr, 64, rel_r.data(), s);
+    if (bad == 0) {
+      std::vector<int> pick(ns);
+      for (int b = 0; b < ns; b++) pick[b] = (rel_r[b] < rel_m[b] || !(rel_m[b] == rel_m[b])) ? 1 : 0;
+      int* pd = (int*)rows_b.get(sizeof(int) * ns, B.device);
+      RBWS_HIP(hipMemcpyAsync(pd, pick.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_pick_rows, dim3(ns), dim3(64), 0, s, cm, (const double*)cr, (const int*)pd);
+      RBWS_HIP(hipGetLastError());
+      lift(cm, x);
+      RBWS_HIP(hipStreamSynchronize(s));  // `pick` outlives the copy
+      for (int b = 0; b < ns; b++) used[b] = pick[b] ? RBWS_INIT_RB : RBWS_INIT_LEARNED;
+      return;
+    }
+  }
+  lift(cm, x);
   resid_norms(B, x, rel_m.data(), nullptr, nullptr, fe, s);
   std::vector<int> pick(ns, 0);
   bool any = false;
@@ -351,6 +378,27 @@ rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, doubl
   API_END
 }
 
+rbws_status rbws_rb_residual_estimate(const rbws_basis* b, const double* mu, int nmu, const double* c, double* rel,
+                                      void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  RBWS_REQUIRE(nmu >= 0, RBWS_EINVAL, "nmu < 0");
+  if (nmu == 0) return RBWS_OK;
+  RBWS_REQUIRE(mu && c && rel, RBWS_EINVAL, "NULL argument");
+  const Basis* B = BB(b);
+  RBWS_REQUIRE(B->est, RBWS_ESTATE, "the basis has no residual decomposition");
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local Batch& bt = *new Batch();
+  RBWS_SCRATCH(cb);
+  std::vector<const Problem*> probs{B->prob};
+  batch_setup(bt, probs, nullptr, nmu, mu, B->prob->p, s);
+  double* cd = (double*)cb.get(sizeof(double) * nmu * B->N, bt.device);
+  RBWS_HIP(hipMemcpyAsync(cd, c, sizeof(double) * nmu * B->N, hipMemcpyHostToDevice, s));
+  std::vector<const Basis*> bl{B};
+  rb_resid_estimate(bt, bl, cd, B->N, rel, s);
+  API_END
+}
+
 rbws_status rbws_rb_lift(const rbws_basis* b, const double* c, int nmu, double* u, int mode, void* stream) {
   API_BEGIN
   RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
@@ -511,7 +559,8 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
     RBWS_REQUIRE(rb_coeffs(B, bl, cd, 64, fe, s) == 0, RBWS_ENUMERIC, "reduced matrix not positive definite");
     lift(cd, x);
   } else {
-    learned_start(B, bl, ml, problem_of, mu, opts->fallback, fe, s, lift, used);
+    learned_start(B, bl, ml, problem_of, mu, opts->fallback, fe, !(opts->flags & RBWS_FLAG_EXPLICIT_FALLBACK), s,
+                  lift, used);
   }
   RBWS_SCRATCH(tbuf);
   unsigned long long* tdev = (unsigned long long*)tbuf.get(sizeof(unsigned long long), B.device);

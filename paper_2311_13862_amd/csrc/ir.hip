@@ -271,7 +271,9 @@ __global__ __launch_bounds__(256) void k_ir_fin1(const SolveDev* __restrict__ sd
         s.k_in = 0;
         s.skip2 = 1;
         s.bb = g0;
-        s.thr_in = s.eta2 * g0;
+        // reduce by eta, and at least to eta ||f|| (scaled units): a start whose
+        // residual exceeds ||f|| needs no more outer steps than the zero start
+        s.thr_in = s.eta2 * fmin(g0, s.ff * s.scale * s.scale);
         if (s.mg) {
           // beta, restart and rho follow the V-cycle on the new right-hand side (k_ir_fin_mg)
         } else if (s.reliable && s.dir_ok && s.rho > 0.0) {

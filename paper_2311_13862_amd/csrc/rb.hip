@@ -382,40 +382,57 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const double* __restrict__ V,
                                                    const long long* __restrict__ off,
                                                    const double* __restrict__ C, int cstride,
                                                    double* __restrict__ u) {
+  // a wave owns two 16-point column tiles (two independent MFMA chains sharing
+  // the C fragments); the C fragments of the next 16 solves are loaded while
+  // the current ones are multiplied
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long c0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  const long long c0 = ((long long)blockIdx.x * 4 + wave) * 32;
   if (c0 >= ndof) return;
   const int col = lane & 15, kq = lane >> 4;
-  const long long cc = c0 + col;
-  const bool cin = cc < ndof;
-  // V fragment for this 16-point tile: K = N padded to a multiple of 4
-  double vb[kMaxN / 4];
+  const long long cc0 = c0 + col, cc1 = c0 + 16 + col;
+  const bool in0 = cc0 < ndof, in1 = cc1 < ndof;
+  // V fragments of the two tiles: K = N padded to a multiple of 4
+  double v0[kMaxN / 4], v1[kMaxN / 4];
   const int ksteps = (N + 3) / 4;
 #pragma unroll
   for (int s = 0; s < kMaxN / 4; s++) {
     const int k = 4 * s + kq;
-    vb[s] = (s < ksteps && k < N && cin) ? V[(long long)k * ndof + cc] : 0.0;
+    const bool kin = s < ksteps && k < N;
+    v0[s] = (kin && in0) ? V[(long long)k * ndof + cc0] : 0.0;
+    v1[s] = (kin && in1) ? V[(long long)k * ndof + cc1] : 0.0;
   }
-  for (int t0 = 0; t0 < nsol; t0 += 16) {
+  auto load_a = [&](int t0, double a[kMaxN / 4]) __attribute__((always_inline)) {
     const int ta = t0 + col;  // the solve row this lane feeds into A
     const int ba = ta < nsol ? (solves ? solves[ta] : ta) : -1;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kMaxN / 4; s++) {
+      const int k = 4 * s + kq;
+      a[s] = (s < ksteps && ba >= 0 && k < N) ? C[(long long)ba * cstride + k] : 0.0;
+    }
+  };
+  double a[kMaxN / 4], an[kMaxN / 4];
+  load_a(0, a);
+  for (int t0 = 0; t0 < nsol; t0 += 16) {
+    if (t0 + 16 < nsol) load_a(t0 + 16, an);
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < kMaxN / 4; s++) {
       if (s < ksteps) {
-        const int k = 4 * s + kq;
-        const double a = (ba >= 0 && k < N) ? C[(long long)ba * cstride + k] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[s], acc, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], v0[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], v1[s], acc1, 0, 0, 0);
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       const int t = t0 + 4 * r + kq;
-      if (t < nsol && cin) {
+      if (t < nsol) {
         const int b = solves ? solves[t] : t;
-        u[off[b] + cc] = acc[r];
+        if (in0) u[off[b] + cc0] = acc0[r];
+        if (in1) u[off[b] + cc1] = acc1[r];
       }
     }
+#pragma unroll
+    for (int s = 0; s < kMaxN / 4; s++) a[s] = an[s];
   }
 }
 
@@ -424,6 +441,12 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const double* __restrict__ V,
 // ---------------------------------------------------------------------------
 void Basis::upload(hipStream_t s) {
   const int dev = prob->device;
+  if (est) {
+    double* gd = (double*)G_d.get(sizeof(double) * G.size(), dev);
+    RBWS_HIP(hipMemcpyAsync(gd, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, s));
+    double* gv = (double*)g_d.get(sizeof(double) * g.size(), dev);
+    RBWS_HIP(hipMemcpyAsync(gv, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, s));
+  }
   double* a = (double*)AqN_d.get(sizeof(double) * AqN.size(), dev);
   RBWS_HIP(hipMemcpyAsync(a, AqN.data(), sizeof(double) * AqN.size(), hipMemcpyHostToDevice, s));
   double* f = (double*)fN_d.get(sizeof(double) * fN.size(), dev);
@@ -616,7 +639,7 @@ void rb_lift_mfma(Batch& B, const Basis* bs, const double* c, int cstride, doubl
   RBWS_REQUIRE(bs != nullptr && bs->N >= 1, RBWS_ESTATE, "a reduced basis is required for this start");
   long long* off = offsets_dev(B, s);
   const long long nd = bs->ndof;
-  const unsigned grid = (unsigned)((nd + 63) / 64);
+  const unsigned grid = (unsigned)((nd + 127) / 128);
   ktimer().begin(s, KK_LIFT);
   hipLaunchKernelGGL(k_lift_mfma, dim3(grid), dim3(256), 0, s, (const double*)bs->V.ptr, bs->N, nd,
                      (const int*)nullptr, B.nsolve, off, c, cstride, u);
@@ -652,6 +675,18 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
     Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, dev);
     const double h = 1.0 / (P->n + 1);
     fill64(f, nd, h * h, s);
+    // residual decomposition: keep every W_(q,i) (at most 8 GB)
+    const bool est = P->desc.f_kind == RBWS_F_ONE && (double)Q * N * nd * sizeof(double) <= 8e9;
+    DevBuf wallb;
+    double* Wall = est ? (double*)wallb.get(sizeof(double) * Q * N * nd, dev) : nullptr;
+    const int QN = Q * N;
+    if (est) {
+      bs->G.assign((size_t)QN * QN, 0.0);
+      bs->g.assign(QN, 0.0);
+      pair_dots({f}, {f}, nd, sc, fe, dev, s);
+      RBWS_HIP(hipMemcpyAsync(&bs->ff, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+    }
     std::vector<const Problem*> probs{P};
     Batch snap, eq, tr;
     // A_q = A(theta = e_q): a batch of Q "solves" with unit theta vectors
@@ -723,6 +758,39 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
           bs->AqN[((size_t)q * N + nb) * N + i] = a;
         }
       bs->fN[nb] = hv.back();
+      if (est) {  // new row and column of G and g: W_(q,nb) against every kept W and f
+        for (int q = 0; q < Q; q++)
+          RBWS_HIP(hipMemcpyAsync(Wall + ((long long)q * N + nb) * nd, W + (long long)q * nd,
+                                  sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+        std::vector<const double*> ws, wt;
+        for (int q = 0; q < Q; q++) {
+          for (int q2 = 0; q2 < Q; q2++)
+            for (int j = 0; j <= nb; j++) {
+              ws.push_back(Wall + ((long long)q * N + nb) * nd);
+              wt.push_back(Wall + ((long long)q2 * N + j) * nd);
+            }
+          ws.push_back(Wall + ((long long)q * N + nb) * nd);
+          wt.push_back(f);
+        }
+        RBWS_SCRATCH(gdots);
+        double* gdd = (double*)gdots.get(sizeof(double) * ws.size(), dev);
+        pair_dots(ws, wt, nd, gdd, fe, dev, s);
+        std::vector<double> gv(ws.size());
+        RBWS_HIP(hipMemcpyAsync(gv.data(), gdd, sizeof(double) * gv.size(), hipMemcpyDeviceToHost, s));
+        RBWS_HIP(hipStreamSynchronize(s));
+        size_t o = 0;
+        for (int q = 0; q < Q; q++) {
+          const size_t r = (size_t)q * N + nb;
+          for (int q2 = 0; q2 < Q; q2++)
+            for (int j = 0; j <= nb; j++) {
+              const size_t c2 = (size_t)q2 * N + j;
+              bs->G[r * QN + c2] = gv[o];
+              bs->G[c2 * QN + r] = gv[o];
+              o++;
+            }
+          bs->g[r] = gv[o++];
+        }
+      }
       nb++;
       bs->N = nb;
       bs->upload(s);
@@ -750,11 +818,106 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
     RBWS_REQUIRE(nb >= 1, RBWS_ENUMERIC, "the first snapshot is zero");
     const double* last = bs->hist.data() + (size_t)(nb - 1) * ntrain;
     bs->final_max = *std::max_element(last, last + ntrain);
+    bs->est = est;
+    bs->upload(s);
   } catch (...) {
     delete bs;
     throw;
   }
   return bs;
+}
+
+// ---------------------------------------------------------------------------
+// residual of the reduced solution from the decomposition (one block per solve)
+// ---------------------------------------------------------------------------
+struct EstDev {
+  const double* G;
+  const double* g;
+  double ff;
+  int Q, ld, N, pad;
+};
+
+__global__ __launch_bounds__(256) void k_rb_est(const SolveDev* __restrict__ sd, const EstDev* __restrict__ ed,
+                                                const double* __restrict__ theta, const double* __restrict__ c,
+                                                int cstride, double* __restrict__ out) {
+  __shared__ double y[kMaxQ * kMaxN];
+  __shared__ double red[4][4];
+  const int b = blockIdx.x;
+  const EstDev E = ed[sd[b].prob];
+  const int QN = E.Q * E.ld;
+  for (int x = threadIdx.x; x < QN; x += blockDim.x) {
+    const int q = x / E.ld, i = x - q * E.ld;
+    y[x] = i < E.N ? theta[(long long)b * kMaxQ + q] * c[(long long)b * cstride + i] : 0.0;
+  }
+  __syncthreads();
+  double quad = 0.0, mag = 0.0, lin = 0.0, maglin = 0.0;
+  for (int r = threadIdx.x; r < QN; r += blockDim.x) {
+    const double yr = y[r];
+    if (yr == 0.0) continue;
+    const double* Gr = E.G + (long long)r * QN;
+    double acc = 0.0, am = 0.0;
+    for (int k = 0; k < QN; k++) {
+      const double gv = Gr[k];
+      acc = __fma_rn(gv, y[k], acc);
+      am = __fma_rn(fabs(gv), fabs(y[k]), am);
+    }
+    quad = __fma_rn(yr, acc, quad);
+    mag = __fma_rn(fabs(yr), am, mag);
+    lin = __fma_rn(yr, E.g[r], lin);
+    maglin = __fma_rn(fabs(yr), fabs(E.g[r]), maglin);
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    quad += __shfl_xor(quad, m, 64);
+    mag += __shfl_xor(mag, m, 64);
+    lin += __shfl_xor(lin, m, 64);
+    maglin += __shfl_xor(maglin, m, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w][0] = quad;
+    red[w][1] = mag;
+    red[w][2] = lin;
+    red[w][3] = maglin;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < (int)(blockDim.x >> 6); v++)
+      for (int e = 0; e < 4; e++) t[e] += red[v][e];
+    out[2 * b] = (E.ff - 2.0 * t[2]) + t[0];
+    out[2 * b + 1] = (E.ff + 2.0 * t[3]) + t[1];
+  }
+}
+
+int rb_resid_estimate(Batch& B, const std::vector<const Basis*>& bases, const double* c, int cstride, double* rel,
+                      hipStream_t s) {
+  const int ns = B.nsolve;
+  if (ns == 0) return 0;
+  std::vector<EstDev> eh(B.nprob);
+  for (int q = 0; q < B.nprob; q++) {
+    const Basis* bs = bases[q];
+    RBWS_REQUIRE(bs != nullptr && bs->est, RBWS_ESTATE, "the basis has no residual decomposition");
+    RBWS_REQUIRE(bs->Q <= kMaxQ && bs->Nmax <= kMaxN, RBWS_EINVAL, "basis too large for the estimator");
+    eh[q] = EstDev{(const double*)bs->G_d.ptr, (const double*)bs->g_d.ptr, bs->ff, bs->Q, bs->Nmax, bs->N, 0};
+  }
+  RBWS_SCRATCH(edb);
+  RBWS_SCRATCH(outb);
+  EstDev* ed = (EstDev*)edb.get(sizeof(EstDev) * eh.size(), B.device);
+  double* o = (double*)outb.get(sizeof(double) * 2 * ns, B.device);
+  RBWS_HIP(hipMemcpyAsync(ed, eh.data(), sizeof(EstDev) * eh.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_rb_est, dim3(ns), dim3(256), 0, s, (const SolveDev*)B.sd.ptr, (const EstDev*)ed,
+                     (const double*)B.theta.ptr, c, cstride, o);
+  RBWS_HIP(hipGetLastError());
+  std::vector<double> h(2 * (size_t)ns);
+  RBWS_HIP(hipMemcpyAsync(h.data(), o, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  int bad = 0;
+  for (int b = 0; b < ns; b++) {
+    const double rr = h[2 * b], mag = h[2 * b + 1], ff = eh[B.sd_h[b].prob].ff;
+    if (std::isfinite(rr) && !(rr >= 1e-8 * mag)) bad++;
+    rel[b] = std::isfinite(rr) ? std::sqrt(std::max(rr, 0.0) / ff) : std::nan("");
+  }
+  return bad;
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,15 @@ struct Basis {
   std::vector<double> hist;  // N x ntrain indicators (row k: k+1 basis vectors)
   int ntrain = 0;
   double final_max = 0.0;    // max over the training set of the final indicator
+  // Residual decomposition for a fixed source f (built by rb_build when f = 1 and
+  // the vectors W_(q,i) = A_q v_i fit in memory): with y_(q,i) = theta_q c_i,
+  //   ||f - A(mu) V c||^2 = ff - 2 y^T g + y^T G y,
+  // G_(q,i),(q',j) = W_(q,i)^T W_(q',j), g_(q,i) = W_(q,i)^T f, ff = f^T f
+  // (correctly rounded dots); index (q, i) = q Nmax + i.
+  bool est = false;
+  double ff = 0.0;
+  std::vector<double> G, g;
+  DevBuf G_d, g_d;
   void upload(hipStream_t s);
 };
 
@@ -31,6 +40,14 @@ struct RbDev {
 
 Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol,
                 int prec, int snap_maxit, int flags, hipStream_t s);
+
+// ||f - A(mu_b) V c_b|| / ||f|| for every solve of B from the residual
+// decomposition of its problem's basis (every basis must have `est`); c device,
+// row b at b * cstride.  rel: host, nsolve values.  Returns the number of
+// solves whose value is not trustworthy (the squared residual below 1e-8 of
+// the magnitude of its terms, where cancellation could dominate).
+int rb_resid_estimate(Batch& B, const std::vector<const Basis*>& bases, const double* c, int cstride, double* rel,
+                      hipStream_t s);
 
 // c (device, nsolve x cstride) for every solve of batch B from the bases of its
 // problems (bases[prob]); theta comes from the batch.  Returns the number of

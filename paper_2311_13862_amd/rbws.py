@@ -27,6 +27,7 @@ LIFT_EXACT, LIFT_MFMA = 0, 1
 IR_RESTART, IR_RELIABLE = 0, 1
 FLAG_FORCE_EXACT_DOTS = 1
 FLAG_NO_GRAPH = 2
+FLAG_EXPLICIT_FALLBACK = 4
 
 
 class RbwsError(RuntimeError):
@@ -78,6 +79,7 @@ def _load():
         "rbws_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
         "rbws_problem_create": (i, [C.POINTER(ProblemDesc), i, C.POINTER(vp)]),
         "rbws_problem_destroy": (None, [vp]),
+        "rbws_rb_residual_estimate": (i, [vp, dp, i, dp, dp, vp]),
         "rbws_mg_apply": (i, [vp, dp, i, i, d, vp, vp, i, vp]),
         "rbws_problem_info": (i, [vp, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(ll)]),
         "rbws_theta": (i, [vp, dp, i, dp]),
@@ -300,6 +302,14 @@ class Basis:
         c = np.empty((mu.shape[0], self.N))
         _check(_L.rbws_rb_coeffs(self.handle, _dp(mu), mu.shape[0], _dp(c), _stream(stream)))
         return c
+
+    def residual_estimate(self, mu, c, stream=None) -> np.ndarray:
+        """||f - A(mu_b) V c_b|| / ||f|| from the basis's residual decomposition."""
+        mu = _f64(mu).reshape(-1, self.problem.p)
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape(mu.shape[0], self.N)
+        rel = np.empty(mu.shape[0])
+        _check(_L.rbws_rb_residual_estimate(self.handle, _dp(mu), mu.shape[0], _dp(c), _dp(rel), _stream(stream)))
+        return rel
 
     def lift(self, c, u, mode=LIFT_EXACT, stream=None):
         """u[b] = V c[b]; c (nmu, N) and u (nmu, ndof) float64 device tensors."""
