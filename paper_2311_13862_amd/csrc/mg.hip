@@ -1438,11 +1438,12 @@ struct MgGroup {
   int q = 0, seg = 0;  // problem index; its segment in the V-cycle solve list
   std::vector<int> sol;
   DevBuf sid, off0;
-  std::vector<MgLevelHost*> lv;
+  std::vector<MgLevelHost*> lv;    // this batch's levels, finest first (a prefix of lvpool)
+  std::vector<MgLevelHost*> lvpool;  // owned; kept across batches so their buffers are reused
   DevBuf L;
   int mc = 0;
   ~MgGroup() {
-    for (MgLevelHost* l : lv) delete l;
+    for (MgLevelHost* l : lvpool) delete l;
   }
 };
 
@@ -1452,11 +1453,12 @@ struct MgRun {
   bool fp32 = false;
   bool fused = false;  // level-0 correction + post-smoothing + r^T s in one tile kernel
   bool rx0 = false;    // FP32 fused: level-0 tiles span whole rows, the pre-smoothing forms the x-sums
-  std::vector<MgGroup*> g;
+  std::vector<MgGroup*> g;     // one per problem of this batch (a prefix of gpool)
+  std::vector<MgGroup*> gpool;  // owned; kept across batches so their buffers are reused
   DevBuf fine;    // MgFine per problem
   DevBuf x0, t0;  // level-0 scratch, laid out like the batch (x0 only without the fused kernels)
   ~MgRun() {
-    for (MgGroup* q : g) delete q;
+    for (MgGroup* q : gpool) delete q;
   }
 };
 
@@ -1497,10 +1499,17 @@ static MgLv view(const MgLevelHost& l, const MgGroup& g, bool level0, bool fp32)
 }
 
 MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
-  static thread_local MgRun* run = nullptr;  // rebuilt per batch; never freed at exit
-  delete run;
-  run = new MgRun();
+  // The hierarchy's objects and device buffers persist across batches (never
+  // freed at exit): a later batch reuses every buffer that is large enough, so
+  // repeated solves of a batch allocate nothing here.
+  static thread_local MgRun* run = nullptr;
+  if (run != nullptr && run->device != B.device) {
+    delete run;
+    run = nullptr;
+  }
+  if (run == nullptr) run = new MgRun();
   MgRun* m = run;
+  m->g.clear();
   m->nu = nu;
   m->omega = omega;
   m->fp32 = fp32;
@@ -1508,10 +1517,14 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   const size_t el = fp32 ? sizeof(float) : sizeof(double);
   m->t0.get(el * std::max<long long>(B.total, 1), B.device);
   for (int q = 0; q < B.nprob; q++) {
-    MgGroup* g = new MgGroup();
+    if ((int)m->gpool.size() <= q) m->gpool.push_back(new MgGroup());
+    MgGroup* g = m->gpool[q];
     m->g.push_back(g);
     g->q = q;
     g->seg = 0;
+    g->sol.clear();
+    g->lv.clear();
+    g->mc = 0;
     for (int b = 0; b < B.nsolve; b++) {
       if (B.sd_h[b].prob == q) g->sol.push_back(b);
       if (B.sd_h[b].prob < q) g->seg++;
@@ -1532,7 +1545,8 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     int nl[16];
     const int L = mg_levels_of(P->n, nl);
     for (int l = 0; l < L; l++) {
-      MgLevelHost* lv = new MgLevelHost();
+      if ((int)g->lvpool.size() <= l) g->lvpool.push_back(new MgLevelHost());
+      MgLevelHost* lv = g->lvpool[l];
       g->lv.push_back(lv);
       lv->prob = coarse_problem(P, nl[l]);
       lv->n = nl[l];
