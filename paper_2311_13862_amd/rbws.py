@@ -220,14 +220,18 @@ def exact_dots(x, y, flags: int = 0, stream=None) -> np.ndarray:
     return out
 
 
-def stats_to_dicts(st, n: int) -> List[dict]:
-    return [{k: getattr(st[i], k) for k, _ in SolveStat._fields_} for i in range(n)]
+def stats_array(st, n: int) -> np.ndarray:
+    """The first n SolveStat records as one numpy structured array: st[b]["iters"]
+    for one solve, st["iters"] for the column.  One allocation per batch (a list
+    of per-solve dicts would create thousands of Python objects per call)."""
+    return np.ctypeslib.as_array(st)[:n].copy()
 
 
 def solve(problems: Sequence[Problem], mu, opts: SolveOpts, problem_of=None, bases=None,
           mlps=None, u_out=None, stream=None):
     """Batched solve (rbws_solve).  u_out: None or a list of device tensors
-    (one per solve).  Returns a list of per-solve stat dicts."""
+    (one per solve).  Returns the per-solve statistics as a numpy structured
+    array with SolveStat's fields (stats_array)."""
     problems = list(problems)
     nprob = len(problems)
     p = problems[0].p
@@ -245,7 +249,7 @@ def solve(problems: Sequence[Problem], mu, opts: SolveOpts, problem_of=None, bas
         uo = (C.c_void_p * nmu)(*[t.data_ptr() if t is not None else None for t in u_out])
     st = (SolveStat * max(nmu, 1))()
     _check(_L.rbws_solve(ph, bh, mh, nprob, po, _dp(mu), nmu, C.byref(opts), _stream(stream), uo, st))
-    return stats_to_dicts(st, nmu)
+    return stats_array(st, nmu)
 
 
 class Basis:
