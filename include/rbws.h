@@ -370,8 +370,12 @@ rbws_status rbws_exact_fallbacks(long long* counts, int reset);
  * RBWS_TUNE_GRID: the sweeps launch one workgroup per work item (0, default)
  * or a persistent grid of one full occupancy that loops over the items (1).
  * RBWS_TUNE_TZ: tile depth of every later batch, a power of two in [4, 64],
- * or 0 (default) for the autotuner's choice or the built-in rule. */
-enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1, RBWS_TUNE_TZ = 2 };
+ * or 0 (default) for the autotuner's choice or the built-in rule.
+ * RBWS_TUNE_MG_PZ: where the tiles of a multigrid level span whole grid rows,
+ * the FP32 post-smoothing interpolates the coarse correction itself (1,
+ * default) or reads the z/y-interpolated rows from a separate pass (0); the
+ * results are the same bits. */
+enum { RBWS_TUNE_SWEEP32 = 0, RBWS_TUNE_GRID = 1, RBWS_TUNE_TZ = 2, RBWS_TUNE_MG_PZ = 3 };
 rbws_status rbws_set_tuning(int key, int value);
 /* Tile autotuner.  Work items are tiles of 1024 grid columns (32 x 32, or a
  * whole row when 32 < n <= 128) by TZ planes; a

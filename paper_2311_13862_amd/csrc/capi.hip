@@ -445,6 +445,9 @@ rbws_status rbws_set_tuning(int key, int value) {
     RBWS_REQUIRE(value == 0 || (value >= 4 && value <= 64 && (value & (value - 1)) == 0), RBWS_EINVAL,
                  "tile depth must be 0 or a power of two in [4, 64]");
     set_tile_depth(value);
+  } else if (key == RBWS_TUNE_MG_PZ) {
+    RBWS_REQUIRE(value == 0 || value == 1, RBWS_EINVAL, "value out of range");
+    set_mg_pz(value);
   } else {
     throw Error{RBWS_EINVAL, "unknown tuning key"};
   }

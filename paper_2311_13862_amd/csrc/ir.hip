@@ -88,8 +88,9 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   }
 }
 
+// three waves per SIMD: 167 VGPRs without spills (177, two waves, unbounded)
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_ir_outer(const int2* __restrict__ items, const int* __restrict__ list,
+__global__ __launch_bounds__(256, 3) void k_ir_outer(const int2* __restrict__ items, const int* __restrict__ list,
                                                   const int* __restrict__ cnt, int nitems,
                                                   const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,

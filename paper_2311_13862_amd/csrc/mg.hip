@@ -668,9 +668,19 @@ struct MgFine {           // per problem: the z/y-interpolated level-1 correctio
   const int* ci;
   const void* cw;
   long long per;          // nf * nf * nc
-  int nc, pad;
+  int nc;
+  int fz;                 // 1: the FP32 post-smoothing interpolates ec itself (ezy not used)
   const int2* lohi;       // fine span of each coarse node
+  const void* ec;         // the coarse correction, group layout t * nc^3
 };
+
+// LDS rings of the FP32 post-smoothing when it interpolates the coarse
+// correction itself (tiles that span whole rows): three coarse planes of the
+// rows the tile needs (at most kPzRing values each) and the z/y-interpolated
+// rows of three fine planes (the tile's rows and its two halo rows, at most
+// kPzRows values each).  The host checks both bounds per level.
+constexpr int kPzRing = 448;
+constexpr int kPzRows = 640;
 
 // Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
 // Jacobi sweep from zero) and t = b - A e1, one z-march per tile; e1 of the
@@ -1256,7 +1266,11 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
   }
 }
 
-template <bool VEC, bool ML>
+// With PZ (tiles that span whole rows) the kernel also does the z/y
+// interpolation of the coarse correction: per tile it stages the coarse planes
+// it needs in an LDS ring and forms ezy of plane k+2 while plane k is smoothed,
+// with the operations of k_mg_pyz, so ezy never goes to memory.
+template <bool VEC, bool ML, bool PZ>
 __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                      const int* __restrict__ cnt, int ntiles,
                                                      const SolveDev* __restrict__ sd,
@@ -1269,6 +1283,10 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
   float* plane = kt + ktab;
   __shared__ double red[4];
   __shared__ int zk[kZkLen];
+  __shared__ float cring[PZ ? 3 * kPzRing : 1];  // coarse planes K at slot K % 3
+  __shared__ float zring[PZ ? 3 * kPzRows : 1];  // ezy of fine plane k at slot k % 3
+  __shared__ int zrow[PZ ? 40 : 1];              // per ezy row: ring offset of row J0 and flags, or -1
+  __shared__ float zwy[PZ ? 40 : 1];             // per ezy row: the y weight
   const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
@@ -1300,6 +1318,68 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
     const int jj = min(G.j, n);
     const int hI0 = hin ? F.ci[G.hi - 1] : 0;
     const float hwx = hin ? cw[G.hi - 1] : 0.0f;
+    // PZ: ezy rows j0-1 .. j0+TY of a plane (row zr = j - j0 + 1, CW values
+    // each) and coarse rows Jb .. Jb+CR-1 of a plane, CW values each
+    const int j0 = G.j - G.ly;
+    const int CW = nc <= 16 ? 16 : nc <= 32 ? 32 : 64;
+    const int cws = CW == 16 ? 4 : CW == 32 ? 5 : 6;
+    const int nz = (P.TY + 2) << cws;
+    const int Jb = F.ci[max(j0 - 1, 1) - 1];
+    const int ncr = (F.ci[min(j0 + P.TY, n) - 1] + 2 - Jb) << cws;
+    const gptr<float> ecs =
+        as_global((const float*)F.ec) + (long long)(ML ? it.x : gidx[it.x]) * ((long long)nc * nc * nc);
+    // ezy row zr (fine row j = j0 - 1 + zr): ring offset of coarse row J0 = ci(j)
+    // (rows outside the grid: offset 0, never read) and the y weight; read after
+    // the prologue's first barrier
+    if constexpr (PZ) {
+      const int zr = threadIdx.x, j = j0 - 1 + zr;
+      if (zr < P.TY + 2) {
+        const bool in = j >= 1 && j <= n;
+        zrow[zr] = in ? (F.ci[j - 1] - Jb) << cws : 0;
+        zwy[zr] = in ? cw[j - 1] : 0.0f;
+      }
+    }
+    // coarse plane K of the tile's rows (zero outside the coarse grid)
+    auto cload = [&](int K, float v[2]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int m = 0; m < 2; m++) {
+        const int e = (int)threadIdx.x + 256 * m;
+        const int J = Jb + (e >> cws), I = (e & (CW - 1)) + 1;
+        v[m] = 0.0f;
+        if (e < ncr && K >= 1 && K <= nc && J >= 1 && J <= nc && I <= nc)
+          v[m] = ecs[((long long)(K - 1) * nc + (J - 1)) * nc + (I - 1)];
+      }
+    };
+    auto cstore = [&](int K, const float v[2]) __attribute__((always_inline)) {
+      float* D = cring + (K % 3) * kPzRing;
+#pragma unroll
+      for (int m = 0; m < 2; m++) {
+        const int e = (int)threadIdx.x + 256 * m;
+        if (e < ncr) D[e] = v[m];
+      }
+    };
+    // ezy of fine plane kk into its slot.  The ring holds zeros for coarse
+    // nodes outside the grid, so every tap is taken: a zero tap adds an exact
+    // zero, and the values are those of k_mg_pyz, which skips such taps.
+    auto zplane = [&](int kk) __attribute__((always_inline)) {
+      if (kk < 1 || kk > n) return;
+      float* Z = zring + (kk % 3) * kPzRows;
+      const int K0 = F.ci[kk - 1];
+      const float wz1 = cw[kk - 1], wz0 = 1.0f - wz1;
+      const float* A = cring + (K0 % 3) * kPzRing;
+      const float* Bq = cring + ((K0 + 1) % 3) * kPzRing;
+#pragma unroll 1
+      for (int e = threadIdx.x; e < nz; e += 256) {
+        const int zr = e >> cws;
+        const int o = zrow[zr] + (e & (CW - 1));
+        const float wy1 = zwy[zr];
+        const float az0 = fmaf(wz1, Bq[o], wz0 * A[o]);
+        const float az1 = fmaf(wz1, Bq[o + CW], wz0 * A[o + CW]);
+        Z[e] = fmaf(wy1, az1, (1.0f - wy1) * az0);
+      }
+    };
+    // the upper coarse plane that ezy of fine plane kk needs
+    auto ptop = [&](int kk) __attribute__((always_inline)) { return F.ci[min(kk, n) - 1] + 1; };
     auto taps = [&](gptr<float> zr, int i0, float& za, float& zb) __attribute__((always_inline)) {
       za = i0 >= 1 ? zr[i0 - 1] : 0.0f;
       zb = i0 + 1 <= nc ? zr[i0] : 0.0f;
@@ -1324,10 +1404,12 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       for (int e = 0; e < 4; e++) q.r[e] = q.z[e] = 0.0f;
       if (nv == 0 || k < 1 || k > n) return;
       ld4<float, VEC>(R, (long long)(k - 1) * n2 + rowoff, nv, q.r);
-      const gptr<float> zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc + W0;
+      if constexpr (!PZ) {
+        const gptr<float> zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc + W0;
 #pragma unroll
-      for (int m = 0; m < 4; m++)
-        if (wv[m]) q.z[m] = zr[m];
+        for (int m = 0; m < 4; m++)
+          if (wv[m]) q.z[m] = zr[m];
+      }
     };
     // tap m of the window (m = dI, dI + 1 in 0..3)
     auto pick = [&](const float z[4], int m) __attribute__((always_inline)) -> float {
@@ -1340,7 +1422,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       h.r = h.za = h.zb = 0.0f;
       if (!hin || k < 1 || k > n) return;
       h.r = R[(long long)(k - 1) * n2 + hoff];
-      taps(ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc, hI0, h.za, h.zb);
+      if constexpr (!PZ) taps(ezy + ((long long)(k - 1) * n + (G.hj - 1)) * nc, hI0, h.za, h.zb);
     };
     DCache32 C;
     InvCache32 Ci;
@@ -1352,11 +1434,47 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       if (nv == 0 || k < 1 || k > n) return;
       const int key = zkey_at(k);
       if (key != Ci.key) inv_fill(Ci, G, kt, key);
+      float z[4];
+#pragma unroll
+      for (int m = 0; m < 4; m++) z[m] = q.z[m];
+      if constexpr (PZ) {
+        const float* Zr = zring + (k % 3) * kPzRows + ((jj - j0 + 1) << cws) + W0;
+#pragma unroll
+        for (int m = 0; m < 4; m++) z[m] = wv[m] ? Zr[m] : 0.0f;
+      }
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + join2(ta[e], tb[e], wx[e], pick(q.z, dI[e]), pick(q.z, dI[e] + 1))
+        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + join2(ta[e], tb[e], wx[e], pick(z, dI[e]), pick(z, dI[e] + 1))
                         : 0.0f;
     };
+    float pf[2] = {0.0f, 0.0f};  // PZ: the next coarse plane, loaded one iteration ahead
+    int Pcur = 0, Pnext = 0;
+    if constexpr (PZ) {
+      // ezy of planes kb-1 .. kb+1 (coarse planes ci(kb-1) .. ci(kb+1)+1, at most three)
+      const int Ka = F.ci[max(G.kb - 1, 1) - 1], Kz = ptop(G.kb + 1);
+      for (int K = Ka; K <= Kz; K++) {
+        float v[2];
+        cload(K, v);
+        cstore(K, v);
+      }
+      __syncthreads();
+      zplane(G.kb - 1);
+      zplane(G.kb);
+      zplane(G.kb + 1);
+      __syncthreads();
+      // the loop's ring: planes Pcur-1 and Pcur (ezy of plane kb+2), the next one prefetched
+      Pcur = ptop(G.kb + 2);
+      Pnext = ptop(G.kb + 3);
+      {
+        float v[2];
+        cload(Pcur - 1, v);
+        cstore(Pcur - 1, v);
+        cload(Pcur, v);
+        cstore(Pcur, v);
+      }
+      if (Pnext != Pcur) cload(Pnext, pf);
+      __syncthreads();
+    }
     float um[4], uc[4], un[4], rc[4];
     Raw qn, qnn;
     {
@@ -1369,6 +1487,8 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
 #pragma unroll
       for (int e = 0; e < 4; e++) rc[e] = qc.r[e];
     }
+    // the first iteration writes the z ring slot that e2_quad(kb - 1) read
+    if constexpr (PZ) __syncthreads();
     RawH hc;
     load_h(G.kb, hc);
     double acc = 0.0;
@@ -1383,7 +1503,23 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       float* pl = plane + buf * QPLANE;
 #pragma unroll
       for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      if constexpr (PZ) {
+        if (hin) {
+          const float* Zh = zring + (k % 3) * kPzRows + ((G.hj - j0 + 1) << cws);
+          hc.za = hI0 >= 1 ? Zh[hI0 - 1] : 0.0f;
+          hc.zb = hI0 + 1 <= nc ? Zh[hI0] : 0.0f;
+        }
+      }
       if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hc.r * C.hinv) + join(hI0, hwx, hc.za, hc.zb) : 0.0f;
+      if constexpr (PZ) {
+        // the ring slot written here is not read in this iteration
+        if (Pnext != Pcur) cstore(Pnext, pf);
+        zplane(k + 2);
+        const int Pn2 = ptop(k + 4);
+        if (Pn2 != Pnext) cload(Pn2, pf);
+        Pcur = Pnext;
+        Pnext = Pn2;
+      }
       __syncthreads();
       if (nv > 0) {
         float q[4], so[4];
@@ -1432,6 +1568,8 @@ struct MgLevelHost {
   DevBuf fine;                // MgFine of this level (levels >= 1 with a coarser level)
   bool quad = false;          // n % 4 == 0 and every vector offset a multiple of 4
   bool rows = false;          // the level's tiles span whole rows
+  bool fz = false;            // its FP32 post-smoothing interpolates the coarse correction itself
+  std::vector<int> ci_h;      // host copy of ci (transfer to the next level)
 };
 
 struct MgGroup {
@@ -1453,6 +1591,7 @@ struct MgRun {
   bool fp32 = false;
   bool fused = false;  // level-0 correction + post-smoothing + r^T s in one tile kernel
   bool rx0 = false;    // FP32 fused: level-0 tiles span whole rows, the pre-smoothing forms the x-sums
+  bool fz0 = false;    // FP32 fused: the level-0 post-smoothing interpolates the coarse correction itself
   std::vector<MgGroup*> g;     // one per problem of this batch (a prefix of gpool)
   std::vector<MgGroup*> gpool;  // owned; kept across batches so their buffers are reused
   DevBuf fine;    // MgFine per problem
@@ -1597,6 +1736,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
                      RBWS_EINVAL, "multigrid restriction block wider than expected");
       }
       MgLevelHost* lv = g->lv[l];
+      lv->ci_h = ci;
       RBWS_HIP(hipMemcpyAsync(lv->ci.get(sizeof(int) * nf, B.device), ci.data(), sizeof(int) * nf,
                               hipMemcpyHostToDevice, s));
       RBWS_HIP(hipMemcpyAsync(lv->cwd.get(sizeof(double) * nf, B.device), cw.data(), sizeof(double) * nf,
@@ -1625,41 +1765,68 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   }
   // the fused level-0 post step needs nu = 1 and a coarse level for every problem
   m->fused = nu == 1;
-  std::vector<MgFine> fh(B.nprob);
-  for (MgGroup* g : m->g) {
-    if (g->sol.empty()) continue;
-    if (g->lv.size() < 2) {
-      m->fused = false;
-      continue;
-    }
-    MgFine& f = fh[g->q];
-    f.ezy = g->lv[0]->vtx.ptr;
-    f.ci = (const int*)g->lv[0]->ci.ptr;
-    f.cw = fp32 ? g->lv[0]->cwf.ptr : g->lv[0]->cwd.ptr;
-    f.per = (long long)g->lv[0]->n * g->lv[0]->n * g->lv[1]->n;
-    f.nc = g->lv[1]->n;
-    f.pad = 0;
-    f.lohi = (const int2*)g->lv[0]->lohi.ptr;
-    // the same for the levels >= 1 that have a coarser level (FP32 fused path)
-    for (size_t l = 1; fp32 && l + 1 < g->lv.size(); l++) {
-      MgLevelHost& lv = *g->lv[l];
-      MgFine fl{lv.vtx.ptr, (const int*)lv.ci.ptr, lv.cwf.ptr, (long long)lv.n * lv.n * g->lv[l + 1]->n,
-                g->lv[l + 1]->n, 0, (const int2*)lv.lohi.ptr};
-      RBWS_HIP(hipMemcpy(lv.fine.get(sizeof(MgFine), B.device), &fl, sizeof(MgFine), hipMemcpyHostToDevice));
-    }
-  }
-  RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
-                          hipMemcpyHostToDevice, s));
+  for (MgGroup* g : m->g)
+    if (!g->sol.empty() && g->lv.size() < 2) m->fused = false;
   // tiles that span whole rows (at most 128 points, so n_c <= 63): the FP32
   // pre-smoothing forms the restriction's x-sums itself
   m->rx0 = fp32 && m->fused;
   for (int q = 0; q < B.nprob; q++) m->rx0 = m->rx0 && B.pd_h[q].ntx == 1 && B.probs[q]->n <= 128;
   for (MgGroup* g : m->g)
     for (MgLevelHost* lv : g->lv) lv->rows = lv->B.nsolve > 0 && lv->B.pd_h[0].ntx == 1 && lv->n <= 128;
+  // ... and the FP32 post-smoothing interpolates the coarse correction itself
+  // when its LDS rings hold what a tile needs
+  auto pz_fits = [](const MgLevelHost& lv, int TY, int nc) {
+    if (nc > 64) return false;
+    const int CW = nc <= 16 ? 16 : nc <= 32 ? 32 : 64, n = lv.n;
+    if ((TY + 2) * CW > kPzRows) return false;
+    for (int j0 = 1; j0 <= n; j0 += TY) {
+      const int Jb = lv.ci_h[std::max(j0 - 1, 1) - 1];
+      if ((lv.ci_h[std::min(j0 + TY, n) - 1] + 2 - Jb) * CW > kPzRing) return false;
+    }
+    return true;
+  };
+  m->fz0 = m->rx0 && mg_pz_enabled();
+  for (MgGroup* g : m->g) {
+    for (MgLevelHost* lv : g->lv) lv->fz = false;
+    if (g->sol.empty()) continue;
+    for (size_t l = 1; fp32 && nu == 1 && mg_pz_enabled() && l + 1 < g->lv.size(); l++) {
+      MgLevelHost& lv = *g->lv[l];
+      lv.fz = lv.rows && pz_fits(lv, lv.B.pd_h[0].TY, g->lv[l + 1]->n);
+    }
+    if (g->lv.size() >= 2) m->fz0 = m->fz0 && pz_fits(*g->lv[0], B.pd_h[g->q].TY, g->lv[1]->n);
+  }
+  for (MgGroup* g : m->g)  // one launch covers every problem at level 0
+    if (!g->sol.empty() && !g->lv.empty()) g->lv[0]->fz = m->fz0;
+  std::vector<MgFine> fh(B.nprob);
+  for (MgGroup* g : m->g) {
+    if (g->sol.empty() || g->lv.size() < 2) continue;
+    MgFine& f = fh[g->q];
+    f.ezy = g->lv[0]->vtx.ptr;
+    f.ci = (const int*)g->lv[0]->ci.ptr;
+    f.cw = fp32 ? g->lv[0]->cwf.ptr : g->lv[0]->cwd.ptr;
+    f.per = (long long)g->lv[0]->n * g->lv[0]->n * g->lv[1]->n;
+    f.nc = g->lv[1]->n;
+    f.fz = m->fz0 ? 1 : 0;
+    f.lohi = (const int2*)g->lv[0]->lohi.ptr;
+    f.ec = g->lv[1]->ve.ptr;
+    // the same for the levels >= 1 that have a coarser level (FP32 fused path)
+    for (size_t l = 1; fp32 && l + 1 < g->lv.size(); l++) {
+      MgLevelHost& lv = *g->lv[l];
+      MgFine fl{lv.vtx.ptr, (const int*)lv.ci.ptr, lv.cwf.ptr, (long long)lv.n * lv.n * g->lv[l + 1]->n,
+                g->lv[l + 1]->n, lv.fz ? 1 : 0, (const int2*)lv.lohi.ptr, g->lv[l + 1]->ve.ptr};
+      RBWS_HIP(hipMemcpy(lv.fine.get(sizeof(MgFine), B.device), &fl, sizeof(MgFine), hipMemcpyHostToDevice));
+    }
+  }
+  RBWS_HIP(hipMemcpyAsync(m->fine.get(sizeof(MgFine) * fh.size(), B.device), fh.data(), sizeof(MgFine) * fh.size(),
+                          hipMemcpyHostToDevice, s));
   if (!m->fused) m->x0.get(el * std::max<long long>(B.total, 1), B.device);
   RBWS_HIP(hipStreamSynchronize(s));
   return m;
 }
+
+static int g_mg_pz = 1;
+bool mg_pz_enabled() { return g_mg_pz != 0; }
+void set_mg_pz(int on) { g_mg_pz = on ? 1 : 0; }
 
 static unsigned grid_for(long long items) {
   const long long g = std::min<long long>(std::max<long long>(items, 1), 65536);
@@ -1729,12 +1896,15 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(grid_for((long long)ns * nrs)), dim3(256), 0, s, v, cv, ml,
                        (const int*)lv.ci.ptr, cw, (const int2*)lv.lohi.ptr, (const T*)tres, (T*)cl.vb.ptr, scale);
   vcycle<T>(m, g, l + 1, (const T*)cl.vb.ptr, (T*)cl.ve.ptr, (T*)cl.ve2.ptr, (T*)cl.vt.ptr, ml, s);
-  // z/y interpolation of the coarse correction (into vtx, free again after the restriction)
-  hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
-                     (const int*)lv.ci.ptr, cw, (const T*)cl.ve.ptr, (T*)lv.vtx.ptr);
+  // z/y interpolation of the coarse correction (into vtx, free again after the
+  // restriction), unless the level's FP32 post-smoothing does it itself
+  if (!lv.fz)
+    hipLaunchKernelGGL(k_mg_pyz<T>, dim3(grid_for((long long)ns * npyz)), dim3(256), 0, s, v, cv, ml,
+                       (const int*)lv.ci.ptr, cw, (const T*)cl.ve.ptr, (T*)lv.vtx.ptr);
   if (pre_only) return;
   if (tiles) {
-    auto k = lv.B.vec ? k_mg_post0_32<true, true> : k_mg_post0_32<false, true>;
+    auto k = lv.fz ? (lv.B.vec ? k_mg_post0_32<true, true, true> : k_mg_post0_32<false, true, true>)
+                   : (lv.B.vec ? k_mg_post0_32<true, true, false> : k_mg_post0_32<false, true, false>);
     hipLaunchKernelGGL(k, tgrid, dim3(256), tlds, s, (const int2*)lv.B.items.ptr, ml.list, ml.cnt, ntiles,
                        (const SolveDev*)lv.B.sd.ptr, (const ProbDev*)lv.B.pd.ptr, (const float*)lv.B.kap32.ptr,
                        (const MgFine*)lv.fine.ptr, nullptr, (const float*)b, (float*)e, nullptr, (float)m->omega,
@@ -1792,7 +1962,8 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* sv, const Lists& L, void*
     kt.begin(st, KK_MG_POST);
     const unsigned grid = tgrid;
     if (m->fp32) {
-      auto k = B.vec ? k_mg_post0_32<true, false> : k_mg_post0_32<false, false>;
+      auto k = m->fz0 ? (B.vec ? k_mg_post0_32<true, false, true> : k_mg_post0_32<false, false, true>)
+                      : (B.vec ? k_mg_post0_32<true, false, false> : k_mg_post0_32<false, false, false>);
       hipLaunchKernelGGL(k, dim3(grid), dim3(256), sizeof(float) * (ktab + 2 * QPLANE), st,
                          (const int2*)B.items.ptr, (const int*)L.ap, (const int*)(L.cnt + WL_AP), 0,
                          (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr, (const float*)B.kap32.ptr,

@@ -28,4 +28,10 @@ bool mg_apply(MgRun* m, Batch& B, const void* r, void* s, const Lists& L, void* 
 // solve listed, then one V-cycle.  Synchronises the stream.
 void mg_apply_all(Batch& B, int nu, double omega, bool fp32, const void* r, void* s, hipStream_t st);
 
+// Whether the FP32 post-smoothing of levels whose tiles span whole rows forms
+// the z/y interpolation of the coarse correction itself (default) or reads it
+// from a separate pass; applies from the next mg_prepare on.
+bool mg_pz_enabled();
+void set_mg_pz(int on);
+
 }  // namespace rbws

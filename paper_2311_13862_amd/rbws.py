@@ -481,6 +481,7 @@ def exact_fallbacks(reset: bool = True):
 TUNE_SWEEP32 = 0
 TUNE_GRID = 1
 TUNE_TZ = 2
+TUNE_MG_PZ = 3
 
 
 def set_tuning(key: int, value: int):

@@ -43,4 +43,7 @@ def test_tuning_knobs_validate_without_a_gpu():
     assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 128) == EINVAL
     assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 32) == 0
     assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 0) == 0
+    RBWS_TUNE_MG_PZ = 3
+    assert lib.rbws_set_tuning(RBWS_TUNE_MG_PZ, 2) == EINVAL
+    assert lib.rbws_set_tuning(RBWS_TUNE_MG_PZ, 1) == 0
     assert lib.rbws_set_tuning(99, 0) == EINVAL

@@ -90,6 +90,64 @@ def test_vcycle_operator_fp32(rb, spec):
         assert err <= 2e-5, (b, err)
 
 
+@pytest.mark.parametrize("n", [20, 33, 64, 70, 72, 128, 129])
+def test_vcycle_fp32_fused_interpolation_same_bits(rb, n):
+    """Where a level's tiles span whole rows, the FP32 post-smoothing forms the
+    z/y interpolation of the coarse correction itself (RBWS_TUNE_MG_PZ = 1)
+    with the same operations as the separate pass (0): the V-cycle gives the
+    same bits either way.  The sizes cover 32 x 32 (n <= 32), 64 x 16 and
+    128 x 8 whole-row tiles, scalar row ends (70), and n = 129, whose finest
+    level has 32 x 32 tiles that do not span the row."""
+    spec = W.Problem(n, W.KIND_OCTANTS_ANISO if n == 20 else W.KIND_OCTANTS)
+    P = rb.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 3, 300 + n)
+    rhs = np.random.default_rng(n + 7).standard_normal((3, P.ndof))
+    r = torch.tensor(rhs, device="cuda", dtype=torch.float32)
+    out = []
+    try:
+        for pz in (1, 0):
+            rb.set_tuning(rb.TUNE_MG_PZ, pz)
+            s = torch.empty_like(r)
+            P.mg_apply(mu, r, s, precision=rb.FP32_IR)
+            out.append(s.cpu().numpy())
+    finally:
+        rb.set_tuning(rb.TUNE_MG_PZ, 1)
+    assert np.array_equal(out[0], out[1])
+    assert np.all(np.isfinite(out[0])) and np.linalg.norm(out[0]) > 0
+
+
+def test_refinement_fused_interpolation_same_bits(rb):
+    """FP32 MGCG inside FP64 refinement on a batch of two grid sizes (40 and 72)
+    gives the same iterations and solutions with and without the fused
+    interpolation."""
+    specs = [W.Problem(40, W.KIND_OCTANTS), W.Problem(72, W.KIND_OCTANTS)]
+    probs = [rb.Problem(sp) for sp in specs]
+    mus = [W.sample_mu(sp, 0.01, 100.0, 3, 400 + sp.n) for sp in specs]
+    problem_of = np.array([0, 1, 1, 0, 1, 0], dtype=np.int32)
+    cnt = [0, 0]
+    mu = []
+    for q in problem_of:
+        mu.append(mus[q][cnt[q]])
+        cnt[q] += 1
+    mu = np.array(mu)
+    opts = rb.default_opts(tol=1e-10, precision=rb.FP32_IR, precond=rb.PREC_MG, ir_mode=rb.IR_RELIABLE,
+                           eta_inner=0.1, mg_omega=0.9)
+    out = []
+    try:
+        for pz in (1, 0):
+            rb.set_tuning(rb.TUNE_MG_PZ, pz)
+            u = [torch.empty(probs[q].ndof, dtype=torch.float64, device="cuda") for q in problem_of]
+            st = rb.solve(probs, mu, opts, problem_of=problem_of, u_out=u)
+            out.append((st, [t.cpu().numpy() for t in u]))
+    finally:
+        rb.set_tuning(rb.TUNE_MG_PZ, 1)
+    (s1, u1), (s0, u0) = out
+    assert all(s["status"] == rb.SOLVE_CONVERGED for s in s1)
+    assert [s["iters"] for s in s1] == [s["iters"] for s in s0]
+    assert [s["outer_iters"] for s in s1] == [s["outer_iters"] for s in s0]
+    assert all(np.array_equal(a, b) for a, b in zip(u1, u0))
+
+
 def test_vcycle_operator_errors(rb):
     spec = W.Problem(8, W.KIND_OCTANTS)
     P = rb.Problem(spec)
