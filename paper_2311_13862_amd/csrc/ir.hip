@@ -435,12 +435,15 @@ __global__ __launch_bounds__(256) void k_ir_fin_mg(const SolveDev* __restrict__ 
 }
 
 // bit 0: A.p sweep with register-cached coefficients; bit 1: the same for the
-// update sweep.  RBWS_SWEEP32 overrides the default (for tuning runs).
+// update sweep.  RBWS_SWEEP32 overrides the default (for tuning runs).  The
+// default 2 measured fastest on whole-row 128 x 8 tiles at 128^3: the A.p sweep
+// reads the class table (80 VGPRs, six waves per SIMD), the update sweep keeps
+// its coefficients in registers.
 static int g_sweep32 = -1;
 int sweep32_variant() {
   if (g_sweep32 < 0) {
     const char* e = std::getenv("RBWS_SWEEP32");
-    g_sweep32 = e ? std::atoi(e) & 3 : 1;
+    g_sweep32 = e ? std::atoi(e) & 3 : 2;
   }
   return g_sweep32;
 }
