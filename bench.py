@@ -341,9 +341,11 @@ def mg_pre0_bytes(n):
 
 
 def mg_post0_bytes(n):
-    """Per finest-level point: read r, write s (FP32), and the z/y-interpolated
-    coarse correction ezy (n x n rows of nc = (n-1)//2 values per solve)."""
-    return 8.0 + 4.0 * ((n - 1) // 2) / n
+    """Per finest-level point: read r, write s (FP32), and read the coarse
+    correction (nc^3 values per solve, nc = (n-1)//2), which the kernel
+    interpolates itself on tiles that span whole rows (n <= 128)."""
+    nc = (n - 1) // 2
+    return 8.0 + 4.0 * (nc / n) ** 3
 
 
 KERNEL_SOURCES = ("fast.hpp", "ir.hip", "mg.hip", "stencil.hpp", "crdot.hpp", "rbws_internal.hpp")
