@@ -268,10 +268,11 @@ def test_refinement_with_multigrid(rb, spec, mode):
         assert st[b]["iters"] <= 2 * so[b]["iters"] + 10, (st[b]["iters"], so[b]["iters"])
 
 
-def test_refinement_with_multigrid_full_size_sample(rb):
+@pytest.mark.parametrize("eta", [0.1, 0.05])
+def test_refinement_with_multigrid_full_size_sample(rb, eta):
     """The bench's configuration (128^3, FP32 MGCG inside FP64 refinement,
-    reliable updates) on 64 solves; two sampled solutions against the oracle's
-    FP64 MGCG solved to 1e-12."""
+    reliable updates, inner tolerance 0.05; and the library default 0.1) on 64
+    solves; two sampled solutions against the oracle's FP64 MGCG solved to 1e-12."""
     wl = W.octants_128()
     spec = wl.problem
     P = rb.Problem(spec)
@@ -279,7 +280,7 @@ def test_refinement_with_multigrid_full_size_sample(rb):
     picks = (0, 37)
     u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") if b in picks else None for b in range(len(mu))]
     opts = rb.default_opts(tol=wl.tol, precision=rb.FP32_IR, precond=rb.PREC_MG, ir_mode=rb.IR_RELIABLE,
-                           eta_inner=0.1)
+                           eta_inner=eta, mg_omega=0.9)
     st = rb.solve([P], mu, opts, u_out=u)
     torch.cuda.synchronize()
     assert all(s["status"] == rb.SOLVE_CONVERGED for s in st)
