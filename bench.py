@@ -255,6 +255,7 @@ def main():
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
         "t_off_s": round(t_off, 2),
+        "bep": break_even(t_off, value, zero_value, learned),
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
         "spmv_batch": nb,
         "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()},
@@ -378,6 +379,42 @@ def traffic_per_launch(kernel):
     return float(v) if v else None
 
 
+def break_even(t_off, rb_value, zero_value, learned):
+    """The paper's break-even point (Sec. 4.1): BEP = t_off / (t_on(MGCG) -
+    t_on(RBWS)), the number of online solves after which the offline stage has
+    paid for itself.  t_on is the mean online time per solve, here the inverse
+    batched throughput; the zero start with the same preconditioner plays MGCG.
+    For the learned start t_off also counts the training pairs and training.
+    None where a start is not faster than the zero start."""
+    if zero_value is None:
+        return None
+    t_zero = 1.0 / zero_value
+
+    def bep(toff, v):
+        gain = t_zero - 1.0 / v
+        return round(toff / gain, 1) if gain > 0 else None
+
+    out = {"definition": "t_off / (t_on(zero start) - t_on(start)), t_on = 1 / throughput",
+           "t_on_ms": {"zero": round(1e3 * t_zero, 5), "rb": round(1e3 / rb_value, 5)},
+           "rb": bep(t_off, rb_value)}
+    if learned is not None:
+        toff_l = t_off + learned["t_pairs_s"] + learned["t_train_s"]
+        out["t_on_ms"]["learned"] = round(1e3 / learned["value"], 5)
+        out["learned"] = bep(toff_l, learned["value"])
+        out["t_off_learned_s"] = round(toff_l, 3)
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s, omega):
     """The oracle's own solver for the same method on the host cores, on a
     bounded sample: `cores` parameters in parallel (one per thread), each for a
@@ -409,7 +446,8 @@ def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s, omega):
     per_solve = wall / cap * (gpu_inner_mean + (0 if mg else 2 * gpu_outer_mean))
     what = "FP64 MGCG iterations" if mg else "FP32 inner iterations (+2 outer residuals)"
     return {"value": round(cores / per_solve, 5), "unit": "mu-solves/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "s_per_solve_one_core": round(per_solve, 3),
             "sample": f"{cores} parameters of the batch, one per thread, {cap} {what} each; "
                       f"wall {wall:.1f} s, scaled to the GPU's mean {gpu_inner_mean:.0f} inner iterations per solve"}
 
