@@ -55,6 +55,7 @@ def lib():
     if _lib is None:
         _lib = C.CDLL(build())
         d, i, l = C.POINTER(C.c_double), C.c_int, C.c_long
+        lp = C.POINTER(C.c_long)
         pp = C.POINTER(_Problem)
         sig = {
             "orc_exact_dot": (C.c_double, [d, d, l]),
@@ -83,6 +84,9 @@ def lib():
                                   C.POINTER(Stats)]),
             "orc_ir_batch": (None, [pp, d, i, d, d, i, C.c_double, C.c_double, i, i, i, d,
                                     C.POINTER(Stats), i]),
+            "orc_l1roc_greedy": (i, [pp, d, i, i, C.c_double, i, i, d, d, lp, C.POINTER(C.c_int), lp, lp,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int), d, C.POINTER(C.c_int), i]),
+            "orc_l1roc_coeffs": (i, [pp, i, d, lp, i, d, d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -340,6 +344,67 @@ def greedy(problem: Problem, mu_train, N: int, snap_tol: float, prec=PREC_JACOBI
     k = nre.value
     return Basis(problem, V[:k].copy(), AqN, fN, sel[:k].copy(), hist[:k].copy(),
                  [st[i].as_dict() for i in range(k)])
+
+
+class L1rocBasis:
+    """An L1ROC basis (Sec. 3.1, Alg. 4): W (N x m, DEIM-normalised), T (W = U T
+    with U the snapshots), the collocation points (ascending grid indices), the
+    snapshot and residual DEIM points, the selected training indices and the
+    L1 indicator history (row k: with k+1 vectors)."""
+
+    def __init__(self, problem, W, T, pts, xs, xr, selected, hist):
+        self.problem, self.W, self.T, self.pts = problem, W, T, pts
+        self.xs, self.xr, self.selected, self.hist = xs, xr, selected, hist
+
+    @property
+    def N(self) -> int:
+        return self.W.shape[0]
+
+    def coeffs(self, mu) -> np.ndarray:
+        """c = argmin || P (f(mu) - A(mu) W c) || over the collocation points (Householder QR)."""
+        mu = _f64(mu)
+        c = np.empty(self.N)
+        rc = lib().orc_l1roc_coeffs(self.problem.ref, self.N, _dp(self.W),
+                                   self.pts.ctypes.data_as(C.POINTER(C.c_long)), len(self.pts), _dp(mu), _dp(c))
+        if rc != 0:
+            raise FloatingPointError("L1ROC least-squares breakdown")
+        return c
+
+    def lift(self, c) -> np.ndarray:
+        """u0 = W c, each entry a correctly rounded dot."""
+        c = _f64(c)
+        u = np.empty(self.problem.ndof)
+        lib().orc_lift(self.N, self.problem.ndof, _dp(self.W), _dp(c), _dp(u))
+        return u
+
+
+def l1roc_greedy(problem: Problem, mu_train, N: int, snap_tol: float, prec=PREC_JACOBI,
+                 snap_maxit=50000, nthreads=None) -> L1rocBasis:
+    """L1ROC offline greedy (Alg. 4): snapshots by Alg. 1, DEIM of each snapshot
+    and of the current approximation's residual, L1 indicator over the
+    training set, argmax with lowest-index tie-break."""
+    mu_train = _f64(mu_train)
+    nt = mu_train.shape[0]
+    m = problem.ndof
+    W = np.zeros((N, m))
+    T = np.zeros((N, N))
+    pts = np.zeros(2 * N, dtype=np.int64)
+    xs = np.zeros(N, dtype=np.int64)
+    xr = np.zeros(N, dtype=np.int64)
+    npts, nre = C.c_int(0), C.c_int(0)
+    nsr = (C.c_int * 2)()
+    sel = np.full(N, -1, dtype=np.int32)
+    hist = np.full((N, nt), np.nan)
+    lp = C.POINTER(C.c_long)
+    rc = lib().orc_l1roc_greedy(problem.ref, _dp(mu_train), nt, N, snap_tol, prec, snap_maxit, _dp(W), _dp(T),
+                                pts.ctypes.data_as(lp), C.byref(npts), xs.ctypes.data_as(lp),
+                                xr.ctypes.data_as(lp), nsr, sel.ctypes.data_as(C.POINTER(C.c_int)), _dp(hist),
+                                C.byref(nre), nthreads or nthreads_default())
+    if rc != 0:
+        raise FloatingPointError("L1ROC greedy: least-squares breakdown")
+    k = nre.value
+    return L1rocBasis(problem, W[:k].copy(), T[:k, :k].copy(), pts[:npts.value].copy(), xs[:nsr[0]].copy(),
+                      xr[:nsr[1]].copy(), sel[:k].copy(), hist[:k].copy())
 
 
 def rbi_cg(basis: Basis, mu, prec=PREC_JACOBI, tol=1e-10, maxit=50000):

@@ -21,6 +21,9 @@
  *   - the Galerkin reduced system A_N = W^T A W, b_N = W^T b and the
  *     RB solution W A_N^{-1} b_N                        (Eq. "RB system")
  *   - the warm-started solve: RB initial value, then PCG          (Alg. 5)
+ *   - the L1-based reduced over-collocation method: DEIM of snapshots and
+ *     residuals, the collocation least-squares online solve and the L1
+ *     indicator of the greedy                            (Sec. 3.1, Alg. 4)
  *   - an FP32-inner / FP64-outer iterative refinement (an addition, not in
  *     the paper; the FP64 outer residual/update fixes the final accuracy).
  *
@@ -1145,4 +1148,240 @@ void orc_ir_batch(const orc_problem *P, const double *mu, int nmu, const double 
     for (int b = 0; b < nmu; b++)
         orc_ir_solve2(P, mu + (long)b * p, f + b * m, u0 ? u0 + b * m : NULL, prec, tol, eta, kin_max,
                       max_outer, reliable, u + b * m, st + b);
+}
+
+/* ------------------------------------------------------------------ */
+/* L1-based reduced over-collocation, L1ROC (Sec. 3.1, Alg. 4)         */
+/* ------------------------------------------------------------------ */
+/* Readings (each listed in the design notes):
+ *  - DEIM vectors are normalised under point evaluation: B_j[pt_j] = 1 and
+ *    B_j[pt_i] = 0 for i < j, so [B_j[pt_i]] is unit lower triangular.  A DEIM
+ *    step interpolates x at the existing points (forward substitution), forms
+ *    r = x - B c (zero at the existing points by construction, stored as exact
+ *    zeros), takes the point of largest |r_i| (lowest index on ties) and the
+ *    new vector r / r[pt].  Every sum is correctly rounded.
+ *  - The online problem is a minimisation (the printed argmax is a typo):
+ *    c = argmin || P (b - A(mu) W c) ||_2 over the distinct points of
+ *    X = X_s u X_r in ascending grid order, by Householder QR.
+ *  - The L1 indicator uses the coefficients in the basis of the snapshots
+ *    themselves: W = U T with T upper triangular from the DEIM steps, so
+ *    c_U = T c_W and Delta = sum_i |c_U,i|.
+ *  - The first parameter is the training set's first (the set is seeded
+ *    random); the greedy stops early when a parameter would be chosen twice
+ *    or a snapshot's DEIM residual vanishes. */
+
+/* (A(mu) x)_P at one unknown, with the order of apply_faces */
+static double stencil_at(const faces *F, int n, const double *x, long P) {
+    long n2 = (long)n * n;
+    int i = (int)(P % n) + 1, j = (int)((P / n) % n) + 1, k = (int)(P / n2) + 1;
+    double c[6];
+    six(F, n, i, j, k, c);
+    double acc = diag_of(c) * x[P];
+    if (i > 1) acc = fma(-c[0], x[P - 1], acc);
+    if (i < n) acc = fma(-c[1], x[P + 1], acc);
+    if (j > 1) acc = fma(-c[2], x[P - n], acc);
+    if (j < n) acc = fma(-c[3], x[P + n], acc);
+    if (k > 1) acc = fma(-c[4], x[P - n2], acc);
+    if (k < n) acc = fma(-c[5], x[P + n2], acc);
+    return acc;
+}
+
+/* One DEIM step against the nb vectors B (rows of length m) and their points
+ * pt.  Writes the interpolation coefficients c (nb), the new normalised vector
+ * out and its scale *s = r[point]; returns the point, or -1 if r vanishes. */
+static long deim_step(const double *B, const long *pt, int nb, long m, const double *x, double *c,
+                      double *out, double *s) {
+    for (int i = 0; i < nb; i++) {
+        xacc a; xacc_clear(&a);
+        xacc_add(&a, x[pt[i]]);
+        for (int j = 0; j < i; j++) xacc_add_prod(&a, -B[(long)j * m + pt[i]], c[j]);
+        c[i] = xacc_round(&a);
+    }
+    for (long k = 0; k < m; k++) {
+        xacc a; xacc_clear(&a);
+        xacc_add(&a, x[k]);
+        for (int j = 0; j < nb; j++) xacc_add_prod(&a, -c[j], B[(long)j * m + k]);
+        out[k] = xacc_round(&a);
+    }
+    for (int i = 0; i < nb; i++) out[pt[i]] = 0.0;
+    long best = -1;
+    double bv = 0.0;
+    for (long k = 0; k < m; k++)
+        if (fabs(out[k]) > bv) { bv = fabs(out[k]); best = k; }
+    if (best < 0) return -1;
+    *s = out[best];
+    for (long k = 0; k < m; k++) out[k] = out[k] / *s;
+    return best;
+}
+
+/* min || A c - b ||_2 for A (M x N row-major, overwritten), M >= N, by
+ * Householder QR; b (M) is overwritten.  Returns -1 on a zero column. */
+static int lsq_qr(int M, int N, double *A, double *b, double *c) {
+    for (int k = 0; k < N; k++) {
+        xacc a; xacc_clear(&a);
+        for (int i = k; i < M; i++) xacc_add_prod(&a, A[(long)i * N + k], A[(long)i * N + k]);
+        double nrm = sqrt(xacc_round(&a));
+        if (!(nrm > 0.0)) return -1;
+        double akk = A[(long)k * N + k];
+        double alpha = akk > 0.0 ? -nrm : nrm;
+        /* v = (akk - alpha, A[k+1..][k]); v^T v = 2 nrm (nrm + |akk|) */
+        double vk = akk - alpha;
+        double vtv = 2.0 * nrm * (nrm + fabs(akk));
+        for (int j = k + 1; j <= N; j++) {            /* j == N: the right-hand side */
+            xacc d; xacc_clear(&d);
+            xacc_add_prod(&d, vk, j < N ? A[(long)k * N + j] : b[k]);
+            for (int i = k + 1; i < M; i++) xacc_add_prod(&d, A[(long)i * N + k], j < N ? A[(long)i * N + j] : b[i]);
+            double t = 2.0 * xacc_round(&d) / vtv;
+            if (j < N) {
+                A[(long)k * N + j] -= t * vk;
+                for (int i = k + 1; i < M; i++) A[(long)i * N + j] -= t * A[(long)i * N + k];
+            } else {
+                b[k] -= t * vk;
+                for (int i = k + 1; i < M; i++) b[i] -= t * A[(long)i * N + k];
+            }
+        }
+        A[(long)k * N + k] = alpha;
+    }
+    for (int k = N - 1; k >= 0; k--) {
+        xacc a; xacc_clear(&a);
+        xacc_add(&a, b[k]);
+        for (int j = k + 1; j < N; j++) xacc_add_prod(&a, -A[(long)k * N + j], c[j]);
+        c[k] = xacc_round(&a) / A[(long)k * N + k];
+    }
+    return 0;
+}
+
+/* the collocation least-squares problem at mu: rows (A(mu) w_j)[x_i] and
+ * f_h(x_i) for the npts points; c (nb).  Returns -1 on breakdown. */
+static int l1roc_solve(const orc_problem *P, const double *mu, int nb, const double *W, const long *pts,
+                       int npts, double *c) {
+    long m = ndof_of(P);
+    if (npts < nb) return -1;
+    faces F = faces_for_mu(P, mu);
+    double *A = malloc(sizeof(double) * npts * nb), *b = malloc(sizeof(double) * npts);
+    double *f = malloc(sizeof(double) * m);
+    orc_rhs(P, mu, f);
+    for (int i = 0; i < npts; i++) {
+        for (int j = 0; j < nb; j++) A[(long)i * nb + j] = stencil_at(&F, P->n, W + (long)j * m, pts[i]);
+        b[i] = f[pts[i]];
+    }
+    int rc = lsq_qr(npts, nb, A, b, c);
+    free(A); free(b); free(f);
+    faces_free(F);
+    return rc;
+}
+
+int orc_l1roc_coeffs(const orc_problem *P, int nb, const double *W, const long *pts, int npts,
+                     const double *mu, double *c) {
+    return l1roc_solve(P, mu, nb, W, pts, npts, c);
+}
+
+/* L1 indicator: || T c_W ||_1 with T (ld x ld, upper triangular) */
+static double l1_indicator(int nb, int ld, const double *T, const double *cw) {
+    double cu[128];
+    for (int i = 0; i < nb; i++) {
+        xacc a; xacc_clear(&a);
+        for (int j = i; j < nb; j++) xacc_add_prod(&a, T[(long)i * ld + j], cw[j]);
+        cu[i] = fabs(xacc_round(&a));
+    }
+    return orc_exact_sum(cu, nb);
+}
+
+static int cmp_long(const void *a, const void *b) {
+    long x = *(const long *)a, y = *(const long *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* distinct points of Xs u Xr in ascending order */
+static int point_set(const long *xs, int ns, const long *xr, int nr, long *out) {
+    int k = 0;
+    for (int i = 0; i < ns; i++) out[k++] = xs[i];
+    for (int i = 0; i < nr; i++) out[k++] = xr[i];
+    qsort(out, k, sizeof(long), cmp_long);
+    int u = 0;
+    for (int i = 0; i < k; i++)
+        if (u == 0 || out[i] != out[u - 1]) out[u++] = out[i];
+    return u;
+}
+
+/* Outputs: W (N x m), T (N x N), pts (2N) and *npts (the point set X), the
+ * snapshot points xs (N) and residual points xr (N) with their counts nsr[2],
+ * selected (N), hist (N x ntrain; row k = L1 indicator with k+1 vectors),
+ * *nreached.  Returns 0, or -1 on a least-squares breakdown or N > 120. */
+int orc_l1roc_greedy(const orc_problem *P, const double *mu_train, int ntrain, int N, double snap_tol,
+                     int prec, int snap_maxit, double *W, double *T, long *pts, int *npts, long *xs,
+                     long *xr, int *nsr, int *selected, double *hist, int *nreached, int nthreads) {
+    if (N > 120) return -1;
+    long m = ndof_of(P);
+    int p = P->kind == ORC_BLOCKS ? P->nblocks : (P->kind == ORC_OCTANTS ? 8 : 24 + (P->f_kind == ORC_F_GAUSS ? 3 : 0));
+    double *R = malloc(sizeof(double) * N * m);
+    double *u = malloc(sizeof(double) * m), *f = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    double *tmp = malloc(sizeof(double) * m);
+    double c[128], cl[128], s = 0.0;
+    int ns = 0, nr = 0, nb = 0, rc = 0;
+    memset(T, 0, sizeof(double) * N * N);
+    *npts = 0;
+    /* first snapshot */
+    orc_rhs(P, mu_train, f);
+    orc_stats st;
+    orc_cg(P, mu_train, f, NULL, prec, snap_tol, snap_maxit, u, &st, NULL);
+    long pt = deim_step(W, xs, 0, m, u, c, W, &s);
+    if (pt >= 0) {
+        T[0] = 1.0 / s;
+        xs[ns++] = pt;
+        selected[nb++] = 0;
+        *npts = point_set(xs, ns, xr, nr, pts);
+    }
+    while (nb > 0) {
+        double *row = hist + (long)(nb - 1) * ntrain;
+        int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+        for (int b = 0; b < ntrain; b++) {
+            double cw[128];
+            if (l1roc_solve(P, mu_train + (long)b * p, nb, W, pts, *npts, cw) != 0) {
+#pragma omp atomic write
+                bad = 1;
+                row[b] = NAN;
+            } else {
+                row[b] = l1_indicator(nb, N, T, cw);
+            }
+        }
+        if (bad) { rc = -1; break; }
+        if (nb == N) break;
+        int best = 0;
+        for (int b = 1; b < ntrain; b++) if (row[b] > row[best]) best = b;
+        int dup = 0;
+        for (int j = 0; j < nb; j++) if (selected[j] == best) dup = 1;
+        if (dup) break;
+        const double *mul = mu_train + (long)best * p;
+        /* residual of the current approximation at the chosen parameter */
+        if (l1roc_solve(P, mul, nb, W, pts, *npts, cl) != 0) { rc = -1; break; }
+        orc_lift(nb, m, W, cl, tmp);
+        orc_apply(P, mul, tmp, r);
+        orc_rhs(P, mul, f);
+        for (long i = 0; i < m; i++) r[i] = f[i] - r[i];
+        /* the snapshot and its DEIM step */
+        orc_cg(P, mul, f, NULL, prec, snap_tol, snap_maxit, u, &st, NULL);
+        pt = deim_step(W, xs, nb, m, u, c, W + (long)nb * m, &s);
+        if (pt < 0) break;
+        /* W_new = (u - sum_j c_j W_j) / s  =>  T[:, nb] = (e_nb - sum_j c_j T[:, j]) / s */
+        for (int i = 0; i < nb; i++) {
+            xacc a; xacc_clear(&a);
+            for (int j = i; j < nb; j++) xacc_add_prod(&a, -c[j], T[(long)i * N + j]);
+            T[(long)i * N + nb] = xacc_round(&a) / s;
+        }
+        T[(long)nb * N + nb] = 1.0 / s;
+        xs[ns++] = pt;
+        /* the residual's DEIM step adds a second point */
+        double sr = 0.0;
+        long ptr = deim_step(R, xr, nr, m, r, c, R + (long)nr * m, &sr);
+        if (ptr >= 0) xr[nr++] = ptr;
+        selected[nb++] = best;
+        *npts = point_set(xs, ns, xr, nr, pts);
+    }
+    *nreached = nb;
+    nsr[0] = ns;
+    nsr[1] = nr;
+    free(R); free(u); free(f); free(r); free(tmp);
+    return rc;
 }
