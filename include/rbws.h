@@ -221,6 +221,36 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
 rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
                           int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
                           double* indicator_hist, int* n_reached);
+/* L1-based reduced over-collocation (Sec. 3.1, Alg. 4), the paper's own RB
+ * variant.  Same arguments as rbws_rb_build; f = 1 only, N in [1, 40].
+ * Step 1: snapshot u(mu_train[0]) by PCG; DEIM gives the first vector
+ * w_1 = u / u(x_1), x_1 = argmax |u|.  Step n: the collocation least-squares
+ * solve c(mu) = argmin || P (f - A(mu) W c) ||_2 at the collocation points X
+ * (the distinct snapshot and residual DEIM points, ascending grid indices,
+ * |X| <= 2n - 1) for every training parameter; the L1 indicator
+ * ||c_U(mu)||_1 in the basis of the snapshots (W = U T); the first maximiser
+ * mu_l; then (i) the residual r = f - A(mu_l) W c(mu_l) and its DEIM step
+ * against the residual basis (a new residual point), (ii) the snapshot
+ * u(mu_l) and its DEIM step against W (a new vector w_n, w_n(x_n) = 1, and a
+ * new snapshot point).  DEIM step of x against vectors B with points x_i:
+ * the unit lower-triangular interpolation system, r = x - B c (exact zeros
+ * at the existing points), x_new = argmax |r| (lowest index on ties),
+ * b_new = r / r(x_new).  Every inner product is correctly rounded and the
+ * least-squares problem is solved by Householder QR with separately rounded
+ * updates, so the basis is reproducible.  rbws_rb_coeffs, rbws_rb_lift and
+ * rbws_solve accept the result like a Galerkin basis; the learned start's
+ * cheap fallback rule, rbws_basis_save and the reduced matrices of
+ * rbws_basis_get do not apply to it.  Errors as rbws_rb_build, plus EINVAL
+ * for a non-constant source. */
+rbws_status rbws_rb_build_l1roc(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
+                                int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
+                                double* indicator_hist, int* n_reached);
+/* The collocation points (npts <= 2N - 1, ascending grid indices), the
+ * snapshot and residual DEIM points in selection order, and T (N x N, upper
+ * triangular, W = U T) of an L1ROC basis; each output nullable; buffers of
+ * 2N, N, N and N^2 entries suffice.  ESTATE for a Galerkin basis. */
+rbws_status rbws_basis_l1roc(const rbws_basis* b, int* npts, long long* pts, int* nxs, long long* xs, int* nxr,
+                             long long* xr, double* T);
 void rbws_basis_destroy(rbws_basis* b);
 /* N (reached), Q, ndof and the largest final indicator over the training set. */
 rbws_status rbws_basis_info(const rbws_basis* b, int* N, int* nq, long long* ndof, double* final_max);

@@ -133,6 +133,8 @@ void learned_start(Batch& B, const std::vector<const Basis*>& bl, const std::vec
   std::vector<int> pick(ns, 0);
   bool any = false;
   for (int b = 0; b < ns; b++) {
+    RBWS_REQUIRE(fallback == 0 || bl[B.sd_h[b].prob]->kind == 0, RBWS_EINVAL,
+                 "the cheap fallback rule needs a Galerkin basis (its indicator is a residual norm)");
     const double thr = bl[B.sd_h[b].prob]->final_max;
     const bool need = fallback == 0 || !(rel_m[b] <= thr);
     pick[b] = need ? 1 : 0;
@@ -319,6 +321,43 @@ rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, i
   API_END
 }
 
+rbws_status rbws_rb_build_l1roc(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
+                                int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
+                                double* indicator_hist, int* n_reached) {
+  API_BEGIN
+  RBWS_REQUIRE(p && mu_train && out, RBWS_EINVAL, "NULL argument");
+  RBWS_REQUIRE(precond == RBWS_PREC_NONE || precond == RBWS_PREC_JACOBI, RBWS_EINVAL, "bad precond");
+  RBWS_REQUIRE(snap_maxit >= 1, RBWS_EINVAL, "snap_maxit < 1");
+  *out = nullptr;
+  Basis* b = rb_build_l1roc(PP(p), mu_train, ntrain, N, snap_tol, precond, snap_maxit, 0, (hipStream_t)stream);
+  if (selected)
+    for (int i = 0; i < N; i++) selected[i] = i < b->N ? b->selected[i] : -1;
+  if (indicator_hist)
+    for (size_t i = 0; i < (size_t)N * ntrain; i++)
+      indicator_hist[i] = i < b->hist.size() ? b->hist[i] : std::nan("");
+  if (n_reached) *n_reached = b->N;
+  *out = reinterpret_cast<rbws_basis*>(b);
+  API_END
+}
+
+rbws_status rbws_basis_l1roc(const rbws_basis* b, int* npts, long long* pts, int* nxs, long long* xs, int* nxr,
+                             long long* xr, double* T) {
+  API_BEGIN
+  RBWS_REQUIRE(b != nullptr, RBWS_EINVAL, "basis is NULL");
+  const Basis* B = BB(b);
+  RBWS_REQUIRE(B->kind == 1, RBWS_ESTATE, "not an L1ROC basis");
+  if (npts) *npts = (int)B->pts.size();
+  if (pts) std::copy(B->pts.begin(), B->pts.end(), pts);
+  if (nxs) *nxs = (int)B->xs.size();
+  if (xs) std::copy(B->xs.begin(), B->xs.end(), xs);
+  if (nxr) *nxr = (int)B->xr.size();
+  if (xr) std::copy(B->xr.begin(), B->xr.end(), xr);
+  if (T)
+    for (int i = 0; i < B->N; i++)
+      for (int j = 0; j < B->N; j++) T[(size_t)i * B->N + j] = B->T[(size_t)i * B->Nmax + j];
+  API_END
+}
+
 void rbws_basis_destroy(rbws_basis* b) { delete BB(b); }
 
 rbws_status rbws_basis_info(const rbws_basis* b, int* N, int* nq, long long* ndof, double* final_max) {
@@ -340,6 +379,7 @@ rbws_status rbws_basis_get(const rbws_basis* b, double* V, double* AqN, double* 
     RBWS_HIP(hipSetDevice(B->prob->device));
     RBWS_HIP(hipMemcpy(V, B->V.ptr, sizeof(double) * B->N * B->ndof, hipMemcpyDeviceToHost));
   }
+  RBWS_REQUIRE(B->kind == 0 || (!AqN && !fN), RBWS_EINVAL, "an L1ROC basis has no reduced matrices");
   if (AqN)
     for (int q = 0; q < B->Q; q++)
       for (int i = 0; i < B->N; i++)

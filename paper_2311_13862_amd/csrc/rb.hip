@@ -197,8 +197,8 @@ struct CholShared {
 
 // value of sum over lanes of the terms each lane added to `a` (all 64 lanes
 // call); exact fallback adds the same terms through `add_terms`
-template <typename F>
-__device__ __forceinline__ double wave_sum(CholShared& sh, CrAcc a, int force_exact, F add_terms) {
+template <typename S, typename F>
+__device__ __forceinline__ double wave_sum(S& sh, CrAcc a, int force_exact, F add_terms) {
   a = cr_wave_reduce(a);
   if (threadIdx.x == 0) {
     double r = 0.0;
@@ -441,6 +441,12 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const double* __restrict__ V,
 // ---------------------------------------------------------------------------
 void Basis::upload(hipStream_t s) {
   const int dev = prob->device;
+  if (kind == 1) {
+    long long* pd = (long long*)pts_d.get(sizeof(long long) * std::max<size_t>(pts.size(), 1), dev);
+    RBWS_HIP(hipMemcpyAsync(pd, pts.data(), sizeof(long long) * pts.size(), hipMemcpyHostToDevice, s));
+    double* td = (double*)T_d.get(sizeof(double) * T.size(), dev);
+    RBWS_HIP(hipMemcpyAsync(td, T.data(), sizeof(double) * T.size(), hipMemcpyHostToDevice, s));
+  }
   if (est) {
     double* gd = (double*)G_d.get(sizeof(double) * G.size(), dev);
     RBWS_HIP(hipMemcpyAsync(gd, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, s));
@@ -556,10 +562,22 @@ static bool project_sources(Batch& B, const std::vector<const Basis*>& bases, do
   return any;
 }
 
+static int l1roc_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride,
+                        double* delta, int force_exact, hipStream_t s);
+
 int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride, int force_exact,
               hipStream_t s) {
   const int ns = B.nsolve;
   if (ns == 0) return 0;
+  int nl1 = 0;
+  for (int b = 0; b < ns; b++) {
+    const Basis* bs = bases[B.sd_h[b].prob];
+    nl1 += bs != nullptr && bs->kind == 1;
+  }
+  if (nl1 > 0) {
+    RBWS_REQUIRE(nl1 == ns, RBWS_EINVAL, "L1ROC and Galerkin bases cannot share a batch");
+    return l1roc_coeffs(B, bases, c, cstride, nullptr, force_exact, s);
+  }
   std::vector<RbDev> h(ns);
   for (int b = 0; b < ns; b++) {
     const Basis* bs = bases[B.sd_h[b].prob];
@@ -933,6 +951,7 @@ struct BasisHeader {
 };
 
 void basis_save(const Basis* b, const char* path) {
+  RBWS_REQUIRE(b->kind == 0, RBWS_EINVAL, "saving an L1ROC basis is not supported");
   RBWS_REQUIRE(b && path, RBWS_EINVAL, "NULL argument");
   BasisHeader h;
   std::memset(&h, 0, sizeof h);
@@ -1009,6 +1028,450 @@ Basis* basis_load(const Problem* P, const char* path, hipStream_t s) {
   }
   std::fclose(fp);
   return b;
+}
+
+// ---------------------------------------------------------------------------
+// L1-based reduced over-collocation, L1ROC (Sec. 3.1, Alg. 4)
+// ---------------------------------------------------------------------------
+// The basis vectors are DEIM-normalised (w_j(x_j) = 1 and w_j(x_i) = 0 for
+// i < j at the snapshot points).  Online, c minimises ||P (f - A(mu) W c)||_2
+// over the collocation points by Householder QR, one wave per parameter:
+// every inner product is correctly rounded and every update is a separately
+// rounded product and difference, so the result is that of the sequential
+// definition, bit for bit.  The greedy's indicator is ||T c||_1 (W = U T).
+
+constexpr int kL1MaxM = 2 * kL1MaxN;
+
+struct L1Dev {           // per solve
+  const double* W;       // nb x ndof
+  const long long* pts;  // npts collocation points
+  const double* T;       // ld x ld, or null
+  int nb, npts, ld, pad;
+};
+
+struct L1Shared {
+  double A[kL1MaxM * kL1MaxN];
+  double b[kL1MaxM];
+  double c[kL1MaxN];
+  XAcc xa;
+  uint32_t dig[XA_WORDS];
+  double val;
+  int ok;
+};
+
+// (A(mu) x) at one unknown: coefficients from the solve's class table, the
+// operations and order of the sweeps (d x, then fma over x-, x+, y-, y+, z-, z+)
+__device__ double point_apply(const GridDev& g, const double* kt, const double* x, long long pt) {
+  const int n = g.n;
+  const long long n2 = (long long)n * n;
+  const int i = (int)(pt % n) + 1, j = (int)((pt / n) % n) + 1, k = (int)(pt / n2) + 1;
+  const int N1 = g.ncode[1], N2 = g.ncode[2];
+  const int oY = g.ndir == 3 ? g.nclass : 0, oZ = g.ndir == 3 ? 2 * g.nclass : 0;
+  const int cxn = g.code[0][0][i - 1], cxm = g.code[0][1][i - 1], cxp = g.code[0][1][i];
+  const int cyn = g.code[1][0][j - 1], cym = g.code[1][1][j - 1], cyp = g.code[1][1][j];
+  const int czn = g.code[2][0][k - 1], czm = g.code[2][1][k - 1], czp = g.code[2][1][k];
+  const double c0 = kt[(cxm * N1 + cyn) * N2 + czn], c1 = kt[(cxp * N1 + cyn) * N2 + czn];
+  const double c2 = kt[oY + (cxn * N1 + cym) * N2 + czn], c3 = kt[oY + (cxn * N1 + cyp) * N2 + czn];
+  const double c4 = kt[oZ + (cxn * N1 + cyn) * N2 + czm], c5 = kt[oZ + (cxn * N1 + cyn) * N2 + czp];
+  const double d = ((((c0 + c1) + c2) + c3) + c4) + c5;
+  double acc = d * x[pt];
+  if (i > 1) acc = __fma_rn(-c0, x[pt - 1], acc);
+  if (i < n) acc = __fma_rn(-c1, x[pt + 1], acc);
+  if (j > 1) acc = __fma_rn(-c2, x[pt - n], acc);
+  if (j < n) acc = __fma_rn(-c3, x[pt + n], acc);
+  if (k > 1) acc = __fma_rn(-c4, x[pt - n2], acc);
+  if (k < n) acc = __fma_rn(-c5, x[pt + n2], acc);
+  return acc;
+}
+
+// Collocation least squares of one solve per 64-thread block (f = 1: f_h = h^2
+// at every point); optionally the L1 indicator sum_i |sum_{j>=i} T_ij c_j|.
+__global__ __launch_bounds__(64) void k_l1_lsq(const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
+                                               const double* __restrict__ kap, const L1Dev* __restrict__ l1,
+                                               double* __restrict__ cout, int cstride, double* __restrict__ delta,
+                                               int* bad, int force_exact) {
+  __shared__ L1Shared sh;
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const SolveDev S = sd[b];
+  const ProbDev& P = pd[S.prob];
+  const L1Dev L = l1[b];
+  const int nb = L.nb, M = L.npts;
+  const long long nd = P.g.ndof;
+  const double* kt = kap + S.kap_off;
+  for (int e = lane; e < M * nb; e += 64) {
+    const int i = e / nb, j = e - i * nb;
+    sh.A[i * kL1MaxN + j] = point_apply(P.g, kt, L.W + (long long)j * nd, L.pts[i]);
+  }
+  for (int i = lane; i < M; i += 64) sh.b[i] = P.h2;
+  __syncthreads();
+  int fail = 0;
+  for (int k = 0; k < nb; k++) {
+    CrAcc a = cr_zero();
+    for (int i = k + lane; i < M; i += 64) cr_add_prod(a, sh.A[i * kL1MaxN + k], sh.A[i * kL1MaxN + k]);
+    const double n2v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      for (int i = k + lane; i < M; i += 64) xa_add_prod(x, sh.A[i * kL1MaxN + k], sh.A[i * kL1MaxN + k]);
+    });
+    const double nrm = sqrt(n2v);
+    if (!(nrm > 0.0)) {
+      fail = 1;
+      break;
+    }
+    const double akk = sh.A[k * kL1MaxN + k];
+    const double alpha = akk > 0.0 ? -nrm : nrm;
+    const double vk = akk - alpha;
+    const double vtv = 2.0 * nrm * (nrm + fabs(akk));
+    for (int j = k + 1; j <= nb; j++) {  // j == nb: the right-hand side
+      auto at = [&](int i) -> double& { return j < nb ? sh.A[i * kL1MaxN + j] : sh.b[i]; };
+      CrAcc d = cr_zero();
+      if (lane == 0) cr_add_prod(d, vk, at(k));
+      for (int i = k + 1 + lane; i < M; i += 64) cr_add_prod(d, sh.A[i * kL1MaxN + k], at(i));
+      const double dv = wave_sum(sh, d, force_exact, [&](XAcc* x) {
+        if (lane == 0) xa_add_prod(x, vk, at(k));
+        for (int i = k + 1 + lane; i < M; i += 64) xa_add_prod(x, sh.A[i * kL1MaxN + k], at(i));
+      });
+      const double t = 2.0 * dv / vtv;
+      if (lane == 0) at(k) = at(k) - t * vk;
+      for (int i = k + 1 + lane; i < M; i += 64) at(i) = at(i) - t * sh.A[i * kL1MaxN + k];
+      __syncthreads();
+    }
+    if (lane == 0) sh.A[k * kL1MaxN + k] = alpha;
+    __syncthreads();
+  }
+  if (fail) {
+    if (lane == 0) {
+      atomicAdd(bad, 1);
+      if (delta) delta[b] = __builtin_nan("");
+    }
+    for (int j = lane; j < cstride; j += 64) cout[(long long)b * cstride + j] = __builtin_nan("");
+    return;
+  }
+  for (int k = nb - 1; k >= 0; k--) {  // R c = Q^T b
+    CrAcc a = cr_zero();
+    if (lane == 0) cr_add(a, sh.b[k]);
+    for (int j = k + 1 + lane; j < nb; j += 64) cr_add_prod(a, -sh.A[k * kL1MaxN + j], sh.c[j]);
+    const double v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane == 0) xa_add(x, sh.b[k]);
+      for (int j = k + 1 + lane; j < nb; j += 64) xa_add_prod(x, -sh.A[k * kL1MaxN + j], sh.c[j]);
+    });
+    if (lane == 0) sh.c[k] = v / sh.A[k * kL1MaxN + k];
+    __syncthreads();
+  }
+  for (int j = lane; j < cstride; j += 64) cout[(long long)b * cstride + j] = j < nb ? sh.c[j] : 0.0;
+  if (delta && L.T) {
+    double cu = 0.0;  // lane i: |(T c)_i|
+    for (int i = 0; i < nb; i++) {
+      CrAcc a = cr_zero();
+      if (lane >= i && lane < nb) cr_add_prod(a, L.T[(long long)i * L.ld + lane], sh.c[lane]);
+      const double v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+        if (lane >= i && lane < nb) xa_add_prod(x, L.T[(long long)i * L.ld + lane], sh.c[lane]);
+      });
+      if (lane == i) cu = fabs(v);
+    }
+    CrAcc a = cr_zero();
+    if (lane < nb) cr_add(a, cu);
+    const double sum = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane < nb) xa_add(x, cu);
+    });
+    if (lane == 0) delta[b] = sum;
+  }
+}
+
+struct WaveShared {
+  XAcc xa;
+  uint32_t dig[XA_WORDS];
+  double val;
+  int ok;
+  double c[kL1MaxN + 1];
+};
+
+// DEIM interpolation coefficients of x against the nb vectors B at their
+// points: sum_{j<=i} B_j(x_i) c_j = x(x_i) with B_i(x_i) = 1 (forward
+// substitution, each entry correctly rounded); one 64-thread block
+__global__ __launch_bounds__(64) void k_deim_coef(const double* __restrict__ B, long long nd,
+                                                  const long long* __restrict__ pts, int nb,
+                                                  const double* __restrict__ x, double* __restrict__ c,
+                                                  int force_exact) {
+  __shared__ WaveShared sh;
+  const int lane = threadIdx.x;
+  for (int i = 0; i < nb; i++) {
+    const long long pi = pts[i];
+    CrAcc a = cr_zero();
+    if (lane == 0) cr_add(a, x[pi]);
+    for (int j = lane; j < i; j += 64) cr_add_prod(a, -B[(long long)j * nd + pi], sh.c[j]);
+    const double v = wave_sum(sh, a, force_exact, [&](XAcc* xa) {
+      if (lane == 0) xa_add(xa, x[pi]);
+      for (int j = lane; j < i; j += 64) xa_add_prod(xa, -B[(long long)j * nd + pi], sh.c[j]);
+    });
+    if (lane == 0) sh.c[i] = v;
+    __syncthreads();
+  }
+  for (int j = lane; j < nb; j += 64) c[j] = sh.c[j];
+}
+
+// T[i][nb] = (-sum_{j=i}^{nb-1} c_j T[i][j]) / s for i < nb, T[nb][nb] = 1 / s
+__global__ __launch_bounds__(64) void k_l1_tcol(double* __restrict__ T, int ld, const double* __restrict__ c,
+                                                int nb, const double* __restrict__ sp, int force_exact) {
+  __shared__ WaveShared sh;
+  const int lane = threadIdx.x;
+  const double s = *sp;
+  for (int i = 0; i < nb; i++) {
+    CrAcc a = cr_zero();
+    if (lane >= i && lane < nb) cr_add_prod(a, -c[lane], T[(long long)i * ld + lane]);
+    const double v = wave_sum(sh, a, force_exact, [&](XAcc* x) {
+      if (lane >= i && lane < nb) xa_add_prod(x, -c[lane], T[(long long)i * ld + lane]);
+    });
+    if (lane == 0) T[(long long)i * ld + nb] = v / s;
+    __syncthreads();
+  }
+  if (lane == 0) T[(long long)nb * ld + nb] = 1.0 / s;
+}
+
+__global__ void k_zero_at(double* __restrict__ r, const long long* __restrict__ pts, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) r[pts[i]] = 0.0;
+}
+
+// largest |r_k|, lowest index on ties: per-block candidates, then one block
+struct ValIdx {
+  double v;
+  long long i;
+};
+__device__ __forceinline__ ValIdx vi_better(ValIdx a, ValIdx b) {
+  return (b.v > a.v || (b.v == a.v && b.i >= 0 && (a.i < 0 || b.i < a.i))) ? b : a;
+}
+__device__ ValIdx vi_block(ValIdx m) {
+  __shared__ ValIdx w[4];
+  for (int o = 32; o >= 1; o >>= 1) {
+    ValIdx t{__shfl_xor(m.v, o, 64), __shfl_xor(m.i, o, 64)};
+    m = vi_better(m, t);
+  }
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = w[0];
+  for (int k = 1; k < (int)(blockDim.x >> 6); k++) m = vi_better(m, w[k]);
+  __syncthreads();
+  return m;
+}
+__global__ __launch_bounds__(256) void k_absmax_part(const double* __restrict__ r, long long nd,
+                                                     ValIdx* __restrict__ part) {
+  ValIdx m{0.0, -1};
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += (long long)gridDim.x * blockDim.x) {
+    const double a = fabs(r[k]);
+    if (a > m.v) m = ValIdx{a, k};  // ascending k per thread: the first maximiser
+  }
+  m = vi_block(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+// part[0] <- the overall winner, with the signed value r[i] in out[0] and 1 / r[i] unused
+__global__ __launch_bounds__(256) void k_absmax_final(ValIdx* __restrict__ part, int nparts,
+                                                      const double* __restrict__ r, double* __restrict__ sval) {
+  ValIdx m{0.0, -1};
+  for (int k = threadIdx.x; k < nparts; k += blockDim.x) m = vi_better(m, part[k]);
+  m = vi_block(m);
+  if (threadIdx.x == 0) {
+    part[0] = m;
+    *sval = m.i >= 0 ? r[m.i] : 0.0;
+  }
+}
+
+__global__ void k_neg(double* __restrict__ out, const double* __restrict__ in, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = -in[i];
+}
+__global__ void k_rhs_minus(double* __restrict__ r, const double* __restrict__ au, double f, long long nd) {
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nd; c += (long long)gridDim.x * blockDim.x)
+    r[c] = f - au[c];
+}
+
+static int l1roc_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride,
+                        double* delta, int force_exact, hipStream_t s) {
+  const int ns = B.nsolve;
+  std::vector<L1Dev> h(ns);
+  for (int b = 0; b < ns; b++) {
+    const Basis* bs = bases[B.sd_h[b].prob];
+    RBWS_REQUIRE(bs != nullptr && bs->kind == 1, RBWS_ESTATE, "an L1ROC basis is required");
+    RBWS_REQUIRE(bs->prob == B.probs[B.sd_h[b].prob], RBWS_EINVAL, "basis belongs to another problem");
+    RBWS_REQUIRE(bs->N <= cstride, RBWS_EINVAL, "coefficient stride too small");
+    RBWS_REQUIRE(bs->N <= kL1MaxN && (int)bs->pts.size() <= kL1MaxM && (int)bs->pts.size() >= bs->N,
+                 RBWS_EINVAL, "L1ROC basis outside the kernel's limits");
+    h[b] = L1Dev{(const double*)bs->V.ptr, (const long long*)bs->pts_d.ptr, (const double*)bs->T_d.ptr, bs->N,
+                 (int)bs->pts.size(), bs->Nmax, 0};
+  }
+  RBWS_SCRATCH(l1d);
+  RBWS_SCRATCH(badb);
+  L1Dev* d = (L1Dev*)l1d.get(sizeof(L1Dev) * ns, B.device);
+  int* bad = (int*)badb.get(sizeof(int), B.device);
+  RBWS_HIP(hipMemcpyAsync(d, h.data(), sizeof(L1Dev) * ns, hipMemcpyHostToDevice, s));
+  RBWS_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  ktimer().begin(s, KK_COEF);
+  hipLaunchKernelGGL(k_l1_lsq, dim3(ns), dim3(64), 0, s, (const SolveDev*)B.sd.ptr, (const ProbDev*)B.pd.ptr,
+                     (const double*)B.kap64.ptr, (const L1Dev*)d, c, cstride, delta, bad, force_exact);
+  ktimer().end(s);
+  RBWS_HIP(hipGetLastError());
+  int hb = 0;
+  RBWS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  return hb;
+}
+
+// one DEIM step of x against the nb vectors in Bv (points pt_d / pt): the
+// new normalised vector goes to out; returns the new point or -1
+static long long deim_gpu(const double* Bv, int nb, const long long* pt_d, long long nd, const double* x,
+                          double* out, double* coef, double* sval, double* sc_host, Redo* redo, ValIdx* part,
+                          int nparts, int fe, hipStream_t s) {
+  hipLaunchKernelGGL(k_deim_coef, dim3(1), dim3(64), 0, s, Bv, nd, pt_d, nb, x, coef, fe);
+  RBWS_HIP(hipMemcpyAsync(out, x, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+  if (nb > 0) {
+    RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
+    hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, out, Bv, (const double*)coef, nb, nd, redo, fe);
+    hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, out, Bv, (const double*)coef, nb, nd,
+                       (const Redo*)redo);
+    hipLaunchKernelGGL(k_zero_at, dim3(1), dim3(64), 0, s, out, pt_d, nb);
+  }
+  hipLaunchKernelGGL(k_absmax_part, dim3(nparts), dim3(256), 0, s, (const double*)out, nd, part);
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, part, nparts, (const double*)out, sval);
+  RBWS_HIP(hipGetLastError());
+  ValIdx w;
+  RBWS_HIP(hipMemcpyAsync(&w, part, sizeof(ValIdx), hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipMemcpyAsync(sc_host, sval, sizeof(double), hipMemcpyDeviceToHost, s));
+  RBWS_HIP(hipStreamSynchronize(s));
+  if (w.i < 0) return -1;
+  hipLaunchKernelGGL(k_div, dim3(2048), dim3(256), 0, s, out, (const double*)out, (const double*)sval, nd);
+  RBWS_HIP(hipGetLastError());
+  return w.i;
+}
+
+Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol, int prec,
+                      int snap_maxit, int flags, hipStream_t s) {
+  RBWS_REQUIRE(ntrain >= 1, RBWS_EINVAL, "empty training set");
+  RBWS_REQUIRE(N >= 1 && N <= kL1MaxN, RBWS_EINVAL, "N must be in [1, 40] for L1ROC");
+  RBWS_REQUIRE(N <= ntrain, RBWS_EINVAL, "N exceeds the training set");
+  RBWS_REQUIRE(snap_tol > 0.0 && std::isfinite(snap_tol), RBWS_EINVAL, "snap_tol must be positive");
+  RBWS_REQUIRE(P->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL, "L1ROC is built for f = 1 only");
+  RBWS_HIP(hipSetDevice(P->device));
+  const int fe = (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
+  const long long nd = P->ndof;
+  const int dev = P->device;
+  Basis* bs = new Basis();
+  try {
+    bs->prob = P;
+    bs->kind = 1;
+    bs->Nmax = N;
+    bs->Q = P->Q;
+    bs->ndof = nd;
+    bs->ntrain = ntrain;
+    bs->T.assign((size_t)N * N, 0.0);
+    double* W = (double*)bs->V.get(sizeof(double) * N * nd, dev);
+    DevBuf rbuf, ubuf, resb, aub, cbuf, scal, redob, partb, xrb, tdb, dlb;
+    double* R = (double*)rbuf.get(sizeof(double) * N * nd, dev);
+    double* r = (double*)resb.get(sizeof(double) * nd, dev);
+    double* au = (double*)aub.get(sizeof(double) * nd, dev);
+    double* sc = (double*)scal.get(sizeof(double) * (4 * kL1MaxN + 8), dev);
+    double* coef = sc;                  // DEIM coefficients
+    double* cl = sc + kL1MaxN;          // collocation coefficients at the chosen parameter
+    double* ncl = sc + 2 * kL1MaxN;     // their negation (lift through the Gram-Schmidt update)
+    double* sval = sc + 3 * kL1MaxN;    // DEIM scale
+    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, dev);
+    const int nparts = 1024;
+    ValIdx* part = (ValIdx*)partb.get(sizeof(ValIdx) * nparts, dev);
+    long long* xs_d = (long long*)ubuf.get(sizeof(long long) * kL1MaxN, dev);
+    long long* xr_d = (long long*)xrb.get(sizeof(long long) * kL1MaxN, dev);
+    double* T_d = (double*)tdb.get(sizeof(double) * N * N, dev);
+    RBWS_HIP(hipMemsetAsync(T_d, 0, sizeof(double) * N * N, s));
+    double* delta_d = (double*)dlb.get(sizeof(double) * ntrain, dev);
+    std::vector<const Problem*> probs{P};
+    Batch snap, one, tr;
+    batch_setup(tr, probs, nullptr, ntrain, mu_train, P->p, s);
+    std::vector<double> delta(ntrain);
+    const double hh = 1.0 / (P->n + 1), h2 = hh * hh;
+    auto snapshot = [&](int l) -> double* {
+      batch_setup(snap, probs, nullptr, 1, mu_train + (long long)l * P->p, P->p, s);
+      double* x = (double*)snap.x.get(sizeof(double) * nd, dev);
+      fill64(x, nd, 0.0, s);
+      cg_fp64_run(snap, CgOpts{snap_tol, snap_maxit, prec, flags, 0}, s);
+      return x;
+    };
+    auto sync_points = [&]() {
+      std::vector<long long> all(bs->xs);
+      all.insert(all.end(), bs->xr.begin(), bs->xr.end());
+      std::sort(all.begin(), all.end());
+      all.erase(std::unique(all.begin(), all.end()), all.end());
+      bs->pts = all;
+      RBWS_HIP(hipMemcpyAsync(xs_d, bs->xs.data(), sizeof(long long) * bs->xs.size(), hipMemcpyHostToDevice, s));
+      if (!bs->xr.empty())
+        RBWS_HIP(hipMemcpyAsync(xr_d, bs->xr.data(), sizeof(long long) * bs->xr.size(), hipMemcpyHostToDevice, s));
+      RBWS_HIP(hipMemcpyAsync(T_d, bs->T.data(), sizeof(double) * N * N, hipMemcpyHostToDevice, s));
+      bs->upload(s);
+    };
+    std::vector<const Basis*> bl{bs};
+    double shost = 0.0;
+    // first snapshot
+    {
+      const double* x = snapshot(0);
+      const long long pt = deim_gpu(W, 0, xs_d, nd, x, W, coef, sval, &shost, redo, part, nparts, fe, s);
+      RBWS_REQUIRE(pt >= 0, RBWS_ENUMERIC, "the first snapshot is zero");
+      bs->T[0] = 1.0 / shost;
+      bs->xs.push_back(pt);
+      bs->selected.push_back(0);
+      bs->N = 1;
+      sync_points();
+    }
+    for (;;) {
+      const int nb = bs->N;
+      RBWS_REQUIRE(l1roc_coeffs(tr, bl, (double*)cbuf.get(sizeof(double) * kL1MaxN * ntrain, dev), kL1MaxN,
+                                delta_d, fe, s) == 0,
+                   RBWS_ENUMERIC, "collocation least squares broke down in the greedy");
+      RBWS_HIP(hipMemcpyAsync(delta.data(), delta_d, sizeof(double) * ntrain, hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+      bs->hist.insert(bs->hist.end(), delta.begin(), delta.end());
+      if (nb == N) break;
+      int best = 0;
+      for (int t = 1; t < ntrain; t++)
+        if (delta[t] > delta[best]) best = t;
+      if (std::find(bs->selected.begin(), bs->selected.end(), best) != bs->selected.end()) break;
+      const double* mul = mu_train + (long long)best * P->p;
+      // residual of the current approximation at the chosen parameter
+      batch_setup(one, probs, nullptr, 1, mul, P->p, s);
+      RBWS_REQUIRE(l1roc_coeffs(one, bl, cl, kL1MaxN, nullptr, fe, s) == 0, RBWS_ENUMERIC,
+                   "collocation least squares broke down in the greedy");
+      hipLaunchKernelGGL(k_neg, dim3(1), dim3(64), 0, s, ncl, (const double*)cl, nb);
+      RBWS_HIP(hipMemsetAsync(au, 0, sizeof(double) * nd, s));  // u = 0 - sum (-c_j) w_j
+      RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
+      hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, au, (const double*)W, (const double*)ncl, nb,
+                         nd, redo, fe);
+      hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, au, (const double*)W, (const double*)ncl, nb, nd,
+                         (const Redo*)redo);
+      double* ux = (double*)one.x.get(sizeof(double) * nd, dev);
+      RBWS_HIP(hipMemcpyAsync(ux, au, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+      spmv_batch(one, ux, au, false, s);
+      hipLaunchKernelGGL(k_rhs_minus, dim3(2048), dim3(256), 0, s, r, (const double*)au, h2, nd);
+      RBWS_HIP(hipGetLastError());
+      // the snapshot's DEIM step
+      const double* x = snapshot(best);
+      const long long pt = deim_gpu(W, nb, xs_d, nd, x, W + (long long)nb * nd, coef, sval, &shost, redo, part,
+                                    nparts, fe, s);
+      if (pt < 0) break;
+      hipLaunchKernelGGL(k_l1_tcol, dim3(1), dim3(64), 0, s, T_d, N, (const double*)coef, nb,
+                         (const double*)sval, fe);
+      RBWS_HIP(hipGetLastError());
+      RBWS_HIP(hipMemcpyAsync(bs->T.data(), T_d, sizeof(double) * N * N, hipMemcpyDeviceToHost, s));
+      RBWS_HIP(hipStreamSynchronize(s));
+      bs->xs.push_back(pt);
+      // the residual's DEIM step adds a second point
+      const int nr = (int)bs->xr.size();
+      const long long ptr = deim_gpu(R, nr, xr_d, nd, r, R + (long long)nr * nd, coef, sval, &shost, redo, part,
+                                     nparts, fe, s);
+      if (ptr >= 0) bs->xr.push_back(ptr);
+      bs->selected.push_back(best);
+      bs->N = nb + 1;
+      sync_points();
+    }
+    const double* last = bs->hist.data() + (size_t)(bs->N - 1) * ntrain;
+    bs->final_max = *std::max_element(last, last + ntrain);
+    bs->upload(s);
+  } catch (...) {
+    delete bs;
+    throw;
+  }
+  return bs;
 }
 
 }  // namespace rbws

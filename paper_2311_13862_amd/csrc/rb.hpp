@@ -27,6 +27,15 @@ struct Basis {
   double ff = 0.0;
   std::vector<double> G, g;
   DevBuf G_d, g_d;
+  // kind 1: an L1ROC basis (Sec. 3.1, Alg. 4).  V holds the DEIM-normalised
+  // vectors W; the online coefficients solve the collocation least-squares
+  // problem at the points pts (ascending grid indices, snapshot points xs and
+  // residual points xr merged); T (Nmax x Nmax, upper triangular) gives W = U T
+  // with U the snapshots, for the L1 indicator.  AqN and fN are unused.
+  int kind = 0;
+  std::vector<long long> pts, xs, xr;
+  std::vector<double> T;
+  DevBuf pts_d, T_d;
   void upload(hipStream_t s);
 };
 
@@ -40,6 +49,13 @@ struct RbDev {
 
 Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol,
                 int prec, int snap_maxit, int flags, hipStream_t s);
+
+// L1ROC greedy (Sec. 3.1, Alg. 4): snapshots by PCG, DEIM of each snapshot and
+// of the current approximation's residual at the chosen parameter, the L1
+// indicator over the training set; f = 1 only, N <= kL1MaxN.
+Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol,
+                      int prec, int snap_maxit, int flags, hipStream_t s);
+constexpr int kL1MaxN = 40;
 
 // ||f - A(mu_b) V c_b|| / ||f|| for every solve of B from the residual
 // decomposition of its problem's basis (every basis must have `est`); c device,

@@ -91,6 +91,10 @@ def _load():
     optional = {
         "rbws_rb_build": (i, [vp, dp, i, i, d, i, i, vp, C.POINTER(vp), C.POINTER(i), dp,
                               C.POINTER(i)]),
+        "rbws_rb_build_l1roc": (i, [vp, dp, i, i, d, i, i, vp, C.POINTER(vp), C.POINTER(i), dp,
+                                    C.POINTER(i)]),
+        "rbws_basis_l1roc": (i, [vp, C.POINTER(i), C.POINTER(ll), C.POINTER(i), C.POINTER(ll), C.POINTER(i),
+                                 C.POINTER(ll), dp]),
         "rbws_basis_destroy": (None, [vp]),
         "rbws_basis_info": (i, [vp, C.POINTER(i), C.POINTER(i), C.POINTER(ll), dp]),
         "rbws_basis_get": (i, [vp, dp, dp, dp]),
@@ -266,16 +270,18 @@ class Basis:
 
     @classmethod
     def build(cls, problem: Problem, mu_train, N: int, snap_tol: float, precond=PREC_JACOBI,
-              snap_maxit: int = 50000, stream=None) -> "Basis":
+              snap_maxit: int = 50000, stream=None, method: str = "galerkin") -> "Basis":
+        """Greedy build: method "galerkin" (rbws_rb_build) or "l1roc" (rbws_rb_build_l1roc)."""
         mu = _f64(mu_train).reshape(-1, problem.p)
         nt = mu.shape[0]
         h = C.c_void_p()
         sel = np.full(N, -1, dtype=np.int32)
         hist = np.full((N, nt), np.nan)
         nre = C.c_int()
-        _check(_L.rbws_rb_build(problem.handle, _dp(mu), nt, N, snap_tol, precond, snap_maxit,
-                                _stream(stream), C.byref(h), sel.ctypes.data_as(C.POINTER(C.c_int)),
-                                _dp(hist), C.byref(nre)))
+        fn = {"galerkin": _L.rbws_rb_build, "l1roc": _L.rbws_rb_build_l1roc}[method]
+        _check(fn(problem.handle, _dp(mu), nt, N, snap_tol, precond, snap_maxit,
+                  _stream(stream), C.byref(h), sel.ctypes.data_as(C.POINTER(C.c_int)),
+                  _dp(hist), C.byref(nre)))
         k = nre.value
         return cls(problem, h, sel[:k].copy(), hist[:k].copy())
 
@@ -306,6 +312,19 @@ class Basis:
         c = np.empty((mu.shape[0], self.N))
         _check(_L.rbws_rb_coeffs(self.handle, _dp(mu), mu.shape[0], _dp(c), _stream(stream)))
         return c
+
+    def l1roc_info(self) -> dict:
+        """Collocation points, snapshot and residual DEIM points and T of an L1ROC basis."""
+        N = self.N
+        npts, nxs, nxr = C.c_int(), C.c_int(), C.c_int()
+        pts = np.zeros(2 * N, dtype=np.int64)
+        xs = np.zeros(N, dtype=np.int64)
+        xr = np.zeros(N, dtype=np.int64)
+        T = np.zeros((N, N))
+        lp = C.POINTER(C.c_longlong)
+        _check(_L.rbws_basis_l1roc(self.handle, C.byref(npts), pts.ctypes.data_as(lp), C.byref(nxs),
+                                   xs.ctypes.data_as(lp), C.byref(nxr), xr.ctypes.data_as(lp), _dp(T)))
+        return {"pts": pts[:npts.value].copy(), "xs": xs[:nxs.value].copy(), "xr": xr[:nxr.value].copy(), "T": T}
 
     def residual_estimate(self, mu, c, stream=None) -> np.ndarray:
         """||f - A(mu_b) V c_b|| / ||f|| from the basis's residual decomposition."""
