@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-zero", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-l1roc", action="store_true")
     ap.add_argument("--mlp-pairs", type=int, default=8192)
     ap.add_argument("--mlp-epochs", type=int, default=200)
     ap.add_argument("--counters", action="store_true",
@@ -196,6 +197,12 @@ def main():
         zero_iters = float(np.mean([s["iters"] for s in zst]))
         log(f"zero start: {zero_value:.2f} mu-solves/s, mean inner iterations {zero_iters:.1f}")
 
+    # the paper's own RB variant: an L1ROC basis from the same training set
+    l1roc = None
+    if not args.no_l1roc:
+        l1roc = l1roc_leg(rbws, torch, wl, P, mu_train, mu, args)
+        log(f"L1ROC start: {l1roc}")
+
     # learned start: a perceptron trained on the GPU on (mu, c(mu)) pairs of the reduced solve
     learned = None
     if not args.no_learned:
@@ -252,10 +259,11 @@ def main():
         "zero_start_inner_iters_mean": zero_iters,
         "rb_over_zero": None if zero_value is None else round(value / zero_value, 4),
         "learned_start": learned,
+        "l1roc_start": l1roc,
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
         "t_off_s": round(t_off, 2),
-        "bep": break_even(t_off, value, zero_value, learned),
+        "bep": break_even(t_off, value, zero_value, learned, l1roc),
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
         "spmv_batch": nb,
         "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()},
@@ -379,7 +387,33 @@ def traffic_per_launch(kernel):
     return float(v) if v else None
 
 
-def break_even(t_off, rb_value, zero_value, learned):
+def l1roc_leg(rbws, torch, wl, P, mu_train, mu, args):
+    """The L1ROC start (Sec. 3.1, Alg. 4): greedy build on the training set
+    (timed as its offline stage), then the batch refined from it exactly like
+    the timed step (after one warm-up solve of the same batch)."""
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lb = rbws.Basis.build(P, mu_train, args.N, wl.snap_tol, precond=rbws.PREC_JACOBI, method="l1roc")
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t
+    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND, eta_inner=args.eta,
+                             init=rbws.INIT_RB, lift=rbws.LIFT_MFMA, ir_mode=rbws.IR_RELIABLE,
+                             mg_omega=args.mg_omega)
+    rbws.solve([P], mu, opts, bases=[lb])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = rbws.solve([P], mu, opts, bases=[lb])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    info = lb.l1roc_info()
+    return {"value": round(args.batch / el, 3), "unit": "mu-solves/s",
+            "all_converged": bool(np.all(st["status"] == rbws.SOLVE_CONVERGED)),
+            "inner_iters_mean": float(np.mean(st["iters"])), "outer_iters_mean": float(np.mean(st["outer_iters"])),
+            "init_relres_median": float(np.median(np.sqrt(st["init_rr"] / st["ff"]))),
+            "rb_dim": lb.N, "collocation_points": int(len(info["pts"])), "t_off_s": round(t_off, 2)}
+
+
+def break_even(t_off, rb_value, zero_value, learned, l1roc=None):
     """The paper's break-even point (Sec. 4.1): BEP = t_off / (t_on(MGCG) -
     t_on(RBWS)), the number of online solves after which the offline stage has
     paid for itself.  t_on is the mean online time per solve, here the inverse
@@ -402,6 +436,9 @@ def break_even(t_off, rb_value, zero_value, learned):
         out["t_on_ms"]["learned"] = round(1e3 / learned["value"], 5)
         out["learned"] = bep(toff_l, learned["value"])
         out["t_off_learned_s"] = round(toff_l, 3)
+    if l1roc is not None:
+        out["t_on_ms"]["l1roc"] = round(1e3 / l1roc["value"], 5)
+        out["l1roc"] = bep(l1roc["t_off_s"], l1roc["value"])
     return out
 
 
