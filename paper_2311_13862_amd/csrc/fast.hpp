@@ -394,8 +394,8 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         }
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
-      if (OP == FOP_UP2) {
-        st4<T, VEC>(X, c, nv, xo);
+      if (OP == FOP_UP2) {  // x is read again only by the next update: streamed
+        st4_stream<T, VEC>(X, c, nv, xo);
         st4<T, VEC>(R, c, nv, ro);
       }
       if (OP == FOP_SPMV) st4_stream<T, VEC>(X, c, nv, qo);
@@ -611,8 +611,8 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
         }
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
-      if (OP == FOP_UP2) {
-        st4<float, VEC>(X, c, nv, xo);
+      if (OP == FOP_UP2) {  // d is read again only by the next update or outer pass: streamed
+        st4_stream<float, VEC>(X, c, nv, xo);
         st4<float, VEC>(R, c, nv, ro);
       }
       if (OP == FOP_SPMV) st4_stream<float, VEC>(X, c, nv, qo);
@@ -720,7 +720,7 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
       st4<float, VEC>(R, c, nv, ro);
-      if (up) st4<double, VEC>(Ud, c, nv, uc);
+      if (up) st4_stream<double, VEC>(Ud, c, nv, uc);  // read again at the next outer pass: streamed
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
