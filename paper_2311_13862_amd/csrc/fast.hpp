@@ -91,6 +91,26 @@ __device__ __forceinline__ void st4_stream(T* __restrict__ a, long long c, int n
   }
 }
 
+// load of a value read once (streamed past the caches)
+template <typename T, bool VEC>
+__device__ __forceinline__ void ld4_stream(const T* __restrict__ a, long long c, int nv, T v[4]) {
+  if (VEC) {
+    if (nv == 4) {
+      if constexpr (sizeof(T) == 4) {
+        const nt_f4 q = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(a + c));
+        v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+      } else {
+        const nt_d2 q0 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(a + c));
+        const nt_d2 q1 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(a + c + 2));
+        v[0] = q0[0]; v[1] = q0[1]; v[2] = q1[0]; v[3] = q1[1];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = e < nv ? __builtin_nontemporal_load(a + c + e) : T(0);
+  }
+}
+
 template <typename T, bool VEC>
 __device__ __forceinline__ void st4(T* __restrict__ a, long long c, int nv, const T v[4]) {
   if (VEC && nv == 4) {
@@ -491,7 +511,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
       return;
     }
     ld4<float, VEC>(R0, c, nv, ra);
-    if (!restart) ld4<float, VEC>(Pold, c, nv, rb);
+    if (!restart) ld4_stream<float, VEC>(Pold, c, nv, rb);  // the old direction is read once
   };
   // reciprocal diagonal of the own quad at plane k (from the cache when the codes match)
   auto quad_inv = [&](int k, float inv[4]) __attribute__((always_inline)) {
@@ -534,7 +554,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
   auto xr_load = [&](int k, float xo[4], float ro[4]) __attribute__((always_inline)) {
     if (OP != FOP_UP2 || nv == 0 || k > G.ke) return;
     const long long c = (long long)(k - 1) * n2 + rowoff;
-    if (!first_x) ld4<float, VEC>(X, c, nv, xo);
+    if (!first_x) ld4_stream<float, VEC>(X, c, nv, xo);  // d is read once
     ld4<float, VEC>(R, c, nv, ro);
   };
 
