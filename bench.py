@@ -76,8 +76,8 @@ def main():
     global PRECOND
     PRECOND = {"mg": 2, "jacobi": 1}[args.precond]
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(solves are independent per parameter; see the design notes for sharding)",
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(solves are independent per parameter: a batch splits across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch

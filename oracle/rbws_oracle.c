@@ -27,7 +27,7 @@
  *   - an FP32-inner / FP64-outer iterative refinement (an addition, not in
  *     the paper; the FP64 outer residual/update fixes the final accuracy).
  *
- * Readings of silent points (listed with reasons in the design notes):
+ * Readings of silent points:
  *   - every dot product is the exact sum of exact products rounded once to
  *     nearest-even (a "correctly rounded" dot), so that the result is a plain
  *     definition that does not depend on summation order;
@@ -1153,7 +1153,7 @@ void orc_ir_batch(const orc_problem *P, const double *mu, int nmu, const double 
 /* ------------------------------------------------------------------ */
 /* L1-based reduced over-collocation, L1ROC (Sec. 3.1, Alg. 4)         */
 /* ------------------------------------------------------------------ */
-/* Readings (each listed in the design notes):
+/* Readings:
  *  - DEIM vectors are normalised under point evaluation: B_j[pt_j] = 1 and
  *    B_j[pt_i] = 0 for i < j, so [B_j[pt_i]] is unit lower triangular.  A DEIM
  *    step interpolates x at the existing points (forward substitution), forms
