@@ -1,0 +1,44 @@
+"""Host logic of bench.py (no GPU): the paper's break-even point, the
+algorithmic bytes of the fused V-cycle kernels, and the one-GPU guard."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_break_even_point(bench):
+    """BEP = t_off / (t_on(zero) - t_on(start)) with t_on = 1 / throughput (Sec. 4.1);
+    None where a start is not faster; the learned start's t_off adds pairs and training."""
+    out = bench.break_even(6.0, 1000.0 / 0.9, 1000.0, {"t_pairs_s": 0.5, "t_train_s": 1.5, "value": 1000.0 / 0.8},
+                           {"t_off_s": 2.0, "value": 900.0})
+    assert out["rb"] == pytest.approx(6.0 / (1e-3 - 0.9e-3), rel=1e-9)
+    assert out["learned"] == pytest.approx(8.0 / (1e-3 - 0.8e-3), rel=1e-9)
+    assert out["t_off_learned_s"] == pytest.approx(8.0)
+    assert out["l1roc"] is None
+    assert bench.break_even(6.0, 1000.0, None, None) is None
+
+
+def test_algorithmic_bytes(bench):
+    """Per finest-level point at 128^3 (n_c = 63): the pre-smoothing reads b and
+    writes the x-sums (4 + 4 n_c / n), the post-smoothing reads r and the
+    coarse correction and writes s (8 + 4 (n_c / n)^3)."""
+    assert bench.mg_pre0_bytes(128) == pytest.approx(4.0 + 4.0 * 63 / 128)
+    assert bench.mg_post0_bytes(128) == pytest.approx(8.0 + 4.0 * (63 / 128) ** 3)
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
