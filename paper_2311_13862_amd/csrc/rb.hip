@@ -126,15 +126,18 @@ struct Redo {
   long long idx[1];  // kRedoCap entries follow
 };
 
-__device__ __forceinline__ void redo_push(Redo* r, long long e) {
+__device__ __forceinline__ void redo_push(Redo* r, long long e, long long cap = kRedoCap) {
   atomicAdd(&g_fallback_rb[1], 1ull);
   int slot = atomicAdd(&r->count, 1);
-  if (slot < kRedoCap) r->idx[slot] = e;
+  if (slot < cap) r->idx[slot] = e;
   else r->overflow = 1;
 }
 
+// v <- v - sum_j coef_j V_j, each entry correctly rounded.  `redo` holds
+// `cap` >= ndof entries, so it cannot overflow: the exact pass then reads the
+// original v of every entry it recomputes.
 __global__ __launch_bounds__(256) void k_gs_update(double* v, const double* V, const double* coef, int nb,
-                                                   long long ndof, Redo* redo, int force_exact) {
+                                                   long long ndof, Redo* redo, int force_exact, long long cap) {
   __shared__ double cs[kMaxN];
   for (int j = threadIdx.x; j < nb; j += blockDim.x) cs[j] = -coef[j];
   __syncthreads();
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(256) void k_gs_update(double* v, const double* V, c
     for (int j = 0; j < nb; j++) cr_add_prod(a, cs[j], V[(long long)j * ndof + c]);
     double r;
     if (!force_exact && cr_finalize(a, &r)) v[c] = r;
-    else redo_push(redo, c);
+    else redo_push(redo, c, cap);
   }
 }
 
@@ -690,7 +693,8 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
     double* W = (double*)wbuf.get(sizeof(double) * Q * nd, dev);
     double* f = (double*)fbuf.get(sizeof(double) * nd, dev);
     double* sc = (double*)scal.get(sizeof(double) * (kMaxN * kMaxQ + 8), dev);
-    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, dev);
+    const long long rcap = std::max<long long>(kRedoCap, nd);
+    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * rcap, dev);
     const double h = 1.0 / (P->n + 1);
     fill64(f, nd, h * h, s);
     // residual decomposition: keep every W_(q,i) (at most 8 GB)
@@ -734,7 +738,7 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
         pair_dots(xs, ys, nd, sc, fe, dev, s);
         RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
         hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, v, (const double*)V, (const double*)sc, nb,
-                           nd, redo, fe);
+                           nd, redo, fe, rcap);
         hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, v, (const double*)V, (const double*)sc, nb,
                            nd, (const Redo*)redo);
         RBWS_HIP(hipGetLastError());
@@ -1315,13 +1319,13 @@ static int l1roc_coeffs(Batch& B, const std::vector<const Basis*>& bases, double
 // one DEIM step of x against the nb vectors in Bv (points pt_d / pt): the
 // new normalised vector goes to out; returns the new point or -1
 static long long deim_gpu(const double* Bv, int nb, const long long* pt_d, long long nd, const double* x,
-                          double* out, double* coef, double* sval, double* sc_host, Redo* redo, ValIdx* part,
-                          int nparts, int fe, hipStream_t s) {
+                          double* out, double* coef, double* sval, double* sc_host, Redo* redo, long long rcap,
+                          ValIdx* part, int nparts, int fe, hipStream_t s) {
   hipLaunchKernelGGL(k_deim_coef, dim3(1), dim3(64), 0, s, Bv, nd, pt_d, nb, x, coef, fe);
   RBWS_HIP(hipMemcpyAsync(out, x, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
   if (nb > 0) {
     RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
-    hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, out, Bv, (const double*)coef, nb, nd, redo, fe);
+    hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, out, Bv, (const double*)coef, nb, nd, redo, fe, rcap);
     hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, out, Bv, (const double*)coef, nb, nd,
                        (const Redo*)redo);
     hipLaunchKernelGGL(k_zero_at, dim3(1), dim3(64), 0, s, out, pt_d, nb);
@@ -1369,7 +1373,8 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
     double* cl = sc + kL1MaxN;          // collocation coefficients at the chosen parameter
     double* ncl = sc + 2 * kL1MaxN;     // their negation (lift through the Gram-Schmidt update)
     double* sval = sc + 3 * kL1MaxN;    // DEIM scale
-    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * kRedoCap, dev);
+    const long long rcap = std::max<long long>(kRedoCap, nd);
+    Redo* redo = (Redo*)redob.get(sizeof(Redo) + sizeof(long long) * rcap, dev);
     const int nparts = 1024;
     ValIdx* part = (ValIdx*)partb.get(sizeof(ValIdx) * nparts, dev);
     long long* xs_d = (long long*)ubuf.get(sizeof(long long) * kL1MaxN, dev);
@@ -1406,7 +1411,7 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
     // first snapshot
     {
       const double* x = snapshot(0);
-      const long long pt = deim_gpu(W, 0, xs_d, nd, x, W, coef, sval, &shost, redo, part, nparts, fe, s);
+      const long long pt = deim_gpu(W, 0, xs_d, nd, x, W, coef, sval, &shost, redo, rcap, part, nparts, fe, s);
       RBWS_REQUIRE(pt >= 0, RBWS_ENUMERIC, "the first snapshot is zero");
       bs->T[0] = 1.0 / shost;
       bs->xs.push_back(pt);
@@ -1436,7 +1441,7 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
       RBWS_HIP(hipMemsetAsync(au, 0, sizeof(double) * nd, s));  // u = 0 - sum (-c_j) w_j
       RBWS_HIP(hipMemsetAsync(redo, 0, sizeof(Redo), s));
       hipLaunchKernelGGL(k_gs_update, dim3(2048), dim3(256), 0, s, au, (const double*)W, (const double*)ncl, nb,
-                         nd, redo, fe);
+                         nd, redo, fe, rcap);
       hipLaunchKernelGGL(k_gs_redo, dim3(1024), dim3(64), 0, s, au, (const double*)W, (const double*)ncl, nb, nd,
                          (const Redo*)redo);
       double* ux = (double*)one.x.get(sizeof(double) * nd, dev);
@@ -1446,7 +1451,7 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
       RBWS_HIP(hipGetLastError());
       // the snapshot's DEIM step
       const double* x = snapshot(best);
-      const long long pt = deim_gpu(W, nb, xs_d, nd, x, W + (long long)nb * nd, coef, sval, &shost, redo, part,
+      const long long pt = deim_gpu(W, nb, xs_d, nd, x, W + (long long)nb * nd, coef, sval, &shost, redo, rcap, part,
                                     nparts, fe, s);
       if (pt < 0) break;
       hipLaunchKernelGGL(k_l1_tcol, dim3(1), dim3(64), 0, s, T_d, N, (const double*)coef, nb,
@@ -1457,7 +1462,7 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
       bs->xs.push_back(pt);
       // the residual's DEIM step adds a second point
       const int nr = (int)bs->xr.size();
-      const long long ptr = deim_gpu(R, nr, xr_d, nd, r, R + (long long)nr * nd, coef, sval, &shost, redo, part,
+      const long long ptr = deim_gpu(R, nr, xr_d, nd, r, R + (long long)nr * nd, coef, sval, &shost, redo, rcap, part,
                                      nparts, fe, s);
       if (ptr >= 0) bs->xr.push_back(ptr);
       bs->selected.push_back(best);
