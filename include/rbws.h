@@ -261,8 +261,11 @@ rbws_status rbws_basis_device_v(const rbws_basis* b, const double** V);
 /* Online RB solve (Eq. "RB system"): c(mu) from A_N(mu) = sum_q theta_q A_q^N
  * (accumulated with fma in q order), Cholesky and two triangular solves, every
  * inner sum correctly rounded; right-hand side f^N (f = 1) or V^T f(mu)
- * (Gaussian source).  mu host (nmu x p), c host (nmu x N).
- * ENUMERIC when a reduced matrix is not positive definite. */
+ * (Gaussian source).  For an L1ROC basis (rbws_rb_build_l1roc): the
+ * collocation least-squares solution instead, one 64-thread block per
+ * parameter.  mu host (nmu x p), c host (nmu x N).
+ * ENUMERIC when a reduced matrix is not positive definite (or, for L1ROC, a
+ * least-squares column vanishes). */
 rbws_status rbws_rb_coeffs(const rbws_basis* b, const double* mu, int nmu, double* c, void* stream);
 /* Lift u_b = V c_b for b < nmu: c device (nmu x N), u device (nmu x ndof).
  * mode RBWS_LIFT_EXACT: every entry a correctly rounded N-term dot;
