@@ -268,23 +268,37 @@ def test_refinement_with_multigrid(rb, spec, mode):
         assert st[b]["iters"] <= 2 * so[b]["iters"] + 10, (st[b]["iters"], so[b]["iters"])
 
 
-@pytest.mark.parametrize("eta", [0.1, 0.05])
-def test_refinement_with_multigrid_full_size_sample(rb, eta):
-    """The bench's configuration (128^3, FP32 MGCG inside FP64 refinement,
-    reliable updates, inner tolerance 0.05; and the library default 0.1) on 64
-    solves; two sampled solutions against the oracle's FP64 MGCG solved to 1e-12."""
+@pytest.mark.parametrize("eta,start", [(0.1, "zero"), (0.05, "rb")])
+def test_refinement_with_multigrid_full_size_sample(rb, eta, start):
+    """128^3, FP32 V-cycle CG inside FP64 refinement with reliable updates, on
+    64 solves: the library default (inner tolerance 0.1, zero start) and the
+    bench's launch configuration (tile depth 32, tolerance 0.05, RB start lifted
+    on the matrix cores, from a small basis here); two sampled solutions against
+    the oracle's FP64 MGCG solved to 1e-12."""
     wl = W.octants_128()
     spec = wl.problem
     P = rb.Problem(spec)
     mu = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, 64, W.SEED_TEST)
     picks = (0, 37)
     u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") if b in picks else None for b in range(len(mu))]
+    kw, bases = {}, None
+    if start == "rb":
+        mut = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, 64, W.SEED_TRAIN)
+        bases = [rb.Basis.build(P, mut, 8, wl.snap_tol)]
+        kw = dict(init=rb.INIT_RB, lift=rb.LIFT_MFMA)
     opts = rb.default_opts(tol=wl.tol, precision=rb.FP32_IR, precond=rb.PREC_MG, ir_mode=rb.IR_RELIABLE,
-                           eta_inner=eta, mg_omega=0.9)
-    st = rb.solve([P], mu, opts, u_out=u)
-    torch.cuda.synchronize()
+                           eta_inner=eta, mg_omega=0.9, **kw)
+    try:
+        if start == "rb":
+            rb.set_tuning(rb.TUNE_TZ, 32)
+        st = rb.solve([P], mu, opts, bases=bases, u_out=u)
+        torch.cuda.synchronize()
+    finally:
+        rb.set_tuning(rb.TUNE_TZ, 0)
     assert all(s["status"] == rb.SOLVE_CONVERGED for s in st)
     assert all(s["final_rr"] <= wl.tol ** 2 * s["ff"] for s in st)
+    if start == "rb":
+        assert all(s["init_used"] == rb.INIT_RB for s in st)
     O = oracle.Problem(spec)
     for b in picks:
         ref, so = O.mgcg(mu[b], tol=1e-12)
