@@ -73,11 +73,17 @@ def l1roc_dense(O, mut, N, follow=None):
     return np.array(Wl), xs, xr, sel, np.array(hist)
 
 
-@pytest.mark.parametrize("kind", [W.KIND_BLOCKS, W.KIND_OCTANTS])
+@pytest.mark.parametrize("kind", [W.KIND_BLOCKS, W.KIND_OCTANTS, W.KIND_OCTANTS_ANISO])
 def test_l1roc_matches_dense_restatement(kind):
-    spec = W.Problem(5, kind, W.BLOCKS3) if kind == W.KIND_BLOCKS else W.Problem(5, kind)
+    """Blocks and octants (f = 1), and anisotropic octants with the Gaussian
+    source, whose collocation right-hand side is f(mu) at the points."""
+    if kind == W.KIND_BLOCKS:
+        spec, lo, hi = W.Problem(5, kind, W.BLOCKS3), 0.1, 10.0
+    elif kind == W.KIND_OCTANTS:
+        spec, lo, hi = W.Problem(5, kind), 0.01, 100.0
+    else:
+        spec, lo, hi = W.Problem(5, kind, (), W.F_GAUSS, 0.02), 0.1, 10.0
     O = oracle.Problem(spec)
-    lo, hi = (0.1, 10.0) if kind == W.KIND_BLOCKS else (0.01, 100.0)
     mut = W.sample_mu(spec, lo, hi, 16, 21 + kind)
     B = oracle.l1roc_greedy(O, mut, 5, 1e-14)
     Wd, xs, xr, sel, hist = l1roc_dense(O, mut, 5, follow=B)
