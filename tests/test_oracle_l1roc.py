@@ -142,3 +142,20 @@ def test_l1roc_warm_start_saves_iterations(l1_16):
         _, sz = O.cg(mu, tol=wl.tol)
         _, sw = O.cg(mu, u0=B.lift(B.coeffs(mu)), tol=wl.tol)
         assert sw["status"] == oracle.CONVERGED and sw["iters"] < sz["iters"], (sw["iters"], sz["iters"])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_collocation_qr_random(seed):
+    """The oracle's Householder QR on arbitrary bases and point sets (not just
+    the greedy's DEIM-structured ones) against numpy.linalg.lstsq."""
+    rng = np.random.default_rng(seed)
+    spec = W.Problem(6, W.KIND_OCTANTS)
+    O = oracle.Problem(spec)
+    N = 3 + seed
+    M = N + 1 + 2 * seed
+    Wr = rng.standard_normal((N, O.ndof))
+    pts = np.sort(rng.choice(O.ndof, size=M, replace=False)).astype(np.int64)
+    B = oracle.L1rocBasis(O, Wr, np.eye(N), pts, pts[:N], pts[N:], np.arange(N), None)
+    mu = W.sample_mu(spec, 0.01, 100.0, 1, 50 + seed)[0]
+    ref = np.linalg.lstsq((O.dense(mu) @ Wr.T)[pts], O.rhs(mu)[pts], rcond=None)[0]
+    np.testing.assert_allclose(B.coeffs(mu), ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
