@@ -114,3 +114,18 @@ def test_ir_reaches_fp64_accuracy(prec):
         assert st["status"] == oracle.CONVERGED and st["outer"] >= 2
         assert st["final_rr"] <= 1e-20 * st["ff"]
         assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_ir_inner_target_bound_by_f():
+    """Reading of the refinement (reliable updates): the inner solve stops at
+    eta * min(||r||, ||f||), so a start whose residual is far above ||f|| (here
+    29 ||f||: thirty times the solution) needs no more outer passes than the
+    zero start.  Reducing only by eta * ||r|| would cost it one more."""
+    spec = W.Problem(10, W.KIND_OCTANTS)
+    O = oracle.Problem(spec)
+    for mu in W.sample_mu(spec, 0.01, 100.0, 3, 9):
+        u = O.cg(mu, tol=1e-13)[0]
+        _, sz = O.ir(mu, tol=1e-10, eta=0.1, reliable=True)
+        _, sb = O.ir(mu, u0=30.0 * u, tol=1e-10, eta=0.1, reliable=True)
+        assert sz["status"] == sb["status"] == oracle.CONVERGED
+        assert sb["outer"] <= sz["outer"], (sb["outer"], sz["outer"])
