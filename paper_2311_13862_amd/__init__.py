@@ -2,7 +2,7 @@
 
 The compute path is the HIP library ``librbws.so`` (C ABI, ``include/rbws.h``);
 ``rbws`` is its thin ctypes binding.  Importing the package loads nothing;
-``paper_2311_13862_amd.rbws`` loads the library on first use and raises if
-it is missing.
+importing ``paper_2311_13862_amd.rbws`` imports torch, then loads the library
+against torch's HIP runtime, and raises if it is missing.
 """
 __all__ = ["workloads", "rbws"]

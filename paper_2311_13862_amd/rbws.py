@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of the solver runs in the HIP library.
 Device buffers are torch tensors on a ROCm device (``tensor.data_ptr()``);
-streams are torch streams.  Importing this module loads the library and
-raises if it has not been built (``python -m paper_2311_13862_amd.build``).
+streams are torch streams.  Importing this module imports torch, then loads
+the library (so that both use torch's HIP runtime), and raises if it has not
+been built (``python -m paper_2311_13862_amd.build``).
 """
 from __future__ import annotations
 
@@ -67,10 +68,41 @@ class MlpTrainCfg(C.Structure):
                 ("seed", C.c_ulonglong), ("use_graph", C.c_int)]
 
 
+_RUNTIMES = ("libamdhip64", "libhsa-runtime64")
+
+
+def mapped_runtimes() -> dict:
+    """Paths of the HIP and HSA runtime libraries mapped into this process, by
+    library name (read from /proc/self/maps)."""
+    found = {k: set() for k in _RUNTIMES}
+    with open("/proc/self/maps") as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) < 6:
+                continue
+            path = parts[-1]
+            base = os.path.basename(path)
+            for k in _RUNTIMES:
+                if base.startswith(k + ".so"):
+                    found[k].add(path)
+    return found
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_13862_amd.build`")
+    # torch provides the device memory and streams the library works on, so the
+    # library must bind torch's HIP runtime.  torch ships its own libamdhip64 and
+    # libhsa-runtime64 and links them by their unversioned names; loaded first,
+    # librbws.so would pull in the system copies under their versioned names,
+    # torch would then map its own pair as well, and with two runtimes in one
+    # process the library's runtime sees no device.  Importing torch first maps
+    # torch's pair, whose sonames then satisfy librbws.so's dependencies.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
+    dup = {k: sorted(v) for k, v in mapped_runtimes().items() if len(v) > 1}
+    if dup:
+        raise ImportError(f"two copies of a HIP runtime are mapped after loading {LIB_PATH}: {dup}")
     vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
     dp = C.POINTER(C.c_double)
     sigs = {

@@ -3,6 +3,8 @@ function that include/rbws.h declares (no compute calls are made here)."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rbws.h")
@@ -24,11 +26,17 @@ def test_header_declares_the_boundary():
     assert len(names) >= 35, names
 
 
-def test_library_exports_every_declared_symbol():
+def _lib():
+    """The library as the binding loads it (after torch, on torch's HIP runtime)."""
     if not os.path.exists(LIB):
         from paper_2311_13862_amd import build
         build.build()
-    lib = ctypes.CDLL(LIB)
+    from paper_2311_13862_amd import rbws
+    return rbws.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     lib.rbws_version.restype = ctypes.c_char_p
@@ -37,7 +45,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_tuning_knobs_validate_without_a_gpu():
     """rbws_set_tuning checks its arguments on the host (no device call)."""
-    lib = ctypes.CDLL(LIB)
+    lib = _lib()
     RBWS_TUNE_TZ, EINVAL = 2, -1
     assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 12) == EINVAL
     assert lib.rbws_set_tuning(RBWS_TUNE_TZ, 128) == EINVAL
@@ -47,3 +55,19 @@ def test_tuning_knobs_validate_without_a_gpu():
     assert lib.rbws_set_tuning(RBWS_TUNE_MG_PZ, 2) == EINVAL
     assert lib.rbws_set_tuning(RBWS_TUNE_MG_PZ, 1) == 0
     assert lib.rbws_set_tuning(99, 0) == EINVAL
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must leave one HIP and one HSA runtime
+    mapped (torch's): with two, the library's runtime sees no device."""
+    _lib()
+    code = ("from paper_2311_13862_amd import rbws\n"
+            "import torch\n"
+            "m = rbws.mapped_runtimes()\n"
+            "print({k: len(v) for k, v in m.items()})\n"
+            "assert all(len(v) == 1 for v in m.values()), m\n"
+            "tl = os.path.dirname(torch.__file__)\n"
+            "assert all(p.startswith(tl) for v in m.values() for p in v), m\n")
+    r = subprocess.run([sys.executable, "-c", "import os\n" + code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
