@@ -71,6 +71,7 @@ def lib():
             "orc_cg_batch": (None, [pp, d, i, d, d, i, C.c_double, i, d, C.POINTER(Stats), i]),
             "orc_mg_levels": (i, [i, C.POINTER(C.c_int)]),
             "orc_mg_apply": (i, [pp, d, i, C.c_double, d, d]),
+            "orc_mg_transfer": (None, [i, i, i, d, d]),
             "orc_mgcg": (i, [pp, d, d, d, i, C.c_double, C.c_double, i, d, C.POINTER(Stats)]),
             "orc_mgcg_batch": (None, [pp, d, i, d, d, i, C.c_double, C.c_double, i, d, C.POINTER(Stats), i]),
             "orc_rb_assemble": (None, [i, i, i, d, d, d]),
@@ -199,6 +200,15 @@ class Problem:
         out = (C.c_int * 16)()
         k = lib().orc_mg_levels(self.n, out)
         return [out[i] for i in range(k)]
+
+    def mg_transfer(self, level: int, x, restrict: bool) -> np.ndarray:
+        """Restriction ((n_c+1)/(n_f+1)) P^T x or prolongation P x between levels
+        level and level + 1 of the V-cycle (Alg. 2)."""
+        ns = self.mg_levels()
+        nf, nc = ns[level], ns[level + 1]
+        out = np.empty(nc ** 3 if restrict else nf ** 3)
+        lib().orc_mg_transfer(nf, nc, 0 if restrict else 1, _dp(_f64(x)), _dp(out))
+        return out
 
     def mg_apply(self, mu, r, nu=MG_NU, omega=MG_OMEGA) -> np.ndarray:
         """s = MG(r): one V-cycle (Alg. 2) with zero initial value."""

@@ -527,7 +527,10 @@ static int cg_faces(const faces *F, int n, const double *f, const double *u0, in
  * Smoother: damped Jacobi e <- e + omega (b - A e) / d, nu sweeps before and
  * after the coarse correction, so the V-cycle is a symmetric operator.
  *
- * Fixed evaluation orders (the GPU follows the same ones):
+ * Fixed evaluation orders.  Alg. 2 fixes the transfer operators, not the
+ * order of their sums; the separable x, y, z chains below are this oracle's
+ * own definition of it (each output is a sum of at most 4^3 or 2^3 weighted
+ * terms, and the tests pin every entry against the dense Kronecker form):
  *   Jacobi: q = A e (stencil order), t = b - q, t = t / d, e' = fma(omega, t, e)
  *   restriction, separable: ax = sum over i of px r (fma chain from 0, i
  *     ascending over the fine points whose weight on the coarse node may be
@@ -753,6 +756,28 @@ static void mg_free(mg_ctx *c) {
         free(c->ci[l]); free(c->cw[l]);
     }
     free(c->L);
+}
+
+/* One level pair's transfers on their own (for tests): dir 0 gives
+ * out = ((nc+1)/(nf+1)) P^T in (in on the nf grid, out on the nc grid),
+ * dir 1 gives out = P in (in on the nc grid, out on the nf grid). */
+void orc_mg_transfer(int nf, int nc, int dir, const double *in, double *out) {
+    mg_ctx c;
+    memset(&c, 0, sizeof c);
+    c.nlev = 2;
+    c.n[0] = nf;
+    c.n[1] = nc;
+    c.ci[0] = malloc(sizeof(int) * nf);
+    c.cw[0] = malloc(sizeof(double) * nf);
+    mg_transfer_table(nf, nc, c.ci[0], c.cw[0]);
+    if (dir == 0) {
+        mg_restrict(&c, 0, in, out);
+    } else {
+        memset(out, 0, sizeof(double) * (size_t)nf * nf * nf);
+        mg_prolong(&c, 0, in, out);
+    }
+    free(c.ci[0]);
+    free(c.cw[0]);
 }
 
 /* s = MG(r) for one mu (the V-cycle as an operator, for tests) */

@@ -129,3 +129,82 @@ def test_ir_inner_target_bound_by_f():
         _, sb = O.ir(mu, u0=30.0 * u, tol=1e-10, eta=0.1, reliable=True)
         assert sz["status"] == sb["status"] == oracle.CONVERGED
         assert sb["outer"] <= sz["outer"], (sb["outer"], sz["outer"])
+
+
+def dense_alg1(A, f, jacobi, tol, maxit):
+    """Alg. 1 written out on a dense matrix (numpy matrix-vector products and
+    dots), P = diag(A)^-1 or I, from u0 = 0; returns (x, iterations, history of
+    ||r_k||^2 including k = 0)."""
+    d = np.diag(A) if jacobi else np.ones(len(f))
+    x = np.zeros_like(f)
+    r = f.copy()
+    s = r / d
+    p = s.copy()
+    rho = r @ s
+    hist = [r @ r]
+    thr = tol * tol * (f @ f)
+    k = 0
+    while hist[-1] > thr and k < maxit:
+        q = A @ p
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        k += 1
+        hist.append(r @ r)
+        if hist[-1] <= thr:
+            break
+        s = r / d
+        rs = r @ s
+        p = s + (rs / rho) * p
+        rho = rs
+    return x, k, np.array(hist)
+
+
+TRAJ_SPECS = [W.Problem(6, W.KIND_BLOCKS, W.BLOCKS3), W.Problem(7, W.KIND_OCTANTS),
+              W.Problem(5, W.KIND_BLOCKS, W.BLOCKS4)]
+
+
+@pytest.mark.parametrize("spec", TRAJ_SPECS, ids=lambda s: f"k{s.kind}n{s.n}")
+def test_jacobi_pcg_trajectory_matches_dense_alg1(spec):
+    """The whole Jacobi-PCG residual history and the iteration count equal those
+    of Alg. 1 written out densely, at coefficient contrast up to 1e4 (so the
+    diagonal is far from constant and r^T s differs from r^T r).  A beta taken
+    from r^T r, a swapped alpha, or a preconditioner applied to the wrong
+    vector moves the history by O(1) from the second iteration on."""
+    O = oracle.Problem(spec)
+    checked = 0
+    for m in W.sample_mu(spec, 0.01, 100.0, 3, 11):
+        A = O.dense(m)
+        f = O.rhs(m)
+        d = np.diag(A)
+        assert d.max() / d.min() > 4   # the diagonal is far from constant
+        x, st, h = O.cg(m, prec=oracle.PREC_JACOBI, tol=1e-8, hist=True)
+        xd, kd, hd = dense_alg1(A, f, True, 1e-8, 5000)
+        thr = 1e-16 * hd[0]
+        L = min(len(h), len(hd))
+        np.testing.assert_allclose(h[:L], hd[:L], rtol=1e-7, atol=0)
+        if hd[-2] > 1.01 * thr and hd[-1] < 0.99 * thr:   # stop decided away from the threshold
+            assert st["iters"] == kd
+            checked += 1
+        assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+    assert checked >= 2
+
+
+@pytest.mark.parametrize("spec", TRAJ_SPECS, ids=lambda s: f"k{s.kind}n{s.n}")
+def test_plain_cg_trajectory_prefix_matches_dense_alg1(spec):
+    """P = I: the first iterations of the residual history equal the dense Alg. 1
+    to rounding (at high contrast plain CG loses orthogonality, and the two
+    rounding sequences part after a few steps, so only the prefix is compared);
+    at mild contrast on the smallest grid the whole history agrees."""
+    O = oracle.Problem(spec)
+    for m in W.sample_mu(spec, 0.01, 100.0, 3, 11):
+        _, _, h = O.cg(m, prec=oracle.PREC_NONE, tol=1e-8, hist=True)
+        _, _, hd = dense_alg1(O.dense(m), O.rhs(m), False, 1e-8, 5000)
+        np.testing.assert_allclose(h[:6], hd[:6], rtol=1e-9, atol=0)
+    spec5 = W.Problem(5, W.KIND_BLOCKS, W.BLOCKS4)
+    O5 = oracle.Problem(spec5)
+    m = W.sample_mu(spec5, 0.5, 2.0, 1, 11)[0]
+    _, st, h = O5.cg(m, prec=oracle.PREC_NONE, tol=1e-10, hist=True)
+    _, kd, hd = dense_alg1(O5.dense(m), O5.rhs(m), False, 1e-10, 5000)
+    assert st["iters"] == kd
+    np.testing.assert_allclose(h, hd, rtol=1e-10, atol=0)

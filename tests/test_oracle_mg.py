@@ -1,6 +1,10 @@
 """Pins for the oracle's multigrid preconditioner (Alg. 2) and MGCG (Alg. 1
 with P = MG), against what mathematics and textbook routines fix:
 
+- every entry of the restriction and prolongation equals the dense Kronecker
+  form scale P^T r and P e (P from numpy.interp) within the rounding bound of
+  a short positive-weight sum, so their separable summation order is one
+  evaluation of the defined operator;
 - the V-cycle equals a dense NumPy restatement of Alg. 2 whose transfer
   operators are built independently with numpy.interp and Kronecker products;
 - on a grid that is already the coarsest level the V-cycle is the exact
@@ -72,6 +76,30 @@ def test_interp_matrix_is_linear_interpolation():
     g = 0.3 + 2.0 * Xc
     inner = (xf >= Xc[0]) & (xf <= Xc[-1])
     np.testing.assert_allclose((P @ g)[inner], (0.3 + 2.0 * xf)[inner], rtol=1e-14)
+
+
+@pytest.mark.parametrize("n,level", [(8, 0), (16, 0), (16, 1), (20, 0), (33, 0), (33, 1)])
+def test_transfers_per_entry_match_kronecker(n, level):
+    O = oracle.Problem(W.Problem(n, W.KIND_OCTANTS))
+    ns = O.mg_levels()
+    nf, nc = ns[level], ns[level + 1]
+    p1 = interp_matrix(nf, nc)
+    P = np.kron(np.kron(p1, p1), p1)
+    scale = (nc + 1) / (nf + 1)
+    rng = np.random.default_rng(n + level)
+    eps = np.finfo(float).eps
+    r = rng.standard_normal(nf ** 3) * np.exp(rng.uniform(-3, 3, nf ** 3))
+    rc = O.mg_transfer(level, r, restrict=True)
+    ref = scale * (P.T @ r)
+    bound = 32 * eps * scale * (np.abs(P.T) @ np.abs(r)) + 1e-300
+    assert (np.abs(rc - ref) <= bound).all(), np.max(np.abs(rc - ref) / bound)
+    e = rng.standard_normal(nc ** 3)
+    ef = O.mg_transfer(level, e, restrict=False)
+    ref = P @ e
+    bound = 32 * eps * (np.abs(P) @ np.abs(e)) + 1e-300
+    assert (np.abs(ef - ref) <= bound).all(), np.max(np.abs(ef - ref) / bound)
+    # and the pair is adjoint up to the scale: <R r, e> = scale <r, P e>
+    assert abs(rc @ e - scale * (r @ ef)) <= 1e-12 * np.abs(rc) @ np.abs(e)
 
 
 @pytest.mark.parametrize("spec", [W.Problem(8, W.KIND_OCTANTS), W.Problem(16, W.KIND_BLOCKS, W.BLOCKS3),

@@ -1,7 +1,7 @@
 """Pins for the FP64 oracle of the learned warm start (an addition to the
 paper's Alg. 5 initial value): gradients against central finite
-differences, Adam's first step against its closed form, GELU against
-textbook values of the normal CDF."""
+differences, Adam's first step and several steps against the closed form of
+its unrolled moment sums, GELU against textbook values of the normal CDF."""
 import math
 
 import numpy as np
@@ -67,6 +67,47 @@ def test_adam_first_step_closed_form():
     for (W0, b0), (W1, b1), (gW, gb) in zip(before, params, grads):
         np.testing.assert_allclose(W0 - W1, lr * gW / (np.abs(gW) + 1e-8), rtol=1e-12)
         np.testing.assert_allclose(b0 - b1, lr * gb / (np.abs(gb) + 1e-8), rtol=1e-12)
+
+
+def adam_unrolled(theta0, gs, lr, b1, b2, eps=1e-8):
+    """Adam's iterate after len(gs) steps from m = v = 0, from the unrolled sums
+    m_t = (1 - b1) sum_i b1^(t-i) g_i and v_t = (1 - b2) sum_i b2^(t-i) g_i^2,
+    each step lr (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps)."""
+    theta = theta0
+    for t in range(1, len(gs) + 1):
+        m = (1 - b1) * math.fsum(b1 ** (t - i) * gs[i - 1] for i in range(1, t + 1))
+        v = (1 - b2) * math.fsum(b2 ** (t - i) * gs[i - 1] ** 2 for i in range(1, t + 1))
+        theta -= lr * (m / (1 - b1 ** t)) / (math.sqrt(v / (1 - b2 ** t)) + eps)
+    return theta
+
+
+def test_adam_several_steps_closed_form():
+    """Four steps with gradients of changing sign and size, for the default and
+    for clearly different (beta1, beta2): swapped betas, a bias correction with
+    the wrong exponent or a missing square on v all move the iterate."""
+    gs = [1.0, -2.0, 3.0, 0.5]
+    # hand value of the third step with the defaults: m3/(1-0.9^3) = 0.201/0.271,
+    # v3/(1-0.999^3) = 0.013994001/0.002997001
+    step3 = 1e-3 * (0.201 / 0.271) / (math.sqrt(0.013994001 / 0.002997001) + 1e-8)
+    assert abs(step3 - 1e-3 * 0.34324108) < 1e-11
+    for b1, b2 in ((0.9, 0.999), (0.8, 0.95), (0.5, 0.7)):
+        W = np.array([[0.25, -1.5]])
+        b = np.array([0.75])
+        params = [(W, b)]
+        m = [(np.zeros_like(W), np.zeros_like(b))]
+        v = [(np.zeros_like(W), np.zeros_like(b))]
+        scale = np.array([1.0, -0.5])                # per-entry gradients g_t * scale
+        for t, g in enumerate(gs, start=1):
+            grads = [(g * scale[None, :], np.array([2.0 * g]))]
+            mlp.adam_step(params, grads, m, v, t, 1e-3, beta1=b1, beta2=b2)
+        for j, (w0, sc) in enumerate(((0.25, 1.0), (-1.5, -0.5))):
+            ref = adam_unrolled(w0, [g * sc for g in gs], 1e-3, b1, b2)
+            assert abs(params[0][0][0, j] - ref) <= 1e-14, (b1, b2, j)
+        assert abs(params[0][1][0] - adam_unrolled(0.75, [2.0 * g for g in gs], 1e-3, b1, b2)) <= 1e-14
+    # the third step on its own (defaults) equals the hand value
+    th2 = adam_unrolled(0.0, gs[:2], 1e-3, 0.9, 0.999)
+    th3 = adam_unrolled(0.0, gs[:3], 1e-3, 0.9, 0.999)
+    assert abs((th2 - th3) - step3) < 1e-15
 
 
 def test_input_scaling():
