@@ -201,6 +201,23 @@ rbws_status rbws_mg_apply(rbws_problem* p, const double* mu, int nmu, int nu, do
 rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int count,
                             double* out, int flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * correctly rounded dots as rbws_exact_dots, bit for bit, written to the
+ * DEVICE array out (count doubles) on `stream`.  The call allocates nothing
+ * and does not synchronise: its partial sums live in a fixed workspace of
+ * RBWS_NOALLOC_SCRATCH_BYTES per GPU, inside the library, which holds
+ * count * ceil(len / 4096) <= RBWS_NOALLOC_SCRATCH_BYTES / 24 partial sums
+ * (e.g. 341 vectors of 128^3 entries).  Every call on one GPU uses that GPU's
+ * workspace, so calls that overlap in time on one GPU (two streams or two
+ * host threads) race; calls ordered on one stream do not.  The first call on
+ * a device looks up the workspace's address there (not capturable; make one
+ * call before capturing).  Errors: EINVAL (NULL pointer, negative size, more
+ * partial sums than the workspace holds; nothing is launched), EDEVICE. */
+#define RBWS_NOALLOC_SCRATCH_BYTES (4u << 20)
+rbws_status rbws_exact_dots_noalloc(const double* x, const double* y, long long len, int count,
+                                    double* out, int flags, void* stream);
+
 /* ---- offline: greedy reduced basis (Alg. 4 skeleton) ---------------------
  * Builds V (N orthonormal vectors), A_q^N = V^T A_q V and f^N = V^T f from the
  * training set mu_train (host, ntrain x p).  Step n: snapshot u(mu_l) by PCG

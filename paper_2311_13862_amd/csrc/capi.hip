@@ -302,6 +302,17 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
   API_END
 }
 
+rbws_status rbws_exact_dots_noalloc(const double* x, const double* y, long long len, int count, double* out,
+                                    int flags, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(len >= 0 && count >= 0, RBWS_EINVAL, "negative size");
+  if (count == 0) return RBWS_OK;
+  RBWS_REQUIRE(out != nullptr, RBWS_EINVAL, "out is NULL");
+  RBWS_REQUIRE(len == 0 || (x && y), RBWS_EINVAL, "NULL pointer");
+  exact_dots_noalloc(x, y, len, count, out, flags, (hipStream_t)stream);
+  API_END
+}
+
 rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, int N, double snap_tol,
                           int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
                           double* indicator_hist, int* n_reached) {

@@ -22,6 +22,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "fast.hpp"
 #include "mg.hpp"
@@ -1071,6 +1074,26 @@ void spmv_batch(Batch& B, const void* x, void* y, bool fp32, hipStream_t s) {
   RBWS_HIP(hipGetLastError());
 }
 
+// Elements per partial sum of the dot kernels, and the number of partials of
+// one vector of length len.
+constexpr int kDotPerBlock = 4096;
+static long long dot_parts(long long len) {
+  long long nb = std::max<long long>(1, (len + kDotPerBlock - 1) / kDotPerBlock);
+  RBWS_REQUIRE(nb < (1LL << 31), RBWS_EINVAL, "vector too long");
+  return nb;
+}
+
+// The two dot kernels on the stream: partial double-double sums into `pp`
+// (nb * count records, every one written), then one correctly rounded value
+// per vector pair into the device array `o`.
+static void launch_dots(const double* x, const double* y, long long len, int count, long long nb, CrAcc* pp,
+                        double* o, int flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_part, dim3((unsigned)nb, count), dim3(256), 0, s, x, y, len, kDotPerBlock, pp);
+  hipLaunchKernelGGL(k_dot_fin, dim3(count), dim3(256), 0, s, x, y, len, (int)nb, pp, o,
+                     (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0);
+  RBWS_HIP(hipGetLastError());
+}
+
 void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
                 int flags, hipStream_t s) {
   if (count <= 0) return;
@@ -1078,17 +1101,50 @@ void exact_dots(const double* x, const double* y, long long len, int count, doub
   RBWS_HIP(hipGetDevice(&dev));
   RBWS_SCRATCH(part);
   RBWS_SCRATCH(out);
-  const int per_block = 4096;
-  long long nb = std::max<long long>(1, (len + per_block - 1) / per_block);
-  RBWS_REQUIRE(nb < (1LL << 31), RBWS_EINVAL, "vector too long");
+  const long long nb = dot_parts(len);
   CrAcc* pp = (CrAcc*)part.get(sizeof(CrAcc) * nb * count, dev);
   double* o = (double*)out.get(sizeof(double) * count, dev);
-  hipLaunchKernelGGL(k_dot_part, dim3((unsigned)nb, count), dim3(256), 0, s, x, y, len, per_block, pp);
-  hipLaunchKernelGGL(k_dot_fin, dim3(count), dim3(256), 0, s, x, y, len, (int)nb, pp, o,
-                     (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0);
-  RBWS_HIP(hipGetLastError());
+  launch_dots(x, y, len, count, nb, pp, o, flags, s);
   RBWS_HIP(hipMemcpyAsync(out_host, o, sizeof(double) * count, hipMemcpyDeviceToHost, s));
   RBWS_HIP(hipStreamSynchronize(s));
+}
+
+// Fixed workspace of exact_dots_noalloc: the partial sums of one call.  Each
+// GPU the library runs on holds its own copy of this array until the process
+// ends.  In host code its name is not a device address: the address on the
+// current device comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[RBWS_NOALLOC_SCRATCH_BYTES];
+
+static void* noalloc_scratch(int dev) {
+  static std::mutex mu;
+  static std::vector<void*> ptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)ptr.size() <= dev) ptr.resize(dev + 1, nullptr);
+  if (!ptr[dev]) {
+    void* a = nullptr;
+    RBWS_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    RBWS_REQUIRE(a != nullptr, RBWS_EDEVICE, "no device address for the workspace");
+    ptr[dev] = a;
+  }
+  return ptr[dev];
+}
+
+void exact_dots_noalloc(const double* x, const double* y, long long len, int count, double* out_dev,
+                        int flags, hipStream_t s) {
+  if (count <= 0) return;
+  int dev = 0;
+  RBWS_HIP(hipGetDevice(&dev));
+  if (len == 0) {
+    fill64(out_dev, count, 0.0, s);
+    return;
+  }
+  const long long nb = dot_parts(len);
+  const unsigned long long need = (unsigned long long)sizeof(CrAcc) * (unsigned long long)nb * (unsigned)count;
+  RBWS_REQUIRE(need <= RBWS_NOALLOC_SCRATCH_BYTES, RBWS_EINVAL,
+               "count * ceil(len / 4096) = " + std::to_string(nb * count) + " partial sums exceed the " +
+                   std::to_string(RBWS_NOALLOC_SCRATCH_BYTES / sizeof(CrAcc)) + " the fixed workspace holds");
+  CrAcc* pp = (CrAcc*)noalloc_scratch(dev);
+  launch_dots(x, y, len, count, nb, pp, out_dev, flags, s);
 }
 
 }  // namespace rbws

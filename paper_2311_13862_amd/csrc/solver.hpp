@@ -227,6 +227,10 @@ void run_rounds(Batch& B, const int* active, long long max_rounds, int check, bo
 // correctly rounded dots of `count` pairs of length len (device vectors)
 void exact_dots(const double* x, const double* y, long long len, int count, double* out_host,
                 int flags, hipStream_t s);
+// the same into device memory, partial sums in a fixed static workspace:
+// no allocation, no host synchronisation
+void exact_dots_noalloc(const double* x, const double* y, long long len, int count, double* out_dev,
+                        int flags, hipStream_t s);
 
 double wall_clock_khz(int device);
 

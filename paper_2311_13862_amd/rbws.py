@@ -117,6 +117,7 @@ def _load():
         "rbws_theta": (i, [vp, dp, i, dp]),
         "rbws_spmv": (i, [vp, dp, i, vp, vp, i, vp]),
         "rbws_exact_dots": (i, [vp, vp, ll, i, dp, i, vp]),
+        "rbws_exact_dots_noalloc": (i, [vp, vp, ll, i, vp, i, vp]),
         "rbws_solve": (i, [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i, C.POINTER(i), dp, i,
                            C.POINTER(SolveOpts), vp, C.POINTER(vp), C.POINTER(SolveStat)]),
     }
@@ -254,6 +255,19 @@ def exact_dots(x, y, flags: int = 0, stream=None) -> np.ndarray:
     _check(_L.rbws_exact_dots(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), length, count,
                               _dp(out), flags, _stream(stream)))
     return out
+
+
+def exact_dots_noalloc(x, y, out, flags: int = 0, stream=None):
+    """rbws_exact_dots_noalloc: the same dots as exact_dots, written to the
+    float64 device tensor out (count,) on the stream; no allocation, no
+    synchronisation (the library's fixed workspace holds the partial sums)."""
+    count, length = x.shape
+    _check(_L.rbws_exact_dots_noalloc(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), length, count,
+                                      C.c_void_p(out.data_ptr()), flags, _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20
+NOALLOC_PARTIAL_BYTES = 24  # one double-double partial sum and its error bound
 
 
 def stats_array(st, n: int) -> np.ndarray:
