@@ -60,6 +60,13 @@ def parse():
     ap.add_argument("--mlp-epochs", type=int, default=200)
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc (a few refinement rounds)")
+    ap.add_argument("--reps", type=int, default=3,
+                    help="interleaved repetitions of every start (zero, RB, learned, L1ROC) after the timed steps")
+    ap.add_argument("--no-c2", action="store_true", help="skip the blocks4-64 FP64 leg")
+    ap.add_argument("--no-c5", action="store_true", help="skip the anisotropic mixed-size leg")
+    ap.add_argument("--c5-ntrain", type=int, default=1024)
+    ap.add_argument("--c5-batch", type=int, default=512)
+    ap.add_argument("--c5-N", type=int, default=60)
     return ap.parse_args()
 
 
@@ -118,7 +125,7 @@ def main():
         vc = float(np.sum([s["vcycles"] for s in st]))
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
-        b.copy_(a)
+        rbws.stream_copy(a, b)  # the library's streaming copy: each byte read and written once
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes_read": a.numel() * 8,
                           "copy_bytes_written": b.numel() * 8,
@@ -152,18 +159,10 @@ def main():
     lat = np.array([s["t_done_ms"] for s in stats])
     relres = np.array([np.sqrt(s["final_rr"] / s["ff"]) for s in stats])
 
-    # copy bandwidth of the device (a plain 1 GiB + 1 GiB copy), for context
-    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
+    # copy bandwidth of the device: the library's streaming copy kernel (16-byte
+    # non-temporal loads and stores) and torch's copy, 1 GiB each way
+    copy = copy_ceiling(rbws, torch)
+    copy_gbs = copy["stream_copy"]
 
     # roofline of the dominant kernel (the single kernel with the most time over the timed
     # steps, from its HIP events), priced at its algorithmic bytes
@@ -181,33 +180,59 @@ def main():
     achieved = dom_bytes / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
     per_launch_bytes = dom_bytes / max(n_launch[dom], 1)
     per_launch_ms = ms[dom] / max(n_launch[dom], 1)
+    step_bytes = sum(alg.values()) / args.steps
+    kern_frac = {k: round(alg[k] / (ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for k in alg if ms.get(k, 0) > 0}
 
-    # zero start with the same preconditioner, precision and tolerance
-    zero_value = None
-    zero_iters = None
-    if not args.no_zero:
-        zopts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
-                                  eta_inner=args.eta, init=rbws.INIT_ZERO, ir_mode=rbws.IR_RELIABLE,
-                                  mg_omega=args.mg_omega)
+    # set-up of the other starts: the paper's L1ROC basis and the learned start
+    l1b = None
+    l1_off = None
+    if not args.no_l1roc:
         torch.cuda.synchronize()
         t = time.perf_counter()
-        zst = rbws.solve([P], mu, zopts)
+        l1b = rbws.Basis.build(P, mu_train, args.N, wl.snap_tol, precond=rbws.PREC_JACOBI, method="l1roc")
         torch.cuda.synchronize()
-        zero_value = args.batch / (time.perf_counter() - t)
-        zero_iters = float(np.mean([s["iters"] for s in zst]))
-        log(f"zero start: {zero_value:.2f} mu-solves/s, mean inner iterations {zero_iters:.1f}")
+        l1_off = time.perf_counter() - t
+    net, learned_info = (None, None) if args.no_learned else train_learned(rbws, torch, W, wl, spec, basis, mu, args)
 
-    # the paper's own RB variant: an L1ROC basis from the same training set
-    l1roc = None
-    if not args.no_l1roc:
-        l1roc = l1roc_leg(rbws, torch, wl, P, mu_train, mu, args)
-        log(f"L1ROC start: {l1roc}")
+    # every start with the same preconditioner, precision, tolerance, kernel timer and
+    # launch mode, interleaved in one process: zero, RB, learned, L1ROC, zero, RB, ...
+    base = dict(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND, eta_inner=args.eta,
+                ir_mode=rbws.IR_RELIABLE, mg_omega=args.mg_omega, lift=rbws.LIFT_MFMA)
+    legs = {}
+    if not args.no_zero:
+        zo = rbws.default_opts(init=rbws.INIT_ZERO, **base)
+        legs["zero"] = lambda: rbws.solve([P], mu, zo)
+    legs["rb"] = lambda: rbws.solve([P], mu, opts, bases=[basis])
+    if net is not None:
+        lo = rbws.default_opts(init=rbws.INIT_LEARNED, fallback=0, **base)
+        legs["learned"] = lambda: rbws.solve([P], mu, lo, bases=[basis], mlps=[net])
+    if l1b is not None:
+        legs["l1roc"] = lambda: rbws.solve([P], mu, opts, bases=[l1b])
+    cmp_runs = interleave(rbws, torch, legs, args.reps)
+    starts = {k: leg_summary(rbws, v, args.batch) for k, v in cmp_runs.items()}
+    if "zero" in cmp_runs:
+        starts["rb"]["over_zero"] = paired_ratio(cmp_runs["rb"], cmp_runs["zero"])
+    if "learned" in starts:
+        st = cmp_runs["learned"]["stats"]
+        starts["learned"].update(learned_info)
+        starts["learned"]["started_from_mlp"] = int(np.sum(st["init_used"] == rbws.INIT_LEARNED))
+        starts["learned"]["over_rb"] = paired_ratio(cmp_runs["learned"], cmp_runs["rb"])
+        starts["learned"]["inner_iters_minus_rb"] = round(
+            starts["learned"]["inner_iters_mean"] - starts["rb"]["inner_iters_mean"], 4)
+        if "zero" in cmp_runs:
+            starts["learned"]["over_zero"] = paired_ratio(cmp_runs["learned"], cmp_runs["zero"])
+    if "l1roc" in starts:
+        info = l1b.l1roc_info()
+        starts["l1roc"].update({"rb_dim": l1b.N, "collocation_points": int(len(info["pts"])),
+                                "t_off_s": round(l1_off, 2)})
+    log(f"starts: { {k: v['value_median'] for k, v in starts.items()} }")
 
-    # learned start: a perceptron trained on the GPU on (mu, c(mu)) pairs of the reduced solve
-    learned = None
-    if not args.no_learned:
-        learned = learned_leg(rbws, W, wl, spec, P, basis, mu, args)
-        log(f"learned start: {learned}")
+    c2 = None if args.no_c2 else c2_leg(rbws, torch, W, args)
+    if c2 is not None:
+        log(f"blocks4-64 FP64: {c2}")
+    c5 = None if args.no_c5 else c5_leg(rbws, torch, W, args)
+    if c5 is not None:
+        log(f"aniso-mixed: {c5}")
 
     # SpMV bandwidth: 256 solves at 128^3 (2.1 GB per FP32 vector, far beyond the 256 MB
     # last-level cache); smaller batches leave the last round of workgroups part-empty
@@ -230,9 +255,10 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(spec, mu, float(np.mean(iters)), float(np.mean(outer)), args.cpu_seconds, args.mg_omega)
+        cpu = cpu_baseline(spec, mu, args.cpu_seconds, args.mg_omega, wl.tol)
         log(f"cpu baseline: {cpu}")
 
+    zero = starts.get("zero")
     line = {
         "metric": "mu-solves/s to rel-res 1e-10 @128^3 (RB warm start; zero start beside it)",
         "value": round(value, 3),
@@ -255,15 +281,21 @@ def main():
         "inner_iters_mean": float(iters.mean()),
         "outer_iters_mean": float(outer.mean()),
         "vcycles_mean": float(vcyc.mean()),
-        "zero_start_value": None if zero_value is None else round(zero_value, 3),
-        "zero_start_inner_iters_mean": zero_iters,
-        "rb_over_zero": None if zero_value is None else round(value / zero_value, 4),
-        "learned_start": learned,
-        "l1roc_start": l1roc,
+        "zero_start_value": None if zero is None else zero["value_median"],
+        "zero_start_inner_iters_mean": None if zero is None else zero["inner_iters_mean"],
+        "rb_over_zero": None if zero is None else starts["rb"]["over_zero"]["median"],
+        "starts": starts,
+        "starts_protocol": (f"after the timed steps, every start once untimed, then {args.reps} rounds of "
+                            f"{', '.join(starts)} in turn, same options, kernel timer on for all; "
+                            "value_* from each run's wall time, over_* the median and range of the ratios "
+                            "of runs in the same round"),
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_note": "completion time of each solve inside its batch (device clock), RB start",
         "t_off_s": round(t_off, 2),
-        "bep": break_even(t_off, value, zero_value, learned, l1roc),
+        "bep": break_even(t_off, starts),
+        "blocks4_64_fp64": c2,
+        "aniso_mixed": c5,
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
         "spmv_batch": nb,
         "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()},
@@ -271,7 +303,9 @@ def main():
         "kernel_ms": {k: round(v, 2) for k, v in ms.items()},
         "kernel_launches": n_launch,
         "launches_before_timed_step": {k: v[1] for k, v in pre.items()},
-        "copy_gbs": round(copy_gbs, 1),
+        "kernel_frac_of_peak": kern_frac,
+        "step_frac_of_peak": round(step_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_gbs": copy,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_per_launch(dom), "bytes_per_launch": per_launch_bytes,
@@ -279,6 +313,69 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def copy_ceiling(rbws, torch, reps=10):
+    """GB/s (bytes read + written) of a 1 GiB device-to-device copy: the library's
+    streaming copy kernel and torch's copy_, each timed with HIP events on the
+    current stream, on which both are launched."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn in (("stream_copy", lambda: rbws.stream_copy(a, b)), ("torch_copy", lambda: b.copy_(a))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(reps * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    assert bool(torch.equal(a, b))
+    del a, b
+    return out
+
+
+def interleave(rbws, torch, legs, reps):
+    """Each leg once untimed (set-up), then `reps` rounds that run every leg once
+    in turn.  Every run has the kernel timer on (the same launch mode for all).
+    Returns per leg the wall seconds of each run, the last run's statistics and
+    the kernel times summed over the timed runs."""
+    for f in legs.values():
+        f()
+    out = {k: {"s": [], "stats": None, "kern": {}} for k in legs}
+    for _ in range(reps):
+        for k, f in legs.items():
+            rbws.profile(True, reset=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = f()
+            torch.cuda.synchronize()
+            out[k]["s"].append(time.perf_counter() - t)
+            out[k]["stats"] = st
+            for kk, (m, n) in rbws.profile(False, reset=True).items():
+                a = out[k]["kern"].setdefault(kk, [0.0, 0])
+                a[0] += m
+                a[1] += n
+    return out
+
+
+def leg_summary(rbws, run, batch):
+    v = batch / np.array(run["s"])
+    st = run["stats"]
+    return {"value_median": round(float(np.median(v)), 3), "value_min": round(float(v.min()), 3),
+            "value_max": round(float(v.max()), 3), "runs": [round(float(x), 3) for x in v],
+            "all_converged": bool(np.all(st["status"] == rbws.SOLVE_CONVERGED)),
+            "inner_iters_mean": float(np.mean(st["iters"])), "outer_iters_mean": float(np.mean(st["outer_iters"])),
+            "init_relres_median": float(np.median(np.sqrt(st["init_rr"] / st["ff"]))),
+            "max_final_relres": float(np.max(np.sqrt(st["final_rr"] / st["ff"])))}
+
+
+def paired_ratio(a, b):
+    """Throughput ratio a/b of the runs of the same round."""
+    r = np.array(b["s"]) / np.array(a["s"])
+    return {"median": round(float(np.median(r)), 4), "min": round(float(r.min()), 4), "max": round(float(r.max()), 4)}
 
 
 def pick_tile_depth(rbws, torch, P, mu, args, cands=(16, 32, 64)):
@@ -303,10 +400,10 @@ def pick_tile_depth(rbws, torch, P, mu, args, cands=(16, 32, 64)):
     return best, ms
 
 
-def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
-    """Pairs from the reduced solve, GPU training, then the batch from the learned
-    start (strict fallback: per solve the smaller true residual of u_MLP, u_RB)."""
-    import torch
+def train_learned(rbws, torch, W, wl, spec, basis, mu, args):
+    """Learned start: (mu, c(mu)) pairs from the reduced solve, a perceptron
+    trained on the GPU on them, and its coefficient error against the reduced
+    solve on the test batch."""
     mup = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.mlp_pairs, W.SEED_MLP_PAIRS)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -322,25 +419,144 @@ def learned_leg(rbws, W, wl, spec, P, basis, mu, args):
     c_rb = basis.coeffs(mu)
     c_nn = net.predict(mu)
     cerr = np.linalg.norm(c_nn - c_rb, axis=1) / np.linalg.norm(c_rb, axis=1)
-    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND,
-                             eta_inner=args.eta, init=rbws.INIT_LEARNED, lift=rbws.LIFT_MFMA,
-                             ir_mode=rbws.IR_RELIABLE, fallback=0, mg_omega=args.mg_omega)
-    rbws.solve([P], mu[:64], opts, bases=[basis], mlps=[net])  # set-up of this start, like the others'
+    return net, {"coef_relerr_vs_rb_median": float(np.median(cerr)), "train_pairs": args.mlp_pairs,
+                 "train_epochs": args.mlp_epochs, "t_pairs_s": round(t_pairs, 3), "t_train_s": round(t_train, 3),
+                 "final_loss": float(np.mean(hist[-32:])), "fallback": "strict (smaller true residual of u_MLP, u_RB)",
+                 "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
+
+
+def c2_leg(rbws, torch, W, args):
+    """blocks4-64: the plain method in FP64 on the GPU.  Four blocks at 64^3,
+    greedy basis N = 30 from 512 training parameters, 256 test parameters in
+    one batched solve to relative residual 1e-10 by Jacobi-PCG (Alg. 1) from
+    the RB start (Alg. 5) and from zero, interleaved.  The FP64 sweeps' roofline
+    is priced at 24 (A p sweep, 16 on a restart) and 40 (update sweep) bytes per
+    unknown and iteration, and 16 per residual evaluation."""
+    wl = W.blocks4_64()
+    spec = wl.problem
+    P = rbws.Problem(spec)
+    mut = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, wl.n_train, W.SEED_TRAIN)
+    mu = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, wl.n_test, W.SEED_TEST)
+    rbws.set_tuning(rbws.TUNE_TZ, 0)  # the library's default tile depth for this size
     torch.cuda.synchronize()
     t = time.perf_counter()
-    st = rbws.solve([P], mu, opts, bases=[basis], mlps=[net])
+    basis = rbws.Basis.build(P, mut, wl.N, wl.snap_tol, precond=rbws.PREC_JACOBI)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t
-    used = [s["init_used"] for s in st]
-    return {"value": round(args.batch / el, 3), "unit": "mu-solves/s",
-            "all_converged": all(s["status"] == rbws.SOLVE_CONVERGED for s in st),
-            "inner_iters_mean": float(np.mean([s["iters"] for s in st])),
-            "init_relres_median": float(np.median([np.sqrt(s["init_rr"] / s["ff"]) for s in st])),
-            "started_from_mlp": int(sum(u == rbws.INIT_LEARNED for u in used)),
-            "coef_relerr_vs_rb_median": float(np.median(cerr)),
-            "train_pairs": args.mlp_pairs, "train_epochs": args.mlp_epochs, "t_pairs_s": round(t_pairs, 3),
-            "t_train_s": round(t_train, 3), "final_loss": float(np.mean(hist[-32:])),
-            "network": f"{spec.p}-256-256-256-{basis.N} GELU, BF16 MFMA / FP32 Adam"}
+    t_off = time.perf_counter() - t
+    base = dict(precision=rbws.FP64, tol=wl.tol, precond=rbws.PREC_JACOBI, lift=rbws.LIFT_MFMA)
+    zo = rbws.default_opts(init=rbws.INIT_ZERO, **base)
+    ro = rbws.default_opts(init=rbws.INIT_RB, **base)
+    runs = interleave(rbws, torch, {"zero": lambda: rbws.solve([P], mu, zo),
+                                    "rb": lambda: rbws.solve([P], mu, ro, bases=[basis])}, args.reps)
+    out = {k: leg_summary(rbws, v, len(mu)) for k, v in runs.items()}
+    out["rb"]["over_zero"] = paired_ratio(runs["rb"], runs["zero"])
+    nd = P.ndof
+    roof = {}
+    for k, run in runs.items():
+        st = run["stats"]
+        it, ex = st["iters"].astype(np.int64), st["extra_spmv"].astype(np.int64)
+        restarts = np.where(it > 0, np.maximum(ex, 1), 0)
+        alg = {"ap_sweep": float(np.sum(24 * it - 8 * restarts)) * nd * args.reps,
+               "up2_sweep": float(np.sum(40 * it)) * nd * args.reps,
+               "resid_pass": float(np.sum(16 * (1 + ex))) * nd * args.reps}
+        r = {}
+        for kk, b in alg.items():
+            ms, nl = run["kern"].get(kk, (0.0, 0))
+            if ms > 0:
+                gbs = b / (ms * 1e-3) / 1e9
+                r[kk] = {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "ms_per_launch": round(ms / max(nl, 1), 4), "bytes_per_launch": b / max(nl, 1)}
+        roof[k] = r
+    tz = {k: v for k, v in roof["rb"].items() if k != "resid_pass"}
+    dom = max(tz, key=lambda k: runs["rb"]["kern"][k][0]) if tz else None
+    return {"config": {"workload": "blocks4-64^3-fp64", "n": spec.n, "batch": len(mu), "rb_dim": basis.N,
+                       "n_train": wl.n_train, "tol": wl.tol, "precond": "jacobi", "dtype": "f64",
+                       "snap_tol": wl.snap_tol},
+            "value": out["rb"]["value_median"], "unit": "mu-solves/s", "zero": out["zero"], "rb": out["rb"],
+            "t_off_s": round(t_off, 2), "bep": break_even(t_off, out),
+            "roofline": {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         **({} if dom is None else roof["rb"][dom])},
+            "sweeps": roof}
+
+
+C5_SIZES = (64, 96, 128)
+
+
+def c5_leg(rbws, torch, W, args):
+    """aniso-mixed: 512 solves (solve i on grid C5_SIZES[i mod 3]) of the
+    anisotropic octant problem with the Gaussian source (27 parameters) in one
+    launch; per-size greedy bases (N = 60) and perceptrons (27-256-256-256-60);
+    FP32 PCG with the V-cycle inside FP64 refinement to 1e-10, from zero, RB and
+    learned starts, interleaved.  Per-solve latency is each solve's completion
+    time inside the uneven batch (device clock)."""
+    probs, bases, nets, specs, info = [], [], [], [], []
+    rbws.set_tuning(rbws.TUNE_TZ, 0)
+    t_off = 0.0
+    t_learn = 0.0
+    for q, n in enumerate(C5_SIZES):
+        wl = W.aniso_mixed(n)
+        spec = wl.problem
+        P = rbws.Problem(spec)
+        mut = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.c5_ntrain, W.SEED_TRAIN + 10 * q)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B = rbws.Basis.build(P, mut, args.c5_N, wl.snap_tol, precond=rbws.PREC_JACOBI)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t
+        t_off += tb
+        mup = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.mlp_pairs, W.SEED_MLP_PAIRS + 10 * q)
+        t = time.perf_counter()
+        c = B.coeffs(mup)
+        net = rbws.Mlp.create(spec.p, B.N, hidden=256, depth=3, log_cols=24, in_m=0.0, in_s=1.0,
+                              lin_lo=0.25, lin_hi=0.75, out_pow=1.0, seed=W.SEED_MLP_INIT + 10 * q)
+        net.fit_output_scaling(mup, c)
+        hist = net.train(mup, c, epochs=args.mlp_epochs, batch=256, lr=1e-3, lr_min=1e-5,
+                         seed=W.SEED_MLP_PAIRS + 10 * q)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t
+        t_learn += tl
+        probs.append(P)
+        bases.append(B)
+        nets.append(net)
+        specs.append(spec)
+        info.append({"n": n, "rb_dim": B.N, "t_off_s": round(tb, 2), "t_learn_s": round(tl, 2),
+                     "final_max_indicator": B.final_max, "final_loss": float(np.mean(hist[-32:]))})
+        log(f"aniso-mixed {n}^3: basis N={B.N} in {tb:.1f} s, network in {tl:.1f} s")
+    nsol = args.c5_batch
+    assign = (np.arange(nsol) % 3).astype(np.int32)
+    mu = np.empty((nsol, specs[0].p))
+    for q in range(3):
+        cnt = int(np.sum(assign == q))
+        mu[assign == q] = W.sample_mu(specs[q], 0.1, 10.0, cnt, W.SEED_TEST + 10 * q)
+    base = dict(precision=rbws.FP32_IR, tol=1e-10, precond=PRECOND, eta_inner=args.eta,
+                ir_mode=rbws.IR_RELIABLE, mg_omega=args.mg_omega, lift=rbws.LIFT_MFMA)
+    legs = {"zero": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_ZERO, **base), problem_of=assign),
+            "rb": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_RB, **base), problem_of=assign,
+                                     bases=bases),
+            "learned": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_LEARNED, fallback=0, **base),
+                                          problem_of=assign, bases=bases, mlps=nets)}
+    runs = interleave(rbws, torch, legs, args.reps)
+    out = {}
+    for k, run in runs.items():
+        sm = leg_summary(rbws, run, nsol)
+        st = run["stats"]
+        lat = st["t_done_ms"]
+        sm["latency_ms_p50"] = round(float(np.percentile(lat, 50)), 3)
+        sm["latency_ms_p99"] = round(float(np.percentile(lat, 99)), 3)
+        sm["inner_iters_by_size"] = {str(n): float(np.mean(st["iters"][assign == q])) for q, n in enumerate(C5_SIZES)}
+        if k == "learned":
+            sm["started_from_mlp"] = int(np.sum(st["init_used"] == rbws.INIT_LEARNED))
+        out[k] = sm
+    out["rb"]["over_zero"] = paired_ratio(runs["rb"], runs["zero"])
+    out["learned"]["over_rb"] = paired_ratio(runs["learned"], runs["rb"])
+    out["learned"]["over_zero"] = paired_ratio(runs["learned"], runs["zero"])
+    return {"config": {"workload": "aniso27-mixed-64/96/128^3-fp32ir", "sizes": list(C5_SIZES), "batch": nsol,
+                       "assignment": "solve i on size index i mod 3", "rb_dim": args.c5_N, "n_train": args.c5_ntrain,
+                       "tol": 1e-10, "precond": "mg-vcycle" if PRECOND == 2 else "jacobi", "p": specs[0].p,
+                       "mlp_pairs": args.mlp_pairs, "mlp_epochs": args.mlp_epochs},
+            "value": out["rb"]["value_median"], "unit": "mu-solves/s", "per_size": info,
+            "t_off_s": round(t_off, 2), "t_learn_s": round(t_learn, 2),
+            "zero": out["zero"], "rb": out["rb"], "learned": out["learned"]}
 
 
 def mg_pre0_bytes(n):
@@ -387,58 +603,34 @@ def traffic_per_launch(kernel):
     return float(v) if v else None
 
 
-def l1roc_leg(rbws, torch, wl, P, mu_train, mu, args):
-    """The L1ROC start (Sec. 3.1, Alg. 4): greedy build on the training set
-    (timed as its offline stage), then the batch refined from it exactly like
-    the timed step (after one warm-up solve of the same batch)."""
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    lb = rbws.Basis.build(P, mu_train, args.N, wl.snap_tol, precond=rbws.PREC_JACOBI, method="l1roc")
-    torch.cuda.synchronize()
-    t_off = time.perf_counter() - t
-    opts = rbws.default_opts(precision=rbws.FP32_IR, tol=wl.tol, precond=PRECOND, eta_inner=args.eta,
-                             init=rbws.INIT_RB, lift=rbws.LIFT_MFMA, ir_mode=rbws.IR_RELIABLE,
-                             mg_omega=args.mg_omega)
-    rbws.solve([P], mu, opts, bases=[lb])
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    st = rbws.solve([P], mu, opts, bases=[lb])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t
-    info = lb.l1roc_info()
-    return {"value": round(args.batch / el, 3), "unit": "mu-solves/s",
-            "all_converged": bool(np.all(st["status"] == rbws.SOLVE_CONVERGED)),
-            "inner_iters_mean": float(np.mean(st["iters"])), "outer_iters_mean": float(np.mean(st["outer_iters"])),
-            "init_relres_median": float(np.median(np.sqrt(st["init_rr"] / st["ff"]))),
-            "rb_dim": lb.N, "collocation_points": int(len(info["pts"])), "t_off_s": round(t_off, 2)}
-
-
-def break_even(t_off, rb_value, zero_value, learned, l1roc=None):
+def break_even(t_off, starts):
     """The paper's break-even point (Sec. 4.1): BEP = t_off / (t_on(MGCG) -
     t_on(RBWS)), the number of online solves after which the offline stage has
     paid for itself.  t_on is the mean online time per solve, here the inverse
-    batched throughput; the zero start with the same preconditioner plays MGCG.
-    For the learned start t_off also counts the training pairs and training.
-    None where a start is not faster than the zero start."""
-    if zero_value is None:
+    median batched throughput; the zero start with the same preconditioner
+    plays MGCG.  For the learned start t_off also counts the training pairs and
+    training, for L1ROC its own build.  None where a start is not faster than
+    the zero start."""
+    if "zero" not in starts:
         return None
-    t_zero = 1.0 / zero_value
+    t_zero = 1.0 / starts["zero"]["value_median"]
 
     def bep(toff, v):
         gain = t_zero - 1.0 / v
         return round(toff / gain, 1) if gain > 0 else None
 
-    out = {"definition": "t_off / (t_on(zero start) - t_on(start)), t_on = 1 / throughput",
-           "t_on_ms": {"zero": round(1e3 * t_zero, 5), "rb": round(1e3 / rb_value, 5)},
-           "rb": bep(t_off, rb_value)}
-    if learned is not None:
-        toff_l = t_off + learned["t_pairs_s"] + learned["t_train_s"]
-        out["t_on_ms"]["learned"] = round(1e3 / learned["value"], 5)
-        out["learned"] = bep(toff_l, learned["value"])
-        out["t_off_learned_s"] = round(toff_l, 3)
-    if l1roc is not None:
-        out["t_on_ms"]["l1roc"] = round(1e3 / l1roc["value"], 5)
-        out["l1roc"] = bep(l1roc["t_off_s"], l1roc["value"])
+    out = {"definition": "t_off / (t_on(zero start) - t_on(start)), t_on = 1 / median throughput",
+           "t_on_ms": {k: round(1e3 / v["value_median"], 5) for k, v in starts.items()}}
+    for k, v in starts.items():
+        if k == "zero":
+            continue
+        toff = t_off
+        if k == "learned":
+            toff = t_off + v.get("t_pairs_s", 0.0) + v.get("t_train_s", 0.0)
+            out["t_off_learned_s"] = round(toff, 3)
+        elif k == "l1roc":
+            toff = v.get("t_off_s", t_off)
+        out[k] = bep(toff, v["value_median"])
     return out
 
 
@@ -452,41 +644,42 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(spec, mu, gpu_inner_mean, gpu_outer_mean, budget_s, omega):
-    """The oracle's own solver for the same method on the host cores, on a
-    bounded sample: `cores` parameters in parallel (one per thread), each for a
-    capped number of iterations; the per-solve cost is scaled to the GPU's mean
-    inner iteration count.  With the multigrid preconditioner the oracle runs
-    MGCG in FP64 (it has no FP32 inner solver for it), with Jacobi its FP32
-    refinement solver."""
+def cpu_baseline(spec, mu, budget_s, omega, tol):
+    """The oracle's own solver for the same problem on the host cores, measured
+    to convergence: `cores` parameters of the batch, one per thread, each solved
+    by FP64 MGCG (the V-cycle of Alg. 2 in Alg. 1, the same levels, smoother and
+    weight as the GPU's) from zero to relative residual `tol`.  The oracle has
+    no reduced basis at this size (its greedy would take hours), so the start
+    is zero.  Timed twice: with the oracle's correctly rounded inner products,
+    and with plain FP64 loops in their place (a conventional CPU code); a
+    variant whose first solve alone would exceed the budget is skipped."""
     import oracle
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     O = oracle.Problem(spec)
     sample = mu[:cores]
-    mg = PRECOND == 2
+    out = {"unit": "mu-solves/s", "cores": cores, "kind": "oracle", "cpu": cpu_model(),
+           "host_cpus": os.cpu_count()}
+    for name, naive in (("exact_dots", False), ("naive_dots", True)):
+        oracle.core.set_naive_dots(naive)
+        try:
+            t = time.perf_counter()
+            _, st = O.mgcg_batch(sample, tol=tol, omega=omega, maxit=400, nthreads=cores)
+            wall = time.perf_counter() - t
+        finally:
+            oracle.core.set_naive_dots(False)
+        its = [int(s["iters"]) for s in st]
+        out[name] = {"value": round(cores / wall, 5), "wall_s": round(wall, 2),
+                     "s_per_solve_one_core": round(wall, 3), "iters_mean": float(np.mean(its)),
+                     "all_converged": all(int(s["status"]) == 0 for s in st)}
+        if wall > budget_s:
+            break
+    out["value"] = out["exact_dots"]["value"]
+    out["cpu_reference_throughput"] = out.get("naive_dots", {}).get("value")
+    out["sample"] = (f"{cores} parameters of the batch, one per thread, FP64 MGCG from zero to {tol:g} "
+                     "(each to its own convergence); value: correctly rounded dots, "
+                     "cpu_reference_throughput: plain FP64 dot loops")
+    return out
 
-    def run(ms, cap, threads):
-        if mg:
-            O.mgcg_batch(ms, tol=1e-30, maxit=cap, nthreads=threads, omega=omega)
-        else:
-            O.ir_batch(ms, prec=oracle.PREC_JACOBI, tol=1e-10, eta=1e-30, kin_max=cap, max_outer=1,
-                       nthreads=threads, reliable=True)
-
-    # probe the cost of a few iterations, then size the sample to the budget
-    t = time.perf_counter()
-    run(sample[:1], 3, 1)
-    per_it = max((time.perf_counter() - t) / 5.0, 1e-3)
-    cap = int(max(3, min(400, budget_s / per_it / 2.0)))
-    t = time.perf_counter()
-    run(sample, cap, cores)
-    wall = time.perf_counter() - t
-    per_solve = wall / cap * (gpu_inner_mean + (0 if mg else 2 * gpu_outer_mean))
-    what = "FP64 MGCG iterations" if mg else "FP32 inner iterations (+2 outer residuals)"
-    return {"value": round(cores / per_solve, 5), "unit": "mu-solves/s", "cores": cores,
-            "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
-            "s_per_solve_one_core": round(per_solve, 3),
-            "sample": f"{cores} parameters of the batch, one per thread, {cap} {what} each; "
-                      f"wall {wall:.1f} s, scaled to the GPU's mean {gpu_inner_mean:.0f} inner iterations per solve"}
 
 if __name__ == "__main__":
     main()

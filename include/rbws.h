@@ -218,6 +218,15 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
 rbws_status rbws_exact_dots_noalloc(const double* x, const double* y, long long len, int count,
                                     double* out, int flags, void* stream);
 
+/* dst[0:bytes) = src[0:bytes): a plain device copy with 16-byte
+ * non-temporal loads and stores, each byte read and written once.  Not a step
+ * of the method: the bandwidth a streaming kernel reaches on this device, the
+ * reference that measured stencil and vector-update bandwidths and HBM
+ * counters are compared with.  src, dst device, 16-byte aligned, not
+ * overlapping; bytes a multiple of 16.  Stream-ordered, not synchronised.
+ * Errors: EINVAL (NULL, misaligned, bytes negative or not a multiple of 16). */
+rbws_status rbws_stream_copy(const void* src, void* dst, long long bytes, void* stream);
+
 /* ---- offline: greedy reduced basis (Alg. 4 skeleton) ---------------------
  * Builds V (N orthonormal vectors), A_q^N = V^T A_q V and f^N = V^T f from the
  * training set mu_train (host, ntrain x p).  Step n: snapshot u(mu_l) by PCG

@@ -60,6 +60,7 @@ def lib():
         sig = {
             "orc_exact_dot": (C.c_double, [d, d, l]),
             "orc_exact_sum": (C.c_double, [d, l]),
+            "orc_set_naive_dots": (None, [i]),
             "orc_nq": (i, [pp]),
             "orc_theta": (None, [pp, d, d]),
             "orc_face_coeffs": (None, [pp, d, d, d, d]),
@@ -283,6 +284,13 @@ def exact_dot(x, y) -> float:
     x, y = _f64(x), _f64(y)
     assert x.shape == y.shape
     return lib().orc_exact_dot(_dp(x), _dp(y), x.size)
+
+
+def set_naive_dots(on: bool) -> None:
+    """Process-wide: the solvers' inner products (PCG, refinement) become a
+    plain FP64 loop instead of correctly rounded dots.  Only for timing a
+    conventional CPU code; every other use keeps the default (off)."""
+    lib().orc_set_naive_dots(1 if on else 0)
 
 
 def exact_sum(x) -> float:

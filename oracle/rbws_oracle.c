@@ -203,6 +203,19 @@ double orc_exact_sum(const double *x, long n) {
     return xacc_round(&a);
 }
 
+/* The solvers' inner products (PCG, refinement): correctly rounded, or, for
+ * timing a conventional CPU code only, a plain left-to-right FP64 loop.  The
+ * switch is process-wide and is set before a solve starts. */
+static int g_naive_dots = 0;
+void orc_set_naive_dots(int on) { g_naive_dots = on ? 1 : 0; }
+
+static double solver_dot(const double *x, const double *y, long n) {
+    if (!g_naive_dots) return orc_exact_dot(x, y, n);
+    double acc = 0.0;
+    for (long i = 0; i < n; i++) acc = fma(x[i], y[i], acc);
+    return acc;
+}
+
 /* ------------------------------------------------------------------ */
 /* face coefficients                                                    */
 /* Coordinates are scaled by 20(n+1) so that they are integers:          */
@@ -436,7 +449,7 @@ static int pcg_core(const faces *F, int n, const double *f, const double *u0, pr
     double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * m);
     double *p = malloc(sizeof(double) * m), *q = malloc(sizeof(double) * m);
     memset(st, 0, sizeof *st);
-    double ff = orc_exact_dot(f, f, m);
+    double ff = solver_dot(f, f, m);
     double thr = (tol * tol) * ff;
     st->ff = ff;
     if (u0) memcpy(x, u0, sizeof(double) * m); else memset(x, 0, sizeof(double) * m);
@@ -444,7 +457,7 @@ static int pcg_core(const faces *F, int n, const double *f, const double *u0, pr
     /* Alg. 1 step 2: r0 = f - A u0 */
     apply_faces(F, n, x, q);
     for (long i = 0; i < m; i++) r[i] = f[i] - q[i];
-    double rr = orc_exact_dot(r, r, m);
+    double rr = solver_dot(r, r, m);
     st->init_rr = rr;
     if (hist) hist[0] = rr;
     int k = 0, extra = 0, status = ORC_MAXITER;
@@ -453,12 +466,12 @@ static int pcg_core(const faces *F, int n, const double *f, const double *u0, pr
     if (rr <= thr) { status = ORC_CONVERGED; goto done; }
     /* Alg. 1 steps 3-4: s0 = P(r0), p0 = s0 */
     pre(ctx, r, s);
-    rho = orc_exact_dot(r, s, m);
+    rho = solver_dot(r, s, m);
     memcpy(p, s, sizeof(double) * m);
     for (;;) {
         if (k >= maxit) { status = ORC_MAXITER; break; }
         apply_faces(F, n, p, q);
-        double gamma = orc_exact_dot(p, q, m);
+        double gamma = solver_dot(p, q, m);
         if (!isfinite(gamma)) { status = ORC_NAN; break; }
         if (!(gamma > 0.0)) { status = ORC_BREAKDOWN; break; }
         double alpha = rho / gamma;
@@ -467,7 +480,7 @@ static int pcg_core(const faces *F, int n, const double *f, const double *u0, pr
             r[i] = fma(-alpha, q[i], r[i]);
         }
         k++;
-        rr = orc_exact_dot(r, r, m);
+        rr = solver_dot(r, r, m);
         if (hist) hist[k] = rr;
         if (!isfinite(rr)) { status = ORC_NAN; break; }
         if (rr <= thr) {
@@ -475,17 +488,17 @@ static int pcg_core(const faces *F, int n, const double *f, const double *u0, pr
             apply_faces(F, n, x, q);
             for (long i = 0; i < m; i++) r[i] = f[i] - q[i];
             extra++;
-            rr = orc_exact_dot(r, r, m);
+            rr = solver_dot(r, r, m);
             if (!isfinite(rr)) { status = ORC_NAN; break; }
             if (rr <= thr) { status = ORC_CONVERGED; break; }
             /* restart from the true residual */
             pre(ctx, r, s);
-            rho = orc_exact_dot(r, s, m);
+            rho = solver_dot(r, s, m);
             memcpy(p, s, sizeof(double) * m);
             continue;
         }
         pre(ctx, r, s);
-        double rs = orc_exact_dot(r, s, m);
+        double rs = solver_dot(r, s, m);
         double beta = rs / rho;
         for (long i = 0; i < m; i++) p[i] = fma(beta, p[i], s[i]);
         rho = rs;
@@ -1090,7 +1103,7 @@ int orc_ir_solve2(const orc_problem *P, const double *mu, const double *f, const
                 dg[(long)(k - 1) * n2 + (long)(j - 1) * n + (i - 1)] = ((((c0 + c1) + c2) + c3) + c4) + c5;
             }
     memset(st, 0, sizeof *st);
-    double ff = orc_exact_dot(f, f, m), thr = (tol * tol) * ff;
+    double ff = solver_dot(f, f, m), thr = (tol * tol) * ff;
     st->ff = ff;
     if (u0) memcpy(u, u0, sizeof(double) * m); else memset(u, 0, sizeof(double) * m);
     int outer = 0, inner = 0, status = ORC_MAXITER;
@@ -1099,7 +1112,7 @@ int orc_ir_solve2(const orc_problem *P, const double *mu, const double *f, const
     for (;;) {
         apply_faces(&F, n, u, q64);
         for (long i = 0; i < m; i++) r[i] = f[i] - q64[i];
-        rr = orc_exact_dot(r, r, m);
+        rr = solver_dot(r, r, m);
         if (outer == 0) st->init_rr = rr;
         if (!isfinite(rr)) { status = ORC_NAN; break; }
         if (rr <= thr) { status = ORC_CONVERGED; break; }

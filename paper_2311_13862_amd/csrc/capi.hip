@@ -302,6 +302,16 @@ rbws_status rbws_exact_dots(const double* x, const double* y, long long len, int
   API_END
 }
 
+rbws_status rbws_stream_copy(const void* src, void* dst, long long bytes, void* stream) {
+  API_BEGIN
+  RBWS_REQUIRE(bytes >= 0 && bytes % 16 == 0, RBWS_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (bytes == 0) return RBWS_OK;
+  RBWS_REQUIRE(src && dst, RBWS_EINVAL, "NULL pointer");
+  RBWS_REQUIRE(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, RBWS_EINVAL, "src and dst must be 16-byte aligned");
+  stream_copy(src, dst, bytes, (hipStream_t)stream);
+  API_END
+}
+
 rbws_status rbws_exact_dots_noalloc(const double* x, const double* y, long long len, int count, double* out,
                                     int flags, void* stream) {
   API_BEGIN

@@ -1109,6 +1109,37 @@ void exact_dots(const double* x, const double* y, long long len, int count, doub
   RBWS_HIP(hipStreamSynchronize(s));
 }
 
+// Plain device copy with 16-byte non-temporal loads and stores: a workgroup
+// moves kCopyWords consecutive 16-byte words, each thread four of them with
+// all loads issued before the stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyWords = 1024;
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                     long long nwords) {
+  const long long base = (long long)blockIdx.x * kCopyWords + threadIdx.x;
+  u32x4 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const long long i = base + u * 256;
+    if (i < nwords) v[u] = __builtin_nontemporal_load(src + i);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const long long i = base + u * 256;
+    if (i < nwords) __builtin_nontemporal_store(v[u], dst + i);
+  }
+}
+
+void stream_copy(const void* src, void* dst, long long bytes, hipStream_t s) {
+  const long long nwords = bytes / 16;
+  const long long blocks = (nwords + kCopyWords - 1) / kCopyWords;
+  RBWS_REQUIRE(blocks < (1LL << 31), RBWS_EINVAL, "copy too large");
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst,
+                     nwords);
+  RBWS_HIP(hipGetLastError());
+}
+
 // Fixed workspace of exact_dots_noalloc: the partial sums of one call.  Each
 // GPU the library runs on holds its own copy of this array until the process
 // ends.  In host code its name is not a device address: the address on the

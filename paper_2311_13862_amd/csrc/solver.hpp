@@ -232,6 +232,9 @@ void exact_dots(const double* x, const double* y, long long len, int count, doub
 void exact_dots_noalloc(const double* x, const double* y, long long len, int count, double* out_dev,
                         int flags, hipStream_t s);
 
+// plain device copy (16-byte non-temporal loads and stores); bytes % 16 == 0
+void stream_copy(const void* src, void* dst, long long bytes, hipStream_t s);
+
 double wall_clock_khz(int device);
 
 // Opt-in HIP-event timing of every launch of the solver's kernels, by kind.

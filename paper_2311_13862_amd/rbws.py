@@ -118,6 +118,7 @@ def _load():
         "rbws_spmv": (i, [vp, dp, i, vp, vp, i, vp]),
         "rbws_exact_dots": (i, [vp, vp, ll, i, dp, i, vp]),
         "rbws_exact_dots_noalloc": (i, [vp, vp, ll, i, vp, i, vp]),
+        "rbws_stream_copy": (i, [vp, vp, ll, vp]),
         "rbws_solve": (i, [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i, C.POINTER(i), dp, i,
                            C.POINTER(SolveOpts), vp, C.POINTER(vp), C.POINTER(SolveStat)]),
     }
@@ -264,6 +265,14 @@ def exact_dots_noalloc(x, y, out, flags: int = 0, stream=None):
     count, length = x.shape
     _check(_L.rbws_exact_dots_noalloc(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), length, count,
                                       C.c_void_p(out.data_ptr()), flags, _stream(stream)))
+
+
+def stream_copy(src, dst, stream=None):
+    """dst = src for two device tensors of the same byte size (a multiple of
+    16), with the library's non-temporal streaming copy kernel."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    _check(_L.rbws_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb, _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 4 << 20

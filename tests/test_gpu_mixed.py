@@ -101,3 +101,50 @@ def test_mixed_batch(rb, mixed, precision):
                 rel = np.linalg.norm(ub - ref) / np.linalg.norm(ref)
                 assert rel <= 1e-8, rel
             assert st[b]["final_rr"] <= tol * tol * st[b]["ff"]
+
+
+def test_aniso_mixed_full_sizes(rb):
+    """The anisotropic workload's uneven batch at its real grid sizes: 24 solves,
+    solve i on 64^3, 96^3 or 128^3 (i mod 3), in one launch, FP32 PCG with the
+    V-cycle inside FP64 refinement from per-size RB starts (small bases: N = 8
+    from 32 training parameters).  One solve per size against the oracle's FP64
+    MGCG to 1e-8; every solve's recursive and device-clock statistics valid."""
+    sizes = (64, 96, 128)
+    probs, bases, specs = [], [], []
+    for q, n in enumerate(sizes):
+        spec = gauss_spec(n)
+        mut = W.sample_mu(spec, 0.1, 10.0, 32, W.SEED_TRAIN + 10 * q)
+        P = rb.Problem(spec)
+        probs.append(P)
+        bases.append(rb.Basis.build(P, mut, 8, 1e-12))
+        specs.append(spec)
+    nsol = 24
+    assign = (np.arange(nsol) % 3).astype(np.int32)
+    mus = np.empty((nsol, specs[0].p))
+    for q in range(3):
+        mus[assign == q] = W.sample_mu(specs[q], 0.1, 10.0, int(np.sum(assign == q)), W.SEED_TEST + 10 * q)
+    u = [torch.empty(probs[q].ndof, dtype=torch.float64, device="cuda") for q in assign]
+    opts = rb.default_opts(tol=1e-10, precision=rb.FP32_IR, precond=rb.PREC_MG, init=rb.INIT_RB,
+                           lift=rb.LIFT_MFMA, eta_inner=0.05, mg_omega=0.9, ir_mode=rb.IR_RELIABLE)
+    st = rb.solve(probs, mus, opts, problem_of=assign, bases=bases, u_out=u)
+    torch.cuda.synchronize()
+    assert np.all(st["status"] == rb.SOLVE_CONVERGED)
+    assert np.all(st["final_rr"] <= 1e-20 * st["ff"])
+    assert np.all(st["t_done_ms"] > 0)
+    # one solve per size (the first of each) against the oracle's FP64 MGCG
+    import concurrent.futures as cf
+
+    def ref(q):
+        b = int(np.flatnonzero(assign == q)[0])
+        O = oracle.Problem(specs[q])
+        x, s = O.mgcg(mus[b], tol=1e-12, omega=0.9)
+        return b, x, s
+
+    with cf.ThreadPoolExecutor(3) as ex:
+        for b, x, s in ex.map(ref, range(3)):
+            assert s["status"] == 0
+            ub = u[b].cpu().numpy()
+            err = np.linalg.norm(ub - x) / np.linalg.norm(x)
+            print(f"solve {b} at {specs[assign[b]].n}^3: error vs the oracle {err:.2e}, "
+                  f"{st[b]['iters']} inner / {st[b]['outer_iters']} outer iterations")
+            assert err <= 1e-8, (b, err)

@@ -211,6 +211,35 @@ def test_learned_start_gain(rb, learned16):
     it = {k: np.mean([s["iters"] for s in v[0]]) for k, v in runs.items()}
     # what the network gains over the zero start, at the same tolerance
     assert it["learned"] < it["zero"], it
+    # and over the method without it (the RB start): iterations, the start stage's
+    # time per batch (reduced solves against network inference), and throughput of
+    # the whole solve, timed in interleaved rounds
+    import time
+    t_stage = {}
+    for name, fn in (("rb_coeffs", lambda: basis.coeffs(mus)), ("mlp_predict", lambda: net.predict(mus))):
+        fn()
+        t = time.perf_counter()
+        for _ in range(5):
+            fn()
+        t_stage[name] = (time.perf_counter() - t) / 5 * 1e3
+    secs = {k: [] for k in ("rb", "strict", "zero")}
+    opt = {"rb": rb.default_opts(tol=wl.tol, init=rb.INIT_RB),
+           "strict": rb.default_opts(tol=wl.tol, init=rb.INIT_LEARNED, fallback=0),
+           "zero": rb.default_opts(tol=wl.tol)}
+    for _ in range(3):
+        for k in secs:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rb.solve([P], mus, opt[k], bases=[basis], mlps=[net])
+            torch.cuda.synchronize()
+            secs[k].append(time.perf_counter() - t)
+    thr = {k: len(mus) / float(np.median(v)) for k, v in secs.items()}
+    print("learned start vs RB start at blocks3-16:",
+          {"inner_iters_mean": {k: float(v) for k, v in it.items()},
+           "iters_gain_over_rb": {"cheap": float(it["rb"] - it["learned"]), "strict": float(it["rb"] - it["strict"])},
+           "start_stage_ms_per_batch": t_stage,
+           "mu_solves_per_s": thr, "strict_over_rb": thr["strict"] / thr["rb"],
+           "started_from_mlp_strict": int(sum(s["init_used"] == rb.INIT_LEARNED for s in runs["strict"][0]))})
     # strict fallback: each solve starts from the smaller of the two true residuals
     for s_strict, s_l, s_r in zip(runs["strict"][0], runs["learned"][0], runs["rb"][0]):
         if s_l["init_used"] == rb.INIT_LEARNED:

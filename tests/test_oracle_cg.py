@@ -208,3 +208,25 @@ def test_plain_cg_trajectory_prefix_matches_dense_alg1(spec):
     _, kd, hd = dense_alg1(O5.dense(m), O5.rhs(m), False, 1e-10, 5000)
     assert st["iters"] == kd
     np.testing.assert_allclose(h, hd, rtol=1e-10, atol=0)
+
+
+def test_naive_dot_variant_is_only_a_timing_aid():
+    """The plain-loop inner products (used only to time a conventional CPU code)
+    reach the same solution to the tolerance's accuracy, and switching them off
+    restores the correctly rounded trajectory bit for bit."""
+    spec = W.Problem(12, W.KIND_OCTANTS)
+    O = oracle.Problem(spec)
+    mu = W.sample_mu(spec, 0.01, 100.0, 3, 21)
+    x1, s1 = O.cg_batch(mu, tol=1e-10)
+    oracle.core.set_naive_dots(True)
+    try:
+        x2, s2 = O.cg_batch(mu, tol=1e-10)
+    finally:
+        oracle.core.set_naive_dots(False)
+    x3, s3 = O.cg_batch(mu, tol=1e-10)
+    assert np.array_equal(x1, x3)
+    assert [s["iters"] for s in s1] == [s["iters"] for s in s3]
+    for b in range(3):
+        assert s2[b]["status"] == 0
+        assert abs(s2[b]["iters"] - s1[b]["iters"]) <= 3
+        assert np.linalg.norm(x2[b] - x1[b]) <= 1e-7 * np.linalg.norm(x1[b])
