@@ -364,7 +364,11 @@ def interleave(rbws, torch, legs, reps):
 def leg_summary(rbws, run, batch):
     v = batch / np.array(run["s"])
     st = run["stats"]
+    nrun = len(run["s"])
+    stage = {k: round(run["kern"][k][0] / nrun, 3) for k in ("rb_project", "rb_coeffs", "lift_mfma")
+             if run["kern"].get(k, (0.0, 0))[1] > 0}
     return {"value_median": round(float(np.median(v)), 3), "value_min": round(float(v.min()), 3),
+            "start_stage_ms": stage,
             "value_max": round(float(v.max()), 3), "runs": [round(float(x), 3) for x in v],
             "all_converged": bool(np.all(st["status"] == rbws.SOLVE_CONVERGED)),
             "inner_iters_mean": float(np.mean(st["iters"])), "outer_iters_mean": float(np.mean(st["outer_iters"])),
@@ -489,7 +493,7 @@ def c5_leg(rbws, torch, W, args):
     FP32 PCG with the V-cycle inside FP64 refinement to 1e-10, from zero, RB and
     learned starts, interleaved.  Per-solve latency is each solve's completion
     time inside the uneven batch (device clock)."""
-    probs, bases, nets, specs, info = [], [], [], [], []
+    probs, bases, nets, specs, info, l1bases = [], [], [], [], [], []
     rbws.set_tuning(rbws.TUNE_TZ, 0)
     t_off = 0.0
     t_learn = 0.0
@@ -504,6 +508,12 @@ def c5_leg(rbws, torch, W, args):
         torch.cuda.synchronize()
         tb = time.perf_counter() - t
         t_off += tb
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        L1 = rbws.Basis.build(P, mut, min(args.c5_N, 60), wl.snap_tol, precond=rbws.PREC_JACOBI, method="l1roc")
+        torch.cuda.synchronize()
+        tl1 = time.perf_counter() - t
+        l1bases.append(L1)
         mup = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.mlp_pairs, W.SEED_MLP_PAIRS + 10 * q)
         t = time.perf_counter()
         c = B.coeffs(mup)
@@ -520,8 +530,11 @@ def c5_leg(rbws, torch, W, args):
         nets.append(net)
         specs.append(spec)
         info.append({"n": n, "rb_dim": B.N, "t_off_s": round(tb, 2), "t_learn_s": round(tl, 2),
-                     "final_max_indicator": B.final_max, "final_loss": float(np.mean(hist[-32:]))})
-        log(f"aniso-mixed {n}^3: basis N={B.N} in {tb:.1f} s, network in {tl:.1f} s")
+                     "final_max_indicator": B.final_max, "final_loss": float(np.mean(hist[-32:])),
+                     "l1roc_dim": L1.N, "l1roc_points": int(len(L1.l1roc_info()["pts"])),
+                     "l1roc_t_off_s": round(tl1, 2)})
+        log(f"aniso-mixed {n}^3: basis N={B.N} in {tb:.1f} s, L1ROC N={L1.N} in {tl1:.1f} s, "
+            f"network in {tl:.1f} s")
     nsol = args.c5_batch
     assign = (np.arange(nsol) % 3).astype(np.int32)
     mu = np.empty((nsol, specs[0].p))
@@ -534,7 +547,9 @@ def c5_leg(rbws, torch, W, args):
             "rb": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_RB, **base), problem_of=assign,
                                      bases=bases),
             "learned": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_LEARNED, fallback=0, **base),
-                                          problem_of=assign, bases=bases, mlps=nets)}
+                                          problem_of=assign, bases=bases, mlps=nets),
+            "l1roc": lambda: rbws.solve(probs, mu, rbws.default_opts(init=rbws.INIT_RB, **base), problem_of=assign,
+                                        bases=l1bases)}
     runs = interleave(rbws, torch, legs, args.reps)
     out = {}
     for k, run in runs.items():
@@ -550,13 +565,17 @@ def c5_leg(rbws, torch, W, args):
     out["rb"]["over_zero"] = paired_ratio(runs["rb"], runs["zero"])
     out["learned"]["over_rb"] = paired_ratio(runs["learned"], runs["rb"])
     out["learned"]["over_zero"] = paired_ratio(runs["learned"], runs["zero"])
+    out["l1roc"]["over_zero"] = paired_ratio(runs["l1roc"], runs["zero"])
     return {"config": {"workload": "aniso27-mixed-64/96/128^3-fp32ir", "sizes": list(C5_SIZES), "batch": nsol,
                        "assignment": "solve i on size index i mod 3", "rb_dim": args.c5_N, "n_train": args.c5_ntrain,
                        "tol": 1e-10, "precond": "mg-vcycle" if PRECOND == 2 else "jacobi", "p": specs[0].p,
                        "mlp_pairs": args.mlp_pairs, "mlp_epochs": args.mlp_epochs},
             "value": out["rb"]["value_median"], "unit": "mu-solves/s", "per_size": info,
             "t_off_s": round(t_off, 2), "t_learn_s": round(t_learn, 2),
-            "zero": out["zero"], "rb": out["rb"], "learned": out["learned"]}
+            "zero": out["zero"], "rb": out["rb"], "learned": out["learned"], "l1roc": out["l1roc"],
+            "online_stage_note": ("start_stage_ms per batch: rb_project = V^T f(mu) on the matrix cores (Galerkin), "
+                                  "rb_coeffs = reduced solves (Galerkin: assembly + Cholesky; L1ROC: the source at "
+                                  "its collocation points + QR), lift_mfma = u0 = V c")}
 
 
 def mg_pre0_bytes(n):

@@ -248,7 +248,7 @@ rbws_status rbws_rb_build(rbws_problem* p, const double* mu_train, int ntrain, i
                           int precond, int snap_maxit, void* stream, rbws_basis** out, int* selected,
                           double* indicator_hist, int* n_reached);
 /* L1-based reduced over-collocation (Sec. 3.1, Alg. 4), the paper's own RB
- * variant.  Same arguments as rbws_rb_build; f = 1 only, N in [1, 40].
+ * variant.  Same arguments as rbws_rb_build; N in [1, 60].
  * Step 1: snapshot u(mu_train[0]) by PCG; DEIM gives the first vector
  * w_1 = u / u(x_1), x_1 = argmax |u|.  Step n: the collocation least-squares
  * solve c(mu) = argmin || P (f - A(mu) W c) ||_2 at the collocation points X
@@ -413,10 +413,12 @@ rbws_status rbws_solve(rbws_problem* const* problems, const rbws_basis* const* b
  * inner products), 5 SpMV, 6 MFMA lift, 7 reduced solves, 8 multigrid
  * V-cycle except its fused finest-level kernels (coarser levels, transfers,
  * the per-solve step after it), 9 the finest level's fused pre-smoothing and
- * residual, 10 its fused coarse correction, post-smoothing and r^T s.  The
- * call first waits for recorded events and returns the totals so far
- * (ms[11], launches[11], both nullable), then zeroes them if `reset`, then
- * turns timing on or off. */
+ * residual, 10 its fused coarse correction, post-smoothing and r^T s,
+ * 11 the projection V^T f(mu) of a parameter-dependent source (Galerkin
+ * bases; L1ROC evaluates f at its collocation points inside 7).  The call
+ * first waits for recorded events and returns the totals so far (ms[12],
+ * launches[12], both nullable), then zeroes them if `reset`, then turns
+ * timing on or off. */
 rbws_status rbws_profile(int enable, double* ms, long long* launches, int reset);
 /* How often a correctly rounded inner product could not be certified from
  * its double-double value and was recomputed exactly (current device):

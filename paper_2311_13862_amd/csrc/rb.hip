@@ -591,7 +591,10 @@ int rb_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int c
   }
   RBWS_SCRATCH(bnb);
   double* bN = (double*)bnb.get(sizeof(double) * (size_t)ns * kMaxN, B.device);
-  if (project_sources(B, bases, bN, s))
+  ktimer().begin(s, KK_PROJ);
+  const bool projected = project_sources(B, bases, bN, s);
+  ktimer().end(s);
+  if (projected)
     for (int b = 0; b < ns; b++)
       if (B.probs[B.sd_h[b].prob]->desc.f_kind != RBWS_F_ONE) h[b].fN = bN + (size_t)b * kMaxN;
   RBWS_SCRATCH(rbd);
@@ -1044,7 +1047,7 @@ Basis* basis_load(const Problem* P, const char* path, hipStream_t s) {
 // rounded product and difference, so the result is that of the sequential
 // definition, bit for bit.  The greedy's indicator is ||T c||_1 (W = U T).
 
-constexpr int kL1MaxM = 2 * kL1MaxN;
+constexpr int kL1MaxM = 2 * kL1MaxN - 1;  // the first step adds one point, every later step at most two
 
 struct L1Dev {           // per solve
   const double* W;       // nb x ndof
@@ -1088,8 +1091,10 @@ __device__ double point_apply(const GridDev& g, const double* kt, const double* 
   return acc;
 }
 
-// Collocation least squares of one solve per 64-thread block (f = 1: f_h = h^2
-// at every point); optionally the L1 indicator sum_i |sum_{j>=i} T_ij c_j|.
+// Collocation least squares of one solve per 64-thread block, right-hand side
+// f_h(mu) at the collocation points (the M point evaluations that replace the
+// projection V^T f(mu) for a parameter-dependent source); optionally the L1
+// indicator sum_i |sum_{j>=i} T_ij c_j|.
 __global__ __launch_bounds__(64) void k_l1_lsq(const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                const double* __restrict__ kap, const L1Dev* __restrict__ l1,
                                                double* __restrict__ cout, int cstride, double* __restrict__ delta,
@@ -1106,7 +1111,11 @@ __global__ __launch_bounds__(64) void k_l1_lsq(const SolveDev* __restrict__ sd, 
     const int i = e / nb, j = e - i * nb;
     sh.A[i * kL1MaxN + j] = point_apply(P.g, kt, L.W + (long long)j * nd, L.pts[i]);
   }
-  for (int i = lane; i < M; i += 64) sh.b[i] = P.h2;
+  for (int i = lane; i < M; i += 64) {
+    const long long pt = L.pts[i];
+    const int n = P.g.n;
+    sh.b[i] = fval(P, S, (int)(pt % n) + 1, (int)((pt / n) % n) + 1, (int)(pt / ((long long)n * n)) + 1);
+  }
   __syncthreads();
   int fail = 0;
   for (int k = 0; k < nb; k++) {
@@ -1280,9 +1289,14 @@ __global__ __launch_bounds__(256) void k_absmax_final(ValIdx* __restrict__ part,
 __global__ void k_neg(double* __restrict__ out, const double* __restrict__ in, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = -in[i];
 }
-__global__ void k_rhs_minus(double* __restrict__ r, const double* __restrict__ au, double f, long long nd) {
+// r = f_h(mu) - A u of the batch's first solve
+__global__ void k_rhs_minus(double* __restrict__ r, const double* __restrict__ au, const ProbDev* __restrict__ pd,
+                            const SolveDev* __restrict__ sd, long long nd) {
+  const SolveDev S = sd[0];
+  const ProbDev& P = pd[S.prob];
+  const int n = P.g.n;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nd; c += (long long)gridDim.x * blockDim.x)
-    r[c] = f - au[c];
+    r[c] = fval(P, S, (int)(c % n) + 1, (int)((c / n) % n) + 1, (int)(c / ((long long)n * n)) + 1) - au[c];
 }
 
 static int l1roc_coeffs(Batch& B, const std::vector<const Basis*>& bases, double* c, int cstride,
@@ -1346,10 +1360,9 @@ static long long deim_gpu(const double* Bv, int nb, const long long* pt_d, long 
 Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol, int prec,
                       int snap_maxit, int flags, hipStream_t s) {
   RBWS_REQUIRE(ntrain >= 1, RBWS_EINVAL, "empty training set");
-  RBWS_REQUIRE(N >= 1 && N <= kL1MaxN, RBWS_EINVAL, "N must be in [1, 40] for L1ROC");
+  RBWS_REQUIRE(N >= 1 && N <= kL1MaxN, RBWS_EINVAL, "N must be in [1, 60] for L1ROC");
   RBWS_REQUIRE(N <= ntrain, RBWS_EINVAL, "N exceeds the training set");
   RBWS_REQUIRE(snap_tol > 0.0 && std::isfinite(snap_tol), RBWS_EINVAL, "snap_tol must be positive");
-  RBWS_REQUIRE(P->desc.f_kind == RBWS_F_ONE, RBWS_EINVAL, "L1ROC is built for f = 1 only");
   RBWS_HIP(hipSetDevice(P->device));
   const int fe = (flags & RBWS_FLAG_FORCE_EXACT_DOTS) ? 1 : 0;
   const long long nd = P->ndof;
@@ -1386,7 +1399,6 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
     Batch snap, one, tr;
     batch_setup(tr, probs, nullptr, ntrain, mu_train, P->p, s);
     std::vector<double> delta(ntrain);
-    const double hh = 1.0 / (P->n + 1), h2 = hh * hh;
     auto snapshot = [&](int l) -> double* {
       batch_setup(snap, probs, nullptr, 1, mu_train + (long long)l * P->p, P->p, s);
       double* x = (double*)snap.x.get(sizeof(double) * nd, dev);
@@ -1447,7 +1459,8 @@ Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int 
       double* ux = (double*)one.x.get(sizeof(double) * nd, dev);
       RBWS_HIP(hipMemcpyAsync(ux, au, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
       spmv_batch(one, ux, au, false, s);
-      hipLaunchKernelGGL(k_rhs_minus, dim3(2048), dim3(256), 0, s, r, (const double*)au, h2, nd);
+      hipLaunchKernelGGL(k_rhs_minus, dim3(2048), dim3(256), 0, s, r, (const double*)au, (const ProbDev*)one.pd.ptr,
+                         (const SolveDev*)one.sd.ptr, nd);
       RBWS_HIP(hipGetLastError());
       // the snapshot's DEIM step
       const double* x = snapshot(best);

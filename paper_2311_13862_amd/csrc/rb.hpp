@@ -52,10 +52,10 @@ Basis* rb_build(const Problem* P, const double* mu_train, int ntrain, int N, dou
 
 // L1ROC greedy (Sec. 3.1, Alg. 4): snapshots by PCG, DEIM of each snapshot and
 // of the current approximation's residual at the chosen parameter, the L1
-// indicator over the training set; f = 1 only, N <= kL1MaxN.
+// indicator over the training set; N <= kL1MaxN.
 Basis* rb_build_l1roc(const Problem* P, const double* mu_train, int ntrain, int N, double snap_tol,
                       int prec, int snap_maxit, int flags, hipStream_t s);
-constexpr int kL1MaxN = 40;
+constexpr int kL1MaxN = 60;
 
 // ||f - A(mu_b) V c_b|| / ||f|| for every solve of B from the residual
 // decomposition of its problem's basis (every basis must have `est`); c device,

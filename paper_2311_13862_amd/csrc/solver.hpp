@@ -239,7 +239,7 @@ double wall_clock_khz(int device);
 
 // Opt-in HIP-event timing of every launch of the solver's kernels, by kind.
 enum KernelKind { KK_AP = 0, KK_RESID = 1, KK_FIN1 = 2, KK_UP2 = 3, KK_FIN2 = 4, KK_SPMV = 5, KK_LIFT = 6,
-                  KK_COEF = 7, KK_MG = 8, KK_MG_PRE = 9, KK_MG_POST = 10, KK_COUNT = 11 };
+                  KK_COEF = 7, KK_MG = 8, KK_MG_PRE = 9, KK_MG_POST = 10, KK_PROJ = 11, KK_COUNT = 12 };
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;

@@ -528,7 +528,7 @@ def pack_params(layers) -> np.ndarray:
 
 
 KERNEL_KINDS = ("ap_sweep", "resid_pass", "fin1", "up2_sweep", "fin2", "spmv", "lift_mfma", "rb_coeffs", "mg_vcycle",
-                "mg_pre0", "mg_post0")
+                "mg_pre0", "mg_post0", "rb_project")
 
 
 def profile(enable: bool, reset: bool = True):
