@@ -156,6 +156,39 @@ struct QuadGeo {
   const int* zk;
 };
 
+// The quad's four values in the LDS plane, one 16-byte LDS operation per four
+// floats (two per four doubles).  Row stride and quad offset are multiples of
+// four elements and the plane starts 16-byte aligned, so the accesses are
+// aligned; four scalar accesses at a four-element stride across the lanes
+// would meet four-way bank conflicts.
+__device__ __forceinline__ void pl_st4(float* p, const float v[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void pl_st4(double* p, const double v[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+__device__ __forceinline__ void pl_ld4(const float* p, float v[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void pl_ld4(const double* p, double v[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+// x neighbours of the quad whose values c[0..3] are in the plane: the last
+// point of the previous quad and the first of the next, taken from the
+// neighbouring lanes of the same row (a row is a run of lxm + 1 lanes inside
+// one wave), else the x-halo column or the boundary zero.  Every lane of the
+// wave must call this (the shuffles read the neighbours' registers).
+template <typename T>
+__device__ __forceinline__ void quad_xnb(const QuadGeo& G, const T* pl, const T c[4], T& left, T& right) {
+  const T l = __shfl_up(c[3], 1, 64), r = __shfl_down(c[0], 1, 64);
+  left = G.lx > 0 ? l : (G.hx ? pl[G.hl] : T(0));
+  right = G.lx < G.lxm ? r : (G.hx ? pl[G.hr] : T(0));
+}
+
 // Deepest tile (planes per z-march) and the length of its staged z codes.
 constexpr int kTzMax = 64;
 constexpr int kZkLen = kTzMax + 4;
@@ -365,7 +398,6 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
   xr_load(G.kb, xo, ro);
   int buf = 0;
   const int mrow = G.mrow;
-  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     // issue the next loads
     quad_load(k + 2, ra, rb);
@@ -376,14 +408,16 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
     xr_load(k + 1, xo2, ro2);
     // consume plane k
     T* pl = plane + buf * QPLANE;
-#pragma unroll
-    for (int e = 0; e < 4; e++) pl[mrow + e] = pc[e];
+    pl_st4(pl + mrow, pc);
     if (G.hslot >= 0) pl[G.hslot] = halo_finish(k, ha, hb);
     __syncthreads();
+    T left, right;
+    quad_xnb<T>(G, pl, pc, left, right);
     if (nv > 0) {
       const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
-      const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
-      const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
+      T ymv[4], ypv[4];
+      pl_ld4(pl + mrow - G.qs, ymv);
+      pl_ld4(pl + mrow + G.qs, ypv);
       T qo[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
@@ -392,7 +426,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         const T dg = diag6T<T>(kk);
         const T xm = e > 0 ? pc[e - 1] : left;
         const T xp = e < 3 ? pc[e + 1] : right;
-        const T ym = pl[mrow - G.qs + e], yp = pl[mrow + G.qs + e];
+        const T ym = ymv[e], yp = ypv[e];
         T q = dg * pc[e];
         q = fmaT(-kk[0], xm, q);
         q = fmaT(-kk[1], xp, q);
@@ -579,7 +613,6 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
   xr_load(G.kb, xo, ro);
   int buf = 0;
   const int mrow = G.mrow;
-  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     quad_load(k + 2, ra, rb);
     float ha2, hb2, xo2[4], ro2[4];
@@ -590,8 +623,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
     const int key = G.zk[k - G.kb + 1];
     if (key != C.key) kc_fill(C, G, kt, key);
     float* pl = plane + buf * QPLANE;
-#pragma unroll
-    for (int e = 0; e < 4; e++) pl[mrow + e] = pc[e];
+    pl_st4(pl + mrow, pc);
     if (G.hslot >= 0) {
       float hv = ha;
       if (OP == FOP_AP && hin) {
@@ -601,15 +633,18 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
       pl[G.hslot] = hv;
     }
     __syncthreads();
+    float left, right;
+    quad_xnb<float>(G, pl, pc, left, right);
     if (nv > 0) {
-      const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
-      const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
+      float ymv[4], ypv[4];
+      pl_ld4(pl + mrow - G.qs, ymv);
+      pl_ld4(pl + mrow + G.qs, ypv);
       float qo[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         const float xm = e > 0 ? pc[e - 1] : left;
         const float xp = e < 3 ? pc[e + 1] : right;
-        const float ym = pl[mrow - G.qs + e], yp = pl[mrow + G.qs + e];
+        const float ym = ymv[e], yp = ypv[e];
         float q = C.dg[e] * pc[e];
         q = fmaf(-C.kx[e], xm, q);
         q = fmaf(-C.kx[e + 1], xp, q);
@@ -695,19 +730,20 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
   double hv = halo_u(G.kb);
   int buf = 0;
   const int mrow = G.mrow;
-  const int hl = G.hl, hr = G.hr;
   for (int k = G.kb; k <= G.ke; k++) {
     quad_u(k + 1, un);
     const double hv2 = halo_u(k + 1);
     double* pl = plane + buf * QPLANE;
-#pragma unroll
-    for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+    pl_st4(pl + mrow, uc);
     if (G.hslot >= 0) pl[G.hslot] = hv;
     __syncthreads();
+    double left, right;
+    quad_xnb<double>(G, pl, uc, left, right);
     if (nv > 0) {
       const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
-      const double left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
-      const double right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
+      double ymv[4], ypv[4];
+      pl_ld4(pl + mrow - G.qs, ymv);
+      pl_ld4(pl + mrow + G.qs, ypv);
       float ro[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
@@ -718,8 +754,8 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
         double q = diag6T<double>(kk) * uc[e];
         q = __fma_rn(-kk[0], xm, q);
         q = __fma_rn(-kk[1], xp, q);
-        q = __fma_rn(-kk[2], pl[mrow - G.qs + e], q);
-        q = __fma_rn(-kk[3], pl[mrow + G.qs + e], q);
+        q = __fma_rn(-kk[2], ymv[e], q);
+        q = __fma_rn(-kk[3], ypv[e], q);
         q = __fma_rn(-kk[4], um[e], q);
         q = __fma_rn(-kk[5], un[e], q);
         ro[e] = 0.0f;

@@ -109,7 +109,7 @@ __device__ __forceinline__ void k_fast32_item(int item, const int2* __restrict__
                                                 const IrState* __restrict__ st, const float* __restrict__ kap,
                                                 float* __restrict__ d, float* __restrict__ r, float* __restrict__ p0,
                                                 float* __restrict__ p1, IrPart* __restrict__ part, int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   float* smem = reinterpret_cast<float*>(smem_raw);
   __shared__ double red[4][2];
   __shared__ int zk[kZkLen];

@@ -694,7 +694,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
                                                  const ProbDev* __restrict__ pd, const T* __restrict__ kap,
                                                  const T* __restrict__ b, T* __restrict__ tout, T omega,
                                                  int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* kt = reinterpret_cast<T*>(smem_raw);
   T* plane = kt + ktab;
   __shared__ int zk[kZkLen];
@@ -769,22 +769,24 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
     quad_e1(G.kb, bc, uc);
     int buf = 0;
     const int mrow = G.mrow;
-    const int hl = G.hl, hr = G.hr;
+
     for (int k = G.kb; k <= G.ke; k++) {
       load_b(k + 2, bnn);
       const T hbn = load_hb(k + 1);
       quad_e1(k + 1, bn, un);
       const T hv = halo_e1(k, hbc);
       T* pl = plane + buf * QPLANE;
-#pragma unroll
-      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      pl_st4(pl + mrow, uc);
       if (G.hslot >= 0) pl[G.hslot] = hv;
       __syncthreads();
+      T left, right;
+      quad_xnb<T>(G, pl, uc, left, right);
       if (nv > 0) {
         const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
-        const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
-        const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
+        T ymv[4], ypv[4];
+        pl_ld4(pl + mrow - G.qs, ymv);
+        pl_ld4(pl + mrow + G.qs, ypv);
         T to[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -794,8 +796,8 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
           T q = dg * uc[e];
           q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
           q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
-          q = fmaT(-kk[2], pl[mrow - G.qs + e], q);
-          q = fmaT(-kk[3], pl[mrow + G.qs + e], q);
+          q = fmaT(-kk[2], ymv[e], q);
+          q = fmaT(-kk[3], ypv[e], q);
           q = fmaT(-kk[4], um[e], q);
           q = fmaT(-kk[5], un[e], q);
           to[e] = bc[e] - q;
@@ -841,7 +843,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
                                                   const MgFine* __restrict__ mf, const int* __restrict__ gidx,
                                                   const T* __restrict__ r, T* __restrict__ sout, void* part,
                                                   T omega, int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* kt = reinterpret_cast<T*>(smem_raw);
   T* plane = kt + ktab;
   __shared__ CrAcc red[4];
@@ -968,7 +970,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
     acc.zero();
     int buf = 0;
     const int mrow = G.mrow;
-    const int hl = G.hl, hr = G.hr;
+
     for (int k = G.kb; k <= G.ke; k++) {
       load_q(k + 2, qnn);
       RawH hn;
@@ -976,15 +978,17 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       fin_q(k + 1, qn, un);
       const T hv = fin_h(k, hc);
       T* pl = plane + buf * QPLANE;
-#pragma unroll
-      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      pl_st4(pl + mrow, uc);
       if (G.hslot >= 0) pl[G.hslot] = hv;
       __syncthreads();
+      T left, right;
+      quad_xnb<T>(G, pl, uc, left, right);
       if (nv > 0) {
         const int zkv = G.zk[k - G.kb + 1], czn = zkv & 255, czm = (zkv >> 8) & 255, czp = zkv >> 16;
         const long long c = (long long)(k - 1) * n2 + rowoff;
-        const T left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);
-        const T right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);
+        T ymv[4], ypv[4];
+        pl_ld4(pl + mrow - G.qs, ymv);
+        pl_ld4(pl + mrow + G.qs, ypv);
         T so[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -994,8 +998,8 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
           T q = dg * uc[e];
           q = fmaT(-kk[0], e > 0 ? uc[e - 1] : left, q);
           q = fmaT(-kk[1], e < 3 ? uc[e + 1] : right, q);
-          q = fmaT(-kk[2], pl[mrow - G.qs + e], q);
-          q = fmaT(-kk[3], pl[mrow + G.qs + e], q);
+          q = fmaT(-kk[2], ymv[e], q);
+          q = fmaT(-kk[3], ypv[e], q);
           q = fmaT(-kk[4], um[e], q);
           q = fmaT(-kk[5], un[e], q);
           T t = rc[e] - q;
@@ -1065,21 +1069,22 @@ __device__ __forceinline__ void inv_fill(InvCache32& C, const QuadGeo& G, const 
   const long long hoff = ((long long)(G.hj - 1)) * n + (G.hi - 1);                      \
   const bool hin = G.hi != 0;                                                           \
   const int mrow = G.mrow;                                          \
-  const int hl = G.hl, hr = G.hr;             \
+  \
   auto zkey_at = [&](int k) __attribute__((always_inline)) { return G.zk[k - G.kb + 1]; };
 
 // q = A u at the own quad of plane k (u of plane k in registers and LDS; the
 // planes k-1, k+1 in um, un), coefficients from the cache
-#define MG0_STENCIL(C, um, uc, un, pl, q)                                               \
+#define MG0_STENCIL(C, um, uc, un, pl, left, right, q)                                  \
   {                                                                                     \
-    const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);                                \
-    const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);                               \
+    float ymv[4], ypv[4];                                                               \
+    pl_ld4(pl + mrow - G.qs, ymv);                                                      \
+    pl_ld4(pl + mrow + G.qs, ypv);                                                      \
     _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
       float a = C.dg[e] * uc[e];                                                        \
       a = fmaf(-C.kx[e], e > 0 ? uc[e - 1] : left, a);                                  \
       a = fmaf(-C.kx[e + 1], e < 3 ? uc[e + 1] : right, a);                             \
-      a = fmaf(-C.kym[e], pl[mrow - G.qs + e], a);                                        \
-      a = fmaf(-C.kyp[e], pl[mrow + G.qs + e], a);                                        \
+      a = fmaf(-C.kym[e], ymv[e], a);                                                   \
+      a = fmaf(-C.kyp[e], ypv[e], a);                                                   \
       a = fmaf(-C.kzm[e], um[e], a);                                                    \
       a = fmaf(-C.kzp[e], un[e], a);                                                    \
       q[e] = a;                                                                         \
@@ -1114,18 +1119,19 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
   }
   C.key = key;
 }
-#define MG0_STENCIL_LDS(C, um, uc, un, pl, q)                                           \
+#define MG0_STENCIL_LDS(C, um, uc, un, pl, left, right, q)                              \
   {                                                                                     \
-    const float left = G.lx > 0 ? pl[mrow - 1] : (G.hx ? pl[hl] : 0);                                \
-    const float right = G.lx < G.lxm ? pl[mrow + 4] : (G.hx ? pl[hr] : 0);                               \
+    float ymv[4], ypv[4];                                                               \
+    pl_ld4(pl + mrow - G.qs, ymv);                                                      \
+    pl_ld4(pl + mrow + G.qs, ypv);                                                      \
     _Pragma("unroll") for (int e = 0; e < 4; e++) {                                     \
       float kk[6];                                                                      \
       quad_kappa<float>(G, kt, e, C.czn, C.czm, C.czp, kk);                             \
       float a = C.dg[e] * uc[e];                                                        \
       a = fmaf(-kk[0], e > 0 ? uc[e - 1] : left, a);                                    \
       a = fmaf(-kk[1], e < 3 ? uc[e + 1] : right, a);                                   \
-      a = fmaf(-kk[2], pl[mrow - G.qs + e], a);                                           \
-      a = fmaf(-kk[3], pl[mrow + G.qs + e], a);                                           \
+      a = fmaf(-kk[2], ymv[e], a);                                                      \
+      a = fmaf(-kk[3], ypv[e], a);                                                      \
       a = fmaf(-kk[4], um[e], a);                                                       \
       a = fmaf(-kk[5], un[e], a);                                                       \
       q[e] = a;                                                                         \
@@ -1144,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
                                                     const float* __restrict__ b, float* __restrict__ tout,
                                                     const MgFine* __restrict__ mf, const int* __restrict__ gidx,
                                                     float omega, int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   float* kt = reinterpret_cast<float*>(smem_raw);
   float* plane = kt + ktab;
   __shared__ int zk[kZkLen];
@@ -1230,14 +1236,15 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       if (key != C.key) kc_fill(C, G, kt, key);
       e1_quad(k + 1, bn, un);
       float* pl = plane + buf * QPLANE;
-#pragma unroll
-      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      pl_st4(pl + mrow, uc);
       if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hbc * C.hinv) : 0.0f;
       __syncthreads();
       if (k > G.kb) xsums(k - 1, buf ^ 1);
+      float left, right;
+      quad_xnb<float>(G, pl, uc, left, right);
       if (nv > 0) {
         float q[4], to[4];
-        MG0_STENCIL(C, um, uc, un, pl, q)
+        MG0_STENCIL(C, um, uc, un, pl, left, right, q)
 #pragma unroll
         for (int e = 0; e < 4; e++) to[e] = bc[e] - q[e];
         if constexpr (RX) {
@@ -1278,7 +1285,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
                                                      const MgFine* __restrict__ mf, const int* __restrict__ gidx,
                                                      const float* __restrict__ r, float* __restrict__ sout,
                                                      IrPart* __restrict__ part, float omega, int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   float* kt = reinterpret_cast<float*>(smem_raw);
   float* plane = kt + ktab;
   __shared__ double red[4];
@@ -1501,8 +1508,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       if (key != C.key) dc_fill(C, G, kt, key);
       e2_quad(k + 1, qn, un);
       float* pl = plane + buf * QPLANE;
-#pragma unroll
-      for (int e = 0; e < 4; e++) pl[mrow + e] = uc[e];
+      pl_st4(pl + mrow, uc);
       if constexpr (PZ) {
         if (hin) {
           const float* Zh = zring + (k % 3) * kPzRows + ((G.hj - j0 + 1) << cws);
@@ -1521,9 +1527,11 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         Pnext = Pn2;
       }
       __syncthreads();
+      float left, right;
+      quad_xnb<float>(G, pl, uc, left, right);
       if (nv > 0) {
         float q[4], so[4];
-        MG0_STENCIL_LDS(C, um, uc, un, pl, q)
+        MG0_STENCIL_LDS(C, um, uc, un, pl, left, right, q)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);

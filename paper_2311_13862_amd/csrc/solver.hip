@@ -412,7 +412,7 @@ __device__ __forceinline__ void k_fast64_item(int item, const int2* __restrict__
                                                 double* __restrict__ r, double* __restrict__ p0,
                                                 double* __restrict__ p1, CrAcc* __restrict__ part,
                                                 int ktab) {
-  extern __shared__ double smem[];
+  extern __shared__ __align__(16) double smem[];
   __shared__ CrAcc red[4];
   __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
@@ -744,7 +744,7 @@ __device__ __forceinline__ void k_spmv_item(int item, const int2* __restrict__ i
                                               const ProbDev* __restrict__ pd,
                                               const T* __restrict__ kap, const T* __restrict__ x,
                                               T* __restrict__ y, int ktab) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   __shared__ int zk[kZkLen];
   __syncthreads();  // LDS of the previous item is free
