@@ -38,6 +38,9 @@ SPMV_CASES = [
     W.Problem(17, W.KIND_OCTANTS),              # nodes on the 1/2 plane
     W.Problem(12, W.KIND_OCTANTS_ANISO, (), W.F_GAUSS, 0.02),
     W.Problem(70, W.KIND_OCTANTS),              # ragged x tiles
+    W.Problem(32, W.KIND_BLOCKS, W.BLOCKS4),    # 32 x 32 tiles spanning the grid
+    W.Problem(64, W.KIND_OCTANTS_ANISO, (), W.F_GAUSS, 0.02),  # 64 x 16 whole-row tiles, three face tables
+    W.Problem(128, W.KIND_OCTANTS),             # 128 x 8 whole-row tiles, the benchmark's grid
 ]
 
 
