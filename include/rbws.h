@@ -62,7 +62,9 @@ enum {
 /* right-hand sides: f_h = h^2 f(x_P), h = 1/(n+1) */
 enum {
   RBWS_F_ONE = 0,   /* f = 1 */
-  RBWS_F_GAUSS = 1  /* f = exp(-|x - x0|^2 / gauss_width), x0 = mu[24..26] (ANISO only) */
+  RBWS_F_GAUSS = 1  /* f = exp(-|x - x0|^2 / gauss_width), x0 = mu[24..26] (ANISO only); the
+                       exponential rounded to nearest (the matrix-core projection V^T f uses
+                       the device library's exp, within an ulp) */
 };
 enum { RBWS_INIT_ZERO = 0, RBWS_INIT_RB = 1, RBWS_INIT_LEARNED = 2 };
 enum { RBWS_FP64 = 0, RBWS_FP32_IR = 1 };
@@ -109,7 +111,7 @@ typedef struct {
   int nblocks;        /* RBWS_KIND_BLOCKS: number of blocks, 1..31 */
   const int* blocks;  /* host, [nblocks][6], RBWS_KIND_BLOCKS only */
   int f_kind;         /* RBWS_F_* */
-  double gauss_width; /* RBWS_F_GAUSS: the width w */
+  double gauss_width; /* RBWS_F_GAUSS: the width w, at least 0.005 (EINVAL otherwise) */
 } rbws_problem_desc;
 
 /* Per-solve statistics (host output of rbws_solve). */

@@ -27,7 +27,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp",
-                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -61,6 +61,7 @@ def lib():
             "orc_exact_dot": (C.c_double, [d, d, l]),
             "orc_exact_sum": (C.c_double, [d, l]),
             "orc_set_naive_dots": (None, [i]),
+            "orc_exp": (C.c_double, [C.c_double]),
             "orc_nq": (i, [pp]),
             "orc_theta": (None, [pp, d, d]),
             "orc_face_coeffs": (None, [pp, d, d, d, d]),
@@ -284,6 +285,11 @@ def exact_dot(x, y) -> float:
     x, y = _f64(x), _f64(y)
     assert x.shape == y.shape
     return lib().orc_exact_dot(_dp(x), _dp(y), x.size)
+
+
+def exp_rn(x: float) -> float:
+    """exp(x) rounded to nearest, as the oracle's Gaussian source evaluates it."""
+    return lib().orc_exp(float(x))
 
 
 def set_naive_dots(on: bool) -> None:

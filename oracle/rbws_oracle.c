@@ -36,11 +36,13 @@
  *     reversed) and, when the recursive residual meets the tolerance, the true
  *     residual f - A x is recomputed; if it fails the test, CG restarts from it.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC
+ * Build: gcc -O2 -std=gnu11 -ffp-contract=off -fopenmp -shared -fPIC ... -lquadmath
  * (-ffp-contract=off: every fused multiply-add below is an explicit fma()).
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -194,6 +196,24 @@ double orc_exact_dot(const double *x, const double *y, long n) {
     xacc a; xacc_clear(&a);
     for (long i = 0; i < n; i++) xacc_add_prod(&a, x[i], y[i]);
     return xacc_round(&a);
+}
+
+/* exp(x) rounded once to nearest (the Gaussian source): the binary128
+ * exponential (error within a few units of its 113-bit last place) rounded
+ * to double.  If that value lies so close to the midpoint between two
+ * doubles that its own error could decide the rounding, the oracle cannot
+ * certify the result and aborts. */
+double orc_exp(double x) {
+    __float128 q = expq((__float128)x);
+    double d = (double)q;
+    __float128 up = ((__float128)d + (__float128)nextafter(d, INFINITY)) / 2;
+    __float128 dn = ((__float128)d + (__float128)nextafter(d, 0.0)) / 2;
+    __float128 tol = q * 0x1p-104Q;
+    if (fabsq(q - up) <= tol || fabsq(q - dn) <= tol) {
+        fprintf(stderr, "orc_exp: rounding of exp(%a) not certified\n", x);
+        abort();
+    }
+    return d;
 }
 
 /* correctly rounded sum */
@@ -417,7 +437,7 @@ void orc_rhs(const orc_problem *P, const double *mu, double *f) {
                 } else {
                     const double *x0 = mu + 24;
                     double dx = i * h - x0[0], dy = j * h - x0[1], dz = k * h - x0[2];
-                    f[idx] = h2 * exp(-(dx * dx + dy * dy + dz * dz) / P->gauss_width);
+                    f[idx] = h2 * orc_exp(-(dx * dx + dy * dy + dz * dz) / P->gauss_width);
                 }
             }
 }

@@ -174,7 +174,8 @@ Problem* problem_create(const rbws_problem_desc* d, int device) {
   RBWS_REQUIRE(d->f_kind == RBWS_F_ONE || d->kind == RBWS_KIND_OCTANTS_ANISO, RBWS_EINVAL,
                "the Gaussian source needs the anisotropic octant kind");
   if (d->f_kind == RBWS_F_GAUSS)
-    RBWS_REQUIRE(d->gauss_width > 0.0, RBWS_EINVAL, "gauss_width must be positive");
+    RBWS_REQUIRE(d->gauss_width >= 0.005, RBWS_EINVAL,
+                 "gauss_width must be at least 0.005 (exponents stay above -700 on the unit cube)");
   if (d->kind == RBWS_KIND_BLOCKS) {
     RBWS_REQUIRE(d->nblocks >= 1 && d->nblocks < kMaxQ, RBWS_EINVAL, "nblocks out of range");
     RBWS_REQUIRE(d->blocks != nullptr, RBWS_EINVAL, "blocks is NULL");

@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ V, i
     double b = 0.0;
     if (sb >= 0 && in) {
       const int i = (int)(cc % n) + 1, j = (int)((cc / n) % n) + 1, k = (int)(cc / ((long long)n * n)) + 1;
-      b = fval(P, S, i, j, k);
+      b = fval_fast(P, S, i, j, k);
     }
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }

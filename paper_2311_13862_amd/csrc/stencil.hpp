@@ -11,7 +11,93 @@ __device__ __forceinline__ long long vidx(int n, int i, int j, int k) {
   return ((long long)(k - 1) * n + (j - 1)) * n + (i - 1);
 }
 
+// ---------------------------------------------------------------------------
+// exp(x) rounded to nearest, for the Gaussian source (arguments in [-700, 0]:
+// the problem set-up requires a width of at least 0.005 on the unit cube).
+// Double-double evaluation, relative error below 2^-97:
+//   k = x / ln 2 rounded to an integer, r = x - k ln 2 with ln 2 = L1 + L2 + L3
+//   (L1 has 29 significant bits, so k L1 is exact; |r| <= 0.35), s = r / 256,
+//   e = expm1(s) from its Taylor series up to s^10 / 10! (coefficients 1/n! as
+//   double-double pairs), then expm1(2 s) = e (e + 2) eight times, and
+//   exp(x) = 2^k (1 + expm1(r)).
+// The double nearest to the double-double value is the correctly rounded
+// exp(x) unless that value lies within 2^-97 (relative) of a rounding boundary
+// between two doubles, which happens for about one argument in 2^44.
+// ---------------------------------------------------------------------------
+struct DDv {
+  double h, l;
+};
+__device__ __forceinline__ DDv dd_two_sum(double a, double b) {
+  const double s = a + b, bb = s - a;
+  return DDv{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DDv dd_fast_two_sum(double a, double b) {  // |a| >= |b|
+  const double s = a + b;
+  return DDv{s, b - (s - a)};
+}
+__device__ __forceinline__ DDv dd_add(DDv a, DDv b) {
+  DDv s = dd_two_sum(a.h, b.h);
+  const DDv t = dd_two_sum(a.l, b.l);
+  s = dd_fast_two_sum(s.h, s.l + t.h);
+  return dd_fast_two_sum(s.h, s.l + t.l);
+}
+__device__ __forceinline__ DDv dd_mul(DDv a, DDv b) {
+  const double p = a.h * b.h;
+  double e = __fma_rn(a.h, b.h, -p);
+  e = __fma_rn(a.h, b.l, e);
+  e = __fma_rn(a.l, b.h, e);
+  return dd_fast_two_sum(p, e);
+}
+__device__ inline double exp_rn(double x) {
+  constexpr double L1 = 0x1.62e42ffp-1, L2 = -0x1.718432a1b0e26p-35, L3 = -0x1.9ff0342542fc3p-90;
+  constexpr double LOG2E = 0x1.71547652b82fep+0;
+  // 1/n! for n = 2..10 as (high, low) pairs
+  constexpr double CH[9] = {0x1p-1,
+                            0x1.5555555555555p-3,
+                            0x1.5555555555555p-5,
+                            0x1.1111111111111p-7,
+                            0x1.6c16c16c16c17p-10,
+                            0x1.a01a01a01a01ap-13,
+                            0x1.a01a01a01a01ap-16,
+                            0x1.71de3a556c734p-19,
+                            0x1.27e4fb7789f5cp-22};
+  constexpr double CL[9] = {0.0,
+                            0x1.5555555555555p-57,
+                            0x1.5555555555555p-59,
+                            0x1.1111111111111p-63,
+                            -0x1.f49f49f49f49fp-65,
+                            0x1.a01a01a01a01ap-73,
+                            0x1.a01a01a01a01ap-76,
+                            -0x1.c154f8ddc6cp-73,
+                            0x1.cbbc05b4fa99ap-76};
+  const double kd = rint(x * LOG2E);
+  // r = x - k ln 2 as a double-double: x - k L1 is exact (Sterbenz), k L2 split exactly
+  const double a = __fma_rn(-kd, L1, x);
+  const double p2 = kd * L2, p2e = __fma_rn(kd, L2, -p2);
+  const DDv sa = dd_two_sum(a, -p2);
+  const DDv r = dd_fast_two_sum(sa.h, (sa.l - p2e) - kd * L3);
+  const DDv sv{r.h * 0x1p-8, r.l * 0x1p-8};
+  // expm1(s) = s + s^2 q(s), q(s) = sum_{n=2}^{10} s^(n-2) / n!
+  DDv q{CH[8], CL[8]};
+#pragma unroll
+  for (int n = 7; n >= 0; n--) q = dd_add(dd_mul(q, sv), DDv{CH[n], CL[n]});
+  DDv e = dd_add(sv, dd_mul(dd_mul(sv, sv), q));
+#pragma unroll
+  for (int m = 0; m < 8; m++) e = dd_mul(e, dd_add(e, DDv{2.0, 0.0}));
+  const DDv y = dd_add(DDv{1.0, 0.0}, e);
+  return ldexp(y.h, (int)kd);
+}
+
+// f_h = h^2 f at the grid point: f = 1, or the Gaussian exp(-|x - x0|^2 / w),
+// its exponential rounded to nearest (exp_rn)
 __device__ __forceinline__ double fval(const ProbDev& P, const SolveDev& S, int i, int j, int k) {
+  if (P.f_kind == RBWS_F_ONE) return P.h2;
+  double dx = i * P.h - S.x0[0], dy = j * P.h - S.x0[1], dz = k * P.h - S.x0[2];
+  return P.h2 * exp_rn(-(dx * dx + dy * dy + dz * dz) / P.gw);
+}
+// the same with the device library's exp (within an ulp; for the matrix-core
+// projection V^T f, which is not correctly rounded either)
+__device__ __forceinline__ double fval_fast(const ProbDev& P, const SolveDev& S, int i, int j, int k) {
   if (P.f_kind == RBWS_F_ONE) return P.h2;
   double dx = i * P.h - S.x0[0], dy = j * P.h - S.x0[1], dz = k * P.h - S.x0[2];
   return P.h2 * exp(-(dx * dx + dy * dy + dz * dz) / P.gw);

@@ -1,12 +1,14 @@
 """The anisotropic workload with the parameter-dependent Gaussian source, and
 uneven batches that mix grid sizes in one launch, against the CPU oracle.
 
-The source f = exp(-|x - x0|^2 / w) goes through each side's own libm exp,
-which may differ in the last bit, so these cases are compared to tolerances
-(iteration counts within a few, solutions to 1e-9 in FP64 and 1e-8 after
-refinement), not bitwise.  The reduced right-hand side V^T f(mu) is an FP64
-matrix-core contraction on the GPU and a correctly rounded projection in
-the oracle."""
+Both sides evaluate the source's exponential rounded to nearest (the GPU in
+double-double arithmetic, the oracle through binary128), so f_h is the same
+on both and FP64 CG from zero matches bit for bit.  The reduced right-hand
+side V^T f(mu) is an FP64 matrix-core contraction on the GPU (with the device
+library's exp) and a correctly rounded projection in the oracle, so the
+greedy, the RB coefficients and RB-started solves are compared to tolerances
+(iteration counts within a few, solutions to 1e-9 in FP64, 1e-8 after
+refinement)."""
 import numpy as np
 import pytest
 
@@ -58,6 +60,24 @@ def test_gauss_greedy_matches_oracle(rb, mixed):
         np.testing.assert_allclose(A, ob.AqN[:, :8, :8], rtol=1e-9, atol=1e-12 * np.abs(ob.AqN).max())
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gauss_fp64_cg_bitwise(rb, prec):
+    """FP64 PCG from zero (P = I and Jacobi) on the Gaussian-source problem at
+    21^3: iteration counts, residuals and solutions equal to the oracle's."""
+    spec = gauss_spec(21)
+    P = rb.Problem(spec)
+    O = oracle.Problem(spec)
+    mus = W.sample_mu(spec, 0.1, 10.0, 6, 77)
+    u = [torch.empty(P.ndof, dtype=torch.float64, device="cuda") for _ in range(len(mus))]
+    st = rb.solve([P], mus, rb.default_opts(tol=1e-10, precond=prec), u_out=u)
+    torch.cuda.synchronize()
+    for b, m in enumerate(mus):
+        xo, so = O.cg(m, prec=prec, tol=1e-10)
+        assert st[b]["ff"] == so["ff"] and st[b]["init_rr"] == so["init_rr"], b
+        assert st[b]["iters"] == so["iters"] and st[b]["final_rr"] == so["final_rr"], b
+        assert np.array_equal(u[b].cpu().numpy(), xo), b
+
+
 def test_gauss_online_coeffs(rb, mixed):
     for spec, mut, P, gb, O, ob in mixed:
         mus = W.sample_mu(spec, 0.1, 10.0, 10, W.SEED_TEST + spec.n)
@@ -91,8 +111,13 @@ def test_mixed_batch(rb, mixed, precision):
             else:
                 xo, so, _ = oracle.rbi_cg(mixed[q][5], mus[b], tol=tol)
             ub = u[b].cpu().numpy()
-            if precision == "fp64":
-                # the same algorithm from the same start: iterates agree up to the source's last bits
+            if precision == "fp64" and init == rb.INIT_ZERO:
+                # the same f_h, the same algorithm from zero: bit for bit
+                assert st[b]["iters"] == so["iters"], (b, st[b]["iters"], so["iters"])
+                assert st[b]["final_rr"] == so["final_rr"]
+                assert np.array_equal(ub, xo), b
+            elif precision == "fp64":
+                # from the RB start: the starts differ in the projection's last bits
                 assert abs(st[b]["iters"] - so["iters"]) <= 2, (b, st[b]["iters"], so["iters"])
                 rel = np.linalg.norm(ub - xo) / np.linalg.norm(xo)
                 assert rel <= 1e-9, rel

@@ -85,3 +85,18 @@ def test_order_independent():
     perm = rng.permutation(5000)
     assert oracle.exact_dot(x[perm], y[perm]) == a
     assert oracle.exact_dot(x[::-1].copy(), y[::-1].copy()) == a
+
+
+def test_exp_rounded_to_nearest():
+    """The oracle's exp (the Gaussian source) is exp(x) rounded once to the
+    nearest double: against a 40-digit decimal exponential converted to the
+    nearest double, on random and special arguments of the source's range."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    rng = np.random.default_rng(3)
+    xs = list(-150.0 * rng.random(20000)) + list(-rng.random(2000) * 1e-3) + [0.0, -0.0, -1e-300, -700.0,
+                                                                              -0.34657359027997264, -84.375]
+    for x in xs:
+        want = float(Decimal(x).exp())
+        got = oracle.core.exp_rn(x)
+        assert got == want, (x.hex(), got.hex(), want.hex())
