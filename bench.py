@@ -129,8 +129,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes_read": a.numel() * 8,
                           "copy_bytes_written": b.numel() * 8,
-                          "up2_algorithmic_bytes": float(np.sum(it * 20 - ou * 4)) * P.ndof,
-                          "ap_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
+                          "up2_sweep_algorithmic_bytes": float(np.sum(it * 20 - ou * 4)) * P.ndof,
+                          "ap_sweep_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
                           "mg_pre0_algorithmic_bytes": vc * mg_pre0_bytes(spec.n) * P.ndof,
                           "mg_post0_algorithmic_bytes": vc * mg_post0_bytes(spec.n) * P.ndof,
                           "launches_before_step": {k: v[1] for k, v in pre.items()},
