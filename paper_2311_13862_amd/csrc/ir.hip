@@ -33,8 +33,9 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,
                                                   const float* __restrict__ kap32, double* __restrict__ u0,
                                                   double* __restrict__ u1, const float* __restrict__ d,
-                                                  float* __restrict__ r, IrPart* __restrict__ part, int ktab) {
-  extern __shared__ double lds[];
+                                                  float* __restrict__ r, IrPart* __restrict__ part,
+                                                  double* __restrict__ fc, int ktab) {
+  extern __shared__ __align__(16) double lds[];
   __shared__ double redd[4][2];
   __shared__ CrAcc redc[4];
   __shared__ int zk[kZkLen];
@@ -61,7 +62,17 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   const int first = s.first;
   double g0 = 0.0, g1 = 0.0;
   CrAcc arr = cr_zero(), aff = cr_zero();
-  auto fv = [&](int i, int j, int k) { return fval(P, S, i, j, k); };
+  // a parameter-dependent source is evaluated (exponential rounded to nearest)
+  // on the solve's first outer pass and kept in fc for the later ones
+  double* F = (fc != nullptr && P.f_kind != RBWS_F_ONE) ? fc + S.off : nullptr;
+  auto fv = [&](int i, int j, int k) {
+    if (F == nullptr) return fval(P, S, i, j, k);
+    const long long c = vidx(g.n, i, j, k);
+    if (!first) return F[c];
+    const double v = fval(P, S, i, j, k);
+    F[c] = v;
+    return v;
+  };
   outer_body<VEC>(G, g, k64, k32, plane, (s.cur ? u1 : u0) + S.off, (s.cur ? u0 : u1) + S.off, d + S.off,
                   r + S.off, s.upd, s.scale, s.prec, first, fv, arr, aff, g0, g1);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -96,10 +107,11 @@ __global__ __launch_bounds__(256, 3) void k_ir_outer(const int2* __restrict__ it
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,
                                                   const float* __restrict__ kap32, double* __restrict__ u0,
                                                   double* __restrict__ u1, const float* __restrict__ d,
-                                                  float* __restrict__ r, IrPart* __restrict__ part, int ktab) {
+                                                  float* __restrict__ r, IrPart* __restrict__ part,
+                                                  double* __restrict__ fc, int ktab) {
   const WorkRange R = work_range(cnt ? *cnt : nitems);
   for (int w = R.w; w < R.w1; w += R.step)
-    k_ir_outer_item<VEC>(list ? list[w] : w, items, sd, pd, st, kap64, kap32, u0, u1, d, r, part, ktab);
+    k_ir_outer_item<VEC>(list ? list[w] : w, items, sd, pd, st, kap64, kap32, u0, u1, d, r, part, fc, ktab);
 }
 
 // inner FP32 iteration sweeps (fast.hpp); p alternates by the parity of k_total
@@ -485,6 +497,12 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   double* u1 = (double*)B.r.get(sizeof(double) * B.total, B.device);
   float* d = (float*)B.d32.get(sizeof(float) * B.total, B.device);
   float* r = (float*)B.r32.get(sizeof(float) * B.total, B.device);
+  // f_h of the solves with a parameter-dependent source, formed on each
+  // solve's first outer pass (its exponentials cost more than the pass's
+  // other arithmetic) and read by the later passes
+  bool gauss = false;
+  for (const Problem* P : B.probs) gauss = gauss || P->desc.f_kind != RBWS_F_ONE;
+  double* fcache = gauss ? (double*)B.fc.get(sizeof(double) * B.total, B.device) : nullptr;
   float* p = (float*)B.p32.get(sizeof(float) * B.total, B.device);
   float* p1 = (float*)B.p32b.get(sizeof(float) * B.total, B.device);
   const int2* items = (const int2*)B.items.ptr;
@@ -531,7 +549,7 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
     kt.end(q);
     kt.begin(q, KK_RESID);
     hipLaunchKernelGGL(outer, dim3(g_res), dim3(256), lds_outer, q, items, L.res, L.cnt + WL_RES, ni, sd, pd, st,
-                       k64, k32, u0, u1, d, r, part, ktab);
+                       k64, k32, u0, u1, d, r, part, fcache, ktab);
     kt.end(q);
     kt.begin(q, KK_FIN1);
     hipLaunchKernelGGL(k_ir_fin1, dim3(ns), dim3(256), 0, q, sd, st, (const IrPart*)part, active, L);

@@ -100,6 +100,7 @@ struct Batch {
   DevBuf x, r, p, p2, sv, need;
   // FP32 inner vectors (refinement; sv32: s from the V-cycle)
   DevBuf d32, r32, p32, p32b, sv32;
+  DevBuf fc;  // FP64 f_h of parameter-dependent sources (refinement outer passes)
   int* active_host = nullptr;  // pinned
   ~Batch();
 };
