@@ -1304,20 +1304,23 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
     float* SO = sout + S.off;
     // the quad's x points take their two coarse taps from the window of four
     // coarse columns W0 .. W0+3 (W0 = I0 of the first point, minus one): with
-    // (nc+1)/(nf+1) <= 1/2, I0 grows by at most 2 over the quad
-    int dI[4];
-    bool ta[4], tb[4];
-    float wx[4];
+    // (nc+1)/(nf+1) <= 1/2, I0 grows by at most 2 over the quad.  Point e
+    // weighs column I0 - 1 - W0 by 1 - w and the next by w (a coarse node
+    // outside the grid by 0) and the others by 0; the weighted sum runs over
+    // the window in ascending order, so the two taps enter in the order of
+    // the separate pass (zero terms add nothing)
+    float xw[4][4];
     const int nc = F.nc;
     const int W0 = F.ci[min(G.i, n) - 1] - 1;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const int i = min(G.i + e, n);
       const int I0 = F.ci[i - 1];
-      dI[e] = I0 - 1 - W0;
-      ta[e] = I0 >= 1;
-      tb[e] = I0 + 1 <= nc;
-      wx[e] = cw[i - 1];
+      const int d = I0 - 1 - W0;
+      const float w = cw[i - 1];
+#pragma unroll
+      for (int m = 0; m < 4; m++)
+        xw[e][m] = (m == d && I0 >= 1) ? 1.0f - w : ((m == d + 1 && I0 + 1 <= nc) ? w : 0.0f);
     }
     bool wv[4];
 #pragma unroll
@@ -1346,16 +1349,21 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         zwy[zr] = in ? cw[j - 1] : 0.0f;
       }
     }
-    // coarse plane K of the tile's rows (zero outside the coarse grid)
-    auto cload = [&](int K, float v[2]) __attribute__((always_inline)) {
+    // coarse plane K of the tile's rows (zero outside the coarse grid); the
+    // thread's two ring entries and their offsets within a coarse plane are
+    // the same for every K
+    int coff[2];
 #pragma unroll
-      for (int m = 0; m < 2; m++) {
-        const int e = (int)threadIdx.x + 256 * m;
-        const int J = Jb + (e >> cws), I = (e & (CW - 1)) + 1;
-        v[m] = 0.0f;
-        if (e < ncr && K >= 1 && K <= nc && J >= 1 && J <= nc && I <= nc)
-          v[m] = ecs[((long long)(K - 1) * nc + (J - 1)) * nc + (I - 1)];
-      }
+    for (int m = 0; m < 2; m++) {
+      const int e = (int)threadIdx.x + 256 * m;
+      const int J = Jb + (e >> cws), I = (e & (CW - 1)) + 1;
+      coff[m] = (e < ncr && J >= 1 && J <= nc && I <= nc) ? (J - 1) * nc + (I - 1) : -1;
+    }
+    auto cload = [&](int K, float v[2]) __attribute__((always_inline)) {
+      const bool kin = K >= 1 && K <= nc;
+      const gptr<float> pk = ecs + (long long)(kin ? K - 1 : 0) * nc * nc;
+#pragma unroll
+      for (int m = 0; m < 2; m++) v[m] = (kin && coff[m] >= 0) ? pk[coff[m]] : 0.0f;
     };
     auto cstore = [&](int K, const float v[2]) __attribute__((always_inline)) {
       float* D = cring + (K % 3) * kPzRing;
@@ -1397,12 +1405,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       if (i0 + 1 <= nc) v = fmaf(wgt, zb, v);
       return v;
     };
-    auto join2 = [&](bool a, bool bb, float wgt, float za, float zb) __attribute__((always_inline)) -> float {
-      float v = 0.0f;
-      if (a) v = fmaf(1.0f - wgt, za, v);
-      if (bb) v = fmaf(wgt, zb, v);
-      return v;
-    };
+
     struct Raw {
       float r[4], z[4];
     };
@@ -1418,10 +1421,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
           if (wv[m]) q.z[m] = zr[m];
       }
     };
-    // tap m of the window (m = dI, dI + 1 in 0..3)
-    auto pick = [&](const float z[4], int m) __attribute__((always_inline)) -> float {
-      return m == 0 ? z[0] : m == 1 ? z[1] : m == 2 ? z[2] : z[3];
-    };
+
     struct RawH {
       float r, za, zb;
     };
@@ -1450,9 +1450,13 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         for (int m = 0; m < 4; m++) z[m] = wv[m] ? Zr[m] : 0.0f;
       }
 #pragma unroll
-      for (int e = 0; e < 4; e++)
-        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + join2(ta[e], tb[e], wx[e], pick(z, dI[e]), pick(z, dI[e] + 1))
-                        : 0.0f;
+      for (int e = 0; e < 4; e++) {
+        float v = xw[e][0] * z[0];
+        v = fmaf(xw[e][1], z[1], v);
+        v = fmaf(xw[e][2], z[2], v);
+        v = fmaf(xw[e][3], z[3], v);
+        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + v : 0.0f;
+      }
     };
     float pf[2] = {0.0f, 0.0f};  // PZ: the next coarse plane, loaded one iteration ahead
     int Pcur = 0, Pnext = 0;
