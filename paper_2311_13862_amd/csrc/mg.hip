@@ -1294,6 +1294,8 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
   __shared__ float zring[PZ ? 3 * kPzRows : 1];  // ezy of fine plane k at slot k % 3
   __shared__ int zrow[PZ ? 40 : 1];              // per ezy row: ring offset of row J0 and flags, or -1
   __shared__ float zwy[PZ ? 40 : 1];             // per ezy row: the y weight
+  __shared__ int zK[PZ ? kZkLen + 2 : 1];        // ci(kk) of the planes kb-1 .. ke+4 (index kk - kb + 1)
+  __shared__ float zW[PZ ? kZkLen + 2 : 1];      // the z weight of the same planes
   const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
@@ -1376,25 +1378,32 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
     // ezy of fine plane kk into its slot.  The ring holds zeros for coarse
     // nodes outside the grid, so every tap is taken: a zero tap adds an exact
     // zero, and the values are those of k_mg_pyz, which skips such taps.
+    // the thread's ezy entries e = tid + 256 q (at most three: nz <= 640), their
+    // ring offsets within a coarse plane and their y weights, the same for
+    // every plane (set after the prologue's first barrier)
+    int zo[3];
+    float zy[3];
     auto zplane = [&](int kk) __attribute__((always_inline)) {
       if (kk < 1 || kk > n) return;
       float* Z = zring + (kk % 3) * kPzRows;
-      const int K0 = F.ci[kk - 1];
-      const float wz1 = cw[kk - 1], wz0 = 1.0f - wz1;
+      const int K0 = zK[kk - G.kb + 1];
+      const float wz1 = zW[kk - G.kb + 1], wz0 = 1.0f - wz1;
       const float* A = cring + (K0 % 3) * kPzRing;
       const float* Bq = cring + ((K0 + 1) % 3) * kPzRing;
-#pragma unroll 1
-      for (int e = threadIdx.x; e < nz; e += 256) {
-        const int zr = e >> cws;
-        const int o = zrow[zr] + (e & (CW - 1));
-        const float wy1 = zwy[zr];
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        if (zo[q] < 0) continue;
+        const int o = zo[q];
+        const float wy1 = zy[q];
         const float az0 = fmaf(wz1, Bq[o], wz0 * A[o]);
         const float az1 = fmaf(wz1, Bq[o + CW], wz0 * A[o + CW]);
-        Z[e] = fmaf(wy1, az1, (1.0f - wy1) * az0);
+        Z[(int)threadIdx.x + 256 * q] = fmaf(wy1, az1, (1.0f - wy1) * az0);
       }
     };
-    // the upper coarse plane that ezy of fine plane kk needs
+    // the upper coarse plane that ezy of fine plane kk needs (from memory in
+    // the prologue, from the staged zK in the march)
     auto ptop = [&](int kk) __attribute__((always_inline)) { return F.ci[min(kk, n) - 1] + 1; };
+    auto ptopL = [&](int kk) __attribute__((always_inline)) { return zK[kk - G.kb + 1] + 1; };
     auto taps = [&](gptr<float> zr, int i0, float& za, float& zb) __attribute__((always_inline)) {
       za = i0 >= 1 ? zr[i0 - 1] : 0.0f;
       zb = i0 + 1 <= nc ? zr[i0] : 0.0f;
@@ -1461,6 +1470,12 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
     float pf[2] = {0.0f, 0.0f};  // PZ: the next coarse plane, loaded one iteration ahead
     int Pcur = 0, Pnext = 0;
     if constexpr (PZ) {
+      // ci and the z weight of the planes kb-1 .. ke+4 (clamped to the grid)
+      for (int t = threadIdx.x; t < G.ke - G.kb + 6; t += 256) {
+        const int kc = min(max(G.kb - 1 + t, 1), n);
+        zK[t] = F.ci[kc - 1];
+        zW[t] = cw[kc - 1];
+      }
       // ezy of planes kb-1 .. kb+1 (coarse planes ci(kb-1) .. ci(kb+1)+1, at most three)
       const int Ka = F.ci[max(G.kb - 1, 1) - 1], Kz = ptop(G.kb + 1);
       for (int K = Ka; K <= Kz; K++) {
@@ -1469,6 +1484,16 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         cstore(K, v);
       }
       __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int e = (int)threadIdx.x + 256 * q;
+        zo[q] = -1;
+        zy[q] = 0.0f;
+        if (e < nz) {
+          zo[q] = zrow[e >> cws] + (e & (CW - 1));
+          zy[q] = zwy[e >> cws];
+        }
+      }
       zplane(G.kb - 1);
       zplane(G.kb);
       zplane(G.kb + 1);
@@ -1525,7 +1550,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         // the ring slot written here is not read in this iteration
         if (Pnext != Pcur) cstore(Pnext, pf);
         zplane(k + 2);
-        const int Pn2 = ptop(k + 4);
+        const int Pn2 = ptopL(k + 4);
         if (Pn2 != Pnext) cload(Pn2, pf);
         Pcur = Pnext;
         Pnext = Pn2;
