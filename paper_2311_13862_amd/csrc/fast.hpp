@@ -177,14 +177,33 @@ __device__ __forceinline__ void pl_ld4(const double* p, double v[4]) {
   v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
+// A value from the previous lane (lane i reads lane i - 1) or the next one
+// (lane i reads lane i + 1): the whole-wave DPP shifts by one lane (GFX9
+// wave_shr:1 / wave_shl:1), a VALU move instead of an LDS permute.  The lane
+// at the wave's end, which has no source, gets 0.
+__device__ __forceinline__ int lane_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int lane_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(lane_prev(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(lane_next(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_prev((int)(unsigned)b), hi = lane_prev((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_next((int)(unsigned)b), hi = lane_next((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // x neighbours of the quad whose values c[0..3] are in the plane: the last
 // point of the previous quad and the first of the next, taken from the
 // neighbouring lanes of the same row (a row is a run of lxm + 1 lanes inside
 // one wave), else the x-halo column or the boundary zero.  Every lane of the
-// wave must call this (the shuffles read the neighbours' registers).
+// wave must call this (the shifts read the neighbours' registers).
 template <typename T>
 __device__ __forceinline__ void quad_xnb(const QuadGeo& G, const T* pl, const T c[4], T& left, T& right) {
-  const T l = __shfl_up(c[3], 1, 64), r = __shfl_down(c[0], 1, 64);
+  const T l = lane_prev(c[3]), r = lane_next(c[0]);
   left = G.lx > 0 ? l : (G.hx ? pl[G.hl] : T(0));
   right = G.lx < G.lxm ? r : (G.hx ? pl[G.hr] : T(0));
 }

@@ -1141,7 +1141,12 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
 // With RX (tiles that span the whole row) the residual t is not written:
 // each fine row of it goes through LDS and the kernel writes the restriction's
 // x-sums ax[k][j][I] = sum_i px t (fma chain from 0, ascending i) into the
-// level's MgFine buffer, n_c values per row instead of n.
+// level's MgFine buffer, n_c values per row instead of n.  The rows in LDS
+// have an odd stride (4 TX/4 + 1), so the two rows a wave covers fall on
+// different banks, and are zeroed per item: every chain takes all kSpan taps,
+// those past the node's span with weight 0 on a finite value, which leaves the
+// chain's value unchanged, without a branch per tap.
+constexpr int kTrow = 1280;  // floats per LDS plane of t: rows x (TX + 1) <= 1024 + 256
 template <bool VEC, bool ML, bool RX>
 __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                     const int* __restrict__ cnt, int ntiles,
@@ -1154,9 +1159,9 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
   float* kt = reinterpret_cast<float*>(smem_raw);
   float* plane = kt + ktab;
   __shared__ int zk[kZkLen];
-  __shared__ float trow[RX ? 2048 : 1];          // the tile's t of two planes (rows of TX)
+  __shared__ __align__(16) float trow[RX ? 2 * kTrow + 8 : 1];  // the tile's t of two planes
   __shared__ float xw[RX ? 64 : 1][kSpan];       // x weights per coarse column
-  __shared__ int xlo[RX ? 64 : 1], xnn[RX ? 64 : 1];
+  __shared__ int xlo[RX ? 64 : 1];
   const WorkRange WR = work_range(ML ? *cnt * ntiles : *cnt);
   for (int w = WR.w; w < WR.w1; w += WR.step) {
     MG0_ITEM_SETUP()
@@ -1164,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
     float* TO = tout + S.off;
     float* txo = nullptr;
     int nc = 0;
-    const int txw = 4 * (G.lxm + 1);  // row length of trow (the tile spans the row)
+    const int txw = 4 * (G.lxm + 1) + 1;  // row stride of trow (the tile spans the row)
     if constexpr (RX) {
       const MgFine F = mf[S.prob];
       nc = F.nc;
@@ -1173,13 +1178,13 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       for (int I = threadIdx.x + 1; I <= nc; I += blockDim.x) {
         const int2 r = F.lohi[I];
         xlo[I - 1] = r.x;
-        xnn[I - 1] = r.y - r.x + 1;
 #pragma unroll
         for (int u = 0; u < kSpan; u++) {
           const int i = r.x + u;
           xw[I - 1][u] = i <= r.y ? (F.ci[i - 1] == I ? 1.0f - cw[i - 1] : cw[i - 1]) : 0.0f;
         }
       }
+      for (int e = threadIdx.x; e < 2 * kTrow + 8; e += blockDim.x) trow[e] = 0.0f;
       __syncthreads();
     }
     auto load_b = [&](int k, float bq[4]) __attribute__((always_inline)) {
@@ -1209,13 +1214,12 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       if constexpr (RX) {
         if (G.j <= n) {
           float* o = txo + ((long long)(k - 1) * n + (G.j - 1)) * nc;
-          const float* tr = trow + tb * 1024 + G.ly * txw - 1;
+          const float* tr = trow + tb * kTrow + G.ly * txw - 1;
           for (int I = G.lx + 1; I <= nc; I += G.lxm + 1) {
-            const int lo = xlo[I - 1], nn = xnn[I - 1];
+            const float* t = tr + xlo[I - 1];
             float ax = 0.0f;
 #pragma unroll
-            for (int u = 0; u < kSpan; u++)
-              if (u < nn) ax = fmaf(xw[I - 1][u], tr[lo + u], ax);
+            for (int u = 0; u < kSpan; u++) ax = fmaf(xw[I - 1][u], t[u], ax);
             o[I - 1] = ax;
           }
         }
@@ -1250,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
         if constexpr (RX) {
 #pragma unroll
           for (int e = 0; e < 4; e++)
-            if (e < nv) trow[buf * 1024 + G.ly * txw + 4 * G.lx + e] = to[e];
+            if (e < nv) trow[buf * kTrow + G.ly * txw + 4 * G.lx + e] = to[e];
         } else {
           st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
         }
