@@ -75,14 +75,16 @@ typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 template <typename T, bool VEC>
 __device__ __forceinline__ void st4_stream(T* __restrict__ a, long long c, int nv, const T v[4]) {
-  if (VEC && nv == 4) {
-    if constexpr (sizeof(T) == 4) {
-      const nt_f4 q = {v[0], v[1], v[2], v[3]};
-      __builtin_nontemporal_store(q, reinterpret_cast<nt_f4*>(a + c));
-    } else {
-      const nt_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
-      __builtin_nontemporal_store(q0, reinterpret_cast<nt_d2*>(a + c));
-      __builtin_nontemporal_store(q1, reinterpret_cast<nt_d2*>(a + c + 2));
+  if constexpr (VEC) {  // nv is 0 or 4 when n % 4 == 0
+    if (nv == 4) {
+      if constexpr (sizeof(T) == 4) {
+        const nt_f4 q = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(q, reinterpret_cast<nt_f4*>(a + c));
+      } else {
+        const nt_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+        __builtin_nontemporal_store(q0, reinterpret_cast<nt_d2*>(a + c));
+        __builtin_nontemporal_store(q1, reinterpret_cast<nt_d2*>(a + c + 2));
+      }
     }
   } else {
 #pragma unroll
@@ -113,15 +115,24 @@ __device__ __forceinline__ void ld4_stream(const T* __restrict__ a, long long c,
 
 template <typename T, bool VEC>
 __device__ __forceinline__ void st4(T* __restrict__ a, long long c, int nv, const T v[4]) {
-  if (VEC && nv == 4) {
-    typename V4T<T>::t q;
-    q.x = v[0]; q.y = v[1]; q.z = v[2]; q.w = v[3];
-    *reinterpret_cast<typename V4T<T>::t*>(a + c) = q;
+  if constexpr (VEC) {  // nv is 0 or 4 when n % 4 == 0
+    if (nv == 4) {
+      typename V4T<T>::t q;
+      q.x = v[0]; q.y = v[1]; q.z = v[2]; q.w = v[3];
+      *reinterpret_cast<typename V4T<T>::t*>(a + c) = q;
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++)
       if (e < nv) a[c + e] = v[e];
   }
+}
+
+// Point e of a quad that holds points (nv > 0): inside the grid.  With VEC
+// (n % 4 == 0) a quad is empty or full, so the test folds away there.
+template <bool VEC>
+__device__ __forceinline__ bool in_quad(int e, int nv) {
+  return VEC || e < nv;
 }
 
 // A pointer known to address global memory: loads through it are global_load,
@@ -364,7 +375,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
         sv = ra[e] / diag6T<T>(kk);
       }
-      out[e] = (e < nv) ? (restart ? sv : fmaT(beta, rb[e], sv)) : T(0);
+      out[e] = in_quad<VEC>(e, nv) ? (restart ? sv : fmaT(beta, rb[e], sv)) : T(0);
     }
   };
   auto halo_load = [&](int k, T& ha, T& hb) __attribute__((always_inline)) {
@@ -454,7 +465,7 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         q = fmaT(-kk[4], pm[e], q);
         q = fmaT(-kk[5], pn[e], q);
         qo[e] = q;
-        if (OP != FOP_SPMV && e < nv) {
+        if (OP != FOP_SPMV && in_quad<VEC>(e, nv)) {
           if (OP == FOP_AP) {
             a0.add(pc[e], q);
           } else {
@@ -590,7 +601,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const float sv = prec ? ra[e] * inv[e] : ra[e];
-      out[e] = (e < nv) ? (restart ? sv : fmaf(beta, rb[e], sv)) : 0.0f;
+      out[e] = in_quad<VEC>(e, nv) ? (restart ? sv : fmaf(beta, rb[e], sv)) : 0.0f;
     }
   };
   auto halo_load = [&](int k, float& ha, float& hb) __attribute__((always_inline)) {
@@ -672,7 +683,7 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
         q = fmaf(-C.kzm[e], pm[e], q);
         q = fmaf(-C.kzp[e], pn[e], q);
         qo[e] = q;
-        if (OP != FOP_SPMV && e < nv) {
+        if (OP != FOP_SPMV && in_quad<VEC>(e, nv)) {
           if (OP == FOP_AP) {
             a0 = __fma_rn((double)pc[e], (double)q, a0);
           } else {
@@ -735,7 +746,7 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
       float dv[4] = {0.f, 0.f, 0.f, 0.f};
       ld4<float, VEC>(D, c, nv, dv);
 #pragma unroll
-      for (int e = 0; e < 4; e++) out[e] = e < nv ? __fma_rn(upd, (double)dv[e], out[e]) : 0.0;
+      for (int e = 0; e < 4; e++) out[e] = in_quad<VEC>(e, nv) ? __fma_rn(upd, (double)dv[e], out[e]) : 0.0;
     }
   };
   auto halo_u = [&](int k) __attribute__((always_inline)) -> double {
@@ -778,7 +789,7 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
         q = __fma_rn(-kk[4], um[e], q);
         q = __fma_rn(-kk[5], un[e], q);
         ro[e] = 0.0f;
-        if (e < nv) {
+        if (in_quad<VEC>(e, nv)) {
           const double f = fv(G.i + e, G.j, k);
           const double rv = f - q;
           const float r32 = (float)(rv * scale);

@@ -680,7 +680,11 @@ struct MgFine {           // per problem: the z/y-interpolated level-1 correctio
 // rows of three fine planes (the tile's rows and its two halo rows, at most
 // kPzRows values each).  The host checks both bounds per level.
 constexpr int kPzRing = 448;
-constexpr int kPzRows = 640;
+constexpr int kPzRows = 680;
+// An ezy row in the ring: CW values behind one zero and followed by three, so
+// that the four-column window of a quad and the halo point's two taps read it
+// without a test for coarse columns outside the grid (they meet the zeros).
+constexpr int kPzPad = 4;
 
 // Level 0, before the coarse correction (nu = 1): e1 = omega b / d (one
 // Jacobi sweep from zero) and t = b - A e1, one z-march per tile; e1 of the
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0(const int2* __restrict__ items,
         const T dg = diag6T<T>(kk);
         T t = bq[e] - T(0);
         t = t / dg;
-        out[e] = e < nv ? fmaT(omega, t, T(0)) : T(0);
+        out[e] = in_quad<VEC>(e, nv) ? fmaT(omega, t, T(0)) : T(0);
       }
     };
     auto halo_e1 = [&](int k, T braw) __attribute__((always_inline)) -> T {
@@ -915,7 +919,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
       const gptr<T> zr = ezy + ((long long)(k - 1) * n + (jj - 1)) * nc;
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        if (e < nv) taps(zr, I0[e], q.za[e], q.zb[e]);
+        if (in_quad<VEC>(e, nv)) taps(zr, I0[e], q.za[e], q.zb[e]);
     };
     auto fin_q = [&](int k, const Raw& q, T out[4]) __attribute__((always_inline)) {
 #pragma unroll
@@ -927,7 +931,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
         T kk[6];
         quad_kappa<T>(G, kt, e, czn, czm, czp, kk);
         const T dg = diag6T<T>(kk);
-        out[e] = e < nv ? jac(q.r[e], dg) + join(I0[e], wx[e], q.za[e], q.zb[e]) : T(0);
+        out[e] = in_quad<VEC>(e, nv) ? jac(q.r[e], dg) + join(I0[e], wx[e], q.za[e], q.zb[e]) : T(0);
       }
     };
     struct RawH {
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_mg_post0(const int2* __restrict__ items
           T t = rc[e] - q;
           t = t / dg;
           so[e] = fmaT(omega, t, uc[e]);
-          if (e < nv) acc.add(rc[e], so[e]);
+          if (in_quad<VEC>(e, nv)) acc.add(rc[e], so[e]);
         }
         st4<T, VEC>(SO, c, nv, so);
       }
@@ -1148,7 +1152,7 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
 // chain's value unchanged, without a branch per tap.
 constexpr int kTrow = 1280;  // floats per LDS plane of t: rows x (TX + 1) <= 1024 + 256
 template <bool VEC, bool ML, bool RX>
-__global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
+__global__ __launch_bounds__(256, 4) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                     const int* __restrict__ cnt, int ntiles,
                                                     const SolveDev* __restrict__ sd,
                                                     const ProbDev* __restrict__ pd, const float* __restrict__ kap,
@@ -1206,7 +1210,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
       const int key = zkey_at(k);
       if (key != Ci.key) inv_fill(Ci, G, kt, key);
 #pragma unroll
-      for (int e = 0; e < 4; e++) out[e] = e < nv ? omega * (bq[e] * Ci.inv[e]) : 0.0f;
+      for (int e = 0; e < 4; e++) out[e] = in_quad<VEC>(e, nv) ? omega * (bq[e] * Ci.inv[e]) : 0.0f;
     };
     // x-sums of plane k's rows from trow (buffer tb); the writes of that plane
     // are ordered before these reads by the next plane's barrier
@@ -1254,7 +1258,7 @@ __global__ __launch_bounds__(256) void k_mg_pre0_32(const int2* __restrict__ ite
         if constexpr (RX) {
 #pragma unroll
           for (int e = 0; e < 4; e++)
-            if (e < nv) trow[buf * kTrow + G.ly * txw + 4 * G.lx + e] = to[e];
+            if (in_quad<VEC>(e, nv)) trow[buf * kTrow + G.ly * txw + 4 * G.lx + e] = to[e];
         } else {
           st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
         }
@@ -1387,6 +1391,11 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
     // every plane (set after the prologue's first barrier)
     int zo[3];
     float zy[3];
+    // ring position of entry e = tid + 256 q: e + kPzPad (e >> cws) + 1, with
+    // e >> cws = (tid >> cws) + q (256 >> cws) since CW divides 256
+    const int zd0 = (int)threadIdx.x + kPzPad * ((int)threadIdx.x >> cws) + 1;
+    const int zdq = 256 + kPzPad * (256 >> cws);
+    const int zrs = CW + kPzPad;  // ring row stride
     auto zplane = [&](int kk) __attribute__((always_inline)) {
       if (kk < 1 || kk > n) return;
       float* Z = zring + (kk % 3) * kPzRows;
@@ -1401,7 +1410,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         const float wy1 = zy[q];
         const float az0 = fmaf(wz1, Bq[o], wz0 * A[o]);
         const float az1 = fmaf(wz1, Bq[o + CW], wz0 * A[o + CW]);
-        Z[(int)threadIdx.x + 256 * q] = fmaf(wy1, az1, (1.0f - wy1) * az0);
+        Z[zd0 + zdq * q] = fmaf(wy1, az1, (1.0f - wy1) * az0);
       }
     };
     // the upper coarse plane that ezy of fine plane kk needs (from memory in
@@ -1458,9 +1467,9 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
 #pragma unroll
       for (int m = 0; m < 4; m++) z[m] = q.z[m];
       if constexpr (PZ) {
-        const float* Zr = zring + (k % 3) * kPzRows + ((jj - j0 + 1) << cws) + W0;
+        const float* Zr = zring + (k % 3) * kPzRows + (jj - j0 + 1) * zrs + 1 + W0;
 #pragma unroll
-        for (int m = 0; m < 4; m++) z[m] = wv[m] ? Zr[m] : 0.0f;
+        for (int m = 0; m < 4; m++) z[m] = Zr[m];
       }
 #pragma unroll
       for (int e = 0; e < 4; e++) {
@@ -1468,7 +1477,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         v = fmaf(xw[e][1], z[1], v);
         v = fmaf(xw[e][2], z[2], v);
         v = fmaf(xw[e][3], z[3], v);
-        out[e] = e < nv ? omega * (q.r[e] * Ci.inv[e]) + v : 0.0f;
+        out[e] = in_quad<VEC>(e, nv) ? omega * (q.r[e] * Ci.inv[e]) + v : 0.0f;
       }
     };
     float pf[2] = {0.0f, 0.0f};  // PZ: the next coarse plane, loaded one iteration ahead
@@ -1480,6 +1489,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
         zK[t] = F.ci[kc - 1];
         zW[t] = cw[kc - 1];
       }
+      for (int t = threadIdx.x; t < 3 * kPzRows; t += 256) zring[t] = 0.0f;  // the rows' zero pads
       // ezy of planes kb-1 .. kb+1 (coarse planes ci(kb-1) .. ci(kb+1)+1, at most three)
       const int Ka = F.ci[max(G.kb - 1, 1) - 1], Kz = ptop(G.kb + 1);
       for (int K = Ka; K <= Kz; K++) {
@@ -1544,12 +1554,16 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
       pl_st4(pl + mrow, uc);
       if constexpr (PZ) {
         if (hin) {
-          const float* Zh = zring + (k % 3) * kPzRows + ((G.hj - j0 + 1) << cws);
-          hc.za = hI0 >= 1 ? Zh[hI0 - 1] : 0.0f;
-          hc.zb = hI0 + 1 <= nc ? Zh[hI0] : 0.0f;
+          const float* Zh = zring + (k % 3) * kPzRows + (G.hj - j0 + 1) * zrs + 1;
+          hc.za = Zh[hI0 - 1];
+          hc.zb = Zh[hI0];
         }
       }
-      if (G.hslot >= 0) pl[G.hslot] = hin ? omega * (hc.r * C.hinv) + join(hI0, hwx, hc.za, hc.zb) : 0.0f;
+      if (G.hslot >= 0) {
+        // with PZ the taps outside the grid read zeros, so both enter unconditionally
+        const float ex = PZ ? fmaf(hwx, hc.zb, fmaf(1.0f - hwx, hc.za, 0.0f)) : join(hI0, hwx, hc.za, hc.zb);
+        pl[G.hslot] = hin ? omega * (hc.r * C.hinv) + ex : 0.0f;
+      }
       if constexpr (PZ) {
         // the ring slot written here is not read in this iteration
         if (Pnext != Pcur) cstore(Pnext, pf);
@@ -1568,7 +1582,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);
-          if (!ML && e < nv) acc = __fma_rn((double)rc[e], (double)so[e], acc);
+          if (!ML && in_quad<VEC>(e, nv)) acc = __fma_rn((double)rc[e], (double)so[e], acc);
         }
         st4<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
       }
@@ -1819,7 +1833,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
   auto pz_fits = [](const MgLevelHost& lv, int TY, int nc) {
     if (nc > 64) return false;
     const int CW = nc <= 16 ? 16 : nc <= 32 ? 32 : 64, n = lv.n;
-    if ((TY + 2) * CW > kPzRows) return false;
+    if ((TY + 2) * (CW + kPzPad) > kPzRows) return false;
     for (int j0 = 1; j0 <= n; j0 += TY) {
       const int Jb = lv.ci_h[std::max(j0 - 1, 1) - 1];
       if ((lv.ci_h[std::min(j0 + TY, n) - 1] + 2 - Jb) * CW > kPzRing) return false;
