@@ -622,7 +622,17 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
     ld4<float, VEC>(R, c, nv, ro);
   };
 
-  float pm[4], pc[4], pn[4], ra[4], rb[4];
+  // Loads in flight are never copied between registers (a copy would wait for
+  // them): slot S[k & 1] holds the raw quad of plane k+2 and the halo, x and r
+  // of plane k, and iteration k fills the other slot with the halo, x and r of
+  // plane k+1 and then the quad of plane k+3, which is finished only at the
+  // end of iteration k+1.  The loop runs two planes per trip with the slots'
+  // roles swapped, so every slot access has a fixed register.
+  struct Slot {
+    float ra[4], rb[4], ha, hb, xo[4], ro[4];
+  };
+  Slot S0, S1;
+  float pm[4], pc[4], pn[4];
   {
     float qa[4], qb[4];
     quad_load(G.kb - 1, qa, qb);
@@ -636,29 +646,27 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
     st4<float, VEC>(Pn, (long long)(G.kb - 1) * n2 + rowoff, nv, pc);
     if (G.kb + 1 <= G.ke) st4<float, VEC>(Pn, (long long)G.kb * n2 + rowoff, nv, pn);
   }
-  float ha, hb, xo[4], ro[4];
-  halo_load(G.kb, ha, hb);
+  halo_load(G.kb, S0.ha, S0.hb);
 #pragma unroll
-  for (int e = 0; e < 4; e++) xo[e] = ro[e] = 0.0f;
-  xr_load(G.kb, xo, ro);
-  int buf = 0;
+  for (int e = 0; e < 4; e++) S0.xo[e] = S0.ro[e] = 0.0f;
+  xr_load(G.kb, S0.xo, S0.ro);
+  quad_load(G.kb + 2, S0.ra, S0.rb);
   const int mrow = G.mrow;
-  for (int k = G.kb; k <= G.ke; k++) {
-    quad_load(k + 2, ra, rb);
-    float ha2, hb2, xo2[4], ro2[4];
-    halo_load(k + 1, ha2, hb2);
+  auto iter = [&](int k, Slot& cur, Slot& nxt) __attribute__((always_inline)) {
+    halo_load(k + 1, nxt.ha, nxt.hb);
 #pragma unroll
-    for (int e = 0; e < 4; e++) xo2[e] = ro2[e] = 0.0f;
-    xr_load(k + 1, xo2, ro2);
+    for (int e = 0; e < 4; e++) nxt.xo[e] = nxt.ro[e] = 0.0f;
+    xr_load(k + 1, nxt.xo, nxt.ro);
+    quad_load(k + 3, nxt.ra, nxt.rb);
     const int key = G.zk[k - G.kb + 1];
     if (key != C.key) kc_fill(C, G, kt, key);
-    float* pl = plane + buf * QPLANE;
+    float* pl = plane + (k & 1) * QPLANE;
     pl_st4(pl + mrow, pc);
     if (G.hslot >= 0) {
-      float hv = ha;
+      float hv = cur.ha;
       if (OP == FOP_AP && hin) {
-        const float sv = prec ? ha * C.hinv : ha;
-        hv = restart ? sv : fmaf(beta, hb, sv);
+        const float sv = prec ? cur.ha * C.hinv : cur.ha;
+        hv = restart ? sv : fmaf(beta, cur.hb, sv);
       }
       pl[G.hslot] = hv;
     }
@@ -687,9 +695,9 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
           if (OP == FOP_AP) {
             a0 = __fma_rn((double)pc[e], (double)q, a0);
           } else {
-            xo[e] = first_x ? alpha * pc[e] : fmaf(alpha, pc[e], xo[e]);
-            const float rv = fmaf(-alpha, q, ro[e]);
-            ro[e] = rv;
+            cur.xo[e] = first_x ? alpha * pc[e] : fmaf(alpha, pc[e], cur.xo[e]);
+            const float rv = fmaf(-alpha, q, cur.ro[e]);
+            cur.ro[e] = rv;
             a0 = __fma_rn((double)rv, (double)rv, a0);
             if (prec) a1 = __fma_rn((double)rv, (double)(rv * C.inv[e]), a1);
           }
@@ -697,8 +705,8 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
       if (OP == FOP_UP2) {  // d is read again only by the next update or outer pass: streamed
-        st4_stream<float, VEC>(X, c, nv, xo);
-        st4<float, VEC>(R, c, nv, ro);
+        st4_stream<float, VEC>(X, c, nv, cur.xo);
+        st4<float, VEC>(R, c, nv, cur.ro);
       }
       if (OP == FOP_SPMV) st4_stream<float, VEC>(X, c, nv, qo);
     }
@@ -706,15 +714,16 @@ __device__ __forceinline__ void fast_body32(const QuadGeo& G, const GridDev& g, 
     for (int e = 0; e < 4; e++) {
       pm[e] = pc[e];
       pc[e] = pn[e];
-      xo[e] = xo2[e];
-      ro[e] = ro2[e];
     }
-    quad_finish(k + 2, ra, rb, pn);
+    quad_finish(k + 2, cur.ra, cur.rb, pn);
     if (OP == FOP_AP && nv > 0 && k + 2 <= G.ke) st4<float, VEC>(Pn, (long long)(k + 1) * n2 + rowoff, nv, pn);
-    ha = ha2;
-    hb = hb2;
-    buf ^= 1;
+  };
+  int k = G.kb;
+  for (; k + 1 <= G.ke; k += 2) {
+    iter(k, S0, S1);
+    iter(k + 1, S1, S0);
   }
+  if (k <= G.ke) iter(k, S0, S1);
 }
 
 // ---------------------------------------------------------------------------
