@@ -145,6 +145,13 @@ template <typename T>
 __device__ __forceinline__ gptr<T> as_global(const T* p) {
   return (gptr<T>)p;
 }
+// the same for stores
+template <typename T>
+using gptr_w = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr_w<T> as_global_w(T* p) {
+  return (gptr_w<T>)p;
+}
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __fma_rn(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }

@@ -1214,12 +1214,16 @@ __global__ __launch_bounds__(256, 4) void k_mg_pre0_32(const int2* __restrict__ 
     };
     // x-sums of plane k's rows from trow (buffer tb); the writes of that plane
     // are ordered before these reads by the next plane's barrier
+    // (a thread has at most two coarse columns: n_c <= (n - 1) / 2 < 2 (lxm + 1))
     auto xsums = [&](int k, int tb) __attribute__((always_inline)) {
       if constexpr (RX) {
         if (G.j <= n) {
-          float* o = txo + ((long long)(k - 1) * n + (G.j - 1)) * nc;
+          const gptr_w<float> o = as_global_w(txo) + ((long long)(k - 1) * n + (G.j - 1)) * nc;
           const float* tr = trow + tb * kTrow + G.ly * txw - 1;
-          for (int I = G.lx + 1; I <= nc; I += G.lxm + 1) {
+#pragma unroll
+          for (int m = 0; m < 2; m++) {
+            const int I = G.lx + 1 + m * (G.lxm + 1);
+            if (I > nc) break;
             const float* t = tr + xlo[I - 1];
             float ax = 0.0f;
 #pragma unroll
