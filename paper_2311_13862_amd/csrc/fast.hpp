@@ -57,6 +57,24 @@ template <typename T> struct V4T;
 template <> struct V4T<float> { typedef float4 t; };
 template <> struct V4T<double> { typedef double4 t; };
 
+// Vectors of a quad at element alignment only (rows of n % 4 != 0 values):
+// the 16-byte memory operations need no more than that on this target.
+typedef float ua_f4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef double ua_d2 __attribute__((ext_vector_type(2), aligned(8)));
+template <typename T>
+__device__ __forceinline__ void ua_ld4(const T* p, T v[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const ua_f4 q = *reinterpret_cast<const ua_f4*>(p);
+    v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+  } else {
+    const ua_d2 q0 = *reinterpret_cast<const ua_d2*>(p), q1 = *reinterpret_cast<const ua_d2*>(p + 2);
+    v[0] = q0[0]; v[1] = q0[1]; v[2] = q1[0]; v[3] = q1[1];
+  }
+}
+
+// The four values of a quad (nv of them inside the grid, the rest 0): one
+// vector access when the quad is full.  With VEC (n % 4 == 0) the quad is
+// 16-byte aligned and either empty or full.
 template <typename T, bool VEC>
 __device__ __forceinline__ void ld4(const T* __restrict__ a, long long c, int nv, T v[4]) {
   if (VEC) {  // nv is 0 or 4 when n % 4 == 0
@@ -64,6 +82,8 @@ __device__ __forceinline__ void ld4(const T* __restrict__ a, long long c, int nv
       const typename V4T<T>::t q = *reinterpret_cast<const typename V4T<T>::t*>(a + c);
       v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
     }
+  } else if (nv == 4) {
+    ua_ld4(a + c, v);
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++) v[e] = e < nv ? a[c + e] : T(0);
@@ -86,6 +106,15 @@ __device__ __forceinline__ void st4_stream(T* __restrict__ a, long long c, int n
         __builtin_nontemporal_store(q1, reinterpret_cast<nt_d2*>(a + c + 2));
       }
     }
+  } else if (nv == 4) {
+    if constexpr (sizeof(T) == 4) {
+      const ua_f4 q = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(q, reinterpret_cast<ua_f4*>(a + c));
+    } else {
+      const ua_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+      __builtin_nontemporal_store(q0, reinterpret_cast<ua_d2*>(a + c));
+      __builtin_nontemporal_store(q1, reinterpret_cast<ua_d2*>(a + c + 2));
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++)
@@ -107,6 +136,15 @@ __device__ __forceinline__ void ld4_stream(const T* __restrict__ a, long long c,
         v[0] = q0[0]; v[1] = q0[1]; v[2] = q1[0]; v[3] = q1[1];
       }
     }
+  } else if (nv == 4) {
+    if constexpr (sizeof(T) == 4) {
+      const ua_f4 q = __builtin_nontemporal_load(reinterpret_cast<const ua_f4*>(a + c));
+      v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+    } else {
+      const ua_d2 q0 = __builtin_nontemporal_load(reinterpret_cast<const ua_d2*>(a + c));
+      const ua_d2 q1 = __builtin_nontemporal_load(reinterpret_cast<const ua_d2*>(a + c + 2));
+      v[0] = q0[0]; v[1] = q0[1]; v[2] = q1[0]; v[3] = q1[1];
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++) v[e] = e < nv ? __builtin_nontemporal_load(a + c + e) : T(0);
@@ -120,6 +158,15 @@ __device__ __forceinline__ void st4(T* __restrict__ a, long long c, int nv, cons
       typename V4T<T>::t q;
       q.x = v[0]; q.y = v[1]; q.z = v[2]; q.w = v[3];
       *reinterpret_cast<typename V4T<T>::t*>(a + c) = q;
+    }
+  } else if (nv == 4) {
+    if constexpr (sizeof(T) == 4) {
+      const ua_f4 q = {v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<ua_f4*>(a + c) = q;
+    } else {
+      const ua_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+      *reinterpret_cast<ua_d2*>(a + c) = q0;
+      *reinterpret_cast<ua_d2*>(a + c + 2) = q1;
     }
   } else {
 #pragma unroll
