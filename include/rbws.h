@@ -433,7 +433,8 @@ rbws_status rbws_exact_fallbacks(long long* counts, int reset);
  * RBWS_TUNE_GRID: the sweeps launch one workgroup per work item (0, default)
  * or a persistent grid of one full occupancy that loops over the items (1).
  * RBWS_TUNE_TZ: tile depth of every later batch, a power of two in [4, 64],
- * or 0 (default) for the autotuner's choice or the built-in rule.
+ * or 0 (default) for the autotuner's choice or the built-in rule; the coarser
+ * levels of the multigrid preconditioner always take the built-in rule.
  * RBWS_TUNE_MG_PZ: where the tiles of a multigrid level span whole grid rows,
  * the FP32 post-smoothing interpolates the coarse correction itself (1,
  * default) or reads the z/y-interpolated rows from a separate pass (0); the

@@ -1750,7 +1750,7 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
       lv->n = nl[l];
       lv->ndof = (long long)nl[l] * nl[l] * nl[l];
       std::vector<const Problem*> pl{lv->prob};
-      batch_setup(lv->B, pl, nullptr, ns, nullptr, P->p, s, th.data());
+      batch_setup(lv->B, pl, nullptr, ns, nullptr, P->p, s, th.data(), l > 0);
       if (l > 0) {
         lv->vb.get(el * ns * lv->ndof, B.device);
         lv->ve.get(el * ns * lv->ndof, B.device);

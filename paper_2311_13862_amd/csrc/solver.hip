@@ -149,11 +149,11 @@ static int count_bucket(long long c) {
   return b;
 }
 
-void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ) {
+void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ, bool internal) {
   // one tile spans the whole row when 32 < n <= 128 (no x-halo, contiguous y-halo rows)
   *TX = n > 128 || n <= 32 ? QX : (n > 64 ? 128 : 64);
   *TY = 1024 / *TX;
-  if (g_force_tz > 0 || g_user_tz > 0) {
+  if (!internal && (g_force_tz > 0 || g_user_tz > 0)) {
     *TZ = std::min(g_force_tz > 0 ? g_force_tz : g_user_tz, n);
     return;
   }
@@ -823,7 +823,7 @@ __global__ __launch_bounds__(256) void k_dot_fin(const double* __restrict__ x,
 // host side
 // ---------------------------------------------------------------------------
 void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
-                 const double* mu, int p, hipStream_t s, const double* theta_override) {
+                 const double* mu, int p, hipStream_t s, const double* theta_override, bool internal) {
   RBWS_REQUIRE(!probs.empty(), RBWS_EINVAL, "no problem");
   B.device = probs[0]->device;
   RBWS_HIP(hipSetDevice(B.device));
@@ -840,7 +840,7 @@ void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* 
     d.g = P->grid;
     long long cnt = 0;
     for (int b = 0; b < nsolve; b++) cnt += (prob_of ? prob_of[b] : 0) == q;
-    choose_tile(P->n, cnt, &d.TX, &d.TY, &d.TZ);
+    choose_tile(P->n, cnt, &d.TX, &d.TY, &d.TZ, internal);
     RBWS_REQUIRE(d.TZ >= 1 && d.TZ <= kTzMax, RBWS_EINVAL, "tile depth out of range");
     d.ntx = (P->n + d.TX - 1) / d.TX;
     d.nty = (P->n + d.TY - 1) / d.TY;

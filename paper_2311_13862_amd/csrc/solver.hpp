@@ -107,8 +107,10 @@ struct Batch {
 
 // tiles: 256 threads of 4 x-points each, 32 x 32 grid columns, or a whole row
 // (64 x 16, 128 x 8) when 32 < n <= 128, by TZ planes; TZ is the largest power
-// of two in [4, 64] that still gives >= 4096 work items
-void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ);
+// of two in [4, 64] that still gives >= 4096 work items.  With `internal`
+// (the coarser multigrid levels) the caller's fixed depth does not apply:
+// those grids are too small for the depth chosen for the finest one.
+void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ, bool internal = false);
 // autotuner of the tile depth (see solver.hip); its choices override the rule above
 int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, double* ms);
 void clear_tile_table();
@@ -129,9 +131,11 @@ int grid_mode();
 void set_grid_mode(int v);
 
 // build the batch description: problems[prob_of[b]] for solve b; mu (nsolve x p) on host
-// theta_override (nsolve x Q of problem 0, host) replaces theta(mu) when given
+// theta_override (nsolve x Q of problem 0, host) replaces theta(mu) when given;
+// internal: tiles by choose_tile's own rule (coarser multigrid levels)
 void batch_setup(Batch& B, const std::vector<const Problem*>& probs, const int* prob_of, int nsolve,
-                 const double* mu, int p, hipStream_t s, const double* theta_override = nullptr);
+                 const double* mu, int p, hipStream_t s, const double* theta_override = nullptr,
+                 bool internal = false);
 
 // ||f - A x_b|| / ||f|| per solve for the x in `x` (laid out like the batch);
 // rr and ff (correctly rounded) are returned too.  Host outputs.
