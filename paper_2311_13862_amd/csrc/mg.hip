@@ -1588,7 +1588,10 @@ __global__ __launch_bounds__(256, 4) void k_mg_post0_32(const int2* __restrict__
           so[e] = fmaf(omega, (rc[e] - q[e]) * C.inv[e], uc[e]);
           if (!ML && in_quad<VEC>(e, nv)) acc = __fma_rn((double)rc[e], (double)so[e], acc);
         }
-        st4<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
+        // the finest level's s is next read by the A.p sweep, far beyond any cache: streamed;
+        // a coarser level's correction is read soon by the finer level's interpolation
+        if constexpr (ML) st4<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
+        else st4_stream<float, VEC>(SO, (long long)(k - 1) * n2 + rowoff, nv, so);
       }
 #pragma unroll
       for (int e = 0; e < 4; e++) {
