@@ -236,22 +236,30 @@ def main():
 
     # SpMV bandwidth: 256 solves at 128^3 (2.1 GB per FP32 vector, far beyond the 256 MB
     # last-level cache); smaller batches leave the last round of workgroups part-empty
-    spmv = {}
+    # The library's autotuner picks a depth from short runs on a zero vector; the
+    # bench also times 10 launches on random data at depths 8, 16 and 32 and
+    # reports the fastest (every depth computes the same y).
+    spmv, spmv_by_tz = {}, {}
     nb = 256
-    rbws.set_tuning(rbws.TUNE_TZ, 0)  # the SpMV takes its own autotuned depth
+    rbws.set_tuning(rbws.TUNE_TZ, 0)
     spmv_tz, _ = rbws.autotune(P, nb, rbws.FP32_IR)
     for name, dt, bpd, prec in (("fp32", torch.float32, 8, rbws.FP32_IR), ("fp64", torch.float64, 16, rbws.FP64)):
         x = torch.randn(nb, nd, dtype=dt, device="cuda")
         y = torch.empty_like(x)
-        P.spmv(mu[:nb], x, y, precision=prec)
-        rbws.profile(True, reset=True)
-        for _ in range(10):
+        spmv_by_tz[name] = {}
+        for tzs in (8, 16, 32):
+            rbws.set_tuning(rbws.TUNE_TZ, tzs)
             P.spmv(mu[:nb], x, y, precision=prec)
-        torch.cuda.synchronize()
-        kk = rbws.profile(False, reset=True)["spmv"]
-        spmv[name] = bpd * nb * nd / (kk[0] / kk[1] * 1e-3) / 1e9
+            rbws.profile(True, reset=True)
+            for _ in range(10):
+                P.spmv(mu[:nb], x, y, precision=prec)
+            torch.cuda.synchronize()
+            kk = rbws.profile(False, reset=True)["spmv"]
+            spmv_by_tz[name][tzs] = round(bpd * nb * nd / (kk[0] / kk[1] * 1e-3) / 1e9, 1)
+        spmv[name] = max(spmv_by_tz[name].values())
         del x, y
-    log(f"SpMV GB/s: {spmv}")
+    rbws.set_tuning(rbws.TUNE_TZ, 0)
+    log(f"SpMV GB/s: {spmv_by_tz}")
 
     cpu = None
     if not args.no_cpu:
@@ -297,6 +305,7 @@ def main():
         "blocks4_64_fp64": c2,
         "aniso_mixed": c5,
         "spmv_gbs": {k: round(v, 1) for k, v in spmv.items()},
+        "spmv_gbs_by_tile_depth": {k: {str(t): v for t, v in d.items()} for k, d in spmv_by_tz.items()},
         "spmv_batch": nb,
         "tile_depth": {"solve": tz, "spmv": spmv_tz, "solve_candidates_ms": {str(k): round(v, 3) for k, v in tz_ms.items()},
                        "picked_by": "short solves of half the batch at each depth"},

@@ -447,8 +447,10 @@ rbws_status rbws_set_tuning(int key, int value);
  * to spread over the 256 compute units.  Times y = A(mu) x for `nsolve` solves
  * of problem p (precision RBWS_FP64 or RBWS_FP32_IR) at TZ = 4, 8, ..., 64 and
  * keeps the fastest for later batches of this grid size whose solve count is
- * in the same power-of-two range (per process).  tz: host, the choice; ms: host,
- * nullable, 5 mean times in milliseconds (0 where not tried).  Results of the
+ * in the same power-of-two range (per process).  Each depth is timed in two
+ * interleaved passes of five launches; its time is the faster pass's mean.
+ * tz: host, the choice; ms: host, nullable, those 5 times in milliseconds (0
+ * where not tried).  Results of the
  * solver do not depend on the tiling.  Errors: EINVAL, ENOMEM, EDEVICE.
  * rbws_autotune_clear drops every choice (back to the built-in rule). */
 rbws_status rbws_autotune(rbws_problem* p, int nsolve, int precision, void* stream, int* tz, double* ms);

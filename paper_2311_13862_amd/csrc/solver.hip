@@ -172,8 +172,8 @@ void choose_tile(int n, long long nsolve_of_this_size, int* TX, int* TY, int* TZ
 // Times the stencil sweep (y = A x over `nsolve` solves of problem P, in FP32
 // or FP64) for every tile depth TZ in {4, 8, 16, 32, 64} (TZ <= n), keeps the
 // fastest for batches with this grid size and a solve count in the same
-// power-of-two range, and returns it.  ms[5] receives the mean times (0 for a
-// depth that was not tried).
+// power-of-two range, and returns it.  ms[5] receives the mean time per
+// launch of each depth's faster pass (0 for a depth that was not tried).
 int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, double* ms) {
   RBWS_REQUIRE(nsolve >= 1, RBWS_EINVAL, "nsolve < 1");
   RBWS_HIP(hipSetDevice(P->device));
@@ -195,26 +195,34 @@ int autotune_tiles(const Problem* P, int nsolve, bool fp32, hipStream_t s, doubl
   const int cand[5] = {4, 8, 16, 32, 64};
   int best = 0;
   double best_ms = 0.0;
+  double tmin[5] = {0, 0, 0, 0, 0};
   try {
+    // two interleaved passes over the depths, five launches each; a depth's
+    // time is its faster pass (a single short pass can rank two depths within
+    // a few per cent of each other either way)
+    for (int pass = 0; pass < 2; pass++) {
+      for (int c = 0; c < 5; c++) {
+        if (cand[c] > P->n && c > 0 && cand[c - 1] >= P->n) continue;
+        g_force_tz = cand[c];
+        batch_setup(B, probs, nullptr, nsolve, mu.data(), P->p, s);
+        g_force_tz = 0;
+        spmv_batch(B, x, y, fp32, s);
+        RBWS_HIP(hipEventRecord(e0, s));
+        const int reps = 5;
+        for (int r = 0; r < reps; r++) spmv_batch(B, x, y, fp32, s);
+        RBWS_HIP(hipEventRecord(e1, s));
+        RBWS_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        RBWS_HIP(hipEventElapsedTime(&t, e0, e1));
+        const double m = t / reps;
+        if (pass == 0 || m < tmin[c]) tmin[c] = m;
+      }
+    }
     for (int c = 0; c < 5; c++) {
-      if (ms) ms[c] = 0.0;
-      if (cand[c] > P->n && c > 0 && cand[c - 1] >= P->n) continue;
-      g_force_tz = cand[c];
-      batch_setup(B, probs, nullptr, nsolve, mu.data(), P->p, s);
-      g_force_tz = 0;
-      spmv_batch(B, x, y, fp32, s);
-      RBWS_HIP(hipEventRecord(e0, s));
-      const int reps = 3;
-      for (int r = 0; r < reps; r++) spmv_batch(B, x, y, fp32, s);
-      RBWS_HIP(hipEventRecord(e1, s));
-      RBWS_HIP(hipEventSynchronize(e1));
-      float t = 0.f;
-      RBWS_HIP(hipEventElapsedTime(&t, e0, e1));
-      const double m = t / reps;
-      if (ms) ms[c] = m;
-      if (best == 0 || m < best_ms) {
+      if (ms) ms[c] = tmin[c];
+      if (tmin[c] > 0.0 && (best == 0 || tmin[c] < best_ms)) {
         best = cand[c];
-        best_ms = m;
+        best_ms = tmin[c];
       }
     }
   } catch (...) {
