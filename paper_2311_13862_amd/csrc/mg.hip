@@ -1146,11 +1146,13 @@ __device__ __forceinline__ void dc_fill(DCache32& C, const QuadGeo& G, const flo
 // each fine row of it goes through LDS and the kernel writes the restriction's
 // x-sums ax[k][j][I] = sum_i px t (fma chain from 0, ascending i) into the
 // level's MgFine buffer, n_c values per row instead of n.  The rows in LDS
-// have an odd stride (4 TX/4 + 1), so the two rows a wave covers fall on
-// different banks, and are zeroed per item: every chain takes all kSpan taps,
-// those past the node's span with weight 0 on a finite value, which leaves the
-// chain's value unchanged, without a branch per tap.
-constexpr int kTrow = 1280;  // floats per LDS plane of t: rows x (TX + 1) <= 1024 + 256
+// have a stride of TX + 4 floats (16-byte aligned: a quad goes in with one
+// 16-byte store; an odd stride would put the two rows a wave covers on
+// different banks for the x-sum reads but needs four scalar stores at two-way
+// conflicts, which measured slower) and are zeroed per item: every chain takes
+// all kSpan taps, those past the node's span with weight 0 on a finite value,
+// which leaves the chain's value unchanged, without a branch per tap.
+constexpr int kTrow = 1280;  // floats per LDS plane of t: rows x (TX + 4) <= 1152 (TX >= 32)
 template <bool VEC, bool ML, bool RX>
 __global__ __launch_bounds__(256, 4) void k_mg_pre0_32(const int2* __restrict__ items, const int* __restrict__ list,
                                                     const int* __restrict__ cnt, int ntiles,
@@ -1173,7 +1175,7 @@ __global__ __launch_bounds__(256, 4) void k_mg_pre0_32(const int2* __restrict__ 
     float* TO = tout + S.off;
     float* txo = nullptr;
     int nc = 0;
-    const int txw = 4 * (G.lxm + 1) + 1;  // row stride of trow (the tile spans the row)
+    const int txw = 4 * (G.lxm + 1) + 4;  // row stride of trow (the tile spans the row)
     if constexpr (RX) {
       const MgFine F = mf[S.prob];
       nc = F.nc;
@@ -1260,9 +1262,13 @@ __global__ __launch_bounds__(256, 4) void k_mg_pre0_32(const int2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 4; e++) to[e] = bc[e] - q[e];
         if constexpr (RX) {
+          if constexpr (VEC) {
+            pl_st4(trow + buf * kTrow + G.ly * txw + 4 * G.lx, to);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; e++)
-            if (in_quad<VEC>(e, nv)) trow[buf * kTrow + G.ly * txw + 4 * G.lx + e] = to[e];
+            for (int e = 0; e < 4; e++)
+              if (in_quad<VEC>(e, nv)) trow[buf * kTrow + G.ly * txw + 4 * G.lx + e] = to[e];
+          }
         } else {
           st4<float, VEC>(TO, (long long)(k - 1) * n2 + rowoff, nv, to);
         }
