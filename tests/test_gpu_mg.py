@@ -70,7 +70,9 @@ def test_vcycle_operator_fp64(rb, spec, nu, omega):
 
 
 @pytest.mark.parametrize("spec", [W.Problem(64, W.KIND_OCTANTS), W.Problem(33, W.KIND_BLOCKS, W.BLOCKS4),
-                                  W.Problem(20, W.KIND_OCTANTS_ANISO)], ids=["oct64", "blk33", "aniso20"])
+                                  W.Problem(20, W.KIND_OCTANTS_ANISO), W.Problem(128, W.KIND_OCTANTS),
+                                  W.Problem(96, W.KIND_OCTANTS_ANISO), W.Problem(70, W.KIND_OCTANTS)],
+                         ids=["oct64", "blk33", "aniso20", "oct128", "aniso96", "oct70"])
 def test_vcycle_operator_fp32(rb, spec):
     """The FP32 V-cycle (float coefficients and vectors, reciprocal-diagonal
     Jacobi on the fused levels) against the oracle's FP64 one: relative 2-norm
