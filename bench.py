@@ -133,6 +133,7 @@ def main():
                           "ap_sweep_algorithmic_bytes": float(np.sum(it * 12 - ou * 4)) * P.ndof,
                           "mg_pre0_algorithmic_bytes": vc * mg_pre0_bytes(spec.n) * P.ndof,
                           "mg_post0_algorithmic_bytes": vc * mg_post0_bytes(spec.n) * P.ndof,
+                          "resid_pass_algorithmic_bytes": float(np.sum(12 + 24 * ou)) * P.ndof,
                           "launches_before_step": {k: v[1] for k, v in pre.items()},
                           "launches_step": {k: v[1] for k, v in stp.items()},
                           "sources_sha256": kernel_sources_hash()}), flush=True)
@@ -172,7 +173,9 @@ def main():
            "ap_sweep": args.steps * float(np.sum(iters * 12 - outer * 4)) * nd,   # R s, p_old; W p_new
            # V-cycle, finest level (FP32): R b, W x-sums of t; and R r, R ezy, W s
            "mg_pre0": args.steps * float(np.sum(vcyc)) * mg_pre0_bytes(spec.n) * nd,
-           "mg_post0": args.steps * float(np.sum(vcyc)) * mg_post0_bytes(spec.n) * nd}
+           "mg_post0": args.steps * float(np.sum(vcyc)) * mg_post0_bytes(spec.n) * nd,
+           # FP64 outer pass: the first R u, W b (12 B); each later one R u, d; W u', b (24 B)
+           "resid_pass": args.steps * float(np.sum(12 + 24 * outer)) * nd}
     ms = {k: v[0] for k, v in kern.items()}
     n_launch = {k: v[1] for k, v in kern.items()}
     dom = max(alg, key=lambda k: ms.get(k, 0.0))

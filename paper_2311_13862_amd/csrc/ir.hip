@@ -26,8 +26,11 @@
 
 namespace rbws {
 
-// Outer pass (FP64) of every solve whose mode is RESID (fast.hpp, outer_body)
-template <bool VEC>
+// Outer pass (FP64) of every solve whose mode is RESID (fast.hpp, outer_body).
+// SRC: some problem of the batch has a parameter-dependent source; without it
+// f_h is the constant h^2 and the exponential's code stays out of the kernel
+// (it would otherwise size the register allocation of the f = 1 case too).
+template <bool VEC, bool SRC>
 __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict__ items,
                                                   const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,
@@ -64,14 +67,19 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   CrAcc arr = cr_zero(), aff = cr_zero();
   // a parameter-dependent source is evaluated (exponential rounded to nearest)
   // on the solve's first outer pass and kept in fc for the later ones
-  double* F = (fc != nullptr && P.f_kind != RBWS_F_ONE) ? fc + S.off : nullptr;
-  auto fv = [&](int i, int j, int k) {
-    if (F == nullptr) return fval(P, S, i, j, k);
-    const long long c = vidx(g.n, i, j, k);
-    if (!first) return F[c];
-    const double v = fval(P, S, i, j, k);
-    F[c] = v;
-    return v;
+  double* F = (SRC && fc != nullptr && P.f_kind != RBWS_F_ONE) ? fc + S.off : nullptr;
+  const double h2 = P.h2;
+  auto fv = [&](int i, int j, int k) -> double {
+    if constexpr (!SRC) {
+      return h2;
+    } else {
+      if (F == nullptr) return fval(P, S, i, j, k);
+      const long long c = vidx(g.n, i, j, k);
+      if (!first) return F[c];
+      const double v = fval(P, S, i, j, k);
+      F[c] = v;
+      return v;
+    }
   };
   outer_body<VEC>(G, g, k64, k32, plane, (s.cur ? u1 : u0) + S.off, (s.cur ? u0 : u1) + S.off, d + S.off,
                   r + S.off, s.upd, s.scale, s.prec, first, fv, arr, aff, g0, g1);
@@ -99,9 +107,12 @@ __device__ __forceinline__ void k_ir_outer_item(int item, const int2* __restrict
   }
 }
 
-// three waves per SIMD: 167 VGPRs without spills (177, two waves, unbounded)
-template <bool VEC>
-__global__ __launch_bounds__(256, 3) void k_ir_outer(const int2* __restrict__ items, const int* __restrict__ list,
+// With a parameter-dependent source: three waves per SIMD, 167 VGPRs without
+// spills (177 and two waves unbounded).  With f = 1: four waves, 128 VGPRs, the
+// few spilled values stored and reloaded outside the z-loop (0.95 against
+// 1.01-1.05 ms per launch at 1024 x 128^3, where three waves took 0.95-0.98).
+template <bool VEC, bool SRC>
+__global__ __launch_bounds__(256, SRC ? 3 : 4) void k_ir_outer(const int2* __restrict__ items, const int* __restrict__ list,
                                                   const int* __restrict__ cnt, int nitems,
                                                   const SolveDev* __restrict__ sd, const ProbDev* __restrict__ pd,
                                                   const IrState* __restrict__ st, const double* __restrict__ kap64,
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(256, 3) void k_ir_outer(const int2* __restrict__ it
                                                   double* __restrict__ fc, int ktab) {
   const WorkRange R = work_range(cnt ? *cnt : nitems);
   for (int w = R.w; w < R.w1; w += R.step)
-    k_ir_outer_item<VEC>(list ? list[w] : w, items, sd, pd, st, kap64, kap32, u0, u1, d, r, part, fc, ktab);
+    k_ir_outer_item<VEC, SRC>(list ? list[w] : w, items, sd, pd, st, kap64, kap32, u0, u1, d, r, part, fc, ktab);
 }
 
 // inner FP32 iteration sweeps (fast.hpp); p alternates by the parity of k_total
@@ -512,7 +523,8 @@ void ir_run(Batch& B, const IrOpts& o, hipStream_t s, std::vector<IrHost>& out) 
   const float* k32 = (const float*)B.kap32.ptr;
   const int ktab = (B.kap_max + 3) & ~3;
   const size_t lds_outer = sizeof(double) * (ktab + (ktab + 1) / 2 + 2 * QPLANE);
-  auto outer = B.vec ? k_ir_outer<true> : k_ir_outer<false>;
+  auto outer = B.vec ? (gauss ? k_ir_outer<true, true> : k_ir_outer<true, false>)
+                     : (gauss ? k_ir_outer<false, true> : k_ir_outer<false, false>);
   const size_t lds_fast = sizeof(float) * (ktab + 2 * QPLANE);
   const int ni = B.nitems;
   // sweep variants: coefficients cached in registers or looked up per plane
