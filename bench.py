@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--reps", type=int, default=3,
                     help="interleaved repetitions of every start (zero, RB, learned, L1ROC) after the timed steps")
     ap.add_argument("--no-c2", action="store_true", help="skip the blocks4-64 FP64 leg")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="only the SpMV measurement (no autotuner launches: for profiling k_spmv)")
     ap.add_argument("--no-c5", action="store_true", help="skip the anisotropic mixed-size leg")
     ap.add_argument("--c5-ntrain", type=int, default=1024)
     ap.add_argument("--c5-batch", type=int, default=512)
@@ -97,6 +99,17 @@ def main():
     P = rbws.Problem(spec)
     mu_train = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.ntrain, W.SEED_TRAIN)
     mu = W.sample_mu(spec, wl.mu_lo, wl.mu_hi, args.batch, W.SEED_TEST)
+    if args.spmv_only:
+        spmv, by_tz, _, nb = spmv_leg(rbws, torch, P, mu, P.ndof, autotune=False)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        rbws.stream_copy(a, b)  # calibrates a profiler's byte counters: each byte read and written once
+        torch.cuda.synchronize()
+        print(json.dumps({"spmv_only": True, "spmv_gbs": spmv, "copy_bytes": a.numel() * 8,
+                          "spmv_gbs_by_tile_depth": {k: {str(t): v for t, v in d.items()} for k, d in by_tz.items()},
+                          "spmv_batch": nb, "dispatch_order": "fp32 then fp64; tile depth 8, 16, 32; "
+                          "per depth 1 untimed + 10 timed launches"}), flush=True)
+        return
 
     log(f"offline: greedy N={args.N} from {args.ntrain} training parameters at {spec.n}^3")
     torch.cuda.synchronize()
@@ -237,31 +250,7 @@ def main():
     if c5 is not None:
         log(f"aniso-mixed: {c5}")
 
-    # SpMV bandwidth: 256 solves at 128^3 (2.1 GB per FP32 vector, far beyond the 256 MB
-    # last-level cache); smaller batches leave the last round of workgroups part-empty
-    # The library's autotuner picks a depth from short runs on a zero vector; the
-    # bench also times 10 launches on random data at depths 8, 16 and 32 and
-    # reports the fastest (every depth computes the same y).
-    spmv, spmv_by_tz = {}, {}
-    nb = 256
-    rbws.set_tuning(rbws.TUNE_TZ, 0)
-    spmv_tz, _ = rbws.autotune(P, nb, rbws.FP32_IR)
-    for name, dt, bpd, prec in (("fp32", torch.float32, 8, rbws.FP32_IR), ("fp64", torch.float64, 16, rbws.FP64)):
-        x = torch.randn(nb, nd, dtype=dt, device="cuda")
-        y = torch.empty_like(x)
-        spmv_by_tz[name] = {}
-        for tzs in (8, 16, 32):
-            rbws.set_tuning(rbws.TUNE_TZ, tzs)
-            P.spmv(mu[:nb], x, y, precision=prec)
-            rbws.profile(True, reset=True)
-            for _ in range(10):
-                P.spmv(mu[:nb], x, y, precision=prec)
-            torch.cuda.synchronize()
-            kk = rbws.profile(False, reset=True)["spmv"]
-            spmv_by_tz[name][tzs] = round(bpd * nb * nd / (kk[0] / kk[1] * 1e-3) / 1e9, 1)
-        spmv[name] = max(spmv_by_tz[name].values())
-        del x, y
-    rbws.set_tuning(rbws.TUNE_TZ, 0)
+    spmv, spmv_by_tz, spmv_tz, nb = spmv_leg(rbws, torch, P, mu, nd)
     log(f"SpMV GB/s: {spmv_by_tz}")
 
     cpu = None
@@ -325,6 +314,36 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def spmv_leg(rbws, torch, P, mu, nd, autotune=True):
+    """SpMV bandwidth: 256 solves at 128^3 (2.1 GB per FP32 vector, far beyond the
+    256 MB last-level cache); smaller batches leave the last round of workgroups
+    part-empty.  The library's autotuner picks a depth from short runs on a zero
+    vector; the bench also times 10 launches on random data at depths 8, 16 and 32
+    and reports the fastest (every depth computes the same y).  Per precision and
+    depth: one untimed launch, then the 10 timed ones."""
+    spmv, spmv_by_tz = {}, {}
+    nb = 256
+    rbws.set_tuning(rbws.TUNE_TZ, 0)
+    spmv_tz = rbws.autotune(P, nb, rbws.FP32_IR)[0] if autotune else None
+    for name, dt, bpd, prec in (("fp32", torch.float32, 8, rbws.FP32_IR), ("fp64", torch.float64, 16, rbws.FP64)):
+        x = torch.randn(nb, nd, dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        spmv_by_tz[name] = {}
+        for tzs in (8, 16, 32):
+            rbws.set_tuning(rbws.TUNE_TZ, tzs)
+            P.spmv(mu[:nb], x, y, precision=prec)
+            rbws.profile(True, reset=True)
+            for _ in range(10):
+                P.spmv(mu[:nb], x, y, precision=prec)
+            torch.cuda.synchronize()
+            kk = rbws.profile(False, reset=True)["spmv"]
+            spmv_by_tz[name][tzs] = round(bpd * nb * nd / (kk[0] / kk[1] * 1e-3) / 1e9, 1)
+        spmv[name] = max(spmv_by_tz[name].values())
+        del x, y
+    rbws.set_tuning(rbws.TUNE_TZ, 0)
+    return spmv, spmv_by_tz, spmv_tz, nb
 
 
 def copy_ceiling(rbws, torch, reps=10):

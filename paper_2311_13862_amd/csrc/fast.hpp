@@ -532,11 +532,20 @@ __device__ __forceinline__ void fast_body(const QuadGeo& G, const GridDev& g, co
         }
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
-      if (OP == FOP_UP2) {  // x is read again only by the next update: streamed
-        st4_stream<T, VEC>(X, c, nv, xo);
+      // FP32: x (read again only by the next update) and the product are streamed.
+      // FP64: a quad is two 16-byte stores per lane, each instruction covering half
+      // of every lane's 32 bytes; streamed, such stores reached memory as 1.12
+      // times the vector's bytes (SpMV), as ordinary stores exactly once
+      constexpr bool nt = sizeof(T) == 4;
+      if (OP == FOP_UP2) {
+        if constexpr (nt) st4_stream<T, VEC>(X, c, nv, xo);
+        else st4<T, VEC>(X, c, nv, xo);
         st4<T, VEC>(R, c, nv, ro);
       }
-      if (OP == FOP_SPMV) st4_stream<T, VEC>(X, c, nv, qo);
+      if (OP == FOP_SPMV) {
+        if constexpr (nt) st4_stream<T, VEC>(X, c, nv, qo);
+        else st4<T, VEC>(X, c, nv, qo);
+      }
     }
     // rotate; finish p_new of plane k+2 and store it when it is ours
 #pragma unroll
