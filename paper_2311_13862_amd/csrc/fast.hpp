@@ -878,7 +878,10 @@ __device__ __forceinline__ void outer_body(const QuadGeo& G, const GridDev& g, c
       }
       const long long c = (long long)(k - 1) * n2 + rowoff;
       st4<float, VEC>(R, c, nv, ro);
-      if (up) st4_stream<double, VEC>(Ud, c, nv, uc);  // read again at the next outer pass: streamed
+      // u' is read again only at the next outer pass, but a streamed FP64 quad (two
+      // 16-byte stores per lane, each covering half of every lane's 32 bytes)
+      // reached memory as more than u's bytes: ordinary stores (0.90 against 0.95 ms)
+      if (up) st4<double, VEC>(Ud, c, nv, uc);
     }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
