@@ -90,31 +90,24 @@ __device__ __forceinline__ void ld4(const T* __restrict__ a, long long c, int nv
   }
 }
 
-// store of a value that is not read again soon (streamed past the caches)
+// store of a value that is not read again soon (streamed past the caches).
+// FP32 only: a thread's quad is one 16-byte store, so each instruction writes
+// whole lines.  An FP64 quad would be two 16-byte stores, each covering half of
+// every lane's 32 bytes; streamed, such stores reached memory as 1.06-1.12
+// times the vector's bytes, so FP64 results go through ordinary stores.
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 template <typename T, bool VEC>
 __device__ __forceinline__ void st4_stream(T* __restrict__ a, long long c, int nv, const T v[4]) {
+  static_assert(sizeof(T) == 4, "streamed quad stores are for 4-byte values");
   if constexpr (VEC) {  // nv is 0 or 4 when n % 4 == 0
     if (nv == 4) {
-      if constexpr (sizeof(T) == 4) {
-        const nt_f4 q = {v[0], v[1], v[2], v[3]};
-        __builtin_nontemporal_store(q, reinterpret_cast<nt_f4*>(a + c));
-      } else {
-        const nt_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
-        __builtin_nontemporal_store(q0, reinterpret_cast<nt_d2*>(a + c));
-        __builtin_nontemporal_store(q1, reinterpret_cast<nt_d2*>(a + c + 2));
-      }
+      const nt_f4 q = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(q, reinterpret_cast<nt_f4*>(a + c));
     }
   } else if (nv == 4) {
-    if constexpr (sizeof(T) == 4) {
-      const ua_f4 q = {v[0], v[1], v[2], v[3]};
-      __builtin_nontemporal_store(q, reinterpret_cast<ua_f4*>(a + c));
-    } else {
-      const ua_d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
-      __builtin_nontemporal_store(q0, reinterpret_cast<ua_d2*>(a + c));
-      __builtin_nontemporal_store(q1, reinterpret_cast<ua_d2*>(a + c + 2));
-    }
+    const ua_f4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<ua_f4*>(a + c));
   } else {
 #pragma unroll
     for (int e = 0; e < 4; e++)
