@@ -654,6 +654,55 @@ __global__ __launch_bounds__(64) void k_mg_coarse(MgLv C, MgList ml, const doubl
   if (lane < mc) e[off + lane] = (T)xv;
 }
 
+// The coarsest operator's inverse from its stored factor, for the FP32 V-cycle:
+// thread (t, j) solves L L^T x = e_j (forward, then backward substitution, FP64)
+// and writes column j of A_c^{-1} (symmetric, stored row-major).
+__global__ void k_mg_inverse(MgLv C, const double* __restrict__ Lall, double* __restrict__ Iall) {
+  const int mc = (int)C.ndof;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)C.nsol * mc) return;
+  const int t = (int)(idx / mc), j = (int)(idx % mc);
+  const double* L = Lall + (long long)t * mc * mc;
+  double* X = Iall + (long long)t * mc * mc;
+  double y[27];
+  for (int i = 0; i < mc; i++) {
+    double sacc = i == j ? 1.0 : 0.0;
+    for (int k = 0; k < i; k++) sacc = __fma_rn(-L[i * mc + k], y[k], sacc);
+    y[i] = sacc / L[i * mc + i];
+  }
+  for (int i = mc - 1; i >= 0; i--) {
+    double sacc = y[i];
+    for (int k = i + 1; k < mc; k++) sacc = __fma_rn(-L[k * mc + i], y[k], sacc);
+    y[i] = sacc / L[i * mc + i];  // y[k > i] now holds x[k]
+  }
+  for (int i = 0; i < mc; i++) X[i * mc + j] = y[i];
+}
+
+// e = A_c^{-1} b for the FP32 V-cycle, one wave per listed solve: lane i forms
+// row i's dot product with b in FP64 (ascending k) and rounds it once to float.
+// The sequential triangular solves of k_mg_coarse (whose order the FP64 path
+// shares with the oracle) take a chain of 2 mc dependent steps with a division
+// each; this is one independent chain per lane.
+__global__ __launch_bounds__(64) void k_mg_coarse_inv(MgLv C, MgList ml, const double* __restrict__ Iall,
+                                                      const float* __restrict__ b, float* __restrict__ e) {
+  __shared__ double Is[27 * 27];
+  __shared__ double bs[27];
+  if ((int)blockIdx.x >= *ml.cnt) return;  // uniform over the block
+  const int lane = threadIdx.x;
+  const int t = ml.list[blockIdx.x];
+  const int mc = (int)C.ndof;
+  const double* I = Iall + (long long)t * mc * mc;
+  const long long off = C.voff ? C.voff[t] : (long long)t * C.ndof;
+  for (int x = lane; x < mc * mc; x += 64) Is[x] = I[x];
+  if (lane < mc) bs[lane] = (double)b[off + lane];
+  __syncthreads();
+  if (lane < mc) {
+    double acc = 0.0;
+    for (int k = 0; k < mc; k++) acc = __fma_rn(Is[lane * mc + k], bs[k], acc);
+    e[off + lane] = (float)acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Level 0, after the coarse correction (nu = 1): one z-march over each tile of
 // the batch (the CG work items) forms e2 = e1 + P e_c at the tile's points and
@@ -1647,6 +1696,7 @@ struct MgGroup {
   std::vector<MgLevelHost*> lv;    // this batch's levels, finest first (a prefix of lvpool)
   std::vector<MgLevelHost*> lvpool;  // owned; kept across batches so their buffers are reused
   DevBuf L;
+  DevBuf Linv;  // FP32 V-cycle: the coarsest operator's inverse per solve (FP64)
   int mc = 0;
   ~MgGroup() {
     for (MgLevelHost* l : lvpool) delete l;
@@ -1830,6 +1880,12 @@ MgRun* mg_prepare(Batch& B, int nu, double omega, bool fp32, hipStream_t s) {
     RBWS_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     RBWS_HIP(hipStreamSynchronize(s));
     RBWS_REQUIRE(hb == 0, RBWS_ENUMERIC, "coarsest multigrid operator not positive definite");
+    if (fp32) {
+      double* Li = (double*)g->Linv.get(sizeof(double) * (size_t)ns * g->mc * g->mc, B.device);
+      const long long nth = (long long)ns * g->mc;
+      hipLaunchKernelGGL(k_mg_inverse, dim3((unsigned)((nth + 63) / 64)), dim3(64), 0, s, cv, (const double*)Lf, Li);
+      RBWS_HIP(hipGetLastError());
+    }
   }
   // the fused level-0 post step needs nu = 1 and a coarse level for every problem
   m->fused = nu == 1;
@@ -1914,6 +1970,12 @@ static void vcycle(MgRun* m, MgGroup& g, int l, const T* b, T* e, T* scratch, T*
   const bool l0 = l == 0;
   const MgLv v = view(lv, g, l0, m->fp32);
   if (l + 1 == (int)g.lv.size()) {
+    if constexpr (sizeof(T) == 4) {
+      if (m->fp32) {
+        hipLaunchKernelGGL(k_mg_coarse_inv, dim3(ns), dim3(64), 0, s, v, ml, (const double*)g.Linv.ptr, b, e);
+        return;
+      }
+    }
     hipLaunchKernelGGL(k_mg_coarse<T>, dim3(ns), dim3(64), 0, s, v, ml, (const double*)g.L.ptr, b, e);
     return;
   }
